@@ -1,0 +1,222 @@
+"""Seeded synthetic workloads for LTL4-C monitoring.
+
+This module only draws inputs: record arrays, the record layout, the
+event-type table and the property specifications (formula text plus the
+quantifier string).  It holds none of the method's arithmetic and is the one
+module that both the product path and the test oracle read.
+
+The paper's own case-study traces (Apache runs, Dropbox and YouTube datasets)
+are not available; these generators stand in for them with the shapes the
+case studies describe: a socket-keyed request/response trace, a two-level
+user/request trace with Zipf-skewed request counts, and long single traces
+with Zipf-skewed cluster lengths.
+
+Every generator uses numpy's PCG64 with an explicit seed.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Layout:
+    """Where the event type and the key fields sit inside one record."""
+    record_bytes: int
+    type_offset: int
+    type_bytes: int
+    key_offsets: list
+    key_bytes: list
+    key_bits: list                  # declared width of every key value
+    class_of_type: np.ndarray       # [256] uint8
+    key_present: np.ndarray         # [256] uint8, bit m = the type carries key m
+    class_props: list               # class -> set of propositions that hold
+    type_names: dict = field(default_factory=dict)
+
+    @property
+    def n_keys(self):
+        return len(self.key_offsets)
+
+    @property
+    def n_classes(self):
+        return len(self.class_props)
+
+
+@dataclass
+class PropertySpec:
+    """phi = Q_0 ... Q_{n-1} psi: quantifiers as (kind, op, const) with kind
+    'A' (percentage) or 'E' (instance count); const is a fraction string for
+    'A' and an integer for 'E'."""
+    formula: str
+    quants: list
+    name: str = ""
+
+
+@dataclass
+class Workload:
+    name: str
+    records: np.ndarray            # structured array
+    layout: Layout
+    props: list                    # [PropertySpec]
+
+    @property
+    def n_events(self):
+        return int(self.records.shape[0])
+
+    def raw(self):
+        return self.records.view(np.uint8).reshape(-1)
+
+
+def _type_table(n_types, class_of, all_keys_mask):
+    cot = np.zeros(256, dtype=np.uint8)
+    kp = np.zeros(256, dtype=np.uint8)
+    for t in range(n_types):
+        cot[t] = class_of[t]
+        kp[t] = all_keys_mask
+    return cot, kp
+
+
+REC12 = np.dtype([("ts", "<u4"), ("type", "<u2"), ("pad", "<u2"), ("key", "<u4")])
+REC16 = np.dtype([("ts", "<u4"), ("type", "<u4"), ("k0", "<u4"), ("k1", "<u4")])
+
+
+def socket_layout():
+    cot, kp = _type_table(4, [0, 1, 2, 3], 0b1)
+    return Layout(12, 4, 2, [8], [4], [10], cot, kp,
+                  [set(), {"receive"}, {"respond"}, set()],
+                  {0: "open", 1: "receive", 2: "respond", 3: "close"})
+
+
+def socket_properties():
+    # Case study 1: at least 95% of sockets answer every request.  The
+    # formula is printed in two ways in the paper; both are monitored.
+    return [PropertySpec("G(receive -> F respond)", [("A", ">=", "19/20")], "sockets-G(r->Fs)"),
+            PropertySpec("(G receive) -> (F respond)", [("A", ">=", "19/20")], "sockets-(Gr)->(Fs)")]
+
+
+def gen_sockets(n_events=100_000, n_sockets=1000, seed=0x14112239 + 1):
+    """Single quantifier over sockets; 12-byte records."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rec = np.zeros(n_events, dtype=REC12)
+    rec["ts"] = np.arange(n_events, dtype=np.uint32)
+    rec["type"] = rng.choice(4, size=n_events, p=[0.1, 0.5, 0.35, 0.05]).astype(np.uint16)
+    rec["key"] = rng.integers(0, n_sockets, size=n_events, dtype=np.uint32)
+    lay = socket_layout()
+    lay.key_bits = [max(1, int(n_sockets - 1).bit_length())]
+    return Workload("sockets", rec, lay, socket_properties())
+
+
+def user_request_layout(user_bits=14, req_bits=22):
+    cot, kp = _type_table(4, [0, 1, 2, 3], 0b11)
+    return Layout(16, 4, 4, [8, 12], [4, 4], [user_bits, req_bits], cot, kp,
+                  [{"issue"}, set(), {"done"}, set()],
+                  {0: "issue", 1: "progress", 2: "done", 3: "other"})
+
+
+def user_request_properties():
+    return [PropertySpec("G(issue -> F done)", [("E", ">=", 500), ("A", ">=", "9/10")],
+                         "users-E>=500-A>=0.9")]
+
+
+def gen_user_requests(n_events=10_000_000, n_users=10_000, zipf_s=1.2, p_done=0.95,
+                      seed=0x14112239 + 2):
+    """Two nested quantifiers (user, request); 16-byte records.
+
+    Request counts per user follow Zipf(zipf_s) over user ranks.  A request
+    emits an issue event, a geometric number (mean 1) of progress events and,
+    with probability p_done, a done event.  Events get random start times and
+    exponential gaps; the trace is their time order, topped up with type-3
+    events on existing requests to exactly n_events.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mean_events = 1.0 + 1.0 + p_done
+    n_req = max(n_users, int(n_events / mean_events))
+    ranks = np.arange(1, n_users + 1, dtype=np.float64)
+    w = ranks ** (-zipf_s)
+    per_user = np.maximum(1, np.round(n_req * w / w.sum())).astype(np.int64)
+    n_req = int(per_user.sum())
+    user_ids = rng.permutation(n_users).astype(np.uint32)
+    req_user = np.repeat(user_ids, per_user)
+    req_ids = rng.permutation(n_req).astype(np.uint32)
+    n_prog = rng.geometric(0.5, size=n_req) - 1
+    done = rng.random(n_req) < p_done
+    per_req = 1 + n_prog + done.astype(np.int64)
+    # drop whole requests from the end until the trace fits
+    csum = np.cumsum(per_req)
+    keep = int(np.searchsorted(csum, n_events, side="right"))
+    req_user, req_ids, n_prog, done, per_req = (a[:keep] for a in (req_user, req_ids, n_prog, done, per_req))
+    total = int(per_req.sum())
+    start = rng.random(keep) * 1e6
+    ev_req = np.repeat(np.arange(keep), per_req)
+    first = np.concatenate([[0], np.cumsum(per_req)[:-1]])
+    pos_in_req = np.arange(total) - np.repeat(first, per_req)
+    gaps = rng.exponential(1.0, size=total)
+    gaps[first] = 0.0
+    # time = start + cumulative gap inside the request
+    cg = np.cumsum(gaps)
+    cg = cg - np.repeat(cg[first], per_req)
+    t = start[ev_req] + cg
+    etype = np.where(pos_in_req == 0, 0, 1).astype(np.uint32)
+    last = first + per_req - 1
+    etype[last[done]] = 2
+    n_noise = n_events - total
+    if n_noise > 0:
+        nr = rng.integers(0, keep, size=n_noise)
+        t = np.concatenate([t, rng.random(n_noise) * 1e6])
+        ev_req = np.concatenate([ev_req, nr])
+        etype = np.concatenate([etype, np.full(n_noise, 3, dtype=np.uint32)])
+    order = np.argsort(t, kind="stable")
+    rec = np.zeros(n_events, dtype=REC16)
+    rec["ts"] = np.arange(n_events, dtype=np.uint32)
+    rec["type"] = etype[order]
+    rec["k0"] = req_user[ev_req[order]]
+    rec["k1"] = req_ids[ev_req[order]]
+    lay = user_request_layout(max(1, int(n_users - 1).bit_length()), max(1, int(n_req - 1).bit_length()))
+    return Workload("users", rec, lay, user_request_properties())
+
+
+def prop_layout(n_props=3, n_levels=1, key_bits=None):
+    """16-byte records whose type field is a bit set of propositions a, b, c, ...
+
+    Class = type; class c carries the propositions whose bit is set in c.
+    """
+    names = "abcd"[:n_props]
+    n_cls = 1 << n_props
+    cot, kp = _type_table(n_cls, list(range(n_cls)), (1 << n_levels) - 1)
+    offs = [8, 12][:n_levels]
+    kb = key_bits or [32] * n_levels
+    return Layout(16, 4, 4, offs, [4] * n_levels, kb, cot, kp,
+                  [{names[i] for i in range(n_props) if (c >> i) & 1} for c in range(n_cls)])
+
+
+def zipf_ranks(rng, n, n_ranks, s):
+    """Draw n ranks in [0, n_ranks) with P(r) proportional to (r+1)^-s."""
+    w = np.arange(1, n_ranks + 1, dtype=np.float64) ** (-s)
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    return np.minimum(np.searchsorted(cdf, rng.random(n), side="right"), n_ranks - 1)
+
+
+def gen_prop_trace(n_events, n_keys, zipf_s, p_props=(0.02, 0.9, 0.5), seed=0, key_space_bits=32,
+                   props=None, name="proptrace"):
+    """One long trace: proposition bits drawn independently, keys Zipf-skewed
+    over n_keys ranks and mapped to distinct random values."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ranks = zipf_ranks(rng, n_events, n_keys, zipf_s)
+    if key_space_bits >= 32:
+        vals = np.unique(rng.integers(0, 1 << 32, size=int(n_keys * 1.2) + 16, dtype=np.uint64))
+        while vals.size < n_keys:
+            vals = np.unique(np.concatenate([vals, rng.integers(0, 1 << 32, size=n_keys, dtype=np.uint64)]))
+        key_of_rank = rng.permutation(vals)[:n_keys].astype(np.uint32)
+    else:
+        key_of_rank = rng.permutation(1 << key_space_bits)[:n_keys].astype(np.uint32)
+    typ = np.zeros(n_events, dtype=np.uint32)
+    for i, p in enumerate(p_props):
+        typ |= (rng.random(n_events) < p).astype(np.uint32) << i
+    rec = np.zeros(n_events, dtype=REC16)
+    rec["ts"] = np.arange(n_events, dtype=np.uint32)
+    rec["type"] = typ
+    rec["k0"] = key_of_rank[ranks]
+    lay = prop_layout(len(p_props), 1, [key_space_bits])
+    return Workload(name, rec, lay, props or [])
