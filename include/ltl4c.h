@@ -1,0 +1,219 @@
+/*
+ * ltl4c.h -- C ABI of the MI355X LTL4-C trace-monitoring library.
+ *
+ * The library evaluates LTL4-C properties phi = Q_0 ... Q_{n-1} psi
+ * (Section 2.4, Eq. 3-4 of arXiv 1411.2239) on an event trace that already
+ * resides in device memory.  Its inputs follow the input line of Algorithm 1:
+ * an LTL4 monitor of psi (Def. 6, as a transition table), the trace u, the
+ * quantifier string Q and the key vector K used to extract the values of the
+ * quantified variables (Section 4.1).  Its outputs are the truth value of the
+ * property (the root of the monitor tree, Section 3.4) and, on request, the
+ * verdict of every submonitor: every LTL4 instance and every quantifier node
+ * with its 6-bin count vector (Def. 8).
+ *
+ * Conventions for every function:
+ *  - the return value is a status code (LTL4C_OK = 0, negative on error);
+ *    no C++ exception crosses the ABI;
+ *  - argument validation is synchronous and happens before anything is
+ *    enqueued; a call that returns an error has enqueued no work;
+ *  - pointers documented as "device" must point to memory of the context's
+ *    device; pointers documented as "host" are read during the call only;
+ *  - work is enqueued on the context's stream (ltl4c_set_stream); results in
+ *    device memory are valid once that stream has been synchronised, and
+ *    ltl4c_wait() both synchronises and reports errors detected on the
+ *    device (a key wider than declared, a capacity overflow);
+ *  - a context is not thread-safe: one host thread drives it at a time.
+ */
+#ifndef LTL4C_H
+#define LTL4C_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define LTL4C_OK            0
+#define LTL4C_EINVAL       -1  /* malformed argument (table, quantifier, layout, pointer) */
+#define LTL4C_ENOMEM       -2  /* device or host allocation failed; workspace too small */
+#define LTL4C_ECAPACITY    -3  /* more nodes/bindings than the capacity given */
+#define LTL4C_EDEVICE      -4  /* a HIP call failed; ltl4c_last_error() has its text */
+#define LTL4C_EADMIT       -5  /* a stream could not be admitted within the memory budget */
+#define LTL4C_ESEQ         -6  /* call on a closed stream or out of sequence */
+#define LTL4C_EUNSUPPORTED -7  /* beyond the library's limits (see below) */
+#define LTL4C_ERANGE       -8  /* an event carried a key wider than its declared width */
+
+/* ---- truth values: B6 in lattice order F < Fc < Fp < Tp < Tc < T
+ *      (Section 2.3); LTL4 verdicts (Def. 5) use F, Fp, Tp, T -------------- */
+enum { LTL4C_BOT = 0, LTL4C_BOT_C = 1, LTL4C_BOT_P = 2,
+       LTL4C_TOP_P = 3, LTL4C_TOP_C = 4, LTL4C_TOP = 5 };
+
+/* ---- quantifiers (Def. 3, Eq. 4): A = percentage, E = instance count ---- */
+enum { LTL4C_Q_PERCENT = 0, LTL4C_Q_COUNT = 1 };
+enum { LTL4C_LT = 0, LTL4C_LE = 1, LTL4C_GT = 2, LTL4C_GE = 3, LTL4C_EQ = 4 };
+
+/* Limits. */
+#define LTL4C_MAX_STATES   16  /* states of one monitor (4-bit state codes) */
+#define LTL4C_MAX_CLASSES  16  /* event classes (letters) of one layout */
+#define LTL4C_MAX_LEVELS    4  /* quantifiers per property */
+#define LTL4C_MAX_PROPS    16  /* properties evaluated in one call */
+#define LTL4C_MAX_EVENTS   ((1ull << 30) - 1)   /* events per ltl4c_eval call */
+
+typedef struct ltl4c_ctx ltl4c_ctx;
+
+/*
+ * Record layout and valuation extraction (epsilon(u_i, K), Section 4.1).
+ * A record is record_bytes long (a multiple of 4, at most 256).  The event
+ * type is an unsigned little-endian field of type_bytes (1, 2 or 4) at
+ * type_offset; key m (the value of the quantified variable x_m) is an
+ * unsigned field of key_bytes[m] (1, 2 or 4) at key_offset[m].  Every field
+ * must be naturally aligned (offset a multiple of its size).
+ *
+ * class_of_type[t] is the letter (event class, < n_classes) of an event of
+ * type t; the monitor tables are indexed by class.  key_present[t] has bit m
+ * set when events of type t carry key m.  An event whose type is >= 256 or
+ * lacks any of the n_keys keys belongs to no cluster (it is ignored, as the
+ * set of value vectors of Eq. 5 only contains complete vectors).
+ *
+ * key_bits[m] (1..32) is the declared width of key m: every key value must be
+ * below 2^key_bits[m].  The composite binding key (key 0 in the most
+ * significant bits) plus the class bits must fit in 63 bits.  A wider value
+ * is detected on the device and reported as LTL4C_ERANGE by ltl4c_wait().
+ */
+typedef struct {
+    uint32_t record_bytes;
+    uint32_t type_offset;
+    uint32_t type_bytes;
+    uint32_t n_keys;                 /* number of quantifier levels, 1..4 */
+    uint32_t key_offset[4];
+    uint32_t key_bytes[4];
+    uint32_t key_bits[4];
+    uint32_t n_classes;              /* 1..16 */
+    uint8_t  class_of_type[256];
+    uint8_t  key_present[256];
+} ltl4c_layout;
+
+/*
+ * An LTL4 monitor (Def. 6): the deterministic machine (Sigma, Q, q0, delta,
+ * lambda) with [u |=4 psi] = lambda(delta(q0, u)).  delta is row-major
+ * [n_states][n_classes] with entries < n_states; label[q] is lambda(q), one of
+ * LTL4C_BOT, LTL4C_BOT_P, LTL4C_TOP_P, LTL4C_TOP.  Host memory, copied.
+ */
+typedef struct {
+    uint32_t n_states;               /* 1..16 */
+    uint32_t n_classes;              /* must equal the layout's n_classes */
+    uint32_t q0;
+    const uint8_t *delta;
+    const uint8_t *label;
+} ltl4c_monitor;
+
+/*
+ * One counting quantifier Q_m = <kind, op, constant> (Eq. 4).  For
+ * LTL4C_Q_PERCENT the constant is the exact rational num/den in [0, 1]
+ * (den > 0, num <= den); for LTL4C_Q_COUNT it is the integer num (den ignored).
+ * The numerical constraint S of Eq. 6 is evaluated exactly: k*den ~ num*N.
+ */
+typedef struct {
+    uint32_t kind;
+    uint32_t op;
+    uint32_t num;
+    uint32_t den;
+} ltl4c_quant;
+
+/* A property: monitor id from ltl4c_add_monitor and Q_0 (outermost) .. Q_{n-1}. */
+typedef struct {
+    int32_t monitor;
+    uint32_t n_levels;               /* must equal the layout's n_keys */
+    ltl4c_quant q[4];
+} ltl4c_property;
+
+/*
+ * Outputs of one evaluation, all in device memory of the context's device.
+ * Instances and nodes are numbered in increasing order of their (packed)
+ * value vectors.  Optional arrays may be NULL; each optional array has room
+ * for `capacity` entries per property, and a run that needs more reports
+ * LTL4C_ECAPACITY from ltl4c_wait() (nothing beyond capacity is written).
+ *
+ *   root_verdict [n_props]                  truth value of each property
+ *   root_counts  [n_props * 6]              child-verdict counts of the root
+ *   sizes        [1 + n_levels]             sizes[0] = number of instances
+ *                                           (full value vectors); sizes[m] =
+ *                                           number of nodes at level m
+ *                                           (m = 1..n_levels-1); unused
+ *                                           entries are 0
+ *   inst_keys    [capacity]                 packed value vector of instance i
+ *   inst_verdict [n_props * capacity]       LTL4 verdict of instance i
+ *   node_keys[m] [capacity]                 packed prefix (keys 0..m-1) of node j
+ *   node_counts[m] [n_props * capacity * 6] 6-bin counts v of node j (Def. 8)
+ *   node_verdict[m] [n_props * capacity]    verdict of node j
+ * (node_* index m runs over 1..n_levels-1; index 0 is unused.)
+ */
+typedef struct {
+    uint8_t  *root_verdict;
+    uint64_t *root_counts;
+    uint64_t *sizes;
+    uint64_t  capacity;
+    uint64_t *inst_keys;
+    uint8_t  *inst_verdict;
+    uint64_t *node_keys[4];
+    uint32_t *node_counts[4];
+    uint8_t  *node_verdict[4];
+} ltl4c_result;
+
+/* ---- context ----------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  Work goes to the null stream
+ * until ltl4c_set_stream() names another.  *out receives the context. */
+int32_t ltl4c_create(ltl4c_ctx **out, int32_t device);
+int32_t ltl4c_destroy(ltl4c_ctx *ctx);
+/* Use `hip_stream` (a hipStream_t, may be NULL for the null stream). */
+int32_t ltl4c_set_stream(ltl4c_ctx *ctx, void *hip_stream);
+/* Text of the last error recorded on this thread (never NULL). */
+const char *ltl4c_last_error(void);
+const char *ltl4c_status_str(int32_t status);
+
+/* Set the record layout; resets the registered properties. */
+int32_t ltl4c_set_layout(ltl4c_ctx *ctx, const ltl4c_layout *layout);
+/* Register a monitor; *id receives its id. EINVAL: entries out of range. */
+int32_t ltl4c_add_monitor(ltl4c_ctx *ctx, const ltl4c_monitor *m, int32_t *id);
+/* Register a property; *id receives its id. EINVAL: bad op/kind/constant. */
+int32_t ltl4c_add_property(ltl4c_ctx *ctx, const ltl4c_property *p, int32_t *id);
+
+/* ---- offline evaluation (Algorithm 1: SortTrace, SpawnMonitors,
+ *      Distribute, ApplyQuantifiers) -------------------------------------- */
+
+/* Bytes of device workspace ltl4c_eval needs for n_events events and the
+ * properties `props` (n_props of them). */
+int32_t ltl4c_workspace_bytes(ltl4c_ctx *ctx, uint64_t n_events, const int32_t *props,
+                              int32_t n_props, uint64_t *bytes);
+
+/* Evaluate the properties `props` (host array of ids) on the trace
+ * d_records (device, n_events records in trace order).  d_workspace is
+ * caller-owned device memory of at least the queried size, 256-byte aligned;
+ * it is clobbered.  Asynchronous on the context's stream. */
+int32_t ltl4c_eval(ltl4c_ctx *ctx, const void *d_records, uint64_t n_events,
+                   const int32_t *props, int32_t n_props,
+                   void *d_workspace, uint64_t workspace_bytes,
+                   const ltl4c_result *out);
+
+/* Synchronise the context's stream and report device-detected errors of the
+ * work enqueued since the previous ltl4c_wait (LTL4C_ERANGE, ECAPACITY). */
+int32_t ltl4c_wait(ltl4c_ctx *ctx);
+
+/* ---- profiling: per-kernel time of the enqueued work ------------------- */
+
+/* When enabled, every kernel launch is bracketed by HIP events on the
+ * context's stream and its duration accumulated per kernel name. */
+int32_t ltl4c_profile_enable(ltl4c_ctx *ctx, int32_t on);
+/* Synchronises, then reports kernel i (0-based): name (copied into name_buf
+ * of name_len bytes), total milliseconds and launch count.  Returns
+ * LTL4C_EINVAL when i is past the last kernel seen. */
+int32_t ltl4c_profile_get(ltl4c_ctx *ctx, int32_t i, char *name_buf, int32_t name_len,
+                          double *total_ms, uint64_t *launches);
+int32_t ltl4c_profile_reset(ltl4c_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LTL4C_H */

@@ -1,0 +1,157 @@
+// Internal declarations shared by the HIP kernels and the host runtime of
+// libltl4c.  Not part of the public ABI (include/ltl4c.h is).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ltl4c {
+
+constexpr int kMaxProps = 16;
+constexpr int kMaxLevels = 4;
+constexpr int kStates = 16;          // nibble-packed maps always carry 16 lanes
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;     // 4096 words per tile
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;     // 4096 words per tile
+constexpr int kCountThreads = 256;
+constexpr int kCountItems = 16;
+constexpr int kCountTile = kCountThreads * kCountItems;
+constexpr int kCountWindow = 64;     // nodes kept in LDS per counting tile
+constexpr uint64_t kIdentityMap = 0xFEDCBA9876543210ull;
+constexpr uint32_t kSpinLimit = 1u << 22;   // bounded waits in decoupled look-back
+
+// Error bits raised on the device and reported by ltl4c_wait().
+enum : uint32_t { kErrRange = 1u, kErrCapacity = 2u, kErrSpin = 4u };
+
+// One property as the kernels see it (lives in device memory).
+struct PropDev {
+    uint8_t delta[kStates * 16];     // delta[q * 16 + c]
+    uint8_t label[kStates];
+    uint64_t colmap[16];             // class c -> packed map q -> delta(q, c); lanes >= n_states identity
+    uint32_t q0, n_states;
+    uint32_t kind[kMaxLevels], op[kMaxLevels], num[kMaxLevels], den[kMaxLevels];
+};
+
+struct Plan {
+    PropDev prop[kMaxProps];
+    uint8_t class_of_type[256];
+    uint8_t key_present[256];
+};
+
+// Look-back record of one scan tile: aggregate and inclusive payloads are
+// kept apart so a reader that saw "aggregate" never reads an overwritten one.
+struct ScanTileStatus {
+    uint32_t agg_cnt[4];
+    uint32_t inc_cnt[4];
+    uint64_t agg_map[kMaxProps];
+    uint64_t inc_map[kMaxProps];
+};
+
+struct ClassifyArgs {
+    const uint8_t* records;
+    uint64_t n;
+    uint32_t record_bytes;
+    uint32_t type_dw, type_shift, type_mask;
+    uint32_t n_keys;
+    uint32_t key_dw[kMaxLevels], key_shift[kMaxLevels], key_mask[kMaxLevels], key_bits[kMaxLevels];
+    uint32_t need_mask;              // key_present bits every event must carry
+    uint32_t check_type_range;       // the type field can exceed 255
+    uint32_t cbits;
+    uint32_t excl_shift;             // bit set in the word of an excluded event
+    uint32_t n_pass;                 // radix passes whose histograms are built here
+    uint32_t sort_shift;             // lowest sorted bit
+    const Plan* plan;
+    uint64_t* words;
+    uint32_t* hist;                  // [n_pass][256]
+    uint32_t* err;
+};
+
+struct SortPassArgs {
+    const uint64_t* in;
+    uint64_t* out;
+    uint32_t n;
+    uint32_t shift;                  // lowest bit of this pass's digit
+    uint32_t nbits;                  // digit width (<= 8)
+    const uint32_t* hist;            // this pass's global histogram [256]
+    uint32_t* status;                // [tiles][256] look-back words
+    uint32_t* ticket;
+    uint32_t* err;
+};
+
+struct ScanArgs {
+    const uint64_t* words;
+    uint32_t n;
+    uint32_t cbits;
+    uint32_t n_levels;
+    uint32_t prefix_shift[kMaxLevels];   // word >> prefix_shift[m] = packed keys 0..m-1 (m>=1)
+    uint32_t valid_shift;                // word >> valid_shift != 0 means excluded
+    uint32_t n_props;
+    const Plan* plan;
+    uint8_t* inst_verdict;               // [n_props][inst_stride]
+    uint64_t inst_stride;
+    uint64_t inst_limit;                 // instances with an id below this are written
+    uint64_t* inst_keys;                 // optional [inst_limit]
+    uint32_t* node_start[kMaxLevels];    // level m: first child of node j
+    uint64_t* node_keys[kMaxLevels];     // optional
+    uint64_t node_limit[kMaxLevels];     // nodes with an id below this are written
+    uint32_t* flags;                     // [tiles] look-back flags
+    ScanTileStatus* status;              // [tiles]
+    uint32_t* ticket;
+    uint64_t* sizes;                     // [1 + n_levels] written by the last tile
+    uint32_t* sizes32;                   // same, 32-bit, for the counting kernels
+    uint32_t* err;
+};
+
+struct CountArgs {
+    uint32_t level;                      // m: the parents' level (0 = root)
+    uint32_t n_levels;
+    uint32_t n_props;
+    const Plan* plan;
+    // children
+    const uint32_t* n_children;          // device count of children
+    uint64_t child_limit;                // children beyond this were not recorded
+    const uint8_t* child_verdict;        // level m+1 == n_levels: instance verdicts [p][child_stride]
+    const uint32_t* child_counts;        // otherwise: counts of level m+1 [p][child_stride][6]
+    uint64_t child_stride;
+    uint8_t* child_verdict_out;          // optional: verdicts of level m+1 nodes [p][child_stride]
+    // parents
+    const uint32_t* node_start;          // level m >= 1: CSR first child per node
+    const uint32_t* n_nodes;             // device count of level-m nodes (m >= 1)
+    uint64_t node_limit;                 // nodes beyond this were not recorded
+    uint32_t* counts;                    // [p][stride][6]
+    uint64_t stride;
+    uint32_t* err;
+};
+
+struct ZeroArgs {
+    uint32_t* ptr;
+    const uint32_t* n_dev;               // if non-null: words = min(*n_dev, limit) * mult
+    uint64_t mult;
+    uint64_t n_words;                    // used when n_dev is null
+    uint64_t limit;
+};
+
+struct FinalizeArgs {
+    uint32_t n_props;
+    const Plan* plan;
+    const uint32_t* root_counts;         // [p][6]
+    uint8_t* root_verdict;
+    uint64_t* root_counts_out;
+    const uint64_t* sizes_ws;            // [n_levels] from the scan
+    uint64_t* sizes_out;                 // [1 + n_levels]
+    uint32_t n_levels;
+};
+
+// Launchers (defined in kernels.hip).
+hipError_t launch_zero(const ZeroArgs& a, uint32_t blocks, hipStream_t s);
+hipError_t launch_classify(const ClassifyArgs& a, hipStream_t s);
+hipError_t launch_sort_pass(const SortPassArgs& a, hipStream_t s);
+hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
+hipError_t launch_count(const CountArgs& a, hipStream_t s);
+hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
+
+}  // namespace ltl4c

@@ -1,0 +1,702 @@
+// HIP kernels of the LTL4-C hot path for gfx950 (CDNA4, wave64).
+//
+//   k_classify   valuation extraction epsilon(u_i, K) (Section 4.1, the map
+//                step of SortTrace in Algorithm 1): record -> letter (event
+//                class) and packed binding key; builds the radix histograms
+//                of every sort pass in the same read.
+//   k_sort_pass  one stable LSD radix pass (ParallelSort of Algorithm 1):
+//                single-pass "onesweep" ranking with wave ballots, LDS-staged
+//                scatter and decoupled look-back across tiles.
+//   k_scan       Distribute / ProcessBuffer of Algorithm 1 as a flat scan:
+//                composes nibble-packed transition maps (a segment head is
+//                the constant map to delta(q0, c)), so each instance's final
+//                state lambda(delta(q0, u^D)) (Def. 6) is found without one
+//                thread per monitor; also the compaction (ParallelCompact)
+//                into instance and node numbering.
+//   k_count      ApplyQuantifiers of Algorithm 1 for one level: the 6-bin
+//                count vector v of every quantifier submonitor (Def. 8) from
+//                its children's verdicts.
+//   k_finalize   Def. 7 at the root.
+#include "internal.h"
+
+namespace ltl4c {
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t ld_acquire_flag(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_flag(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t map_const(uint32_t s) { return (uint64_t)s * 0x1111111111111111ull; }
+__device__ __forceinline__ bool map_is_const(uint64_t f) { return f == (f & 15ull) * 0x1111111111111111ull; }
+__device__ __forceinline__ uint32_t map_at(uint64_t f, uint32_t q) { return (uint32_t)(f >> (4u * q)) & 15u; }
+
+// (g o f)[q] = g[f[q]] over all 16 lanes.
+__device__ __forceinline__ uint64_t map_compose_full(uint64_t g, uint64_t f) {
+    uint64_t r = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        uint32_t fq = (uint32_t)(f >> (4 * q)) & 15u;
+        r |= ((g >> (4u * fq)) & 15ull) << (4 * q);
+    }
+    return r;
+}
+
+// g after f, with the constant-map shortcuts.
+__device__ __forceinline__ uint64_t map_compose(uint64_t g, uint64_t f) {
+    if (map_is_const(g)) return g;
+    if (map_is_const(f)) return map_const(map_at(g, (uint32_t)(f & 15u)));
+    return map_compose_full(g, f);
+}
+
+__device__ __forceinline__ uint64_t shfl_up64(uint64_t v, int off) {
+    uint32_t lo = __shfl_up((uint32_t)v, off, 64);
+    uint32_t hi = __shfl_up((uint32_t)(v >> 32), off, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t o = __shfl_up(v, off, 64);
+        if (lane >= off) v += o;
+    }
+    return v;
+}
+
+// Exclusive scan of one value per thread over a 256-thread block.
+__device__ __forceinline__ uint32_t block256_excl_scan(uint32_t v, uint32_t* s_tmp /*[4]*/, uint32_t* total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t incl = wave_incl_scan_u32(v);
+    if (lane == 63) s_tmp[w] = incl;
+    __syncthreads();
+    uint32_t pre = 0;
+    for (int i = 0; i < w; ++i) pre += s_tmp[i];
+    *total = s_tmp[0] + s_tmp[1] + s_tmp[2] + s_tmp[3];
+    __syncthreads();
+    return pre + incl - v;
+}
+
+// Eq. 6 and Def. 7 (device restatement; exact integers).
+__device__ __forceinline__ bool cmp_op(uint64_t a, uint32_t op, uint64_t b) {
+    switch (op) {
+        case 0: return a < b;
+        case 1: return a <= b;
+        case 2: return a > b;
+        case 3: return a >= b;
+        default: return a == b;
+    }
+}
+
+__device__ __forceinline__ bool constraint_S(uint32_t kind, uint32_t op, uint32_t num, uint32_t den,
+                                             uint64_t k, uint64_t n) {
+    if (kind == 0) return cmp_op(k * (uint64_t)den, op, (uint64_t)num * n);   // percentage
+    return cmp_op(k, op, (uint64_t)num);                                       // instance count
+}
+
+// Table 1 and the rule for A=1, extended to every operator: can no
+// extension move the count of T children out of the constraint?
+__device__ __forceinline__ bool forever_sat(uint32_t kind, uint32_t op, uint32_t num, uint32_t den,
+                                            uint64_t top, uint64_t bot) {
+    if (kind == 1) return (op == 2 && top > num) || (op == 3 && top >= num);
+    const bool zero = num == 0, one = num == den;
+    switch (op) {
+        case 3: return zero;
+        case 2: return zero && top >= 1;
+        case 1: return one;
+        case 0: return one && bot >= 1;
+        default: return false;
+    }
+}
+
+// Can no extension bring the count of non-F children into the constraint?
+__device__ __forceinline__ bool forever_viol(uint32_t kind, uint32_t op, uint32_t num, uint32_t den,
+                                             uint64_t top, uint64_t bot) {
+    if (kind == 1) return ((op == 4 || op == 1) && top > num) || (op == 0 && top >= num);
+    const bool zero = num == 0, one = num == den;
+    switch (op) {
+        case 3: return one && bot >= 1;
+        case 2: return one;
+        case 1: return zero && top >= 1;
+        case 0: return zero;
+        default: return (one && bot >= 1) || (zero && top >= 1);
+    }
+}
+
+// Def. 7: the highest truth value whose condition holds.
+__device__ __forceinline__ uint32_t valuate(const PropDev& P, int m, const uint32_t* v) {
+    const uint32_t kind = P.kind[m], op = P.op[m], num = P.num[m], den = P.den[m];
+    const uint64_t n = (uint64_t)v[0] + v[1] + v[2] + v[3] + v[4] + v[5];
+    const uint64_t t = v[5];                 // {T}
+    const uint64_t tc = t + v[4];            // {T, Tc}
+    const uint64_t tp = tc + v[3];           // {T, Tc, Tp}
+    const uint64_t nf2 = tp + v[2];          // B6 - {F, Fc}
+    const uint64_t nf1 = nf2 + v[1];         // B6 - {F}
+    if (constraint_S(kind, op, num, den, t, n) && forever_sat(kind, op, num, den, t, v[0])) return 5;
+    if (constraint_S(kind, op, num, den, tc, n)) return 4;
+    if (constraint_S(kind, op, num, den, tp, n)) return 3;
+    if (constraint_S(kind, op, num, den, nf2, n)) return 2;
+    if (!constraint_S(kind, op, num, den, nf1, n) && forever_viol(kind, op, num, den, t, v[0])) return 0;
+    return 1;
+}
+
+// ---------------------------------------------------------------------------
+// zero fill (look-back flags, histograms, counters; counts of a level)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_zero(ZeroArgs a) {
+    const uint64_t n = a.n_dev ? min<uint64_t>(*a.n_dev, a.limit) * a.mult : a.n_words;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) a.ptr[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// classify: record -> (binding key, class) word + radix histograms
+// ---------------------------------------------------------------------------
+template <int RDW>
+__device__ __forceinline__ void load_record(const ClassifyArgs& a, uint64_t i, uint32_t* dw) {
+    if constexpr (RDW == 4) {
+        uint4 r = reinterpret_cast<const uint4*>(a.records)[i];
+        dw[0] = r.x; dw[1] = r.y; dw[2] = r.z; dw[3] = r.w;
+    } else if constexpr (RDW == 3) {
+        const uint32_t* p = reinterpret_cast<const uint32_t*>(a.records) + 3 * i;
+        dw[0] = p[0]; dw[1] = p[1]; dw[2] = p[2];
+    }
+}
+
+template <int RDW>
+__global__ __launch_bounds__(1024) void k_classify(ClassifyArgs a) {
+    __shared__ uint8_t s_cls[256];
+    __shared__ uint8_t s_kp[256];
+    __shared__ uint32_t s_hist[8][256];
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) {
+        s_cls[i] = a.plan->class_of_type[i];
+        s_kp[i] = a.plan->key_present[i];
+    }
+    for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) (&s_hist[0][0])[i] = 0;
+    __syncthreads();
+    uint32_t err = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+        uint32_t t, f[kMaxLevels];
+        if constexpr (RDW > 0) {
+            uint32_t dw[RDW];
+            load_record<RDW>(a, i, dw);
+            t = (dw[a.type_dw] >> a.type_shift) & a.type_mask;
+#pragma unroll
+            for (int m = 0; m < kMaxLevels; ++m)
+                f[m] = m < (int)a.n_keys ? (dw[a.key_dw[m]] >> a.key_shift[m]) & a.key_mask[m] : 0u;
+        } else {
+            const uint32_t* rec = reinterpret_cast<const uint32_t*>(a.records + i * a.record_bytes);
+            t = (rec[a.type_dw] >> a.type_shift) & a.type_mask;
+#pragma unroll
+            for (int m = 0; m < kMaxLevels; ++m)
+                f[m] = m < (int)a.n_keys ? (rec[a.key_dw[m]] >> a.key_shift[m]) & a.key_mask[m] : 0u;
+        }
+        bool ok = !(a.check_type_range && t > 255u);
+        const uint32_t t8 = t & 255u;
+        ok = ok && ((s_kp[t8] & a.need_mask) == a.need_mask);
+        uint64_t key = 0;
+        uint32_t over = 0;
+#pragma unroll
+        for (int m = 0; m < kMaxLevels; ++m) {
+            if (m < (int)a.n_keys) {
+                const uint32_t b = a.key_bits[m];
+                over |= b < 32 ? (f[m] >> b) : 0u;
+                key = (key << b) | f[m];
+            }
+        }
+        if (ok && over) err |= kErrRange;
+        const uint64_t word = ok ? ((key << a.cbits) | s_cls[t8]) : (1ull << a.excl_shift);
+        a.words[i] = word;
+        for (uint32_t p = 0; p < a.n_pass; ++p)
+            atomicAdd(&s_hist[p][(uint32_t)(word >> (a.sort_shift + kRadixBits * p)) & (kRadix - 1)], 1u);
+    }
+    if (err) atomicOr(a.err, err);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < a.n_pass * 256u; i += blockDim.x) {
+        const uint32_t v = (&s_hist[0][0])[i];
+        if (v) atomicAdd(a.hist + i, v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// one stable radix pass (onesweep: rank in-tile, look back across tiles)
+// ---------------------------------------------------------------------------
+constexpr uint32_t kFlagAgg = 1u << 30, kFlagInc = 2u << 30, kValMask = (1u << 30) - 1;
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_pass(SortPassArgs a) {
+    __shared__ uint64_t s_keys[kSortTile];
+    __shared__ uint32_t s_wcnt[4][kRadix];
+    __shared__ uint32_t s_lstart[kRadix];
+    __shared__ uint32_t s_gbase[kRadix];
+    __shared__ uint32_t s_tmp[2][4];
+    __shared__ uint32_t s_tile;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
+    for (int i = tid; i < 4 * kRadix; i += kSortThreads) (&s_wcnt[0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint64_t base = (uint64_t)tile * kSortTile;
+    const uint32_t dmask = (1u << a.nbits) - 1u;
+    const uint64_t lt = (1ull << lane) - 1ull;
+
+    uint64_t key[kSortItems];
+    uint32_t dig[kSortItems];
+    uint32_t rank[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const uint64_t idx = base + (uint64_t)w * (kSortItems * 64) + r * 64 + lane;
+        key[r] = idx < a.n ? a.in[idx] : 0ull;
+        dig[r] = (uint32_t)(key[r] >> a.shift) & dmask;
+    }
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const uint64_t idx = base + (uint64_t)w * (kSortItems * 64) + r * 64 + lane;
+        const bool valid = idx < a.n;
+        uint64_t m = __ballot(valid);
+        for (uint32_t b = 0; b < a.nbits; ++b) {
+            const bool bit = (dig[r] >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        const uint32_t below = (uint32_t)__popcll(m & lt);
+        const uint32_t prev = s_wcnt[w][dig[r]];
+        rank[r] = prev + below;
+        if (valid && below == 0) s_wcnt[w][dig[r]] = prev + (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    // per bucket: wave offsets, tile count, publish the aggregate
+    const uint32_t c0 = s_wcnt[0][tid], c1 = s_wcnt[1][tid], c2 = s_wcnt[2][tid], c3 = s_wcnt[3][tid];
+    const uint32_t tot = c0 + c1 + c2 + c3;
+    s_wcnt[0][tid] = 0;
+    s_wcnt[1][tid] = c0;
+    s_wcnt[2][tid] = c0 + c1;
+    s_wcnt[3][tid] = c0 + c1 + c2;
+    uint32_t* my_status = a.status + (uint64_t)tile * kRadix;
+    st_flag(my_status + tid, (tile == 0 ? kFlagInc : kFlagAgg) | tot);
+    uint32_t dummy;
+    const uint32_t lstart = block256_excl_scan(tot, s_tmp[0], &dummy);
+    const uint32_t gexcl = block256_excl_scan(a.hist[tid], s_tmp[1], &dummy);
+    // decoupled look-back for bucket tid
+    uint32_t prefix = 0;
+    if (tile > 0) {
+        uint64_t j = tile - 1;
+        for (;;) {
+            uint32_t s, spins = 0;
+            while (((s = ld_acquire_flag(a.status + j * kRadix + tid)) >> 30) == 0u) {
+                if (++spins > kSpinLimit) {
+                    atomicOr(a.err, kErrSpin);
+                    s = kFlagInc;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            prefix += s & kValMask;
+            if ((s & ~kValMask) == kFlagInc || j == 0) break;
+            --j;
+        }
+        st_flag(my_status + tid, kFlagInc | (prefix + tot));
+    }
+    s_lstart[tid] = lstart;
+    s_gbase[tid] = gexcl + prefix;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r) {
+        const uint64_t idx = base + (uint64_t)w * (kSortItems * 64) + r * 64 + lane;
+        const uint32_t pos = s_lstart[dig[r]] + s_wcnt[w][dig[r]] + rank[r];
+        if (idx < a.n && pos < (uint32_t)kSortTile) s_keys[pos] = key[r];
+    }
+    __syncthreads();
+    const uint32_t tile_n = (uint32_t)min<uint64_t>(kSortTile, a.n - base);
+    for (uint32_t i = tid; i < tile_n; i += kSortThreads) {
+        const uint64_t k = s_keys[i];
+        const uint32_t d = (uint32_t)(k >> a.shift) & dmask;
+        const uint64_t dst = (uint64_t)s_gbase[d] + (i - s_lstart[d]);
+        if (dst < a.n) a.out[dst] = k;
+        else atomicOr(a.err, kErrSpin);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// segmented transition-map scan
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t pad_idx(uint32_t i) { return i + (i >> 4); }
+
+__global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
+    __shared__ uint64_t s_w[kScanTile + kScanTile / 16 + 1];
+    __shared__ uint8_t s_delta[kMaxProps][kStates * 16];
+    __shared__ uint8_t s_label[kMaxProps][kStates];
+    __shared__ uint64_t s_colmap[kMaxProps][16];
+    __shared__ uint32_t s_q0[kMaxProps];
+    __shared__ uint64_t s_wtot[kMaxProps][4];
+    __shared__ uint32_t s_ctot[4][4];
+    __shared__ uint64_t s_tprefix[kMaxProps];
+    __shared__ uint64_t s_tagg[kMaxProps];
+    __shared__ uint32_t s_cagg[4];
+    __shared__ uint32_t s_tcnt[4];
+    __shared__ uint64_t s_prev, s_next;
+    __shared__ uint32_t s_tile;
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t P = a.n_props;
+    if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
+    for (uint32_t i = tid; i < P * kStates * 16; i += kScanThreads)
+        s_delta[i / (kStates * 16)][i % (kStates * 16)] = a.plan->prop[i / (kStates * 16)].delta[i % (kStates * 16)];
+    if (tid < (int)(P * 16)) {
+        s_label[tid / 16][tid % 16] = a.plan->prop[tid / 16].label[tid % 16];
+        s_colmap[tid / 16][tid % 16] = a.plan->prop[tid / 16].colmap[tid % 16];
+    }
+    if (tid < (int)P) s_q0[tid] = a.plan->prop[tid].q0;
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint64_t base = (uint64_t)tile * kScanTile;
+    const uint64_t kInvalid = ~0ull;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        const uint64_t idx = base + r * kScanThreads + tid;
+        s_w[pad_idx(r * kScanThreads + tid)] = idx < a.n ? a.words[idx] : kInvalid;
+    }
+    if (tid == 0) s_prev = base > 0 ? a.words[base - 1] : kInvalid;
+    if (tid == 1) s_next = base + kScanTile < a.n ? a.words[base + kScanTile] : kInvalid;
+    __syncthreads();
+
+    uint64_t wv[kScanItems];
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) wv[j] = s_w[pad_idx(tid * kScanItems + j)];
+    const uint64_t wp = tid == 0 ? s_prev : s_w[pad_idx(tid * kScanItems - 1)];
+    const uint64_t wn = tid == kScanThreads - 1 ? s_next : s_w[pad_idx(tid * kScanItems + kScanItems)];
+    const bool has_prev = base + (uint64_t)tid * kScanItems > 0;
+    const uint32_t cb = a.cbits, vs = a.valid_shift, L = a.n_levels;
+    const uint32_t cmask = (1u << cb) - 1u;
+
+    // per-event flags as bit masks
+    uint32_t m_valid = 0, m_head = 0, m_end = 0, m_lvl[kMaxLevels] = {0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const uint64_t x = wv[j];
+        if ((x >> vs) != 0) continue;
+        m_valid |= 1u << j;
+        const uint64_t prv = j == 0 ? wp : wv[j - 1];
+        const bool first = (j == 0 && !has_prev);
+        const uint64_t nxt = j == kScanItems - 1 ? wn : wv[j + 1];
+        if (first || (prv >> cb) != (x >> cb)) m_head |= 1u << j;
+        if ((nxt >> vs) != 0 || (nxt >> cb) != (x >> cb)) m_end |= 1u << j;
+#pragma unroll
+        for (int m = 1; m < kMaxLevels; ++m) {
+            if (m >= (int)L) break;
+            const uint32_t sh = a.prefix_shift[m];
+            if (first || (prv >> sh) != (x >> sh)) m_lvl[m] |= 1u << j;
+        }
+    }
+    uint32_t cnt[4];
+    cnt[0] = __popc(m_head);
+#pragma unroll
+    for (int m = 1; m < 4; ++m) cnt[m] = (uint32_t)m < L ? __popc(m_lvl[m]) : 0u;
+
+    // summaries: the map from the state before this run to the state after it
+    uint64_t summ[kMaxProps];
+#pragma unroll
+    for (int p = 0; p < kMaxProps; ++p) {
+        summ[p] = kIdentityMap;
+        if (p >= (int)P) continue;
+        uint64_t f = kIdentityMap;
+        bool cst = false;
+        uint32_t s = 0;
+        for (int j = 0; j < kScanItems; ++j) {
+            if (!((m_valid >> j) & 1u)) break;
+            const uint32_t c = (uint32_t)wv[j] & cmask;
+            if ((m_head >> j) & 1u) {
+                cst = true;
+                s = s_delta[p][s_q0[p] * 16 + c];
+            } else if (cst) {
+                s = s_delta[p][s * 16 + c];
+            } else {
+                f = map_compose_full(s_colmap[p][c], f);
+            }
+        }
+        summ[p] = cst ? map_const(s) : f;
+    }
+
+    // block-wide exclusive scan of the summaries (composition) and counts
+    uint64_t excl[kMaxProps];
+#pragma unroll
+    for (int p = 0; p < kMaxProps; ++p) {
+        if (p >= (int)P) { excl[p] = kIdentityMap; continue; }
+        uint64_t v = summ[p];
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint64_t o = shfl_up64(v, off);
+            if (lane >= off) v = map_compose(v, o);
+        }
+        const uint64_t e = shfl_up64(v, 1);
+        excl[p] = lane == 0 ? kIdentityMap : e;
+        if (lane == 63) s_wtot[p][w] = v;
+    }
+    uint32_t cexcl[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t incl = wave_incl_scan_u32(cnt[k]);
+        cexcl[k] = incl - cnt[k];
+        if (lane == 63) s_ctot[k][w] = incl;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < kMaxProps; ++p) {
+        if (p >= (int)P) continue;
+        uint64_t pre = kIdentityMap;
+        for (int i = 0; i < w; ++i) pre = map_compose(s_wtot[p][i], pre);
+        excl[p] = map_compose(excl[p], pre);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        uint32_t pre = 0;
+        for (int i = 0; i < w; ++i) pre += s_ctot[k][i];
+        cexcl[k] += pre;
+    }
+    // tile aggregates: thread p composes property p, threads 32..35 sum counts
+    if (tid < (int)P) {
+        uint64_t t = kIdentityMap;
+        for (int i = 0; i < 4; ++i) t = map_compose(s_wtot[tid][i], t);
+        s_tagg[tid] = t;
+    }
+    if (tid >= 32 && tid < 36) {
+        const int k = tid - 32;
+        s_cagg[k] = s_ctot[k][0] + s_ctot[k][1] + s_ctot[k][2] + s_ctot[k][3];
+    }
+    __syncthreads();
+
+    // publish this tile's aggregate, then look back (wave 0)
+    ScanTileStatus* st = a.status + tile;
+    if (tid < (int)P) {
+        st->agg_map[tid] = s_tagg[tid];
+        if (tile == 0) st->inc_map[tid] = s_tagg[tid];
+    }
+    if (tid >= 32 && tid < 36) {
+        st->agg_cnt[tid - 32] = s_cagg[tid - 32];
+        if (tile == 0) st->inc_cnt[tid - 32] = s_cagg[tid - 32];
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) st_flag(a.flags + tile, tile == 0 ? 2u : 1u);
+    if (w == 0) {
+        uint64_t acc = kIdentityMap;
+        uint32_t accc = 0;
+        if (tile > 0) {
+            uint64_t j = tile - 1;
+            for (;;) {
+                uint32_t fl, spins = 0;
+                while ((fl = ld_acquire_flag(a.flags + j)) == 0u) {
+                    if (++spins > kSpinLimit) {
+                        if (lane == 0) atomicOr(a.err, kErrSpin);
+                        fl = 2u;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                __threadfence();
+                const ScanTileStatus* sj = a.status + j;
+                if (lane < (int)P) acc = map_compose(acc, fl == 2u ? sj->inc_map[lane] : sj->agg_map[lane]);
+                if (lane >= 32 && lane < 36) accc += fl == 2u ? sj->inc_cnt[lane - 32] : sj->agg_cnt[lane - 32];
+                if (fl == 2u || j == 0) break;
+                --j;
+            }
+            if (lane < (int)P) st->inc_map[lane] = map_compose(s_tagg[lane], acc);
+            if (lane >= 32 && lane < 36) st->inc_cnt[lane - 32] = accc + s_cagg[lane - 32];
+            __threadfence();
+            if (lane == 0) st_flag(a.flags + tile, 2u);
+        }
+        if (lane < (int)P) s_tprefix[lane] = acc;
+        if (lane >= 32 && lane < 36) s_tcnt[lane - 32] = accc;
+    }
+    __syncthreads();
+
+    // second walk: final state at every instance end; numbering of nodes
+    uint32_t cur[kMaxProps];
+#pragma unroll
+    for (int p = 0; p < kMaxProps; ++p)
+        cur[p] = p < (int)P ? map_at(map_compose(excl[p], s_tprefix[p]), 0) : 0u;
+    uint32_t inst = s_tcnt[0] + cexcl[0];
+    uint32_t lvl[4];
+#pragma unroll
+    for (int m = 1; m < 4; ++m) lvl[m] = s_tcnt[m] + cexcl[m];
+    uint32_t err = 0;
+    for (int j = 0; j < kScanItems; ++j) {
+        if (!((m_valid >> j) & 1u)) break;
+        const uint64_t x = wv[j];
+        const uint32_t c = (uint32_t)x & cmask;
+        if ((m_head >> j) & 1u) {
+            ++inst;
+#pragma unroll
+            for (int p = 0; p < kMaxProps; ++p) cur[p] = p < (int)P ? s_q0[p] : 0u;
+#pragma unroll
+            for (int m = kMaxLevels - 1; m >= 1; --m) {
+                if (m >= (int)L || !((m_lvl[m] >> j) & 1u)) continue;
+                ++lvl[m];
+                const uint64_t id = lvl[m] - 1;
+                const uint32_t child = m == (int)L - 1 ? inst - 1 : lvl[m < 3 ? m + 1 : 3] - 1;
+                if (id < a.node_limit[m]) {
+                    a.node_start[m][id] = child;
+                    if (a.node_keys[m]) a.node_keys[m][id] = x >> a.prefix_shift[m];
+                } else {
+                    err |= kErrCapacity;
+                }
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < kMaxProps; ++p)
+            if (p < (int)P) cur[p] = s_delta[p][cur[p] * 16 + c];
+        if ((m_end >> j) & 1u) {
+            const uint64_t id = inst - 1;
+            if (id < a.inst_limit) {
+#pragma unroll
+                for (int p = 0; p < kMaxProps; ++p)
+                    if (p < (int)P) a.inst_verdict[p * a.inst_stride + id] = s_label[p][cur[p]];
+                if (a.inst_keys) a.inst_keys[id] = x >> cb;
+            } else {
+                err |= kErrCapacity;
+            }
+        }
+    }
+    if (err) atomicOr(a.err, err);
+    // the thread holding the last event publishes the totals
+    const uint64_t my0 = base + (uint64_t)tid * kScanItems;
+    if (my0 <= a.n - 1 && a.n - 1 < my0 + kScanItems) {
+#pragma unroll
+        for (int m = 0; m < kMaxLevels; ++m) {
+            if (m >= (int)L) break;
+            const uint32_t tot = s_tcnt[m] + cexcl[m] + cnt[m];
+            a.sizes[m] = tot;
+            a.sizes32[m] = tot;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// counting for one level
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t node_of(const uint32_t* start, uint32_t nn, uint32_t c) {
+    // last node j with start[j] <= c
+    uint32_t lo = 0, hi = nn;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (start[mid] <= c) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kCountThreads) void k_count(CountArgs a) {
+    __shared__ uint32_t s_cnt[kMaxProps * kCountWindow * 6];
+    __shared__ uint32_t s_lo;
+    const int tid = threadIdx.x;
+    const uint32_t P = a.n_props;
+    const uint32_t nch_all = *a.n_children;
+    const uint32_t nn_all = a.level == 0 ? 1u : *a.n_nodes;
+    const uint32_t nch = (uint32_t)min<uint64_t>(nch_all, a.child_limit);
+    const uint32_t nn = (uint32_t)min<uint64_t>(nn_all, a.level == 0 ? 1ull : a.node_limit);
+    const bool leaves = a.level + 1 == a.n_levels;
+    const uint32_t ntiles = (nch + kCountTile - 1) / kCountTile;
+    if (blockIdx.x == 0 && tid == 0 && (nch < nch_all || nn < nn_all)) atomicOr(a.err, kErrCapacity);
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t c0 = tile * kCountTile;
+        for (uint32_t i = tid; i < P * kCountWindow * 6; i += kCountThreads) s_cnt[i] = 0;
+        if (tid == 0) s_lo = a.level == 0 ? 0u : node_of(a.node_start, nn, c0);
+        __syncthreads();
+        const uint32_t lo = s_lo;
+        const uint32_t cbeg = c0 + tid * kCountItems;
+        if (cbeg < nch) {
+            const uint32_t cend = min(cbeg + kCountItems, nch);
+            uint32_t node = a.level == 0 ? 0u : node_of(a.node_start, nn, cbeg);
+            for (uint32_t c = cbeg; c < cend; ++c) {
+                if (a.level > 0)
+                    while (node + 1 < nn && a.node_start[node + 1] <= c) ++node;
+                for (uint32_t p = 0; p < P; ++p) {
+                    uint32_t b;
+                    if (leaves) {
+                        b = a.child_verdict[p * a.child_stride + c];
+                    } else {
+                        b = valuate(a.plan->prop[p], (int)a.level + 1, a.child_counts + (p * a.child_stride + c) * 6);
+                        if (a.child_verdict_out) a.child_verdict_out[p * a.child_stride + c] = (uint8_t)b;
+                    }
+                    if (b > 5u) {
+                        atomicOr(a.err, kErrSpin);
+                        continue;
+                    }
+                    const uint32_t slot = node - lo;
+                    if (slot < (uint32_t)kCountWindow)
+                        atomicAdd(&s_cnt[(p * kCountWindow + slot) * 6 + b], 1u);
+                    else if (node < nn)
+                        atomicAdd(&a.counts[((uint64_t)p * a.stride + node) * 6 + b], 1u);
+                }
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < P * kCountWindow * 6; i += kCountThreads) {
+            const uint32_t v = s_cnt[i];
+            if (!v) continue;
+            const uint32_t p = i / (kCountWindow * 6), slot = (i / 6) % kCountWindow, b = i % 6;
+            const uint32_t node = lo + slot;
+            if (node < nn) atomicAdd(&a.counts[((uint64_t)p * a.stride + node) * 6 + b], v);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_finalize(FinalizeArgs a) {
+    const uint32_t p = threadIdx.x;
+    if (p <= a.n_levels) a.sizes_out[p] = p < a.n_levels ? a.sizes_ws[p] : 0ull;
+    if (p >= a.n_props) return;
+    const uint32_t* v = a.root_counts + p * 6;
+    a.root_verdict[p] = (uint8_t)valuate(a.plan->prop[p], 0, v);
+    for (int b = 0; b < 6; ++b) a.root_counts_out[p * 6 + b] = v[b];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_zero(const ZeroArgs& a, uint32_t blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_classify(const ClassifyArgs& a, hipStream_t s) {
+    const uint64_t want = (a.n + 1023) / 1024;
+    const uint32_t blocks = (uint32_t)(want < 512 ? (want ? want : 1) : 512);
+    if (a.record_bytes == 16 && (reinterpret_cast<uintptr_t>(a.records) & 15) == 0)
+        hipLaunchKernelGGL(k_classify<4>, dim3(blocks), dim3(1024), 0, s, a);
+    else if (a.record_bytes == 12)
+        hipLaunchKernelGGL(k_classify<3>, dim3(blocks), dim3(1024), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_classify<0>, dim3(blocks), dim3(1024), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_pass(const SortPassArgs& a, hipStream_t s) {
+    const uint32_t tiles = (a.n + kSortTile - 1) / kSortTile;
+    hipLaunchKernelGGL(k_sort_pass, dim3(tiles), dim3(kSortThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const ScanArgs& a, hipStream_t s) {
+    const uint32_t tiles = (a.n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_scan, dim3(tiles), dim3(kScanThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_count(const CountArgs& a, hipStream_t s) {
+    const uint64_t want = (a.child_limit + kCountTile - 1) / kCountTile;
+    const uint32_t blocks = (uint32_t)(want < 1024 ? (want ? want : 1) : 1024);
+    hipLaunchKernelGGL(k_count, dim3(blocks), dim3(kCountThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace ltl4c

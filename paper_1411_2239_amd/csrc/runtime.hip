@@ -1,0 +1,656 @@
+// Host runtime of libltl4c: the C ABI of include/ltl4c.h.
+//
+// Validates descriptors, keeps per-context device copies of the monitor
+// tables and quantifiers ("plans"), lays out the caller's workspace and
+// enqueues the kernel sequence of one evaluation on the context's stream:
+//   zero -> classify -> radix passes -> scan -> (zero, count) per level
+//   -> finalize
+// which is Algorithm 1 (SortTrace, SpawnMonitors/Distribute as one flat scan,
+// ApplyQuantifiers level by level) without host round trips.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "ltl4c.h"
+
+using namespace ltl4c;
+
+namespace {
+
+thread_local std::string g_last_error = "";
+
+int32_t fail(int32_t code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(LTL4C_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+struct MonitorHost {
+    uint32_t n_states, n_classes, q0;
+    std::vector<uint8_t> delta, label;
+};
+
+struct Timed {
+    const char* name;
+    hipEvent_t start, stop;
+};
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+uint32_t bits_for(uint32_t n_values) {  // bits to hold values 0..n_values-1
+    uint32_t b = 0;
+    while ((1u << b) < n_values) ++b;
+    return b;
+}
+
+}  // namespace
+
+struct ltl4c_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool has_layout = false;
+    ltl4c_layout layout{};
+    std::vector<MonitorHost> monitors;
+    std::vector<ltl4c_property> props;
+    std::map<std::vector<int32_t>, Plan*> plans;
+    uint32_t* err_dev = nullptr;
+    bool prof = false;
+    std::vector<Timed> timed;
+    std::vector<hipEvent_t> free_events;
+    std::vector<std::pair<std::string, std::pair<double, uint64_t>>> prof_acc;
+};
+
+namespace {
+
+// Derived quantities of a layout shared by the workspace query and eval.
+struct Geometry {
+    uint32_t cbits, key_bits_total, sort_bits, n_pass;
+    bool excl;
+    uint32_t prefix_bits[kMaxLevels];       // bits of keys 0..m-1
+};
+
+Geometry geometry(const ltl4c_layout& L) {
+    Geometry g{};
+    g.cbits = bits_for(L.n_classes);
+    uint32_t kb = 0;
+    for (uint32_t m = 0; m < L.n_keys; ++m) {
+        g.prefix_bits[m] = kb;
+        kb += L.key_bits[m];
+    }
+    g.key_bits_total = kb;
+    const uint32_t need = (1u << L.n_keys) - 1u;
+    g.excl = L.type_bytes > 1;
+    for (int t = 0; t < 256 && !g.excl; ++t)
+        if ((L.key_present[t] & need) != need) g.excl = true;
+    g.sort_bits = kb + (g.excl ? 1u : 0u);
+    g.n_pass = (g.sort_bits + kRadixBits - 1) / kRadixBits;
+    return g;
+}
+
+struct WsLayout {
+    uint64_t total;
+    uint64_t zero_off, zero_words;
+    uint64_t hist_off, sort_ticket_off, scan_ticket_off, root_counts_off, sizes32_off, sizes64_off;
+    uint64_t sort_status_off, scan_flags_off;
+    uint64_t words_a_off, words_b_off, scan_status_off, inst_verdict_off;
+    uint64_t node_start_off[kMaxLevels], counts_off[kMaxLevels];
+    uint64_t cap_node[kMaxLevels];
+    uint32_t tiles_sort, tiles_scan;
+};
+
+WsLayout plan_workspace(const ltl4c_layout& L, const Geometry& g, uint64_t n, uint32_t P) {
+    WsLayout w{};
+    w.tiles_sort = (uint32_t)((n + kSortTile - 1) / kSortTile);
+    w.tiles_scan = (uint32_t)((n + kScanTile - 1) / kScanTile);
+    // zero block, in 32-bit words
+    uint64_t z = 0;
+    w.hist_off = z;        z += (uint64_t)g.n_pass * kRadix;
+    w.sort_ticket_off = z; z += 64;
+    w.scan_ticket_off = z; z += 64;
+    w.root_counts_off = z; z += kMaxProps * 6;
+    w.sizes32_off = z;     z += 64;
+    w.sizes64_off = z;     z += 64;                      // 32 x uint64
+    w.sort_status_off = z; z += (uint64_t)g.n_pass * w.tiles_sort * kRadix;
+    w.scan_flags_off = z;  z += w.tiles_scan;
+    z = (z + 63) & ~63ull;
+    w.zero_off = 0;
+    w.zero_words = z;
+    uint64_t off = align256(z * 4);
+    w.words_a_off = off;   off = align256(off + n * 8);
+    w.words_b_off = off;   off = align256(off + n * 8);
+    w.scan_status_off = off; off = align256(off + (uint64_t)w.tiles_scan * sizeof(ScanTileStatus));
+    w.inst_verdict_off = off; off = align256(off + (uint64_t)P * n);
+    for (uint32_t m = 1; m < L.n_keys; ++m) {
+        uint64_t cap = n;
+        if (g.prefix_bits[m] < 40) cap = std::min<uint64_t>(cap, 1ull << g.prefix_bits[m]);
+        w.cap_node[m] = cap;
+        w.node_start_off[m] = off; off = align256(off + cap * 4);
+        w.counts_off[m] = off;     off = align256(off + (uint64_t)P * cap * 6 * 4);
+    }
+    w.total = off;
+    return w;
+}
+
+int32_t check_layout(const ltl4c_layout* L) {
+    if (!L) return fail(LTL4C_EINVAL, "layout is NULL");
+    if (L->record_bytes < 4 || L->record_bytes > 256 || L->record_bytes % 4)
+        return fail(LTL4C_EINVAL, "record_bytes must be a multiple of 4 in [4, 256]");
+    auto field_ok = [&](uint32_t off, uint32_t bytes) {
+        return (bytes == 1 || bytes == 2 || bytes == 4) && off % bytes == 0 && off + bytes <= L->record_bytes;
+    };
+    if (!field_ok(L->type_offset, L->type_bytes)) return fail(LTL4C_EINVAL, "bad type field");
+    if (L->n_keys < 1 || L->n_keys > kMaxLevels) return fail(LTL4C_EUNSUPPORTED, "n_keys must be 1..4");
+    for (uint32_t m = 0; m < L->n_keys; ++m) {
+        if (!field_ok(L->key_offset[m], L->key_bytes[m])) return fail(LTL4C_EINVAL, "bad key field");
+        if (L->key_bits[m] < 1 || L->key_bits[m] > 8 * L->key_bytes[m])
+            return fail(LTL4C_EINVAL, "key_bits must be in [1, 8*key_bytes]");
+    }
+    if (L->n_classes < 1 || L->n_classes > LTL4C_MAX_CLASSES)
+        return fail(LTL4C_EUNSUPPORTED, "n_classes must be 1..16");
+    for (int t = 0; t < 256; ++t)
+        if (L->class_of_type[t] >= L->n_classes) return fail(LTL4C_EINVAL, "class_of_type entry >= n_classes");
+    Geometry g = geometry(*L);
+    if (g.cbits + g.key_bits_total + (g.excl ? 1 : 0) > 63)
+        return fail(LTL4C_EUNSUPPORTED, "packed binding key plus class bits exceed 63 bits");
+    return LTL4C_OK;
+}
+
+PropDev make_prop(const MonitorHost& M, const ltl4c_property& p) {
+    PropDev d;
+    std::memset(&d, 0, sizeof d);
+    for (uint32_t q = 0; q < M.n_states; ++q)
+        for (uint32_t c = 0; c < M.n_classes; ++c) d.delta[q * 16 + c] = M.delta[q * M.n_classes + c];
+    for (uint32_t q = 0; q < M.n_states; ++q) d.label[q] = M.label[q];
+    for (uint32_t c = 0; c < 16; ++c) {
+        uint64_t m = 0;
+        for (uint32_t q = 0; q < 16; ++q) {
+            uint64_t to = (c < M.n_classes && q < M.n_states) ? M.delta[q * M.n_classes + c] : q;
+            m |= to << (4 * q);
+        }
+        d.colmap[c] = m;
+    }
+    d.q0 = M.q0;
+    d.n_states = M.n_states;
+    for (uint32_t l = 0; l < p.n_levels; ++l) {
+        d.kind[l] = p.q[l].kind;
+        d.op[l] = p.q[l].op;
+        d.num[l] = p.q[l].num;
+        d.den[l] = p.q[l].kind == LTL4C_Q_PERCENT ? p.q[l].den : 1u;
+    }
+    return d;
+}
+
+int32_t get_plan(ltl4c_ctx* ctx, const int32_t* props, int32_t n_props, Plan** out) {
+    std::vector<int32_t> key(props, props + n_props);
+    auto it = ctx->plans.find(key);
+    if (it != ctx->plans.end()) {
+        *out = it->second;
+        return LTL4C_OK;
+    }
+    Plan host;
+    std::memset(&host, 0, sizeof host);
+    for (int32_t i = 0; i < n_props; ++i) {
+        const ltl4c_property& p = ctx->props[props[i]];
+        host.prop[i] = make_prop(ctx->monitors[p.monitor], p);
+    }
+    std::memcpy(host.class_of_type, ctx->layout.class_of_type, 256);
+    std::memcpy(host.key_present, ctx->layout.key_present, 256);
+    Plan* dev = nullptr;
+    HIP_TRY(hipMalloc(&dev, sizeof(Plan)));
+    hipError_t e = hipMemcpy(dev, &host, sizeof(Plan), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(dev);
+        return fail(LTL4C_EDEVICE, std::string("plan upload: ") + hipGetErrorString(e));
+    }
+    ctx->plans[key] = dev;
+    *out = dev;
+    return LTL4C_OK;
+}
+
+void drop_plans(ltl4c_ctx* ctx) {
+    for (auto& kv : ctx->plans) (void)hipFree(kv.second);
+    ctx->plans.clear();
+}
+
+int32_t check_props(ltl4c_ctx* ctx, const int32_t* props, int32_t n_props) {
+    if (!ctx) return fail(LTL4C_EINVAL, "ctx is NULL");
+    if (!ctx->has_layout) return fail(LTL4C_EINVAL, "no layout set");
+    if (!props || n_props < 1 || n_props > kMaxProps) return fail(LTL4C_EINVAL, "n_props must be 1..16");
+    for (int32_t i = 0; i < n_props; ++i)
+        if (props[i] < 0 || props[i] >= (int32_t)ctx->props.size()) return fail(LTL4C_EINVAL, "unknown property id");
+    return LTL4C_OK;
+}
+
+// Kernel launches with optional event timing.
+hipEvent_t take_event(ltl4c_ctx* ctx) {
+    if (!ctx->free_events.empty()) {
+        hipEvent_t e = ctx->free_events.back();
+        ctx->free_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+template <typename F>
+int32_t launch(ltl4c_ctx* ctx, const char* name, F&& f) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (ctx->prof) {
+        a = take_event(ctx);
+        b = take_event(ctx);
+        if (a) (void)hipEventRecord(a, ctx->stream);
+    }
+    hipError_t e = f();
+    if (ctx->prof && a && b) {
+        (void)hipEventRecord(b, ctx->stream);
+        ctx->timed.push_back({name, a, b});
+    }
+    if (e != hipSuccess) return fail(LTL4C_EDEVICE, std::string(name) + ": " + hipGetErrorString(e));
+    return LTL4C_OK;
+}
+
+int32_t drain_profile(ltl4c_ctx* ctx) {
+    if (ctx->timed.empty()) return LTL4C_OK;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    for (auto& t : ctx->timed) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, t.start, t.stop);
+        bool found = false;
+        for (auto& acc : ctx->prof_acc) {
+            if (acc.first == t.name) {
+                acc.second.first += ms;
+                acc.second.second += 1;
+                found = true;
+                break;
+            }
+        }
+        if (!found) ctx->prof_acc.push_back({t.name, {ms, 1}});
+        ctx->free_events.push_back(t.start);
+        ctx->free_events.push_back(t.stop);
+    }
+    ctx->timed.clear();
+    return LTL4C_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ltl4c_last_error(void) { return g_last_error.c_str(); }
+
+const char* ltl4c_status_str(int32_t s) {
+    switch (s) {
+        case LTL4C_OK: return "ok";
+        case LTL4C_EINVAL: return "invalid argument";
+        case LTL4C_ENOMEM: return "out of memory or workspace too small";
+        case LTL4C_ECAPACITY: return "capacity exceeded";
+        case LTL4C_EDEVICE: return "device error";
+        case LTL4C_EADMIT: return "admission refused";
+        case LTL4C_ESEQ: return "out of sequence";
+        case LTL4C_EUNSUPPORTED: return "unsupported";
+        case LTL4C_ERANGE: return "key wider than declared";
+        default: return "unknown status";
+    }
+}
+
+int32_t ltl4c_create(ltl4c_ctx** out, int32_t device) {
+    if (!out) return fail(LTL4C_EINVAL, "out is NULL");
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(LTL4C_EINVAL, "no such device");
+    HIP_TRY(hipSetDevice(device));
+    ltl4c_ctx* ctx = new ltl4c_ctx();
+    ctx->device = device;
+    hipError_t e = hipMalloc(&ctx->err_dev, 256);
+    if (e == hipSuccess) e = hipMemset(ctx->err_dev, 0, 256);
+    if (e != hipSuccess) {
+        delete ctx;
+        return fail(LTL4C_EDEVICE, std::string("context allocation: ") + hipGetErrorString(e));
+    }
+    *out = ctx;
+    return LTL4C_OK;
+}
+
+int32_t ltl4c_destroy(ltl4c_ctx* ctx) {
+    if (!ctx) return LTL4C_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    drop_plans(ctx);
+    for (auto& t : ctx->timed) {
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
+    for (auto e : ctx->free_events) (void)hipEventDestroy(e);
+    (void)hipFree(ctx->err_dev);
+    delete ctx;
+    return LTL4C_OK;
+}
+
+int32_t ltl4c_set_stream(ltl4c_ctx* ctx, void* hip_stream) {
+    if (!ctx) return fail(LTL4C_EINVAL, "ctx is NULL");
+    ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    return LTL4C_OK;
+}
+
+int32_t ltl4c_set_layout(ltl4c_ctx* ctx, const ltl4c_layout* L) {
+    if (!ctx) return fail(LTL4C_EINVAL, "ctx is NULL");
+    int32_t s = check_layout(L);
+    if (s) return s;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    drop_plans(ctx);
+    ctx->layout = *L;
+    ctx->has_layout = true;
+    ctx->monitors.clear();
+    ctx->props.clear();
+    return LTL4C_OK;
+}
+
+int32_t ltl4c_add_monitor(ltl4c_ctx* ctx, const ltl4c_monitor* m, int32_t* id) {
+    if (!ctx || !m || !id) return fail(LTL4C_EINVAL, "NULL argument");
+    if (!ctx->has_layout) return fail(LTL4C_EINVAL, "set a layout first");
+    if (m->n_states < 1 || m->n_states > LTL4C_MAX_STATES) return fail(LTL4C_EUNSUPPORTED, "n_states must be 1..16");
+    if (m->n_classes != ctx->layout.n_classes) return fail(LTL4C_EINVAL, "monitor n_classes differs from the layout");
+    if (m->q0 >= m->n_states) return fail(LTL4C_EINVAL, "q0 out of range");
+    if (!m->delta || !m->label) return fail(LTL4C_EINVAL, "delta/label is NULL");
+    MonitorHost h{m->n_states, m->n_classes, m->q0, {}, {}};
+    h.delta.assign(m->delta, m->delta + (size_t)m->n_states * m->n_classes);
+    h.label.assign(m->label, m->label + m->n_states);
+    for (uint8_t d : h.delta)
+        if (d >= m->n_states) return fail(LTL4C_EINVAL, "delta entry out of range");
+    for (uint8_t l : h.label)
+        if (!(l == LTL4C_BOT || l == LTL4C_BOT_P || l == LTL4C_TOP_P || l == LTL4C_TOP))
+            return fail(LTL4C_EINVAL, "label must be an LTL4 verdict (F, Fp, Tp, T)");
+    ctx->monitors.push_back(std::move(h));
+    *id = (int32_t)ctx->monitors.size() - 1;
+    return LTL4C_OK;
+}
+
+int32_t ltl4c_add_property(ltl4c_ctx* ctx, const ltl4c_property* p, int32_t* id) {
+    if (!ctx || !p || !id) return fail(LTL4C_EINVAL, "NULL argument");
+    if (!ctx->has_layout) return fail(LTL4C_EINVAL, "set a layout first");
+    if (p->monitor < 0 || p->monitor >= (int32_t)ctx->monitors.size()) return fail(LTL4C_EINVAL, "unknown monitor id");
+    if (p->n_levels != ctx->layout.n_keys) return fail(LTL4C_EINVAL, "n_levels must equal the layout's n_keys");
+    for (uint32_t l = 0; l < p->n_levels; ++l) {
+        const ltl4c_quant& q = p->q[l];
+        if (q.kind > 1) return fail(LTL4C_EINVAL, "quantifier kind must be PERCENT or COUNT");
+        if (q.op > 4) return fail(LTL4C_EINVAL, "comparison operator out of range");
+        if (q.kind == LTL4C_Q_PERCENT && (q.den == 0 || q.num > q.den))
+            return fail(LTL4C_EINVAL, "percentage constant must be num/den in [0, 1]");
+    }
+    ctx->props.push_back(*p);
+    *id = (int32_t)ctx->props.size() - 1;
+    return LTL4C_OK;
+}
+
+int32_t ltl4c_workspace_bytes(ltl4c_ctx* ctx, uint64_t n_events, const int32_t* props, int32_t n_props,
+                              uint64_t* bytes) {
+    int32_t s = check_props(ctx, props, n_props);
+    if (s) return s;
+    if (!bytes) return fail(LTL4C_EINVAL, "bytes is NULL");
+    if (n_events > LTL4C_MAX_EVENTS) return fail(LTL4C_EUNSUPPORTED, "too many events for one call");
+    Geometry g = geometry(ctx->layout);
+    *bytes = plan_workspace(ctx->layout, g, n_events, (uint32_t)n_props).total;
+    return LTL4C_OK;
+}
+
+int32_t ltl4c_eval(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int32_t* props, int32_t n_props,
+                   void* d_ws, uint64_t ws_bytes, const ltl4c_result* out) {
+    int32_t s = check_props(ctx, props, n_props);
+    if (s) return s;
+    if (n > LTL4C_MAX_EVENTS) return fail(LTL4C_EUNSUPPORTED, "too many events for one call");
+    if (n > 0 && !d_records) return fail(LTL4C_EINVAL, "records is NULL");
+    if (!out || !out->root_verdict || !out->root_counts || !out->sizes)
+        return fail(LTL4C_EINVAL, "root_verdict, root_counts and sizes are required");
+    if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) & 255)) return fail(LTL4C_EINVAL, "workspace must be 256-byte aligned");
+    const ltl4c_layout& L = ctx->layout;
+    const uint32_t P = (uint32_t)n_props, NL = L.n_keys;
+    if (n > 0 && (reinterpret_cast<uintptr_t>(d_records) & 3))
+        return fail(LTL4C_EINVAL, "records must be 4-byte aligned");
+    Geometry g = geometry(L);
+    WsLayout w = plan_workspace(L, g, n, P);
+    if (ws_bytes < w.total) return fail(LTL4C_ENOMEM, "workspace smaller than ltl4c_workspace_bytes()");
+    if ((out->inst_keys != nullptr) != (out->inst_verdict != nullptr))
+        return fail(LTL4C_EINVAL, "inst_keys and inst_verdict are given together or not at all");
+    bool any_optional = out->inst_verdict != nullptr;
+    for (uint32_t m = 1; m < L.n_keys; ++m) {
+        const bool k = out->node_keys[m] != nullptr, c = out->node_counts[m] != nullptr,
+                   v = out->node_verdict[m] != nullptr;
+        if (k != c || c != v)
+            return fail(LTL4C_EINVAL, "node_keys, node_counts and node_verdict of a level go together");
+        any_optional = any_optional || c;
+    }
+    if (any_optional && out->capacity == 0)
+        return fail(LTL4C_EINVAL, "capacity must be > 0 when optional outputs are given");
+    Plan* plan = nullptr;
+    s = get_plan(ctx, props, n_props, &plan);
+    if (s) return s;
+    HIP_TRY(hipSetDevice(ctx->device));
+
+    uint8_t* ws = static_cast<uint8_t*>(d_ws);
+    uint32_t* z = reinterpret_cast<uint32_t*>(ws);
+    uint32_t* hist = z + w.hist_off;
+    uint32_t* sort_ticket = z + w.sort_ticket_off;
+    uint32_t* scan_ticket = z + w.scan_ticket_off;
+    uint32_t* root_counts = z + w.root_counts_off;
+    uint32_t* sizes32 = z + w.sizes32_off;
+    uint64_t* sizes64 = reinterpret_cast<uint64_t*>(z + w.sizes64_off);
+    uint32_t* sort_status = z + w.sort_status_off;
+    uint32_t* scan_flags = z + w.scan_flags_off;
+    uint64_t* words_a = reinterpret_cast<uint64_t*>(ws + w.words_a_off);
+    uint64_t* words_b = reinterpret_cast<uint64_t*>(ws + w.words_b_off);
+    ScanTileStatus* scan_status = reinterpret_cast<ScanTileStatus*>(ws + w.scan_status_off);
+    const hipStream_t st = ctx->stream;
+
+    {
+        ZeroArgs za{z, nullptr, 0, w.zero_words, 0};
+        uint32_t blocks = (uint32_t)std::min<uint64_t>(1024, (w.zero_words + 255) / 256);
+        s = launch(ctx, "zero", [&] { return launch_zero(za, blocks ? blocks : 1, st); });
+        if (s) return s;
+    }
+    uint64_t* sorted = words_a;
+    if (n > 0) {
+        ClassifyArgs ca{};
+        ca.records = static_cast<const uint8_t*>(d_records);
+        ca.n = n;
+        ca.record_bytes = L.record_bytes;
+        ca.type_dw = L.type_offset / 4;
+        ca.type_shift = (L.type_offset % 4) * 8;
+        ca.type_mask = L.type_bytes == 4 ? 0xFFFFFFFFu : ((1u << (8 * L.type_bytes)) - 1u);
+        ca.n_keys = NL;
+        for (uint32_t m = 0; m < NL; ++m) {
+            ca.key_dw[m] = L.key_offset[m] / 4;
+            ca.key_shift[m] = (L.key_offset[m] % 4) * 8;
+            ca.key_mask[m] = L.key_bytes[m] == 4 ? 0xFFFFFFFFu : ((1u << (8 * L.key_bytes[m])) - 1u);
+            ca.key_bits[m] = L.key_bits[m];
+        }
+        ca.need_mask = (1u << NL) - 1u;
+        ca.check_type_range = L.type_bytes > 1;
+        ca.cbits = g.cbits;
+        ca.excl_shift = g.cbits + g.key_bits_total;
+        ca.n_pass = g.n_pass;
+        ca.sort_shift = g.cbits;
+        ca.plan = plan;
+        ca.words = words_a;
+        ca.hist = hist;
+        ca.err = ctx->err_dev;
+        s = launch(ctx, "classify", [&] { return launch_classify(ca, st); });
+        if (s) return s;
+
+        uint64_t* in = words_a;
+        uint64_t* outw = words_b;
+        for (uint32_t p = 0; p < g.n_pass; ++p) {
+            SortPassArgs sa{};
+            sa.in = in;
+            sa.out = outw;
+            sa.n = (uint32_t)n;
+            sa.shift = g.cbits + kRadixBits * p;
+            sa.nbits = std::min<uint32_t>(kRadixBits, g.sort_bits - kRadixBits * p);
+            sa.hist = hist + (uint64_t)p * kRadix;
+            sa.status = sort_status + (uint64_t)p * w.tiles_sort * kRadix;
+            sa.ticket = sort_ticket + p;
+            sa.err = ctx->err_dev;
+            s = launch(ctx, "sort_pass", [&] { return launch_sort_pass(sa, st); });
+            if (s) return s;
+            std::swap(in, outw);
+        }
+        sorted = in;
+    }
+
+    // per-instance arrays: the verdicts always exist (caller's or workspace)
+    uint8_t* inst_verdict = out->inst_verdict ? out->inst_verdict : ws + w.inst_verdict_off;
+    const uint64_t inst_stride = out->inst_verdict ? out->capacity : std::max<uint64_t>(n, 1);
+    // per-level node arrays; node_start always lives in the workspace
+    uint32_t* node_counts[kMaxLevels] = {nullptr, nullptr, nullptr, nullptr};
+    uint64_t node_stride[kMaxLevels] = {0, 0, 0, 0};
+    uint64_t node_limit[kMaxLevels] = {0, 0, 0, 0};
+    uint32_t* node_start[kMaxLevels] = {nullptr, nullptr, nullptr, nullptr};
+    for (uint32_t m = 1; m < NL; ++m) {
+        node_start[m] = reinterpret_cast<uint32_t*>(ws + w.node_start_off[m]);
+        if (out->node_counts[m]) {
+            node_counts[m] = out->node_counts[m];
+            node_stride[m] = out->capacity;
+        } else {
+            node_counts[m] = reinterpret_cast<uint32_t*>(ws + w.counts_off[m]);
+            node_stride[m] = w.cap_node[m];
+        }
+        node_limit[m] = std::min(node_stride[m], w.cap_node[m]);
+    }
+
+    if (n > 0) {
+        ScanArgs sa{};
+        sa.words = sorted;
+        sa.n = (uint32_t)n;
+        sa.cbits = g.cbits;
+        sa.n_levels = NL;
+        for (uint32_t m = 1; m < NL; ++m) sa.prefix_shift[m] = g.cbits + (g.key_bits_total - g.prefix_bits[m]);
+        sa.valid_shift = g.cbits + g.key_bits_total;
+        sa.n_props = P;
+        sa.plan = plan;
+        sa.inst_verdict = inst_verdict;
+        sa.inst_stride = inst_stride;
+        sa.inst_limit = inst_stride;
+        sa.inst_keys = out->inst_keys;
+        for (uint32_t m = 1; m < NL; ++m) {
+            sa.node_start[m] = node_start[m];
+            sa.node_keys[m] = out->node_keys[m];
+            sa.node_limit[m] = node_limit[m];
+        }
+        sa.flags = scan_flags;
+        sa.status = scan_status;
+        sa.ticket = scan_ticket;
+        sa.sizes = sizes64;
+        sa.sizes32 = sizes32;
+        sa.err = ctx->err_dev;
+        s = launch(ctx, "scan", [&] { return launch_scan(sa, st); });
+        if (s) return s;
+
+        for (int m = (int)NL - 1; m >= 0; --m) {
+            CountArgs c{};
+            c.level = (uint32_t)m;
+            c.n_levels = NL;
+            c.n_props = P;
+            c.plan = plan;
+            c.err = ctx->err_dev;
+            if ((uint32_t)m + 1 == NL) {
+                c.n_children = sizes32 + 0;
+                c.child_limit = inst_stride;
+                c.child_verdict = inst_verdict;
+                c.child_stride = inst_stride;
+            } else {
+                c.n_children = sizes32 + (m + 1);
+                c.child_limit = node_limit[m + 1];
+                c.child_counts = node_counts[m + 1];
+                c.child_stride = node_stride[m + 1];
+                c.child_verdict_out = out->node_verdict[m + 1];
+            }
+            if (m == 0) {
+                c.counts = root_counts;
+                c.stride = 1;
+                c.node_limit = 1;
+            } else {
+                c.node_start = node_start[m];
+                c.n_nodes = sizes32 + m;
+                c.node_limit = node_limit[m];
+                c.counts = node_counts[m];
+                c.stride = node_stride[m];
+                // zero the used part of this level's counts: P segments of nodes*6 words
+                for (uint32_t p = 0; p < P; ++p) {
+                    ZeroArgs za{node_counts[m] + (uint64_t)p * node_stride[m] * 6, sizes32 + m, 6, 0, node_limit[m]};
+                    s = launch(ctx, "zero", [&] { return launch_zero(za, 512, st); });
+                    if (s) return s;
+                }
+            }
+            s = launch(ctx, "count", [&] { return launch_count(c, st); });
+            if (s) return s;
+        }
+    }
+    FinalizeArgs fa{};
+    fa.n_props = P;
+    fa.plan = plan;
+    fa.root_counts = root_counts;
+    fa.root_verdict = out->root_verdict;
+    fa.root_counts_out = out->root_counts;
+    fa.sizes_ws = sizes64;
+    fa.sizes_out = out->sizes;
+    fa.n_levels = NL;
+    s = launch(ctx, "finalize", [&] { return launch_finalize(fa, st); });
+    return s;
+}
+
+int32_t ltl4c_wait(ltl4c_ctx* ctx) {
+    if (!ctx) return fail(LTL4C_EINVAL, "ctx is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    uint32_t err = 0;
+    HIP_TRY(hipMemcpy(&err, ctx->err_dev, 4, hipMemcpyDeviceToHost));
+    if (err) {
+        HIP_TRY(hipMemset(ctx->err_dev, 0, 4));
+        if (err & kErrSpin) return fail(LTL4C_EDEVICE, "a look-back wait exceeded its bound");
+        if (err & kErrRange) return fail(LTL4C_ERANGE, "an event key exceeds its declared key_bits");
+        if (err & kErrCapacity) return fail(LTL4C_ECAPACITY, "more instances or nodes than the capacity");
+    }
+    return LTL4C_OK;
+}
+
+int32_t ltl4c_profile_enable(ltl4c_ctx* ctx, int32_t on) {
+    if (!ctx) return fail(LTL4C_EINVAL, "ctx is NULL");
+    ctx->prof = on != 0;
+    return LTL4C_OK;
+}
+
+int32_t ltl4c_profile_get(ltl4c_ctx* ctx, int32_t i, char* name_buf, int32_t name_len, double* total_ms,
+                          uint64_t* launches) {
+    if (!ctx) return fail(LTL4C_EINVAL, "ctx is NULL");
+    int32_t s = drain_profile(ctx);
+    if (s) return s;
+    if (i < 0 || i >= (int32_t)ctx->prof_acc.size()) return LTL4C_EINVAL;
+    const auto& acc = ctx->prof_acc[i];
+    if (name_buf && name_len > 0) {
+        std::strncpy(name_buf, acc.first.c_str(), name_len - 1);
+        name_buf[name_len - 1] = 0;
+    }
+    if (total_ms) *total_ms = acc.second.first;
+    if (launches) *launches = acc.second.second;
+    return LTL4C_OK;
+}
+
+int32_t ltl4c_profile_reset(ltl4c_ctx* ctx) {
+    if (!ctx) return fail(LTL4C_EINVAL, "ctx is NULL");
+    int32_t s = drain_profile(ctx);
+    ctx->prof_acc.clear();
+    return s;
+}
+
+}  // extern "C"

@@ -1,0 +1,305 @@
+"""ctypes binding of the C ABI in include/ltl4c.h.
+
+Argument marshalling only: every step of the monitoring path runs in the HIP
+kernels of libltl4c.so.  Device memory and streams come from PyTorch (ROCm):
+records, the workspace and the outputs are torch tensors on the context's
+device, and work is enqueued on torch's current stream.
+
+If the library has not been built, `load()` raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from fractions import Fraction
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libltl4c.so")
+
+OK, EINVAL, ENOMEM, ECAPACITY, EDEVICE, EADMIT, ESEQ, EUNSUPPORTED, ERANGE = 0, -1, -2, -3, -4, -5, -6, -7, -8
+BOT, BOT_C, BOT_P, TOP_P, TOP_C, TOP = range(6)
+VERDICT_NAMES = ["F", "Fc", "Fp", "Tp", "Tc", "T"]
+KIND = {"A": 0, "E": 1}
+OP = {"<": 0, "<=": 1, ">": 2, ">=": 3, "=": 4}
+
+
+class LTL4CError(RuntimeError):
+    def __init__(self, status, where, msg):
+        super().__init__(f"{where}: status {status}: {msg}")
+        self.status = status
+
+
+class Layout(C.Structure):
+    _fields_ = [("record_bytes", C.c_uint32), ("type_offset", C.c_uint32), ("type_bytes", C.c_uint32),
+                ("n_keys", C.c_uint32), ("key_offset", C.c_uint32 * 4), ("key_bytes", C.c_uint32 * 4),
+                ("key_bits", C.c_uint32 * 4), ("n_classes", C.c_uint32),
+                ("class_of_type", C.c_uint8 * 256), ("key_present", C.c_uint8 * 256)]
+
+
+class MonitorDesc(C.Structure):
+    _fields_ = [("n_states", C.c_uint32), ("n_classes", C.c_uint32), ("q0", C.c_uint32),
+                ("delta", C.POINTER(C.c_uint8)), ("label", C.POINTER(C.c_uint8))]
+
+
+class Quant(C.Structure):
+    _fields_ = [("kind", C.c_uint32), ("op", C.c_uint32), ("num", C.c_uint32), ("den", C.c_uint32)]
+
+
+class PropertyDesc(C.Structure):
+    _fields_ = [("monitor", C.c_int32), ("n_levels", C.c_uint32), ("q", Quant * 4)]
+
+
+class Result(C.Structure):
+    _fields_ = [("root_verdict", C.c_void_p), ("root_counts", C.c_void_p), ("sizes", C.c_void_p),
+                ("capacity", C.c_uint64), ("inst_keys", C.c_void_p), ("inst_verdict", C.c_void_p),
+                ("node_keys", C.c_void_p * 4), ("node_counts", C.c_void_p * 4), ("node_verdict", C.c_void_p * 4)]
+
+
+_lib = None
+
+# (name, restype, argtypes) for every function of include/ltl4c.h
+SIGNATURES = [
+    ("ltl4c_create", C.c_int32, [C.POINTER(C.c_void_p), C.c_int32]),
+    ("ltl4c_destroy", C.c_int32, [C.c_void_p]),
+    ("ltl4c_set_stream", C.c_int32, [C.c_void_p, C.c_void_p]),
+    ("ltl4c_last_error", C.c_char_p, []),
+    ("ltl4c_status_str", C.c_char_p, [C.c_int32]),
+    ("ltl4c_set_layout", C.c_int32, [C.c_void_p, C.POINTER(Layout)]),
+    ("ltl4c_add_monitor", C.c_int32, [C.c_void_p, C.POINTER(MonitorDesc), C.POINTER(C.c_int32)]),
+    ("ltl4c_add_property", C.c_int32, [C.c_void_p, C.POINTER(PropertyDesc), C.POINTER(C.c_int32)]),
+    ("ltl4c_workspace_bytes", C.c_int32,
+     [C.c_void_p, C.c_uint64, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_uint64)]),
+    ("ltl4c_eval", C.c_int32,
+     [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(C.c_int32), C.c_int32, C.c_void_p, C.c_uint64,
+      C.POINTER(Result)]),
+    ("ltl4c_wait", C.c_int32, [C.c_void_p]),
+    ("ltl4c_profile_enable", C.c_int32, [C.c_void_p, C.c_int32]),
+    ("ltl4c_profile_get", C.c_int32,
+     [C.c_void_p, C.c_int32, C.c_char_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
+    ("ltl4c_profile_reset", C.c_int32, [C.c_void_p]),
+]
+
+
+def load(path=LIB_PATH):
+    """Open libltl4c.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                               "(there is no fallback path)")
+        lib = C.CDLL(path)
+        for name, res, args in SIGNATURES:
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(status, where):
+    if status != OK:
+        lib = load()
+        raise LTL4CError(status, where, lib.ltl4c_last_error().decode())
+
+
+def quant_desc(kind, op, const):
+    """('A', '>=', '19/20') or ('E', '<=', 3) -> Quant."""
+    if kind == "A":
+        fr = Fraction(str(const))
+        if not (0 <= fr <= 1):
+            raise ValueError("percentage constant must be in [0, 1]")
+        return Quant(KIND[kind], OP[op], fr.numerator, fr.denominator)
+    return Quant(KIND[kind], OP[op], int(const), 1)
+
+
+def layout_desc(layout):
+    """workloads.Layout -> ctypes Layout."""
+    d = Layout()
+    d.record_bytes = layout.record_bytes
+    d.type_offset = layout.type_offset
+    d.type_bytes = layout.type_bytes
+    d.n_keys = layout.n_keys
+    for m in range(layout.n_keys):
+        d.key_offset[m] = layout.key_offsets[m]
+        d.key_bytes[m] = layout.key_bytes[m]
+        d.key_bits[m] = layout.key_bits[m]
+    d.n_classes = layout.n_classes
+    C.memmove(d.class_of_type, np.ascontiguousarray(layout.class_of_type, dtype=np.uint8).ctypes.data, 256)
+    C.memmove(d.key_present, np.ascontiguousarray(layout.key_present, dtype=np.uint8).ctypes.data, 256)
+    return d
+
+
+@dataclass
+class EvalResult:
+    """Device tensors of one evaluation (valid after Context.wait())."""
+    root_verdict: object
+    root_counts: object
+    sizes: object
+    inst_keys: object = None
+    inst_verdict: object = None
+    node_keys: list = None
+    node_counts: list = None
+    node_verdict: list = None
+
+
+class Context:
+    """One ltl4c context on a HIP device, driven from torch tensors."""
+
+    def __init__(self, device=0):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        self.device = device
+        h = C.c_void_p()
+        _check(self.lib.ltl4c_create(C.byref(h), device), "ltl4c_create")
+        self.h = h
+        self.n_levels = None
+        self._workspace = None
+
+    def close(self):
+        if self.h:
+            self.lib.ltl4c_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _bind_stream(self):
+        s = self.torch.cuda.current_stream(self.device).cuda_stream
+        _check(self.lib.ltl4c_set_stream(self.h, C.c_void_p(s)), "ltl4c_set_stream")
+
+    def set_layout(self, layout):
+        self.n_levels = layout.n_keys
+        self.record_bytes = layout.record_bytes
+        self.n_classes = layout.n_classes
+        self.class_props = layout.class_props
+        _check(self.lib.ltl4c_set_layout(self.h, C.byref(layout_desc(layout))), "ltl4c_set_layout")
+
+    def add_monitor(self, mon):
+        delta = np.ascontiguousarray(mon.delta, dtype=np.uint8)
+        label = np.ascontiguousarray(mon.label, dtype=np.uint8)
+        d = MonitorDesc(delta.shape[0], delta.shape[1], int(mon.q0),
+                        delta.ctypes.data_as(C.POINTER(C.c_uint8)), label.ctypes.data_as(C.POINTER(C.c_uint8)))
+        i = C.c_int32()
+        _check(self.lib.ltl4c_add_monitor(self.h, C.byref(d), C.byref(i)), "ltl4c_add_monitor")
+        return i.value
+
+    def add_property(self, monitor_id, quants):
+        p = PropertyDesc()
+        p.monitor = monitor_id
+        p.n_levels = len(quants)
+        for m, (kind, op, const) in enumerate(quants):
+            p.q[m] = quant_desc(kind, op, const)
+        i = C.c_int32()
+        _check(self.lib.ltl4c_add_property(self.h, C.byref(p), C.byref(i)), "ltl4c_add_property")
+        return i.value
+
+    def add_spec(self, spec):
+        """Compile a workloads.PropertySpec for the current layout and register it."""
+        from .monitor import compile_monitor
+        mon = compile_monitor(spec.formula, self.class_props)
+        return self.add_property(self.add_monitor(mon), spec.quants)
+
+    def workspace_bytes(self, n_events, props):
+        arr = (C.c_int32 * len(props))(*props)
+        b = C.c_uint64()
+        _check(self.lib.ltl4c_workspace_bytes(self.h, n_events, arr, len(props), C.byref(b)),
+               "ltl4c_workspace_bytes")
+        return b.value
+
+    def workspace(self, n_events, props):
+        need = self.workspace_bytes(n_events, props)
+        ws = self._workspace
+        if ws is None or ws.numel() < need:
+            ws = self.torch.empty(max(need, 256), dtype=self.torch.uint8, device=f"cuda:{self.device}")
+            self._workspace = ws
+        return ws
+
+    def alloc_result(self, n_props, capacity=0, instances=False, nodes=False):
+        t, dev = self.torch, f"cuda:{self.device}"
+        L = self.n_levels
+        r = EvalResult(t.empty(n_props, dtype=t.uint8, device=dev),
+                       t.empty(n_props * 6, dtype=t.int64, device=dev),
+                       t.empty(1 + L, dtype=t.int64, device=dev))
+        if instances:
+            r.inst_keys = t.empty(capacity, dtype=t.int64, device=dev)
+            r.inst_verdict = t.empty(n_props * capacity, dtype=t.uint8, device=dev)
+        if nodes:
+            r.node_keys = [None] + [t.empty(capacity, dtype=t.int64, device=dev) for _ in range(1, L)]
+            r.node_counts = [None] + [t.empty(n_props * capacity * 6, dtype=t.int32, device=dev)
+                                      for _ in range(1, L)]
+            r.node_verdict = [None] + [t.empty(n_props * capacity, dtype=t.uint8, device=dev)
+                                       for _ in range(1, L)]
+        r.capacity = capacity
+        return r
+
+    def eval_into(self, records, n_events, props, result, workspace):
+        """Enqueue one evaluation; `records` is a device tensor of n_events records."""
+        self._bind_stream()
+        res = Result()
+        res.root_verdict = result.root_verdict.data_ptr()
+        res.root_counts = result.root_counts.data_ptr()
+        res.sizes = result.sizes.data_ptr()
+        res.capacity = getattr(result, "capacity", 0)
+        if result.inst_verdict is not None:
+            res.inst_keys = result.inst_keys.data_ptr()
+            res.inst_verdict = result.inst_verdict.data_ptr()
+        if result.node_counts is not None:
+            for m in range(1, self.n_levels):
+                res.node_keys[m] = result.node_keys[m].data_ptr()
+                res.node_counts[m] = result.node_counts[m].data_ptr()
+                res.node_verdict[m] = result.node_verdict[m].data_ptr()
+        arr = (C.c_int32 * len(props))(*props)
+        _check(self.lib.ltl4c_eval(self.h, C.c_void_p(records.data_ptr() if n_events else 0), n_events, arr,
+                                   len(props), C.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                   C.byref(res)), "ltl4c_eval")
+
+    def eval(self, records, props, instances=False, nodes=False, capacity=None):
+        """Evaluate and wait; returns an EvalResult of device tensors."""
+        n = records.numel() // self.record_bytes
+        if capacity is None:
+            capacity = max(n, 1)
+        r = self.alloc_result(len(props), capacity, instances, nodes)
+        self.eval_into(records, n, props, r, self.workspace(n, props))
+        self.wait()
+        return r
+
+    def wait(self):
+        _check(self.lib.ltl4c_wait(self.h), "ltl4c_wait")
+
+    def profile(self, on=True):
+        _check(self.lib.ltl4c_profile_enable(self.h, 1 if on else 0), "ltl4c_profile_enable")
+
+    def profile_reset(self):
+        _check(self.lib.ltl4c_profile_reset(self.h), "ltl4c_profile_reset")
+
+    def profile_read(self):
+        """{kernel name: (total ms, launches)} since the last reset."""
+        out, i = {}, 0
+        buf = C.create_string_buffer(64)
+        while True:
+            ms, cnt = C.c_double(), C.c_uint64()
+            s = self.lib.ltl4c_profile_get(self.h, i, buf, 64, C.byref(ms), C.byref(cnt))
+            if s != OK:
+                break
+            out[buf.value.decode()] = (ms.value, cnt.value)
+            i += 1
+        return out
+
+
+def open_workload(wl, device=0):
+    """Context with the workload's layout and properties registered.
+
+    Returns (ctx, prop_ids, device records tensor)."""
+    import torch
+    ctx = Context(device)
+    ctx.set_layout(wl.layout)
+    ids = [ctx.add_spec(p) for p in wl.props]
+    rec = torch.from_numpy(np.ascontiguousarray(wl.raw())).to(f"cuda:{device}")
+    return ctx, ids, rec

@@ -1,0 +1,107 @@
+"""Parity of the HIP path (through the C ABI) with the oracle: every root
+verdict, root count, instance verdict, node count and node verdict must be
+equal, element by element.  Integer work: bit-exact is the bar."""
+import numpy as np
+import pytest
+
+from oracle.run import evaluate_workload
+from paper_1411_2239_amd import workloads as W
+
+from _util import compare_full, pack_keys, prop_workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(wl, instances=True, nodes=True):
+    import torch
+    from paper_1411_2239_amd import lib
+    print(f"[case] {wl.name} n={wl.n_events} props={len(wl.props)} levels={wl.layout.n_keys}", flush=True)
+    ctx, ids, rec = lib.open_workload(wl)
+    r = ctx.eval(rec, ids, instances=instances, nodes=nodes)
+    torch.cuda.synchronize()
+    ctx.close()
+    return r, len(ids)
+
+
+def _check(wl, **kw):
+    r, P = _run(wl, **kw)
+    o = evaluate_workload(wl)
+    compare_full(r, o, P, wl.layout.n_keys)
+    if r.inst_keys is not None:
+        n_inst = int(r.sizes[0].item())
+        keys = r.inst_keys.cpu().numpy()[:n_inst].astype(np.uint64)
+        assert np.array_equal(keys, pack_keys(o.inst_keys, wl.layout.key_bits))
+    return r, o
+
+
+def test_sockets_full_size():
+    _check(W.gen_sockets())
+
+
+def test_users_small():
+    _check(W.gen_user_requests(n_events=300_000, n_users=500, seed=11))
+
+
+def test_users_full_size():
+    _check(W.gen_user_requests())
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 4095, 4096, 4097, 8191, 12289])
+def test_ragged_sizes(n):
+    _check(prop_workload(n, 1, [37], seed=n, n_props=4))
+
+
+def test_empty_trace():
+    import torch
+    from paper_1411_2239_amd import lib
+    wl = prop_workload(1, 2, [3, 3], seed=5, n_props=2)
+    ctx, ids, rec = lib.open_workload(wl)
+    r = ctx.alloc_result(len(ids), 1, instances=True, nodes=True)
+    ctx.eval_into(rec, 0, ids, r, ctx.workspace(0, ids))
+    ctx.wait()
+    o = evaluate_workload(wl, records=wl.records[:0])
+    compare_full(r, o, len(ids), 2)
+    ctx.close()
+
+
+def test_one_cluster_spanning_many_tiles():
+    # every event carries the same binding: one instance over 25 scan tiles
+    _check(prop_workload(100_000, 1, [1], seed=3, n_props=8))
+
+
+def test_every_event_its_own_instance():
+    wl = prop_workload(20_000, 1, [1 << 30], seed=4, n_props=3, key_bits=[30])
+    wl.records["k0"] = np.random.default_rng(4).permutation(1 << 20)[:20_000].astype(np.uint32)
+    _check(wl)
+
+
+def test_sixteen_properties():
+    _check(prop_workload(60_000, 1, [500], seed=21, n_props=16))
+
+
+@pytest.mark.parametrize("levels,keys", [(2, [40, 50]), (3, [5, 7, 9]), (4, [3, 4, 5, 6])])
+def test_nested_quantifiers(levels, keys):
+    _check(prop_workload(80_000, levels, keys, seed=100 + levels, n_props=5))
+
+
+def test_wide_keys():
+    # 3 x 19-bit keys: a 57-bit binding key plus the exclusion bit, 8 radix passes
+    wl = prop_workload(50_000, 3, [1 << 19, 1 << 19, 1 << 19], seed=8, n_props=2, key_bits=[19, 19, 19])
+    rng = np.random.default_rng(8)
+    for m in range(3):
+        wl.records[f"k{m}"] = rng.integers(0, 3 if m < 2 else 1 << 19, size=50_000).astype(np.uint32)
+    _check(wl)
+
+
+def test_excluded_events():
+    # 2-byte types: types >= 256 and types without the level-1 key join no cluster
+    wl = prop_workload(40_000, 2, [20, 30], seed=9, n_props=3)
+    rng = np.random.default_rng(9)
+    t = wl.records["type"].copy()
+    t[rng.random(40_000) < 0.1] = 300
+    t[rng.random(40_000) < 0.1] = 9
+    wl.records["type"] = t
+    wl.layout.type_bytes = 2
+    wl.layout.key_present[9] = 0b01
+    wl.layout.class_of_type[9] = 0
+    _check(wl)
