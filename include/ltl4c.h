@@ -201,6 +201,15 @@ int32_t ltl4c_eval(ltl4c_ctx *ctx, const void *d_records, uint64_t n_events,
  * work enqueued since the previous ltl4c_wait (LTL4C_ERANGE, ECAPACITY). */
 int32_t ltl4c_wait(ltl4c_ctx *ctx);
 
+/* ---- tuning ------------------------------------------------------------- */
+
+/* Kernel schedule options (set before ltl4c_workspace_bytes, which depends
+ * on them).  LTL4C_OPT_SORT_TILE selects the radix-pass tile shape:
+ * 0 = 256 threads x 16 words, 1 = 512 x 16 (default), 2 = 256 x 24,
+ * 3 = 256 x 8, 4 = 512 x 8. */
+enum { LTL4C_OPT_SORT_TILE = 0 };
+int32_t ltl4c_set_option(ltl4c_ctx *ctx, int32_t option, int64_t value);
+
 /* ---- profiling: per-kernel time of the enqueued work ------------------- */
 
 /* When enabled, every kernel launch is bracketed by HIP events on the

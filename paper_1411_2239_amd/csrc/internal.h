@@ -42,13 +42,16 @@ struct Plan {
     uint8_t key_present[256];
 };
 
-// Look-back record of one scan tile: aggregate and inclusive payloads are
-// kept apart so a reader that saw "aggregate" never reads an overwritten one.
+// Look-back record of one scan tile.  Every 64-bit word carries its own
+// validity bit (bit 32) above a 32-bit payload, so readers need no memory
+// fence: a word is either zero (not yet published) or complete.  Words
+// [0, 2*kMaxProps) are the low/high halves of the property maps, words
+// [2*kMaxProps, 2*kMaxProps+4) the instance / node counts.  Aggregate and
+// inclusive values are kept apart.
+constexpr int kScanStatusWords = 2 * kMaxProps + 4;
 struct ScanTileStatus {
-    uint32_t agg_cnt[4];
-    uint32_t inc_cnt[4];
-    uint64_t agg_map[kMaxProps];
-    uint64_t inc_map[kMaxProps];
+    uint64_t agg[kScanStatusWords];
+    uint64_t inc[kScanStatusWords];
 };
 
 struct ClassifyArgs {
@@ -98,8 +101,7 @@ struct ScanArgs {
     uint32_t* node_start[kMaxLevels];    // level m: first child of node j
     uint64_t* node_keys[kMaxLevels];     // optional
     uint64_t node_limit[kMaxLevels];     // nodes with an id below this are written
-    uint32_t* flags;                     // [tiles] look-back flags
-    ScanTileStatus* status;              // [tiles]
+    ScanTileStatus* status;              // [tiles], zeroed before the launch
     uint32_t* ticket;
     uint64_t* sizes;                     // [1 + n_levels] written by the last tile
     uint32_t* sizes32;                   // same, 32-bit, for the counting kernels
@@ -149,7 +151,9 @@ struct FinalizeArgs {
 // Launchers (defined in kernels.hip).
 hipError_t launch_zero(const ZeroArgs& a, uint32_t blocks, hipStream_t s);
 hipError_t launch_classify(const ClassifyArgs& a, hipStream_t s);
-hipError_t launch_sort_pass(const SortPassArgs& a, hipStream_t s);
+hipError_t launch_sort_pass(const SortPassArgs& a, int variant, hipStream_t s);
+uint32_t sort_tile(int variant);      // words per radix tile of a sort variant
+constexpr int kSortVariants = 5;
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
 hipError_t launch_count(const CountArgs& a, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);

@@ -35,8 +35,10 @@ __device__ __forceinline__ uint64_t map_const(uint32_t s) { return (uint64_t)s *
 __device__ __forceinline__ bool map_is_const(uint64_t f) { return f == (f & 15ull) * 0x1111111111111111ull; }
 __device__ __forceinline__ uint32_t map_at(uint64_t f, uint32_t q) { return (uint32_t)(f >> (4u * q)) & 15u; }
 
-// (g o f)[q] = g[f[q]] over all 16 lanes.
-__device__ __forceinline__ uint64_t map_compose_full(uint64_t g, uint64_t f) {
+// (g o f)[q] = g[f[q]] over all 16 lanes.  Kept out of line: it is the rare
+// path (runs with no segment head) and inlining it everywhere blows the
+// kernel past the instruction cache.
+__device__ __noinline__ uint64_t map_compose_full(uint64_t g, uint64_t f) {
     uint64_t r = 0;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
@@ -69,14 +71,15 @@ __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
     return v;
 }
 
-// Exclusive scan of one value per thread over a 256-thread block.
+// Exclusive scan of one value per thread over threads 0..255 of the block
+// (every thread of the block must call it; threads >= 256 get garbage).
 __device__ __forceinline__ uint32_t block256_excl_scan(uint32_t v, uint32_t* s_tmp /*[4]*/, uint32_t* total) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t incl = wave_incl_scan_u32(v);
-    if (lane == 63) s_tmp[w] = incl;
+    if (lane == 63 && w < 4) s_tmp[w] = incl;
     __syncthreads();
     uint32_t pre = 0;
-    for (int i = 0; i < w; ++i) pre += s_tmp[i];
+    for (int i = 0; i < w && i < 4; ++i) pre += s_tmp[i];
     *total = s_tmp[0] + s_tmp[1] + s_tmp[2] + s_tmp[3];
     __syncthreads();
     return pre + incl - v;
@@ -228,35 +231,42 @@ __global__ __launch_bounds__(1024) void k_classify(ClassifyArgs a) {
 // one stable radix pass (onesweep: rank in-tile, look back across tiles)
 // ---------------------------------------------------------------------------
 constexpr uint32_t kFlagAgg = 1u << 30, kFlagInc = 2u << 30, kValMask = (1u << 30) - 1;
+constexpr int kSortLookWindow = 1;
+constexpr int kScanLookWindow = 4;
 
-__global__ __launch_bounds__(kSortThreads) void k_sort_pass(SortPassArgs a) {
-    __shared__ uint64_t s_keys[kSortTile];
-    __shared__ uint32_t s_wcnt[4][kRadix];
+template <int THREADS, int ITEMS>
+__global__ __launch_bounds__(THREADS) void k_sort_pass(SortPassArgs a) {
+    constexpr int TILE = THREADS * ITEMS;
+    constexpr int WAVES = THREADS / 64;
+    __shared__ uint64_t s_keys[TILE];
+    __shared__ uint32_t s_wcnt[WAVES][kRadix];
     __shared__ uint32_t s_lstart[kRadix];
     __shared__ uint32_t s_gbase[kRadix];
     __shared__ uint32_t s_tmp[2][4];
     __shared__ uint32_t s_tile;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
-    for (int i = tid; i < 4 * kRadix; i += kSortThreads) (&s_wcnt[0][0])[i] = 0;
+    for (int i = tid; i < WAVES * kRadix; i += THREADS) (&s_wcnt[0][0])[i] = 0;
     __syncthreads();
     const uint32_t tile = s_tile;
-    const uint64_t base = (uint64_t)tile * kSortTile;
+    const uint64_t base = (uint64_t)tile * TILE;
     const uint32_t dmask = (1u << a.nbits) - 1u;
     const uint64_t lt = (1ull << lane) - 1ull;
 
-    uint64_t key[kSortItems];
-    uint32_t dig[kSortItems];
-    uint32_t rank[kSortItems];
+    uint64_t key[ITEMS];
+    uint32_t dig[ITEMS];
+    uint32_t rank[ITEMS];
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        const uint64_t idx = base + (uint64_t)w * (kSortItems * 64) + r * 64 + lane;
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint64_t idx = base + (uint64_t)w * (ITEMS * 64) + r * 64 + lane;
         key[r] = idx < a.n ? a.in[idx] : 0ull;
         dig[r] = (uint32_t)(key[r] >> a.shift) & dmask;
     }
+    // rank inside the wave: lanes with the same digit found by one ballot per
+    // digit bit; per-wave counters in LDS carry the count across rounds
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        const uint64_t idx = base + (uint64_t)w * (kSortItems * 64) + r * 64 + lane;
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint64_t idx = base + (uint64_t)w * (ITEMS * 64) + r * 64 + lane;
         const bool valid = idx < a.n;
         uint64_t m = __ballot(valid);
         for (uint32_t b = 0; b < a.nbits; ++b) {
@@ -270,50 +280,69 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(SortPassArgs a) {
         if (valid && below == 0) s_wcnt[w][dig[r]] = prev + (uint32_t)__popcll(m);
     }
     __syncthreads();
-    // per bucket: wave offsets, tile count, publish the aggregate
-    const uint32_t c0 = s_wcnt[0][tid], c1 = s_wcnt[1][tid], c2 = s_wcnt[2][tid], c3 = s_wcnt[3][tid];
-    const uint32_t tot = c0 + c1 + c2 + c3;
-    s_wcnt[0][tid] = 0;
-    s_wcnt[1][tid] = c0;
-    s_wcnt[2][tid] = c0 + c1;
-    s_wcnt[3][tid] = c0 + c1 + c2;
-    uint32_t* my_status = a.status + (uint64_t)tile * kRadix;
-    st_flag(my_status + tid, (tile == 0 ? kFlagInc : kFlagAgg) | tot);
+    // per bucket (threads 0..255): wave offsets, tile count, aggregate, look-back
+    uint32_t tot = 0, h = 0;
+    if (tid < kRadix) {
+        uint32_t run = 0;
+#pragma unroll
+        for (int ww = 0; ww < WAVES; ++ww) {
+            const uint32_t c = s_wcnt[ww][tid];
+            s_wcnt[ww][tid] = run;
+            run += c;
+        }
+        tot = run;
+        st_flag(a.status + (uint64_t)tile * kRadix + tid, (tile == 0 ? kFlagInc : kFlagAgg) | tot);
+        h = a.hist[tid];
+    }
     uint32_t dummy;
     const uint32_t lstart = block256_excl_scan(tot, s_tmp[0], &dummy);
-    const uint32_t gexcl = block256_excl_scan(a.hist[tid], s_tmp[1], &dummy);
-    // decoupled look-back for bucket tid
-    uint32_t prefix = 0;
-    if (tile > 0) {
-        uint64_t j = tile - 1;
-        for (;;) {
-            uint32_t s, spins = 0;
-            while (((s = ld_acquire_flag(a.status + j * kRadix + tid)) >> 30) == 0u) {
-                if (++spins > kSpinLimit) {
-                    atomicOr(a.err, kErrSpin);
-                    s = kFlagInc;
-                    break;
+    const uint32_t gexcl = block256_excl_scan(h, s_tmp[1], &dummy);
+    if (tid < kRadix) {
+        uint32_t prefix = 0;
+        if (tile > 0) {
+            // windowed look-back: one round trip fetches kSortLookWindow predecessors
+            int64_t j = (int64_t)tile - 1;
+            uint32_t spins = 0;
+            bool done = false;
+            while (!done) {
+                uint32_t sv[kSortLookWindow];
+#pragma unroll
+                for (int k = 0; k < kSortLookWindow; ++k)
+                    sv[k] = j - k >= 0 ? ld_acquire_flag(a.status + (uint64_t)(j - k) * kRadix + tid) : kFlagInc;
+                int used = 0;
+#pragma unroll
+                for (int k = 0; k < kSortLookWindow; ++k) {
+                    if (done || used < k) continue;          // stop at the first gap
+                    if ((sv[k] >> 30) == 0u) continue;       // not published yet: poll again from here
+                    prefix += sv[k] & kValMask;
+                    used = k + 1;
+                    if ((sv[k] & ~kValMask) == kFlagInc) done = true;
                 }
-                __builtin_amdgcn_s_sleep(1);
+                j -= used;
+                if (!done && j < 0) done = true;
+                if (!done && used == 0) {
+                    if (++spins > kSpinLimit) {
+                        atomicOr(a.err, kErrSpin);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
             }
-            prefix += s & kValMask;
-            if ((s & ~kValMask) == kFlagInc || j == 0) break;
-            --j;
+            st_flag(a.status + (uint64_t)tile * kRadix + tid, kFlagInc | (prefix + tot));
         }
-        st_flag(my_status + tid, kFlagInc | (prefix + tot));
+        s_lstart[tid] = lstart;
+        s_gbase[tid] = gexcl + prefix;
     }
-    s_lstart[tid] = lstart;
-    s_gbase[tid] = gexcl + prefix;
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kSortItems; ++r) {
-        const uint64_t idx = base + (uint64_t)w * (kSortItems * 64) + r * 64 + lane;
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint64_t idx = base + (uint64_t)w * (ITEMS * 64) + r * 64 + lane;
         const uint32_t pos = s_lstart[dig[r]] + s_wcnt[w][dig[r]] + rank[r];
-        if (idx < a.n && pos < (uint32_t)kSortTile) s_keys[pos] = key[r];
+        if (idx < a.n && pos < (uint32_t)TILE) s_keys[pos] = key[r];
     }
     __syncthreads();
-    const uint32_t tile_n = (uint32_t)min<uint64_t>(kSortTile, a.n - base);
-    for (uint32_t i = tid; i < tile_n; i += kSortThreads) {
+    const uint32_t tile_n = (uint32_t)min<uint64_t>(TILE, a.n - base);
+    for (uint32_t i = tid; i < tile_n; i += THREADS) {
         const uint64_t k = s_keys[i];
         const uint32_t d = (uint32_t)(k >> a.shift) & dmask;
         const uint64_t dst = (uint64_t)s_gbase[d] + (i - s_lstart[d]);
@@ -327,20 +356,22 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(SortPassArgs a) {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t pad_idx(uint32_t i) { return i + (i >> 4); }
 
+template <int PMAX>
 __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
     __shared__ uint64_t s_w[kScanTile + kScanTile / 16 + 1];
-    __shared__ uint8_t s_delta[kMaxProps][kStates * 16];
-    __shared__ uint8_t s_label[kMaxProps][kStates];
-    __shared__ uint64_t s_colmap[kMaxProps][16];
-    __shared__ uint32_t s_q0[kMaxProps];
-    __shared__ uint64_t s_wtot[kMaxProps][4];
+    __shared__ uint8_t s_delta[PMAX][kStates * 16];
+    __shared__ uint8_t s_label[PMAX][kStates];
+    __shared__ uint64_t s_colmap[PMAX][16];
+    __shared__ uint32_t s_q0[PMAX];
+    __shared__ uint64_t s_wtot[PMAX][4];
     __shared__ uint32_t s_ctot[4][4];
-    __shared__ uint64_t s_tprefix[kMaxProps];
-    __shared__ uint64_t s_tagg[kMaxProps];
+    __shared__ uint64_t s_tprefix[PMAX];
+    __shared__ uint64_t s_tagg[PMAX];
     __shared__ uint32_t s_cagg[4];
     __shared__ uint32_t s_tcnt[4];
     __shared__ uint64_t s_prev, s_next;
     __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_red[2][4];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t P = a.n_props;
@@ -399,9 +430,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
     for (int m = 1; m < 4; ++m) cnt[m] = (uint32_t)m < L ? __popc(m_lvl[m]) : 0u;
 
     // summaries: the map from the state before this run to the state after it
-    uint64_t summ[kMaxProps];
+    uint64_t summ[PMAX];
 #pragma unroll
-    for (int p = 0; p < kMaxProps; ++p) {
+    for (int p = 0; p < PMAX; ++p) {
         summ[p] = kIdentityMap;
         if (p >= (int)P) continue;
         uint64_t f = kIdentityMap;
@@ -423,9 +454,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
     }
 
     // block-wide exclusive scan of the summaries (composition) and counts
-    uint64_t excl[kMaxProps];
+    uint64_t excl[PMAX];
 #pragma unroll
-    for (int p = 0; p < kMaxProps; ++p) {
+    for (int p = 0; p < PMAX; ++p) {
         if (p >= (int)P) { excl[p] = kIdentityMap; continue; }
         uint64_t v = summ[p];
 #pragma unroll
@@ -446,7 +477,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
     }
     __syncthreads();
 #pragma unroll
-    for (int p = 0; p < kMaxProps; ++p) {
+    for (int p = 0; p < PMAX; ++p) {
         if (p >= (int)P) continue;
         uint64_t pre = kIdentityMap;
         for (int i = 0; i < w; ++i) pre = map_compose(s_wtot[p][i], pre);
@@ -470,60 +501,104 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
     }
     __syncthreads();
 
-    // publish this tile's aggregate, then look back (wave 0)
+    // publish this tile's aggregate, then look back (wave 0).  Lane p < P
+    // owns property p's map (two status words), lanes 32..35 the counts.
     ScanTileStatus* st = a.status + tile;
-    if (tid < (int)P) {
-        st->agg_map[tid] = s_tagg[tid];
-        if (tile == 0) st->inc_map[tid] = s_tagg[tid];
-    }
-    if (tid >= 32 && tid < 36) {
-        st->agg_cnt[tid - 32] = s_cagg[tid - 32];
-        if (tile == 0) st->inc_cnt[tid - 32] = s_cagg[tid - 32];
-    }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) st_flag(a.flags + tile, tile == 0 ? 2u : 1u);
+    const uint64_t kValid = 1ull << 32;
     if (w == 0) {
+        if (lane < (int)P) {
+            const uint64_t m = s_tagg[lane];
+            __hip_atomic_store(&st->agg[2 * lane], kValid | (m & 0xFFFFFFFFull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&st->agg[2 * lane + 1], kValid | (m >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (lane >= 32 && lane < 36)
+            __hip_atomic_store(&st->agg[2 * kMaxProps + lane - 32], kValid | s_cagg[lane - 32], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        const bool owns = lane < (int)P || (lane >= 32 && lane < 36);
+        const int w0 = lane < 32 ? 2 * lane : 2 * kMaxProps + lane - 32;   // first word of this lane
+        const int nw = lane < 32 ? 2 : 1;
         uint64_t acc = kIdentityMap;
         uint32_t accc = 0;
         if (tile > 0) {
-            uint64_t j = tile - 1;
-            for (;;) {
-                uint32_t fl, spins = 0;
-                while ((fl = ld_acquire_flag(a.flags + j)) == 0u) {
+            // windowed look-back: every owning lane fetches the aggregate and
+            // inclusive words of kScanLookWindow predecessors in one round trip,
+            // then folds them nearest first until an inclusive tile
+            int64_t j = (int64_t)tile - 1;
+            uint32_t spins = 0;
+            bool done = false;
+            while (!done) {
+                uint64_t ia[kScanLookWindow], ib[kScanLookWindow], aa[kScanLookWindow], ab[kScanLookWindow];
+#pragma unroll
+                for (int k = 0; k < kScanLookWindow; ++k) {
+                    ia[k] = ib[k] = aa[k] = ab[k] = kValid;
+                    if (owns && j - k >= 0) {
+                        const ScanTileStatus* sj = a.status + (j - k);
+                        ia[k] = __hip_atomic_load(&sj->inc[w0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        aa[k] = __hip_atomic_load(&sj->agg[w0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (nw == 2) {
+                            ib[k] = __hip_atomic_load(&sj->inc[w0 + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            ab[k] = __hip_atomic_load(&sj->agg[w0 + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                    }
+                }
+                int used = 0;
+                bool stop = false;
+#pragma unroll
+                for (int k = 0; k < kScanLookWindow; ++k) {
+                    if (stop || done) continue;
+                    if (j - k < 0) { done = true; continue; }
+                    const bool inc_ok = __all(((ia[k] & kValid) != 0) && ((ib[k] & kValid) != 0));
+                    const bool agg_ok = __all(((aa[k] & kValid) != 0) && ((ab[k] & kValid) != 0));
+                    if (!inc_ok && !agg_ok) { stop = true; continue; }
+                    const uint64_t v0 = inc_ok ? ia[k] : aa[k], v1 = inc_ok ? ib[k] : ab[k];
+                    if (lane < (int)P) acc = map_compose(acc, (v0 & 0xFFFFFFFFull) | ((v1 & 0xFFFFFFFFull) << 32));
+                    if (lane >= 32 && lane < 36) accc += (uint32_t)v0;
+                    used = k + 1;
+                    if (inc_ok) done = true;
+                }
+                j -= used;
+                if (!done && j < 0) done = true;
+                if (!done && used == 0) {
                     if (++spins > kSpinLimit) {
                         if (lane == 0) atomicOr(a.err, kErrSpin);
-                        fl = 2u;
                         break;
                     }
                     __builtin_amdgcn_s_sleep(1);
                 }
-                __threadfence();
-                const ScanTileStatus* sj = a.status + j;
-                if (lane < (int)P) acc = map_compose(acc, fl == 2u ? sj->inc_map[lane] : sj->agg_map[lane]);
-                if (lane >= 32 && lane < 36) accc += fl == 2u ? sj->inc_cnt[lane - 32] : sj->agg_cnt[lane - 32];
-                if (fl == 2u || j == 0) break;
-                --j;
             }
-            if (lane < (int)P) st->inc_map[lane] = map_compose(s_tagg[lane], acc);
-            if (lane >= 32 && lane < 36) st->inc_cnt[lane - 32] = accc + s_cagg[lane - 32];
-            __threadfence();
-            if (lane == 0) st_flag(a.flags + tile, 2u);
         }
-        if (lane < (int)P) s_tprefix[lane] = acc;
-        if (lane >= 32 && lane < 36) s_tcnt[lane - 32] = accc;
+        // publish the inclusive value
+        if (lane < (int)P) {
+            const uint64_t m = tile > 0 ? map_compose(s_tagg[lane], acc) : s_tagg[lane];
+            __hip_atomic_store(&st->inc[2 * lane], kValid | (m & 0xFFFFFFFFull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&st->inc[2 * lane + 1], kValid | (m >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_tprefix[lane] = acc;
+        }
+        if (lane >= 32 && lane < 36) {
+            __hip_atomic_store(&st->inc[2 * kMaxProps + lane - 32], kValid | (accc + s_cagg[lane - 32]),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_tcnt[lane - 32] = accc;
+        }
     }
     __syncthreads();
 
     // second walk: final state at every instance end; numbering of nodes
-    uint32_t cur[kMaxProps];
+    uint32_t cur[PMAX];
 #pragma unroll
-    for (int p = 0; p < kMaxProps; ++p)
+    for (int p = 0; p < PMAX; ++p)
         cur[p] = p < (int)P ? map_at(map_compose(excl[p], s_tprefix[p]), 0) : 0u;
     uint32_t inst = s_tcnt[0] + cexcl[0];
     uint32_t lvl[4];
 #pragma unroll
     for (int m = 1; m < 4; ++m) lvl[m] = s_tcnt[m] + cexcl[m];
+    // Instance verdicts are staged in LDS (the word buffer is free now) and
+    // written out contiguously: the instances ending in this tile have the
+    // consecutive ids [s_ilo, s_ihi], all >= s_tcnt[0] - 1.
+    const bool stage = P <= 8;
+    uint8_t* s_iv = reinterpret_cast<uint8_t*>(s_w);
+    constexpr uint32_t kIvStride = kScanTile + 1;
+    const uint32_t id_base = s_tcnt[0];             // slot of id = id + 1 - id_base
+    uint32_t my_lo = 0xFFFFFFFFu, my_hi = 0u;       // ids [my_lo, my_hi) this thread staged
     uint32_t err = 0;
     for (int j = 0; j < kScanItems; ++j) {
         if (!((m_valid >> j) & 1u)) break;
@@ -532,7 +607,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
         if ((m_head >> j) & 1u) {
             ++inst;
 #pragma unroll
-            for (int p = 0; p < kMaxProps; ++p) cur[p] = p < (int)P ? s_q0[p] : 0u;
+            for (int p = 0; p < PMAX; ++p) cur[p] = p < (int)P ? s_q0[p] : 0u;
 #pragma unroll
             for (int m = kMaxLevels - 1; m >= 1; --m) {
                 if (m >= (int)L || !((m_lvl[m] >> j) & 1u)) continue;
@@ -548,14 +623,23 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
             }
         }
 #pragma unroll
-        for (int p = 0; p < kMaxProps; ++p)
+        for (int p = 0; p < PMAX; ++p)
             if (p < (int)P) cur[p] = s_delta[p][cur[p] * 16 + c];
         if ((m_end >> j) & 1u) {
             const uint64_t id = inst - 1;
             if (id < a.inst_limit) {
+                if (stage) {
+                    const uint32_t slot = (uint32_t)id + 1u - id_base;
 #pragma unroll
-                for (int p = 0; p < kMaxProps; ++p)
-                    if (p < (int)P) a.inst_verdict[p * a.inst_stride + id] = s_label[p][cur[p]];
+                    for (int p = 0; p < (PMAX < 8 ? PMAX : 8); ++p)
+                        if (p < (int)P) s_iv[p * kIvStride + slot] = s_label[p][cur[p]];
+                    my_lo = min(my_lo, (uint32_t)id);
+                    my_hi = max(my_hi, (uint32_t)id + 1u);
+                } else {
+#pragma unroll
+                    for (int p = 0; p < PMAX; ++p)
+                        if (p < (int)P) a.inst_verdict[p * a.inst_stride + id] = s_label[p][cur[p]];
+                }
                 if (a.inst_keys) a.inst_keys[id] = x >> cb;
             } else {
                 err |= kErrCapacity;
@@ -563,6 +647,27 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
         }
     }
     if (err) atomicOr(a.err, err);
+    if (stage) {
+        // block min / max of the staged id range
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            my_lo = min(my_lo, (uint32_t)__shfl_xor(my_lo, off, 64));
+            my_hi = max(my_hi, (uint32_t)__shfl_xor(my_hi, off, 64));
+        }
+        if (lane == 0) {
+            s_red[0][w] = my_lo;
+            s_red[1][w] = my_hi;
+        }
+        __syncthreads();
+        const uint32_t lo = min(min(s_red[0][0], s_red[0][1]), min(s_red[0][2], s_red[0][3]));
+        const uint32_t hi = max(max(s_red[1][0], s_red[1][1]), max(s_red[1][2], s_red[1][3]));
+        if (lo < hi) {
+            const uint32_t cnt_iv = hi - lo, slot0 = lo + 1u - id_base;
+            for (uint32_t p = 0; p < P; ++p)
+                for (uint32_t i = tid; i < cnt_iv; i += kScanThreads)
+                    a.inst_verdict[p * a.inst_stride + lo + i] = s_iv[p * kIvStride + slot0 + i];
+        }
+    }
     // the thread holding the last event publishes the totals
     const uint64_t my0 = base + (uint64_t)tid * kScanItems;
     if (my0 <= a.n - 1 && a.n - 1 < my0 + kScanItems) {
@@ -675,15 +780,41 @@ hipError_t launch_classify(const ClassifyArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_sort_pass(const SortPassArgs& a, hipStream_t s) {
-    const uint32_t tiles = (a.n + kSortTile - 1) / kSortTile;
-    hipLaunchKernelGGL(k_sort_pass, dim3(tiles), dim3(kSortThreads), 0, s, a);
+uint32_t sort_tile(int variant) {
+    switch (variant) {
+        case 1: return 512 * 16;
+        case 2: return 256 * 24;
+        case 3: return 256 * 8;
+        case 4: return 512 * 8;
+        default: return 256 * 16;
+    }
+}
+
+hipError_t launch_sort_pass(const SortPassArgs& a, int variant, hipStream_t s) {
+    const uint32_t tile = sort_tile(variant);
+    const uint32_t tiles = (a.n + tile - 1) / tile;
+    switch (variant) {
+        case 1: hipLaunchKernelGGL((k_sort_pass<512, 16>), dim3(tiles), dim3(512), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_sort_pass<256, 24>), dim3(tiles), dim3(256), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_sort_pass<256, 8>), dim3(tiles), dim3(256), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_sort_pass<512, 8>), dim3(tiles), dim3(512), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_sort_pass<256, 16>), dim3(tiles), dim3(256), 0, s, a); break;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s) {
     const uint32_t tiles = (a.n + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(k_scan, dim3(tiles), dim3(kScanThreads), 0, s, a);
+    if (a.n_props <= 1)
+        hipLaunchKernelGGL(k_scan<1>, dim3(tiles), dim3(kScanThreads), 0, s, a);
+    else if (a.n_props <= 2)
+        hipLaunchKernelGGL(k_scan<2>, dim3(tiles), dim3(kScanThreads), 0, s, a);
+    else if (a.n_props <= 4)
+        hipLaunchKernelGGL(k_scan<4>, dim3(tiles), dim3(kScanThreads), 0, s, a);
+    else if (a.n_props <= 8)
+        hipLaunchKernelGGL(k_scan<8>, dim3(tiles), dim3(kScanThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_scan<16>, dim3(tiles), dim3(kScanThreads), 0, s, a);
     return hipGetLastError();
 }
 

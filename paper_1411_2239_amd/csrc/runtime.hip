@@ -64,6 +64,7 @@ struct ltl4c_ctx {
     std::vector<ltl4c_property> props;
     std::map<std::vector<int32_t>, Plan*> plans;
     uint32_t* err_dev = nullptr;
+    int sort_variant = 1;
     bool prof = false;
     std::vector<Timed> timed;
     std::vector<hipEvent_t> free_events;
@@ -101,16 +102,17 @@ struct WsLayout {
     uint64_t total;
     uint64_t zero_off, zero_words;
     uint64_t hist_off, sort_ticket_off, scan_ticket_off, root_counts_off, sizes32_off, sizes64_off;
-    uint64_t sort_status_off, scan_flags_off;
-    uint64_t words_a_off, words_b_off, scan_status_off, inst_verdict_off;
+    uint64_t sort_status_off, scan_status_off;
+    uint64_t words_a_off, words_b_off, inst_verdict_off;
     uint64_t node_start_off[kMaxLevels], counts_off[kMaxLevels];
     uint64_t cap_node[kMaxLevels];
     uint32_t tiles_sort, tiles_scan;
 };
 
-WsLayout plan_workspace(const ltl4c_layout& L, const Geometry& g, uint64_t n, uint32_t P) {
+WsLayout plan_workspace(const ltl4c_layout& L, const Geometry& g, uint64_t n, uint32_t P, int sort_variant) {
     WsLayout w{};
-    w.tiles_sort = (uint32_t)((n + kSortTile - 1) / kSortTile);
+    const uint64_t st = sort_tile(sort_variant);
+    w.tiles_sort = (uint32_t)((n + st - 1) / st);
     w.tiles_scan = (uint32_t)((n + kScanTile - 1) / kScanTile);
     // zero block, in 32-bit words
     uint64_t z = 0;
@@ -121,14 +123,14 @@ WsLayout plan_workspace(const ltl4c_layout& L, const Geometry& g, uint64_t n, ui
     w.sizes32_off = z;     z += 64;
     w.sizes64_off = z;     z += 64;                      // 32 x uint64
     w.sort_status_off = z; z += (uint64_t)g.n_pass * w.tiles_sort * kRadix;
-    w.scan_flags_off = z;  z += w.tiles_scan;
+    z = (z + 63) & ~63ull;
+    w.scan_status_off = z; z += (uint64_t)w.tiles_scan * (sizeof(ScanTileStatus) / 4);
     z = (z + 63) & ~63ull;
     w.zero_off = 0;
     w.zero_words = z;
     uint64_t off = align256(z * 4);
     w.words_a_off = off;   off = align256(off + n * 8);
     w.words_b_off = off;   off = align256(off + n * 8);
-    w.scan_status_off = off; off = align256(off + (uint64_t)w.tiles_scan * sizeof(ScanTileStatus));
     w.inst_verdict_off = off; off = align256(off + (uint64_t)P * n);
     for (uint32_t m = 1; m < L.n_keys; ++m) {
         uint64_t cap = n;
@@ -401,7 +403,7 @@ int32_t ltl4c_workspace_bytes(ltl4c_ctx* ctx, uint64_t n_events, const int32_t* 
     if (!bytes) return fail(LTL4C_EINVAL, "bytes is NULL");
     if (n_events > LTL4C_MAX_EVENTS) return fail(LTL4C_EUNSUPPORTED, "too many events for one call");
     Geometry g = geometry(ctx->layout);
-    *bytes = plan_workspace(ctx->layout, g, n_events, (uint32_t)n_props).total;
+    *bytes = plan_workspace(ctx->layout, g, n_events, (uint32_t)n_props, ctx->sort_variant).total;
     return LTL4C_OK;
 }
 
@@ -419,7 +421,7 @@ int32_t ltl4c_eval(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int3
     if (n > 0 && (reinterpret_cast<uintptr_t>(d_records) & 3))
         return fail(LTL4C_EINVAL, "records must be 4-byte aligned");
     Geometry g = geometry(L);
-    WsLayout w = plan_workspace(L, g, n, P);
+    WsLayout w = plan_workspace(L, g, n, P, ctx->sort_variant);
     if (ws_bytes < w.total) return fail(LTL4C_ENOMEM, "workspace smaller than ltl4c_workspace_bytes()");
     if ((out->inst_keys != nullptr) != (out->inst_verdict != nullptr))
         return fail(LTL4C_EINVAL, "inst_keys and inst_verdict are given together or not at all");
@@ -447,10 +449,9 @@ int32_t ltl4c_eval(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int3
     uint32_t* sizes32 = z + w.sizes32_off;
     uint64_t* sizes64 = reinterpret_cast<uint64_t*>(z + w.sizes64_off);
     uint32_t* sort_status = z + w.sort_status_off;
-    uint32_t* scan_flags = z + w.scan_flags_off;
     uint64_t* words_a = reinterpret_cast<uint64_t*>(ws + w.words_a_off);
     uint64_t* words_b = reinterpret_cast<uint64_t*>(ws + w.words_b_off);
-    ScanTileStatus* scan_status = reinterpret_cast<ScanTileStatus*>(ws + w.scan_status_off);
+    ScanTileStatus* scan_status = reinterpret_cast<ScanTileStatus*>(z + w.scan_status_off);
     const hipStream_t st = ctx->stream;
 
     {
@@ -501,7 +502,7 @@ int32_t ltl4c_eval(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int3
             sa.status = sort_status + (uint64_t)p * w.tiles_sort * kRadix;
             sa.ticket = sort_ticket + p;
             sa.err = ctx->err_dev;
-            s = launch(ctx, "sort_pass", [&] { return launch_sort_pass(sa, st); });
+            s = launch(ctx, "sort_pass", [&] { return launch_sort_pass(sa, ctx->sort_variant, st); });
             if (s) return s;
             std::swap(in, outw);
         }
@@ -547,7 +548,6 @@ int32_t ltl4c_eval(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int3
             sa.node_keys[m] = out->node_keys[m];
             sa.node_limit[m] = node_limit[m];
         }
-        sa.flags = scan_flags;
         sa.status = scan_status;
         sa.ticket = scan_ticket;
         sa.sizes = sizes64;
@@ -622,6 +622,18 @@ int32_t ltl4c_wait(ltl4c_ctx* ctx) {
         if (err & kErrCapacity) return fail(LTL4C_ECAPACITY, "more instances or nodes than the capacity");
     }
     return LTL4C_OK;
+}
+
+int32_t ltl4c_set_option(ltl4c_ctx* ctx, int32_t option, int64_t value) {
+    if (!ctx) return fail(LTL4C_EINVAL, "ctx is NULL");
+    switch (option) {
+        case LTL4C_OPT_SORT_TILE:
+            if (value < 0 || value >= kSortVariants) return fail(LTL4C_EINVAL, "sort tile variant out of range");
+            ctx->sort_variant = (int)value;
+            return LTL4C_OK;
+        default:
+            return fail(LTL4C_EINVAL, "unknown option");
+    }
 }
 
 int32_t ltl4c_profile_enable(ltl4c_ctx* ctx, int32_t on) {

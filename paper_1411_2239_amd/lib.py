@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "libltl4c.so")
 
 OK, EINVAL, ENOMEM, ECAPACITY, EDEVICE, EADMIT, ESEQ, EUNSUPPORTED, ERANGE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 BOT, BOT_C, BOT_P, TOP_P, TOP_C, TOP = range(6)
+OPT_SORT_TILE = 0
 VERDICT_NAMES = ["F", "Fc", "Fp", "Tp", "Tc", "T"]
 KIND = {"A": 0, "E": 1}
 OP = {"<": 0, "<=": 1, ">": 2, ">=": 3, "=": 4}
@@ -76,6 +77,7 @@ SIGNATURES = [
      [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(C.c_int32), C.c_int32, C.c_void_p, C.c_uint64,
       C.POINTER(Result)]),
     ("ltl4c_wait", C.c_int32, [C.c_void_p]),
+    ("ltl4c_set_option", C.c_int32, [C.c_void_p, C.c_int32, C.c_int64]),
     ("ltl4c_profile_enable", C.c_int32, [C.c_void_p, C.c_int32]),
     ("ltl4c_profile_get", C.c_int32,
      [C.c_void_p, C.c_int32, C.c_char_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
@@ -84,9 +86,14 @@ SIGNATURES = [
 
 
 def load(path=LIB_PATH):
-    """Open libltl4c.so; raises if it has not been built."""
+    """Open libltl4c.so; raises if it has not been built.
+
+    torch is imported first so that the library binds to the HIP runtime torch
+    already loaded: one process must not hold two HIP runtimes."""
     global _lib
     if _lib is None:
+        import torch  # noqa: F401
+
         if not os.path.exists(path):
             raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
                                "(there is no fallback path)")
@@ -272,6 +279,10 @@ class Context:
 
     def wait(self):
         _check(self.lib.ltl4c_wait(self.h), "ltl4c_wait")
+
+    def set_option(self, option, value):
+        _check(self.lib.ltl4c_set_option(self.h, option, value), "ltl4c_set_option")
+        self._workspace = None
 
     def profile(self, on=True):
         _check(self.lib.ltl4c_profile_enable(self.h, 1 if on else 0), "ltl4c_profile_enable")

@@ -105,3 +105,17 @@ def test_excluded_events():
     wl.layout.key_present[9] = 0b01
     wl.layout.class_of_type[9] = 0
     _check(wl)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
+def test_sort_tile_variants(variant):
+    import torch
+    from paper_1411_2239_amd import lib
+    wl = W.gen_user_requests(n_events=400_000, n_users=700, seed=31 + variant)
+    print(f"[case] sort variant {variant}", flush=True)
+    ctx, ids, rec = lib.open_workload(wl)
+    ctx.set_option(lib.OPT_SORT_TILE, variant)
+    r = ctx.eval(rec, ids, instances=True, nodes=True)
+    torch.cuda.synchronize()
+    ctx.close()
+    compare_full(r, evaluate_workload(wl), len(ids), 2)
