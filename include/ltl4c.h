@@ -149,6 +149,8 @@ typedef struct {
  *   node_verdict[m] [n_props * capacity]    verdict of node j
  * (node_* index m runs over 1..n_levels-1; index 0 is unused.)
  */
+/* (inst_keys and inst_verdict are given together or not at all; so are the
+ * three node_* arrays of a level.) */
 typedef struct {
     uint8_t  *root_verdict;
     uint64_t *root_counts;
@@ -200,6 +202,59 @@ int32_t ltl4c_eval(ltl4c_ctx *ctx, const void *d_records, uint64_t n_events,
 /* Synchronise the context's stream and report device-detected errors of the
  * work enqueued since the previous ltl4c_wait (LTL4C_ERANGE, ECAPACITY). */
 int32_t ltl4c_wait(ltl4c_ctx *ctx);
+
+/* ---- online monitoring: stream groups ----------------------------------
+ *
+ * Online mode of Section 4: the monitor tree persists across invocations and
+ * every new piece of trace updates it incrementally (the truth value evolves
+ * with the trace).  A stream group keeps the trees of up to max_streams
+ * independent traces ("streams") resident in device memory, all monitored for
+ * the same properties with the context's layout.  Per binding (full value
+ * vector) it keeps the monitor state of every property (the LTL4 submonitor of
+ * Section 3.1); per quantifier node its 6-bin count vector and verdict
+ * (Def. 8); per stream the root verdict.  Instantiation on first occurrence
+ * (Section 3.3) is a device hash-table insert; after each push only the
+ * touched nodes are re-valued, level by level up to the roots.
+ *
+ * Limits: the monitors of the group's properties have at most 16 states in
+ * total; a push carries at most 4096 chunks and max_batch events; the stream
+ * id, the keys and the class bits fit in 63 bits.  The library allocates the
+ * group's device memory itself, within the context's memory budget. */
+
+/* Cap on the device memory the context's stream groups may hold (default:
+ * unlimited).  A group that would exceed it is refused with LTL4C_EADMIT. */
+int32_t ltl4c_set_memory_budget(ltl4c_ctx *ctx, uint64_t bytes);
+
+/* Device bytes a group with these limits would take. */
+int32_t ltl4c_group_bytes(ltl4c_ctx *ctx, const int32_t *props, int32_t n_props, uint32_t max_streams,
+                          uint32_t max_bindings, uint64_t max_batch, uint64_t *bytes);
+
+/* Open a group: max_bindings bounds the bindings of one stream, max_batch the
+ * events of one push.  *group receives its id.  Synchronous. */
+int32_t ltl4c_group_open(ltl4c_ctx *ctx, const int32_t *props, int32_t n_props, uint32_t max_streams,
+                         uint32_t max_bindings, uint64_t max_batch, int32_t *group);
+int32_t ltl4c_group_close(ltl4c_ctx *ctx, int32_t group);
+
+/* Append n_chunks chunks: chunk i is records [offsets[i], offsets[i+1]) of
+ * d_records (device, trace order) and continues stream streams[i].
+ * offsets[0] = 0; chunks of one stream appear in arrival order.  offsets and
+ * streams are host arrays read during the call.  Asynchronous on the
+ * context's stream; the records must stay valid until it has run.
+ * Bindings beyond max_bindings or a full table give LTL4C_ECAPACITY from
+ * ltl4c_wait(). */
+int32_t ltl4c_group_push(ltl4c_ctx *ctx, int32_t group, const void *d_records, const uint64_t *offsets,
+                         const uint32_t *streams, int32_t n_chunks);
+
+/* Current truth values (device outputs): root_verdict[s * n_props + p],
+ * root_counts[(s * n_props + p) * 6 + b], bindings[s] (may be NULL). */
+int32_t ltl4c_group_read(ltl4c_ctx *ctx, int32_t group, uint8_t *d_root_verdict, uint64_t *d_root_counts,
+                         uint64_t *d_bindings);
+
+/* Checkpoint / resume: copy the group's resident state to host memory
+ * (*bytes is its size; host == NULL only queries it) and back.  Both
+ * synchronise the context's stream. */
+int32_t ltl4c_group_snapshot(ltl4c_ctx *ctx, int32_t group, void *host, uint64_t *bytes);
+int32_t ltl4c_group_restore(ltl4c_ctx *ctx, int32_t group, const void *host, uint64_t bytes);
 
 /* ---- tuning ------------------------------------------------------------- */
 

@@ -23,6 +23,7 @@ constexpr int kCountTile = kCountThreads * kCountItems;
 constexpr int kCountWindow = 64;     // nodes kept in LDS per counting tile
 constexpr uint64_t kIdentityMap = 0xFEDCBA9876543210ull;
 constexpr uint32_t kSpinLimit = 1u << 22;   // bounded waits in decoupled look-back
+constexpr uint32_t kMaxChunks = 4096;        // chunks in one stream-group push
 
 // Error bits raised on the device and reported by ltl4c_wait().
 enum : uint32_t { kErrRange = 1u, kErrCapacity = 2u, kErrSpin = 4u };
@@ -71,6 +72,12 @@ struct ClassifyArgs {
     uint64_t* words;
     uint32_t* hist;                  // [n_pass][256]
     uint32_t* err;
+    // stream groups: event i belongs to the chunk c with
+    // chunk_off[c] <= i < chunk_off[c+1]; its stream id goes above the keys
+    const uint32_t* chunk_off;       // [n_chunks + 1], or nullptr
+    const uint32_t* chunk_stream;    // [n_chunks]
+    uint32_t n_chunks;
+    uint32_t stream_shift;
 };
 
 struct SortPassArgs {
@@ -102,6 +109,7 @@ struct ScanArgs {
     uint64_t* node_keys[kMaxLevels];     // optional
     uint64_t node_limit[kMaxLevels];     // nodes with an id below this are written
     ScanTileStatus* status;              // [tiles], zeroed before the launch
+    uint32_t emit_state;                 // write final states instead of verdicts
     uint32_t* ticket;
     uint64_t* sizes;                     // [1 + n_levels] written by the last tile
     uint32_t* sizes32;                   // same, 32-bit, for the counting kernels
@@ -148,6 +156,50 @@ struct FinalizeArgs {
     uint32_t n_levels;
 };
 
+// Online monitoring: the resident monitor tree of a stream group.
+// Bindings and quantifier nodes live in open-addressing hash tables keyed by
+// the packed (stream, key...) prefix; a node's id is its slot.
+constexpr uint64_t kEmptyKey = ~0ull;
+constexpr uint8_t kNoVerdict = 0xFF;     // node not yet counted in its parent
+
+struct GroupState {
+    uint32_t n_props, n_levels;
+    uint32_t vbase[kMaxProps];           // first virtual property of property p
+    const Plan* plan;                    // real properties (labels, q0, quantifiers)
+    uint32_t level_shift[kMaxLevels];    // key >> level_shift[m] = (stream, keys 0..m-1), m >= 1
+    uint32_t stream_shift;               // key >> stream_shift = stream
+    uint32_t max_streams, max_bindings;
+    // bindings
+    uint64_t* bkeys;                     // [bcap]
+    uint64_t bmask;
+    uint8_t* bstate;                     // [P][bcap]
+    uint32_t* bparent;                   // [bcap]
+    uint32_t* stream_bindings;           // [max_streams]
+    // quantifier nodes of levels 1..n_levels-1
+    uint64_t* nkeys[kMaxLevels];         // [ncap]
+    uint64_t nmask;
+    uint32_t* ncounts[kMaxLevels];       // [P][ncap][6]
+    uint8_t* nverdict[kMaxLevels];       // [P][ncap]
+    uint32_t* nparent[kMaxLevels];       // [ncap]
+    uint32_t* ndirty[kMaxLevels];        // [ncap]
+    uint32_t* nlist[kMaxLevels];         // [ncap]
+    // stream roots
+    uint32_t* rcounts;                   // [S][P][6]
+    uint8_t* rverdict;                   // [S][P]
+    uint32_t* rdirty;                    // [S]
+    uint32_t* rlist;                     // [S]
+    uint32_t* list_cnt;                  // [kMaxLevels]: dirty-list lengths (index 0 = roots)
+    uint32_t* err;
+};
+
+struct GroupUpdateArgs {
+    GroupState g;
+    const uint32_t* n_seg;               // segments (instances) of this push
+    const uint64_t* seg_key;             // [n_seg] packed (stream, keys)
+    const uint8_t* seg_state;            // [V][seg_stride] final state per start state
+    uint64_t seg_stride;
+};
+
 // Launchers (defined in kernels.hip).
 hipError_t launch_zero(const ZeroArgs& a, uint32_t blocks, hipStream_t s);
 hipError_t launch_classify(const ClassifyArgs& a, hipStream_t s);
@@ -157,5 +209,12 @@ constexpr int kSortVariants = 5;
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
 hipError_t launch_count(const CountArgs& a, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
+hipError_t launch_group_update(const GroupUpdateArgs& a, uint64_t max_seg, hipStream_t s);
+hipError_t launch_group_level(const GroupState& g, uint32_t level, hipStream_t s);
+hipError_t launch_group_roots(const GroupState& g, bool all, hipStream_t s);
+hipError_t launch_group_read(const GroupState& g, uint8_t* verdict, uint64_t* counts, uint64_t* bindings,
+                             hipStream_t s);
+hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* p, uint64_t n, uint8_t v, hipStream_t s);
 
 }  // namespace ltl4c

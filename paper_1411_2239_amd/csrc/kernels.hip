@@ -171,16 +171,22 @@ __device__ __forceinline__ void load_record(const ClassifyArgs& a, uint64_t i, u
     }
 }
 
-template <int RDW>
+template <int RDW, bool GROUP>
 __global__ __launch_bounds__(1024) void k_classify(ClassifyArgs a) {
     __shared__ uint8_t s_cls[256];
     __shared__ uint8_t s_kp[256];
     __shared__ uint32_t s_hist[8][256];
+    __shared__ uint32_t s_coff[GROUP ? kMaxChunks + 1 : 1];
+    __shared__ uint32_t s_cstream[GROUP ? kMaxChunks : 1];
     for (int i = threadIdx.x; i < 256; i += blockDim.x) {
         s_cls[i] = a.plan->class_of_type[i];
         s_kp[i] = a.plan->key_present[i];
     }
     for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) (&s_hist[0][0])[i] = 0;
+    if constexpr (GROUP) {
+        for (uint32_t i = threadIdx.x; i <= a.n_chunks; i += blockDim.x) s_coff[i] = a.chunk_off[i];
+        for (uint32_t i = threadIdx.x; i < a.n_chunks; i += blockDim.x) s_cstream[i] = a.chunk_stream[i];
+    }
     __syncthreads();
     uint32_t err = 0;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -214,6 +220,15 @@ __global__ __launch_bounds__(1024) void k_classify(ClassifyArgs a) {
             }
         }
         if (ok && over) err |= kErrRange;
+        if constexpr (GROUP) {
+            // chunk c with s_coff[c] <= i < s_coff[c+1]
+            uint32_t lo = 0, hi = a.n_chunks;
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (s_coff[mid] <= (uint32_t)i) lo = mid; else hi = mid;
+            }
+            key |= (uint64_t)s_cstream[lo] << a.stream_shift;
+        }
         const uint64_t word = ok ? ((key << a.cbits) | s_cls[t8]) : (1ull << a.excl_shift);
         a.words[i] = word;
         for (uint32_t p = 0; p < a.n_pass; ++p)
@@ -632,13 +647,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
                     const uint32_t slot = (uint32_t)id + 1u - id_base;
 #pragma unroll
                     for (int p = 0; p < (PMAX < 8 ? PMAX : 8); ++p)
-                        if (p < (int)P) s_iv[p * kIvStride + slot] = s_label[p][cur[p]];
+                        if (p < (int)P) s_iv[p * kIvStride + slot] = a.emit_state ? cur[p] : s_label[p][cur[p]];
                     my_lo = min(my_lo, (uint32_t)id);
                     my_hi = max(my_hi, (uint32_t)id + 1u);
                 } else {
 #pragma unroll
                     for (int p = 0; p < PMAX; ++p)
-                        if (p < (int)P) a.inst_verdict[p * a.inst_stride + id] = s_label[p][cur[p]];
+                        if (p < (int)P)
+                            a.inst_verdict[p * a.inst_stride + id] = a.emit_state ? cur[p] : s_label[p][cur[p]];
                 }
                 if (a.inst_keys) a.inst_keys[id] = x >> cb;
             } else {
@@ -761,6 +777,188 @@ __global__ void k_finalize(FinalizeArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// online monitoring: incremental update of a stream group's monitor tree
+// (Section 4: online mode; SpawnMonitors / AddToTree of Algorithm 1 become
+// hash-table inserts, ApplyQuantifiers a re-valuation of the touched nodes)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdull;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ull;
+    x ^= x >> 33;
+    return x;
+}
+
+// Insert-or-find `key` in an open-addressing table; returns its slot and
+// whether this call inserted it, or ~0 when the table is full.
+__device__ uint64_t table_slot(uint64_t* keys, uint64_t mask, uint64_t key, bool* fresh) {
+    uint64_t h = mix64(key) & mask;
+    for (uint64_t probe = 0; probe <= mask; ++probe) {
+        const uint64_t k = __hip_atomic_load(keys + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (k == key) {
+            *fresh = false;
+            return h;
+        }
+        if (k == kEmptyKey) {
+            const uint64_t prev = atomicCAS(reinterpret_cast<unsigned long long*>(keys + h), kEmptyKey, key);
+            if (prev == kEmptyKey) {
+                *fresh = true;
+                return h;
+            }
+            if (prev == key) {
+                *fresh = false;
+                return h;
+            }
+        }
+        h = (h + 1) & mask;
+    }
+    *fresh = false;
+    return ~0ull;
+}
+
+__device__ __forceinline__ void mark_node(const GroupState& g, uint32_t level, uint32_t slot) {
+    if (level == 0) {
+        if (atomicExch(g.rdirty + slot, 1u) == 0u) g.rlist[atomicAdd(g.list_cnt + 0, 1u)] = slot;
+    } else {
+        if (atomicExch(g.ndirty[level] + slot, 1u) == 0u) g.nlist[level][atomicAdd(g.list_cnt + level, 1u)] = slot;
+    }
+}
+
+__device__ __forceinline__ uint32_t* counts_of(const GroupState& g, uint32_t level, uint32_t slot, uint32_t p) {
+    if (level == 0) return g.rcounts + ((uint64_t)slot * g.n_props + p) * 6;
+    return g.ncounts[level] + ((uint64_t)p * (g.nmask + 1) + slot) * 6;
+}
+
+// One thread per binding segment of the pushed chunks.
+__global__ __launch_bounds__(256) void k_group_update(GroupUpdateArgs a) {
+    const GroupState& g = a.g;
+    const uint32_t nseg = *a.n_seg;
+    const uint32_t L = g.n_levels;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nseg; i += gridDim.x * blockDim.x) {
+        const uint64_t key = a.seg_key[i];
+        const uint32_t stream = (uint32_t)(key >> g.stream_shift);
+        bool fresh = false;
+        const uint64_t b = table_slot(g.bkeys, g.bmask, key, &fresh);
+        if (b == ~0ull || stream >= g.max_streams) {
+            atomicOr(g.err, kErrCapacity);
+            continue;
+        }
+        uint32_t parent;
+        if (fresh) {
+            if (atomicAdd(g.stream_bindings + stream, 1u) >= g.max_bindings) atomicOr(g.err, kErrCapacity);
+            if (L == 1) {
+                parent = stream;
+            } else {
+                // find or create the chain of quantifier nodes above this binding
+                bool nf = false;
+                uint64_t slot = table_slot(g.nkeys[L - 1], g.nmask, key >> g.level_shift[L - 1], &nf);
+                if (slot == ~0ull) {
+                    atomicOr(g.err, kErrCapacity);
+                    continue;
+                }
+                parent = (uint32_t)slot;
+                for (uint32_t m = L - 1; nf && m >= 1; --m) {
+                    if (m == 1) {
+                        g.nparent[1][slot] = stream;
+                        break;
+                    }
+                    bool pf = false;
+                    const uint64_t ps = table_slot(g.nkeys[m - 1], g.nmask, key >> g.level_shift[m - 1], &pf);
+                    if (ps == ~0ull) {
+                        atomicOr(g.err, kErrCapacity);
+                        break;
+                    }
+                    g.nparent[m][slot] = (uint32_t)ps;
+                    slot = ps;
+                    nf = pf;
+                }
+            }
+            g.bparent[b] = parent;
+        } else {
+            parent = g.bparent[b];
+        }
+        const uint32_t plevel = L - 1;
+        bool touched = false;
+        for (uint32_t p = 0; p < g.n_props; ++p) {
+            const PropDev& P = g.plan->prop[p];
+            uint8_t* sp = g.bstate + (uint64_t)p * (g.bmask + 1) + b;
+            const uint32_t s_old = fresh ? P.q0 : *sp;
+            const uint32_t s_new = a.seg_state[(uint64_t)(g.vbase[p] + s_old) * a.seg_stride + i];
+            *sp = (uint8_t)s_new;
+            const uint32_t v_new = P.label[s_new];
+            uint32_t* c = counts_of(g, plevel, parent, p);
+            if (fresh) {
+                atomicAdd(c + v_new, 1u);
+                touched = true;
+            } else {
+                const uint32_t v_old = P.label[s_old];
+                if (v_old != v_new) {
+                    atomicSub(c + v_old, 1u);
+                    atomicAdd(c + v_new, 1u);
+                    touched = true;
+                }
+            }
+        }
+        if (touched) mark_node(g, plevel, parent);
+    }
+}
+
+// Re-valuate the dirty nodes of one level (>= 1) and pass changed verdicts up.
+__global__ __launch_bounds__(256) void k_group_level(GroupState g, uint32_t level) {
+    const uint32_t n = g.list_cnt[level];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t slot = g.nlist[level][i];
+        g.ndirty[level][slot] = 0u;
+        const uint32_t parent = g.nparent[level][slot];
+        bool touched = false;
+        for (uint32_t p = 0; p < g.n_props; ++p) {
+            const uint32_t v = valuate(g.plan->prop[p], (int)level, counts_of(g, level, slot, p));
+            uint8_t* vp = g.nverdict[level] + (uint64_t)p * (g.nmask + 1) + slot;
+            const uint32_t v_old = *vp;
+            if (v_old == v) continue;
+            *vp = (uint8_t)v;
+            uint32_t* c = counts_of(g, level - 1, parent, p);
+            if (v_old != kNoVerdict) atomicSub(c + v_old, 1u);
+            atomicAdd(c + v, 1u);
+            touched = true;
+        }
+        if (touched) mark_node(g, level - 1, parent);
+    }
+}
+
+// Def. 7 at every dirty stream root (or at all roots).
+__global__ __launch_bounds__(256) void k_group_roots(GroupState g, uint32_t all) {
+    const uint32_t n = all ? g.max_streams : g.list_cnt[0];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t s = all ? i : g.rlist[i];
+        g.rdirty[s] = 0u;
+        for (uint32_t p = 0; p < g.n_props; ++p)
+            g.rverdict[(uint64_t)s * g.n_props + p] = (uint8_t)valuate(g.plan->prop[p], 0, counts_of(g, 0, s, p));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_group_read(GroupState g, uint8_t* verdict, uint64_t* counts,
+                                                    uint64_t* bindings) {
+    const uint32_t n = g.max_streams * g.n_props;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        verdict[i] = g.rverdict[i];
+        for (int b = 0; b < 6; ++b) counts[(uint64_t)i * 6 + b] = g.rcounts[(uint64_t)i * 6 + b];
+        if (bindings && i % g.n_props == 0) bindings[i / g.n_props] = g.stream_bindings[i / g.n_props];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_fill_u8(uint8_t* p, uint64_t n, uint8_t v) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_zero(const ZeroArgs& a, uint32_t blocks, hipStream_t s) {
@@ -771,12 +969,17 @@ hipError_t launch_zero(const ZeroArgs& a, uint32_t blocks, hipStream_t s) {
 hipError_t launch_classify(const ClassifyArgs& a, hipStream_t s) {
     const uint64_t want = (a.n + 1023) / 1024;
     const uint32_t blocks = (uint32_t)(want < 512 ? (want ? want : 1) : 512);
-    if (a.record_bytes == 16 && (reinterpret_cast<uintptr_t>(a.records) & 15) == 0)
-        hipLaunchKernelGGL(k_classify<4>, dim3(blocks), dim3(1024), 0, s, a);
-    else if (a.record_bytes == 12)
-        hipLaunchKernelGGL(k_classify<3>, dim3(blocks), dim3(1024), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_classify<0>, dim3(blocks), dim3(1024), 0, s, a);
+    const bool group = a.chunk_off != nullptr;
+    if (a.record_bytes == 16 && (reinterpret_cast<uintptr_t>(a.records) & 15) == 0) {
+        if (group) hipLaunchKernelGGL((k_classify<4, true>), dim3(blocks), dim3(1024), 0, s, a);
+        else hipLaunchKernelGGL((k_classify<4, false>), dim3(blocks), dim3(1024), 0, s, a);
+    } else if (a.record_bytes == 12) {
+        if (group) hipLaunchKernelGGL((k_classify<3, true>), dim3(blocks), dim3(1024), 0, s, a);
+        else hipLaunchKernelGGL((k_classify<3, false>), dim3(blocks), dim3(1024), 0, s, a);
+    } else {
+        if (group) hipLaunchKernelGGL((k_classify<0, true>), dim3(blocks), dim3(1024), 0, s, a);
+        else hipLaunchKernelGGL((k_classify<0, false>), dim3(blocks), dim3(1024), 0, s, a);
+    }
     return hipGetLastError();
 }
 
@@ -827,6 +1030,43 @@ hipError_t launch_count(const CountArgs& a, hipStream_t s) {
 
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace ltl4c
+
+namespace ltl4c {
+
+hipError_t launch_group_update(const GroupUpdateArgs& a, uint64_t max_seg, hipStream_t s) {
+    const uint64_t want = (max_seg + 255) / 256;
+    const uint32_t blocks = (uint32_t)(want < 2048 ? (want ? want : 1) : 2048);
+    hipLaunchKernelGGL(k_group_update, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_level(const GroupState& g, uint32_t level, hipStream_t s) {
+    hipLaunchKernelGGL(k_group_level, dim3(512), dim3(256), 0, s, g, level);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_roots(const GroupState& g, bool all, hipStream_t s) {
+    hipLaunchKernelGGL(k_group_roots, dim3(64), dim3(256), 0, s, g, all ? 1u : 0u);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_read(const GroupState& g, uint8_t* verdict, uint64_t* counts, uint64_t* bindings,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_group_read, dim3(64), dim3(256), 0, s, g, verdict, counts, bindings);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u64, dim3(1024), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t* p, uint64_t n, uint8_t v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u8, dim3(1024), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 

@@ -65,6 +65,8 @@ struct ltl4c_ctx {
     std::map<std::vector<int32_t>, Plan*> plans;
     uint32_t* err_dev = nullptr;
     int sort_variant = 1;
+    uint64_t budget = ~0ull, used = 0;
+    std::vector<struct GroupHost*> groups;
     bool prof = false;
     std::vector<Timed> timed;
     std::vector<hipEvent_t> free_events;
@@ -76,14 +78,16 @@ namespace {
 // Derived quantities of a layout shared by the workspace query and eval.
 struct Geometry {
     uint32_t cbits, key_bits_total, sort_bits, n_pass;
+    uint32_t stream_bits;                   // stream id above the keys (stream groups)
     bool excl;
-    uint32_t prefix_bits[kMaxLevels];       // bits of keys 0..m-1
+    uint32_t prefix_bits[kMaxLevels];       // bits of the stream id and keys 0..m-1
 };
 
-Geometry geometry(const ltl4c_layout& L) {
+Geometry geometry(const ltl4c_layout& L, uint32_t stream_bits = 0) {
     Geometry g{};
     g.cbits = bits_for(L.n_classes);
-    uint32_t kb = 0;
+    g.stream_bits = stream_bits;
+    uint32_t kb = stream_bits;
     for (uint32_t m = 0; m < L.n_keys; ++m) {
         g.prefix_bits[m] = kb;
         kb += L.key_bits[m];
@@ -285,6 +289,213 @@ int32_t drain_profile(ltl4c_ctx* ctx) {
     return LTL4C_OK;
 }
 
+// zero-block must already be cleared.  Enqueues classify and the radix
+// passes; *sorted receives the buffer holding the sorted words.
+int32_t enqueue_front(ltl4c_ctx* ctx, const ltl4c_layout& L, const Geometry& g, const WsLayout& w, uint8_t* ws,
+                      const void* d_records, uint64_t n, const Plan* plan, const uint32_t* chunk_off,
+                      const uint32_t* chunk_stream, uint32_t n_chunks, uint64_t** sorted) {
+    const uint32_t NL = L.n_keys;
+    uint32_t* z = reinterpret_cast<uint32_t*>(ws);
+    uint32_t* hist = z + w.hist_off;
+    uint32_t* sort_ticket = z + w.sort_ticket_off;
+    uint32_t* sort_status = z + w.sort_status_off;
+    uint64_t* words_a = reinterpret_cast<uint64_t*>(ws + w.words_a_off);
+    uint64_t* words_b = reinterpret_cast<uint64_t*>(ws + w.words_b_off);
+    const hipStream_t st = ctx->stream;
+    int32_t s;
+    ClassifyArgs ca{};
+    ca.records = static_cast<const uint8_t*>(d_records);
+    ca.n = n;
+    ca.record_bytes = L.record_bytes;
+    ca.type_dw = L.type_offset / 4;
+    ca.type_shift = (L.type_offset % 4) * 8;
+    ca.type_mask = L.type_bytes == 4 ? 0xFFFFFFFFu : ((1u << (8 * L.type_bytes)) - 1u);
+    ca.n_keys = NL;
+    for (uint32_t m = 0; m < NL; ++m) {
+        ca.key_dw[m] = L.key_offset[m] / 4;
+        ca.key_shift[m] = (L.key_offset[m] % 4) * 8;
+        ca.key_mask[m] = L.key_bytes[m] == 4 ? 0xFFFFFFFFu : ((1u << (8 * L.key_bytes[m])) - 1u);
+        ca.key_bits[m] = L.key_bits[m];
+    }
+    ca.need_mask = (1u << NL) - 1u;
+    ca.check_type_range = L.type_bytes > 1;
+    ca.cbits = g.cbits;
+    ca.excl_shift = g.cbits + g.key_bits_total;
+    ca.n_pass = g.n_pass;
+    ca.sort_shift = g.cbits;
+    ca.plan = plan;
+    ca.words = words_a;
+    ca.hist = hist;
+    ca.err = ctx->err_dev;
+    ca.chunk_off = chunk_off;
+    ca.chunk_stream = chunk_stream;
+    ca.n_chunks = n_chunks;
+    ca.stream_shift = g.key_bits_total - g.stream_bits;
+    s = launch(ctx, "classify", [&] { return launch_classify(ca, st); });
+    if (s) return s;
+    uint64_t* in = words_a;
+    uint64_t* outw = words_b;
+    for (uint32_t p = 0; p < g.n_pass; ++p) {
+        SortPassArgs sa{};
+        sa.in = in;
+        sa.out = outw;
+        sa.n = (uint32_t)n;
+        sa.shift = g.cbits + kRadixBits * p;
+        sa.nbits = std::min<uint32_t>(kRadixBits, g.sort_bits - kRadixBits * p);
+        sa.hist = hist + (uint64_t)p * kRadix;
+        sa.status = sort_status + (uint64_t)p * w.tiles_sort * kRadix;
+        sa.ticket = sort_ticket + p;
+        sa.err = ctx->err_dev;
+        s = launch(ctx, "sort_pass", [&] { return launch_sort_pass(sa, ctx->sort_variant, st); });
+        if (s) return s;
+        std::swap(in, outw);
+    }
+    *sorted = in;
+    return LTL4C_OK;
+}
+
+}  // namespace
+
+
+// A stream group: the resident monitor tree of up to max_streams streams.
+struct GroupHost {
+    std::vector<int32_t> props;
+    uint32_t P = 0, V = 0, S = 0, max_bindings = 0;
+    uint64_t max_batch = 0;
+    Geometry g{};
+    ltl4c_layout lay_ws{};             // layout copy with one level for workspace sizing
+    Plan* vplan = nullptr;             // one virtual property per (property, start state)
+    Plan* rplan = nullptr;             // the real properties
+    uint8_t* state = nullptr;
+    uint64_t state_bytes = 0;
+    uint8_t* ws = nullptr;
+    uint64_t ws_bytes = 0;
+    WsLayout w{};
+    uint64_t seg_keys_off = 0;         // inside ws, after the eval workspace
+    GroupState gs{};
+    uint32_t* chunk_dev = nullptr;     // [kMaxChunks + 1 offsets][kMaxChunks streams]
+    uint32_t* chunk_host = nullptr;    // pinned ring of kChunkRing tables
+    hipEvent_t ring_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    int ring_i = 0;
+    uint64_t total_bytes = 0;
+};
+
+namespace {
+
+constexpr int kChunkRing = 4;
+constexpr uint64_t kChunkTableWords = 2 * kMaxChunks + 1;
+
+uint64_t pow2_at_least(uint64_t x) {
+    uint64_t p = 1024;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// Offsets of the resident state of a group; fills gs pointers when base != nullptr.
+uint64_t group_state_layout(const GroupHost& G, uint32_t L, uint8_t* base, GroupState* gs) {
+    const uint64_t bcap = pow2_at_least(2ull * G.S * G.max_bindings);
+    const uint64_t ncap = bcap;
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        uint64_t o = off;
+        off = align256(off + bytes);
+        return base ? base + o : nullptr;
+    };
+    uint8_t* bkeys = take(8 * bcap);
+    uint8_t* bstate = take((uint64_t)G.P * bcap);
+    uint8_t* bparent = take(4 * bcap);
+    uint8_t* sb = take(4ull * G.S);
+    uint8_t* nk[kMaxLevels] = {}, *nc[kMaxLevels] = {}, *nv[kMaxLevels] = {}, *np[kMaxLevels] = {},
+             *nd[kMaxLevels] = {}, *nl[kMaxLevels] = {};
+    for (uint32_t m = 1; m < L; ++m) {
+        nk[m] = take(8 * ncap);
+        nc[m] = take(24ull * G.P * ncap);
+        nv[m] = take((uint64_t)G.P * ncap);
+        np[m] = take(4 * ncap);
+        nd[m] = take(4 * ncap);
+        nl[m] = take(4 * ncap);
+    }
+    uint8_t* rc = take(24ull * G.S * G.P);
+    uint8_t* rv = take((uint64_t)G.S * G.P);
+    uint8_t* rd = take(4ull * G.S);
+    uint8_t* rl = take(4ull * G.S);
+    uint8_t* lc = take(4 * kMaxLevels);
+    if (gs) {
+        gs->bkeys = reinterpret_cast<uint64_t*>(bkeys);
+        gs->bmask = bcap - 1;
+        gs->bstate = bstate;
+        gs->bparent = reinterpret_cast<uint32_t*>(bparent);
+        gs->stream_bindings = reinterpret_cast<uint32_t*>(sb);
+        gs->nmask = ncap - 1;
+        for (uint32_t m = 1; m < L; ++m) {
+            gs->nkeys[m] = reinterpret_cast<uint64_t*>(nk[m]);
+            gs->ncounts[m] = reinterpret_cast<uint32_t*>(nc[m]);
+            gs->nverdict[m] = nv[m];
+            gs->nparent[m] = reinterpret_cast<uint32_t*>(np[m]);
+            gs->ndirty[m] = reinterpret_cast<uint32_t*>(nd[m]);
+            gs->nlist[m] = reinterpret_cast<uint32_t*>(nl[m]);
+        }
+        gs->rcounts = reinterpret_cast<uint32_t*>(rc);
+        gs->rverdict = rv;
+        gs->rdirty = reinterpret_cast<uint32_t*>(rd);
+        gs->rlist = reinterpret_cast<uint32_t*>(rl);
+        gs->list_cnt = reinterpret_cast<uint32_t*>(lc);
+    }
+    return off;
+}
+
+int32_t group_configure(ltl4c_ctx* ctx, GroupHost& G, const int32_t* props, int32_t n_props, uint32_t max_streams,
+                        uint32_t max_bindings, uint64_t max_batch) {
+    int32_t s = check_props(ctx, props, n_props);
+    if (s) return s;
+    if (max_streams < 1 || max_bindings < 1) return fail(LTL4C_EINVAL, "max_streams and max_bindings must be >= 1");
+    if (max_batch < 1 || max_batch > LTL4C_MAX_EVENTS) return fail(LTL4C_EUNSUPPORTED, "max_batch out of range");
+    if ((uint64_t)max_streams * max_bindings > (1ull << 31))
+        return fail(LTL4C_EUNSUPPORTED, "max_streams * max_bindings exceeds 2^31");
+    const ltl4c_layout& L = ctx->layout;
+    G.props.assign(props, props + n_props);
+    G.P = (uint32_t)n_props;
+    G.S = max_streams;
+    G.max_bindings = max_bindings;
+    G.max_batch = max_batch;
+    G.V = 0;
+    for (int32_t i = 0; i < n_props; ++i) G.V += ctx->monitors[ctx->props[props[i]].monitor].n_states;
+    if (G.V > (uint32_t)kMaxProps)
+        return fail(LTL4C_EUNSUPPORTED, "a stream group takes properties whose monitors have 16 states in total");
+    const uint32_t sb = std::max<uint32_t>(1, bits_for(max_streams));
+    G.g = geometry(L, sb);
+    if (G.g.cbits + G.g.key_bits_total + (G.g.excl ? 1 : 0) > 63)
+        return fail(LTL4C_EUNSUPPORTED, "stream id, keys and class bits exceed 63 bits");
+    G.lay_ws = L;
+    G.lay_ws.n_keys = 1;
+    G.w = plan_workspace(G.lay_ws, G.g, max_batch, G.V, ctx->sort_variant);
+    G.seg_keys_off = align256(G.w.total);
+    G.ws_bytes = G.seg_keys_off + 8 * max_batch;
+    G.state_bytes = group_state_layout(G, L.n_keys, nullptr, nullptr);
+    G.total_bytes = G.state_bytes + G.ws_bytes + 4 * kChunkTableWords;
+    return LTL4C_OK;
+}
+
+void group_free(GroupHost* G) {
+    if (!G) return;
+    (void)hipFree(G->state);
+    (void)hipFree(G->ws);
+    (void)hipFree(G->chunk_dev);
+    (void)hipHostFree(G->chunk_host);
+    for (auto& e : G->ring_ev)
+        if (e) (void)hipEventDestroy(e);
+    (void)hipFree(G->vplan);
+    (void)hipFree(G->rplan);
+    delete G;
+}
+
+int32_t get_group(ltl4c_ctx* ctx, int32_t id, GroupHost** out) {
+    if (!ctx) return fail(LTL4C_EINVAL, "ctx is NULL");
+    if (id < 0 || id >= (int32_t)ctx->groups.size() || !ctx->groups[id]) return fail(LTL4C_ESEQ, "no such open group");
+    *out = ctx->groups[id];
+    return LTL4C_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -329,6 +540,8 @@ int32_t ltl4c_destroy(ltl4c_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     drop_plans(ctx);
+    for (auto* G : ctx->groups) group_free(G);
+    ctx->groups.clear();
     for (auto& t : ctx->timed) {
         (void)hipEventDestroy(t.start);
         (void)hipEventDestroy(t.stop);
@@ -349,6 +562,8 @@ int32_t ltl4c_set_layout(ltl4c_ctx* ctx, const ltl4c_layout* L) {
     if (!ctx) return fail(LTL4C_EINVAL, "ctx is NULL");
     int32_t s = check_layout(L);
     if (s) return s;
+    for (auto* G : ctx->groups)
+        if (G) return fail(LTL4C_ESEQ, "close the open stream groups before changing the layout");
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     drop_plans(ctx);
@@ -442,15 +657,11 @@ int32_t ltl4c_eval(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int3
 
     uint8_t* ws = static_cast<uint8_t*>(d_ws);
     uint32_t* z = reinterpret_cast<uint32_t*>(ws);
-    uint32_t* hist = z + w.hist_off;
-    uint32_t* sort_ticket = z + w.sort_ticket_off;
     uint32_t* scan_ticket = z + w.scan_ticket_off;
     uint32_t* root_counts = z + w.root_counts_off;
     uint32_t* sizes32 = z + w.sizes32_off;
     uint64_t* sizes64 = reinterpret_cast<uint64_t*>(z + w.sizes64_off);
-    uint32_t* sort_status = z + w.sort_status_off;
     uint64_t* words_a = reinterpret_cast<uint64_t*>(ws + w.words_a_off);
-    uint64_t* words_b = reinterpret_cast<uint64_t*>(ws + w.words_b_off);
     ScanTileStatus* scan_status = reinterpret_cast<ScanTileStatus*>(z + w.scan_status_off);
     const hipStream_t st = ctx->stream;
 
@@ -462,51 +673,8 @@ int32_t ltl4c_eval(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int3
     }
     uint64_t* sorted = words_a;
     if (n > 0) {
-        ClassifyArgs ca{};
-        ca.records = static_cast<const uint8_t*>(d_records);
-        ca.n = n;
-        ca.record_bytes = L.record_bytes;
-        ca.type_dw = L.type_offset / 4;
-        ca.type_shift = (L.type_offset % 4) * 8;
-        ca.type_mask = L.type_bytes == 4 ? 0xFFFFFFFFu : ((1u << (8 * L.type_bytes)) - 1u);
-        ca.n_keys = NL;
-        for (uint32_t m = 0; m < NL; ++m) {
-            ca.key_dw[m] = L.key_offset[m] / 4;
-            ca.key_shift[m] = (L.key_offset[m] % 4) * 8;
-            ca.key_mask[m] = L.key_bytes[m] == 4 ? 0xFFFFFFFFu : ((1u << (8 * L.key_bytes[m])) - 1u);
-            ca.key_bits[m] = L.key_bits[m];
-        }
-        ca.need_mask = (1u << NL) - 1u;
-        ca.check_type_range = L.type_bytes > 1;
-        ca.cbits = g.cbits;
-        ca.excl_shift = g.cbits + g.key_bits_total;
-        ca.n_pass = g.n_pass;
-        ca.sort_shift = g.cbits;
-        ca.plan = plan;
-        ca.words = words_a;
-        ca.hist = hist;
-        ca.err = ctx->err_dev;
-        s = launch(ctx, "classify", [&] { return launch_classify(ca, st); });
+        s = enqueue_front(ctx, L, g, w, ws, d_records, n, plan, nullptr, nullptr, 0, &sorted);
         if (s) return s;
-
-        uint64_t* in = words_a;
-        uint64_t* outw = words_b;
-        for (uint32_t p = 0; p < g.n_pass; ++p) {
-            SortPassArgs sa{};
-            sa.in = in;
-            sa.out = outw;
-            sa.n = (uint32_t)n;
-            sa.shift = g.cbits + kRadixBits * p;
-            sa.nbits = std::min<uint32_t>(kRadixBits, g.sort_bits - kRadixBits * p);
-            sa.hist = hist + (uint64_t)p * kRadix;
-            sa.status = sort_status + (uint64_t)p * w.tiles_sort * kRadix;
-            sa.ticket = sort_ticket + p;
-            sa.err = ctx->err_dev;
-            s = launch(ctx, "sort_pass", [&] { return launch_sort_pass(sa, ctx->sort_variant, st); });
-            if (s) return s;
-            std::swap(in, outw);
-        }
-        sorted = in;
     }
 
     // per-instance arrays: the verdicts always exist (caller's or workspace)
@@ -621,6 +789,250 @@ int32_t ltl4c_wait(ltl4c_ctx* ctx) {
         if (err & kErrRange) return fail(LTL4C_ERANGE, "an event key exceeds its declared key_bits");
         if (err & kErrCapacity) return fail(LTL4C_ECAPACITY, "more instances or nodes than the capacity");
     }
+    return LTL4C_OK;
+}
+
+
+int32_t ltl4c_set_memory_budget(ltl4c_ctx* ctx, uint64_t bytes) {
+    if (!ctx) return fail(LTL4C_EINVAL, "ctx is NULL");
+    ctx->budget = bytes;
+    return LTL4C_OK;
+}
+
+int32_t ltl4c_group_bytes(ltl4c_ctx* ctx, const int32_t* props, int32_t n_props, uint32_t max_streams,
+                          uint32_t max_bindings, uint64_t max_batch, uint64_t* bytes) {
+    if (!bytes) return fail(LTL4C_EINVAL, "bytes is NULL");
+    GroupHost G;
+    int32_t s = group_configure(ctx, G, props, n_props, max_streams, max_bindings, max_batch);
+    if (s) return s;
+    *bytes = G.total_bytes;
+    return LTL4C_OK;
+}
+
+int32_t ltl4c_group_open(ltl4c_ctx* ctx, const int32_t* props, int32_t n_props, uint32_t max_streams,
+                         uint32_t max_bindings, uint64_t max_batch, int32_t* group) {
+    if (!group) return fail(LTL4C_EINVAL, "group is NULL");
+    GroupHost* G = new GroupHost();
+    int32_t s = group_configure(ctx, *G, props, n_props, max_streams, max_bindings, max_batch);
+    if (s) {
+        delete G;
+        return s;
+    }
+    if (ctx->used + G->total_bytes > ctx->budget) {
+        delete G;
+        return fail(LTL4C_EADMIT, "the group does not fit the memory budget");
+    }
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess) e = hipMalloc(&G->state, G->state_bytes);
+    if (e == hipSuccess) e = hipMalloc(&G->ws, G->ws_bytes);
+    if (e == hipSuccess) e = hipMalloc(&G->chunk_dev, 4 * kChunkTableWords);
+    if (e == hipSuccess) e = hipHostMalloc(&G->chunk_host, 4 * kChunkTableWords * kChunkRing, hipHostMallocDefault);
+    for (int i = 0; i < kChunkRing && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&G->ring_ev[i], hipEventDisableTiming);
+    if (e != hipSuccess) {
+        group_free(G);
+        return fail(e == hipErrorOutOfMemory ? LTL4C_ENOMEM : LTL4C_EDEVICE,
+                    std::string("group allocation: ") + hipGetErrorString(e));
+    }
+    // plans: the real properties, and one virtual property per (property, start state)
+    Plan host;
+    std::memset(&host, 0, sizeof host);
+    std::memcpy(host.class_of_type, ctx->layout.class_of_type, 256);
+    std::memcpy(host.key_present, ctx->layout.key_present, 256);
+    Plan vhost = host;
+    uint32_t v = 0;
+    for (uint32_t p = 0; p < G->P; ++p) {
+        const ltl4c_property& prop = ctx->props[G->props[p]];
+        const MonitorHost& M = ctx->monitors[prop.monitor];
+        host.prop[p] = make_prop(M, prop);
+        G->gs.vbase[p] = v;
+        for (uint32_t q = 0; q < M.n_states; ++q) {
+            vhost.prop[v] = make_prop(M, prop);
+            vhost.prop[v].q0 = q;
+            ++v;
+        }
+    }
+    e = hipMalloc(&G->rplan, sizeof(Plan));
+    if (e == hipSuccess) e = hipMalloc(&G->vplan, sizeof(Plan));
+    if (e == hipSuccess) e = hipMemcpy(G->rplan, &host, sizeof(Plan), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(G->vplan, &vhost, sizeof(Plan), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        group_free(G);
+        return fail(LTL4C_EDEVICE, std::string("group plan upload: ") + hipGetErrorString(e));
+    }
+    const uint32_t L = ctx->layout.n_keys;
+    group_state_layout(*G, L, G->state, &G->gs);
+    GroupState& gs = G->gs;
+    gs.n_props = G->P;
+    gs.n_levels = L;
+    gs.plan = G->rplan;
+    for (uint32_t m = 1; m < L; ++m) gs.level_shift[m] = G->g.key_bits_total - G->g.prefix_bits[m];
+    gs.stream_shift = G->g.key_bits_total - G->g.stream_bits;
+    gs.max_streams = G->S;
+    gs.max_bindings = G->max_bindings;
+    gs.err = ctx->err_dev;
+    // empty tree: no keys, no verdicts yet, zero counts; then value every root
+    const hipStream_t st = ctx->stream;
+    e = hipMemsetAsync(G->state, 0, G->state_bytes, st);
+    if (e == hipSuccess) e = launch_fill_u64(gs.bkeys, gs.bmask + 1, kEmptyKey, st);
+    for (uint32_t m = 1; m < L && e == hipSuccess; ++m) {
+        e = launch_fill_u64(gs.nkeys[m], gs.nmask + 1, kEmptyKey, st);
+        if (e == hipSuccess) e = launch_fill_u8(gs.nverdict[m], (uint64_t)G->P * (gs.nmask + 1), kNoVerdict, st);
+    }
+    if (e == hipSuccess) e = launch_group_roots(gs, true, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        group_free(G);
+        return fail(LTL4C_EDEVICE, std::string("group initialisation: ") + hipGetErrorString(e));
+    }
+    ctx->used += G->total_bytes;
+    int32_t id = -1;
+    for (size_t i = 0; i < ctx->groups.size(); ++i)
+        if (!ctx->groups[i]) {
+            id = (int32_t)i;
+            break;
+        }
+    if (id < 0) {
+        id = (int32_t)ctx->groups.size();
+        ctx->groups.push_back(nullptr);
+    }
+    ctx->groups[id] = G;
+    *group = id;
+    return LTL4C_OK;
+}
+
+int32_t ltl4c_group_close(ltl4c_ctx* ctx, int32_t group) {
+    GroupHost* G = nullptr;
+    int32_t s = get_group(ctx, group, &G);
+    if (s) return s;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->used -= G->total_bytes;
+    group_free(G);
+    ctx->groups[group] = nullptr;
+    return LTL4C_OK;
+}
+
+int32_t ltl4c_group_push(ltl4c_ctx* ctx, int32_t group, const void* d_records, const uint64_t* offsets,
+                         const uint32_t* streams, int32_t n_chunks) {
+    GroupHost* G = nullptr;
+    int32_t s = get_group(ctx, group, &G);
+    if (s) return s;
+    if (n_chunks < 1 || n_chunks > (int32_t)kMaxChunks) return fail(LTL4C_EINVAL, "n_chunks must be 1..4096");
+    if (!offsets || !streams) return fail(LTL4C_EINVAL, "offsets / streams are NULL");
+    if (offsets[0] != 0) return fail(LTL4C_EINVAL, "offsets[0] must be 0");
+    for (int32_t i = 0; i < n_chunks; ++i) {
+        if (offsets[i + 1] < offsets[i]) return fail(LTL4C_EINVAL, "offsets must be non-decreasing");
+        if (streams[i] >= G->S) return fail(LTL4C_EINVAL, "stream id >= max_streams");
+    }
+    const uint64_t n = offsets[n_chunks];
+    if (n > G->max_batch) return fail(LTL4C_ECAPACITY, "batch larger than the group's max_batch");
+    if (n > 0 && (!d_records || (reinterpret_cast<uintptr_t>(d_records) & 3)))
+        return fail(LTL4C_EINVAL, "records must be non-NULL and 4-byte aligned");
+    if (n == 0) return LTL4C_OK;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const hipStream_t st = ctx->stream;
+    // chunk table through a pinned ring slot (reused only after its copy ran)
+    uint32_t* slot = G->chunk_host + (uint64_t)G->ring_i * kChunkTableWords;
+    HIP_TRY(hipEventSynchronize(G->ring_ev[G->ring_i]));
+    for (int32_t i = 0; i <= n_chunks; ++i) slot[i] = (uint32_t)offsets[i];
+    for (int32_t i = 0; i < n_chunks; ++i) slot[kMaxChunks + 1 + i] = streams[i];
+    HIP_TRY(hipMemcpyAsync(G->chunk_dev, slot, 4 * kChunkTableWords, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(G->ring_ev[G->ring_i], st));
+    G->ring_i = (G->ring_i + 1) % kChunkRing;
+
+    const ltl4c_layout& L = ctx->layout;
+    const WsLayout& w = G->w;
+    uint8_t* ws = G->ws;
+    uint32_t* z = reinterpret_cast<uint32_t*>(ws);
+    {
+        ZeroArgs za{z, nullptr, 0, w.zero_words, 0};
+        uint32_t blocks = (uint32_t)std::min<uint64_t>(1024, (w.zero_words + 255) / 256);
+        s = launch(ctx, "zero", [&] { return launch_zero(za, blocks ? blocks : 1, st); });
+        if (s) return s;
+        ZeroArgs zl{G->gs.list_cnt, nullptr, 0, kMaxLevels, 0};
+        s = launch(ctx, "zero", [&] { return launch_zero(zl, 1, st); });
+        if (s) return s;
+    }
+    uint64_t* sorted = nullptr;
+    s = enqueue_front(ctx, L, G->g, w, ws, d_records, n, G->vplan, G->chunk_dev, G->chunk_dev + kMaxChunks + 1,
+                      (uint32_t)n_chunks, &sorted);
+    if (s) return s;
+    uint64_t* seg_keys = reinterpret_cast<uint64_t*>(ws + G->seg_keys_off);
+    uint8_t* seg_state = ws + w.inst_verdict_off;
+    uint32_t* sizes32 = z + w.sizes32_off;
+    {
+        ScanArgs sa{};
+        sa.words = sorted;
+        sa.n = (uint32_t)n;
+        sa.cbits = G->g.cbits;
+        sa.n_levels = 1;
+        sa.valid_shift = G->g.cbits + G->g.key_bits_total;
+        sa.n_props = G->V;
+        sa.plan = G->vplan;
+        sa.inst_verdict = seg_state;
+        sa.inst_stride = G->max_batch;
+        sa.inst_limit = G->max_batch;
+        sa.inst_keys = seg_keys;
+        sa.status = reinterpret_cast<ScanTileStatus*>(z + w.scan_status_off);
+        sa.ticket = z + w.scan_ticket_off;
+        sa.sizes = reinterpret_cast<uint64_t*>(z + w.sizes64_off);
+        sa.sizes32 = sizes32;
+        sa.err = ctx->err_dev;
+        sa.emit_state = 1;
+        s = launch(ctx, "scan", [&] { return launch_scan(sa, st); });
+        if (s) return s;
+    }
+    GroupUpdateArgs ua{};
+    ua.g = G->gs;
+    ua.n_seg = sizes32;
+    ua.seg_key = seg_keys;
+    ua.seg_state = seg_state;
+    ua.seg_stride = G->max_batch;
+    s = launch(ctx, "group_update", [&] { return launch_group_update(ua, n, st); });
+    if (s) return s;
+    for (int m = (int)L.n_keys - 1; m >= 1; --m) {
+        s = launch(ctx, "group_level", [&] { return launch_group_level(G->gs, (uint32_t)m, st); });
+        if (s) return s;
+    }
+    return launch(ctx, "group_roots", [&] { return launch_group_roots(G->gs, false, st); });
+}
+
+int32_t ltl4c_group_read(ltl4c_ctx* ctx, int32_t group, uint8_t* d_root_verdict, uint64_t* d_root_counts,
+                         uint64_t* d_bindings) {
+    GroupHost* G = nullptr;
+    int32_t s = get_group(ctx, group, &G);
+    if (s) return s;
+    if (!d_root_verdict || !d_root_counts) return fail(LTL4C_EINVAL, "outputs are NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    return launch(ctx, "group_read",
+                  [&] { return launch_group_read(G->gs, d_root_verdict, d_root_counts, d_bindings, ctx->stream); });
+}
+
+int32_t ltl4c_group_snapshot(ltl4c_ctx* ctx, int32_t group, void* host, uint64_t* bytes) {
+    GroupHost* G = nullptr;
+    int32_t s = get_group(ctx, group, &G);
+    if (s) return s;
+    if (!bytes) return fail(LTL4C_EINVAL, "bytes is NULL");
+    if (!host) {
+        *bytes = G->state_bytes;
+        return LTL4C_OK;
+    }
+    if (*bytes < G->state_bytes) return fail(LTL4C_EINVAL, "snapshot buffer too small");
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipMemcpy(host, G->state, G->state_bytes, hipMemcpyDeviceToHost));
+    *bytes = G->state_bytes;
+    return LTL4C_OK;
+}
+
+int32_t ltl4c_group_restore(ltl4c_ctx* ctx, int32_t group, const void* host, uint64_t bytes) {
+    GroupHost* G = nullptr;
+    int32_t s = get_group(ctx, group, &G);
+    if (s) return s;
+    if (!host || bytes != G->state_bytes) return fail(LTL4C_EINVAL, "snapshot size does not match this group");
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipMemcpy(G->state, host, G->state_bytes, hipMemcpyHostToDevice));
     return LTL4C_OK;
 }
 

@@ -77,6 +77,17 @@ SIGNATURES = [
      [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(C.c_int32), C.c_int32, C.c_void_p, C.c_uint64,
       C.POINTER(Result)]),
     ("ltl4c_wait", C.c_int32, [C.c_void_p]),
+    ("ltl4c_set_memory_budget", C.c_int32, [C.c_void_p, C.c_uint64]),
+    ("ltl4c_group_bytes", C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32, C.c_uint32, C.c_uint32,
+                                      C.c_uint64, C.POINTER(C.c_uint64)]),
+    ("ltl4c_group_open", C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32, C.c_uint32, C.c_uint32,
+                                     C.c_uint64, C.POINTER(C.c_int32)]),
+    ("ltl4c_group_close", C.c_int32, [C.c_void_p, C.c_int32]),
+    ("ltl4c_group_push", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_uint64),
+                                     C.POINTER(C.c_uint32), C.c_int32]),
+    ("ltl4c_group_read", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("ltl4c_group_snapshot", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_uint64)]),
+    ("ltl4c_group_restore", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_uint64]),
     ("ltl4c_set_option", C.c_int32, [C.c_void_p, C.c_int32, C.c_int64]),
     ("ltl4c_profile_enable", C.c_int32, [C.c_void_p, C.c_int32]),
     ("ltl4c_profile_get", C.c_int32,
@@ -284,6 +295,16 @@ class Context:
         _check(self.lib.ltl4c_set_option(self.h, option, value), "ltl4c_set_option")
         self._workspace = None
 
+    def set_memory_budget(self, nbytes):
+        _check(self.lib.ltl4c_set_memory_budget(self.h, nbytes), "ltl4c_set_memory_budget")
+
+    def group_bytes(self, props, max_streams, max_bindings, max_batch):
+        arr = (C.c_int32 * len(props))(*props)
+        b = C.c_uint64()
+        _check(self.lib.ltl4c_group_bytes(self.h, arr, len(props), max_streams, max_bindings, max_batch,
+                                          C.byref(b)), "ltl4c_group_bytes")
+        return b.value
+
     def profile(self, on=True):
         _check(self.lib.ltl4c_profile_enable(self.h, 1 if on else 0), "ltl4c_profile_enable")
 
@@ -302,6 +323,62 @@ class Context:
             out[buf.value.decode()] = (ms.value, cnt.value)
             i += 1
         return out
+
+
+class StreamGroup:
+    """Online monitoring of many streams with device-resident state."""
+
+    def __init__(self, ctx, props, max_streams, max_bindings, max_batch):
+        self.ctx, self.lib, self.props = ctx, ctx.lib, list(props)
+        self.max_streams = max_streams
+        arr = (C.c_int32 * len(props))(*props)
+        g = C.c_int32()
+        _check(self.lib.ltl4c_group_open(ctx.h, arr, len(props), max_streams, max_bindings, max_batch,
+                                         C.byref(g)), "ltl4c_group_open")
+        self.id = g.value
+        t, dev = ctx.torch, f"cuda:{ctx.device}"
+        self.verdict = t.empty(max_streams * len(props), dtype=t.uint8, device=dev)
+        self.counts = t.empty(max_streams * len(props) * 6, dtype=t.int64, device=dev)
+        self.bindings = t.empty(max_streams, dtype=t.int64, device=dev)
+
+    def push(self, records, offsets, streams):
+        """Enqueue chunks: records is a device tensor; offsets (len n+1) and
+        streams (len n) are host sequences."""
+        self.ctx._bind_stream()
+        n = len(streams)
+        off = (C.c_uint64 * (n + 1))(*[int(x) for x in offsets])
+        st = (C.c_uint32 * n)(*[int(x) for x in streams])
+        _check(self.lib.ltl4c_group_push(self.ctx.h, self.id, C.c_void_p(records.data_ptr()), off, st, n),
+               "ltl4c_group_push")
+
+    def read(self):
+        """(verdict [S, P], counts [S, P, 6], bindings [S]) as numpy, after a wait."""
+        self.ctx._bind_stream()
+        _check(self.lib.ltl4c_group_read(self.ctx.h, self.id, C.c_void_p(self.verdict.data_ptr()),
+                                         C.c_void_p(self.counts.data_ptr()), C.c_void_p(self.bindings.data_ptr())),
+               "ltl4c_group_read")
+        self.ctx.wait()
+        P = len(self.props)
+        return (self.verdict.cpu().numpy().reshape(self.max_streams, P),
+                self.counts.cpu().numpy().reshape(self.max_streams, P, 6),
+                self.bindings.cpu().numpy())
+
+    def snapshot(self):
+        n = C.c_uint64()
+        _check(self.lib.ltl4c_group_snapshot(self.ctx.h, self.id, None, C.byref(n)), "ltl4c_group_snapshot")
+        buf = np.empty(n.value, dtype=np.uint8)
+        _check(self.lib.ltl4c_group_snapshot(self.ctx.h, self.id, C.c_void_p(buf.ctypes.data), C.byref(n)),
+               "ltl4c_group_snapshot")
+        return buf
+
+    def restore(self, buf):
+        _check(self.lib.ltl4c_group_restore(self.ctx.h, self.id, C.c_void_p(buf.ctypes.data), buf.size),
+               "ltl4c_group_restore")
+
+    def close(self):
+        if self.id is not None:
+            self.lib.ltl4c_group_close(self.ctx.h, self.id)
+            self.id = None
 
 
 def open_workload(wl, device=0):
