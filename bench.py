@@ -74,6 +74,166 @@ def cpu_baseline(wl, min_seconds=10.0):
             "sample": f"the full {wl.n_events}-event trace, {reps} run(s), single thread, input in host RAM"}
 
 
+def serving_bench(n_chunks=3000, pool_events=1_000_000, n_streams=64, plain_chunks=300, log=print):
+    """Online monitoring under open-loop Poisson arrivals (2e9 events/s offered,
+    64 streams, chunks of 4k-256k events, 100k bindings per stream).
+
+    Batched: every push takes all chunks that have arrived (at most two pushes
+    in flight).  Plain: one synchronous push per chunk, in arrival order.
+    Latency = verdict visible (push completed) - chunk arrival."""
+    import collections
+    import numpy as np
+    import torch
+    from paper_1411_2239_amd import lib, workloads
+
+    log("[bench] serving: generating stream pools")
+    lay = workloads.serving_layout(n_streams)
+    spec = workloads.user_request_properties()[0]
+    pools = [torch.from_numpy(workloads.gen_serving_pool(s, pool_events).view(np.uint8)).to("cuda:0")
+             for s in range(n_streams)]
+    arr, streams, sizes = workloads.serving_schedule(n_chunks, n_streams)
+    ctx = lib.Context(0)
+    ctx.set_layout(lay)
+    pid = ctx.add_spec(spec)
+    rb = lay.record_bytes
+    max_batch = 1 << 24
+
+    def chunk_ptrs():
+        pos = [0] * n_streams
+        out = []
+        for st, sz in zip(streams, sizes):
+            if pos[st] + sz > pool_events:
+                pos[st] = 0
+            out.append(pools[st].data_ptr() + pos[st] * rb)
+            pos[st] += sz
+        return out
+
+    ptrs = chunk_ptrs()
+    torch.cuda.synchronize()
+
+    def run_batched(grp, count):
+        lat = np.zeros(count)
+        inflight = collections.deque()
+        i, done_events = 0, 0
+        t0 = time.perf_counter()
+        t_last = t0
+        while i < count or inflight:
+            now = time.perf_counter() - t0
+            while inflight and inflight[0][0].query():
+                ev, a, b = inflight.popleft()
+                t_done = time.perf_counter() - t0
+                lat[a:b] = t_done - arr[a:b]
+                t_last = t_done
+            if i < count and len(inflight) < 2 and arr[i] <= now:
+                j, tot = i, 0
+                while j < count and arr[j] <= now and j - i < 4096 and tot + sizes[j] <= max_batch:
+                    tot += int(sizes[j])
+                    j += 1
+                grp.push_chunks(ptrs[i:j], sizes[i:j], streams[i:j])
+                ev = torch.cuda.Event()
+                ev.record()
+                inflight.append((ev, i, j))
+                done_events += tot
+                i = j
+        ctx.wait()
+        return lat, done_events, t_last
+
+    def run_plain(grp, count):
+        lat = np.zeros(count)
+        total = 0
+        t0 = time.perf_counter()
+        for i in range(count):
+            while time.perf_counter() - t0 < arr[i]:
+                pass
+            grp.push_chunks(ptrs[i:i + 1], sizes[i:i + 1], streams[i:i + 1])
+            torch.cuda.synchronize()
+            lat[i] = time.perf_counter() - t0 - arr[i]
+            total += int(sizes[i])
+        return lat, total, time.perf_counter() - t0
+
+    grp = lib.StreamGroup(ctx, [pid], n_streams, 100_000, max_batch)
+    log("[bench] serving: warmup")
+    run_batched(grp, min(200, n_chunks))
+    grp.close()
+    grp = lib.StreamGroup(ctx, [pid], n_streams, 100_000, max_batch)
+    log(f"[bench] serving: batched, {n_chunks} chunks")
+    lat, ev, el = run_batched(grp, n_chunks)
+    v, c, b = grp.read()
+    batched = {"events_per_s": ev / el, "chunks": n_chunks, "events": ev, "seconds": el,
+               "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+               "live_bindings": int(b.sum())}
+    grp.close()
+    grp = lib.StreamGroup(ctx, [pid], n_streams, 100_000, max_batch)
+    log(f"[bench] serving: plain, {plain_chunks} chunks")
+    lat_p, ev_p, el_p = run_plain(grp, plain_chunks)
+    plain = {"events_per_s": ev_p / el_p, "chunks": plain_chunks, "events": ev_p, "seconds": el_p,
+             "p50_ms": float(np.percentile(lat_p, 50) * 1e3), "p99_ms": float(np.percentile(lat_p, 99) * 1e3)}
+    grp.close()
+    ctx.close()
+    offered = float(sizes[:n_chunks].sum() / arr[n_chunks - 1])
+    return {"workload": f"{n_streams} streams, 100k bindings each, chunks 4k-256k log-uniform, Poisson arrivals, "
+                        f"device-resident chunk pools",
+            "offered_events_per_s": offered, "batched": batched, "plain_per_chunk": plain,
+            "batched_vs_plain_throughput": batched["events_per_s"] / plain["events_per_s"]}
+
+
+def batching_bench(n_traces=4096, reps=3, log=print):
+    """Many traces x 16 properties in one ltl4c_eval_batch call against the
+    plain path (one ltl4c_eval per trace, synchronised each time)."""
+    import numpy as np
+    import torch
+    from paper_1411_2239_amd import lib, workloads
+
+    log(f"[bench] batching: generating {n_traces} traces")
+    wl, offsets = workloads.gen_batch(n_traces)
+    ctx, ids, rec = lib.open_workload(wl)
+    n = wl.n_events
+    rb = wl.layout.record_bytes
+    ws = ctx.batch_workspace(n, n_traces, ids)
+    v = torch.empty(n_traces * len(ids), dtype=torch.uint8, device="cuda:0")
+    c = torch.empty(n_traces * len(ids) * 6, dtype=torch.int64, device="cuda:0")
+    ctx.eval_batch_into(rec, offsets, ids, v, c, ws)
+    ctx.wait()
+    log(f"[bench] batching: {reps} batched passes over {n} events")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.eval_batch_into(rec, offsets, ids, v, c, ws)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    ctx.wait()
+    ctx.profile(True)
+    ctx.profile_reset()
+    ctx.eval_batch_into(rec, offsets, ids, v, c, ws)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    vb = v.cpu().numpy().reshape(n_traces, len(ids))
+    log("[bench] batching: plain per-trace loop")
+    del ws
+    ctx._workspace = None
+    big = int(np.diff(offsets).max())
+    wsp = ctx.workspace(big, ids)
+    res = ctx.alloc_result(len(ids))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    same = True
+    for t in range(n_traces):
+        a, b = int(offsets[t]), int(offsets[t + 1])
+        ctx.eval_into(rec[a * rb:b * rb], b - a, ids, res, wsp)
+        torch.cuda.synchronize()
+    el_plain = time.perf_counter() - t0
+    ctx.wait()
+    # the last trace: plain and batched agree
+    same = bool(np.array_equal(res.root_verdict.cpu().numpy(), vb[n_traces - 1]))
+    ctx.close()
+    return {"workload": f"{n_traces} traces, lengths log-uniform 1k-1M, 16 properties with 3-16-state monitors",
+            "events": n, "traces": n_traces, "properties": len(ids),
+            "batched_events_per_s": n / el, "batched_ms": el * 1e3,
+            "plain_events_per_s": n / el_plain, "plain_ms": el_plain * 1e3,
+            "batched_vs_plain": el_plain / el, "last_trace_plain_equals_batched": same,
+            "batched_kernel_ms": {k: round(x[0], 3) for k, x in prof.items()}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +242,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--events", type=int, default=10_000_000)
     ap.add_argument("--sort-tile", type=int, default=None, help="radix tile variant (LTL4C_OPT_SORT_TILE)")
+    ap.add_argument("--scan-tile", type=int, default=None, help="map-scan tile variant (LTL4C_OPT_SCAN_TILE)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the online-monitoring section")
+    ap.add_argument("--no-batching", action="store_true", help="skip the batched-traces section")
+    ap.add_argument("--batch-traces", type=int, default=4096)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -100,6 +264,8 @@ def main():
     ctx, ids, rec0 = lib.open_workload(wl)
     if args.sort_tile is not None:
         ctx.set_option(lib.OPT_SORT_TILE, args.sort_tile)
+    if args.scan_tile is not None:
+        ctx.set_option(lib.OPT_SCAN_TILE, args.scan_tile)
     n = wl.n_events
     copies = [rec0] + [rec0.clone() for _ in range(3)]
     ws = ctx.workspace(n, ids)
@@ -151,6 +317,13 @@ def main():
     root = res.root_verdict.cpu().numpy().tolist()
     counts = res.root_counts.cpu().numpy().reshape(len(ids), 6).tolist()
 
+    serving = None
+    if not args.no_serving:
+        serving = serving_bench(log=log)
+    batching = None
+    if not args.no_batching:
+        batching = batching_bench(args.batch_traces, log=log)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (C oracle)")
@@ -173,6 +346,10 @@ def main():
                              "frac_of_hbm_peak": scan_frac},
         "per_kernel": per_kernel,
         "root_verdict": [lib.VERDICT_NAMES[v] for v in root], "root_counts": counts,
+        "serving": serving,
+        "batching": batching,
+        "batched_vs_plain_speedup": batching["batched_vs_plain"] if batching else None,
+        "p99_chunk_latency_ms": serving["batched"]["p99_ms"] if serving else None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -199,6 +199,21 @@ int32_t ltl4c_eval(ltl4c_ctx *ctx, const void *d_records, uint64_t n_events,
                    void *d_workspace, uint64_t workspace_bytes,
                    const ltl4c_result *out);
 
+/* ---- batches: many independent traces in one pass -------------------------
+ *
+ * Evaluate the properties on n_traces (1..4096) independent traces at once:
+ * trace t is records [offsets[t], offsets[t+1]) of d_records (offsets is a
+ * host array of n_traces + 1 entries, offsets[0] = 0).  The trace id becomes
+ * the top of the sort key, so every kernel of ltl4c_eval runs once for the
+ * whole batch.  Outputs (device): root_verdict[t * n_props + p] and
+ * root_counts[(t * n_props + p) * 6 + b], the same values ltl4c_eval gives for
+ * trace t alone.  Properties of a batch have at most 3 quantifiers. */
+int32_t ltl4c_batch_workspace_bytes(ltl4c_ctx *ctx, uint64_t n_events, int32_t n_traces, const int32_t *props,
+                                    int32_t n_props, uint64_t *bytes);
+int32_t ltl4c_eval_batch(ltl4c_ctx *ctx, const void *d_records, const uint64_t *offsets, int32_t n_traces,
+                         const int32_t *props, int32_t n_props, void *d_workspace, uint64_t workspace_bytes,
+                         uint8_t *d_root_verdict, uint64_t *d_root_counts);
+
 /* Synchronise the context's stream and report device-detected errors of the
  * work enqueued since the previous ltl4c_wait (LTL4C_ERANGE, ECAPACITY). */
 int32_t ltl4c_wait(ltl4c_ctx *ctx);
@@ -245,6 +260,11 @@ int32_t ltl4c_group_close(ltl4c_ctx *ctx, int32_t group);
 int32_t ltl4c_group_push(ltl4c_ctx *ctx, int32_t group, const void *d_records, const uint64_t *offsets,
                          const uint32_t *streams, int32_t n_chunks);
 
+/* The same with every chunk in its own device buffer: chunk i is sizes[i]
+ * records at d_chunks[i] (host arrays of n_chunks entries). */
+int32_t ltl4c_group_push_chunks(ltl4c_ctx *ctx, int32_t group, const void *const *d_chunks, const uint64_t *sizes,
+                                const uint32_t *streams, int32_t n_chunks);
+
 /* Current truth values (device outputs): root_verdict[s * n_props + p],
  * root_counts[(s * n_props + p) * 6 + b], bindings[s] (may be NULL). */
 int32_t ltl4c_group_read(ltl4c_ctx *ctx, int32_t group, uint8_t *d_root_verdict, uint64_t *d_root_counts,
@@ -262,7 +282,9 @@ int32_t ltl4c_group_restore(ltl4c_ctx *ctx, int32_t group, const void *host, uin
  * on them).  LTL4C_OPT_SORT_TILE selects the radix-pass tile shape:
  * 0 = 256 threads x 16 words, 1 = 512 x 16 (default), 2 = 256 x 24,
  * 3 = 256 x 8, 4 = 512 x 8. */
-enum { LTL4C_OPT_SORT_TILE = 0 };
+enum { LTL4C_OPT_SORT_TILE = 0, LTL4C_OPT_SCAN_TILE = 1 };
+/* LTL4C_OPT_SCAN_TILE: map-scan tile of 0 = 256 threads x 16 words (default)
+ * or 1 = 512 x 16. */
 int32_t ltl4c_set_option(ltl4c_ctx *ctx, int32_t option, int64_t value);
 
 /* ---- profiling: per-kernel time of the enqueued work ------------------- */

@@ -76,8 +76,10 @@ struct ClassifyArgs {
     // chunk_off[c] <= i < chunk_off[c+1]; its stream id goes above the keys
     const uint32_t* chunk_off;       // [n_chunks + 1], or nullptr
     const uint32_t* chunk_stream;    // [n_chunks]
+    const uint64_t* chunk_ptr;       // [n_chunks] device address of each chunk, or nullptr
     uint32_t n_chunks;
     uint32_t stream_shift;
+    uint32_t vec_ok;                 // every record address is 16-byte aligned (16-byte records)
 };
 
 struct SortPassArgs {
@@ -200,13 +202,29 @@ struct GroupUpdateArgs {
     uint64_t seg_stride;
 };
 
+// Per-trace results of a batch: trace t's root is the level-1 node whose key
+// is t (traces without events get Def. 7 on empty counts).
+struct BatchOutArgs {
+    uint32_t n_props, n_traces;
+    const Plan* plan;
+    const uint32_t* n_nodes;             // level-1 nodes
+    const uint64_t* node_keys;           // [n_nodes] trace ids, increasing
+    const uint32_t* node_counts;         // [P][stride][6]
+    const uint8_t* node_verdict;         // [P][stride]
+    uint64_t stride;
+    uint8_t* verdict;                    // [n_traces][P]
+    uint64_t* counts;                    // [n_traces][P][6]
+};
+
 // Launchers (defined in kernels.hip).
 hipError_t launch_zero(const ZeroArgs& a, uint32_t blocks, hipStream_t s);
 hipError_t launch_classify(const ClassifyArgs& a, hipStream_t s);
 hipError_t launch_sort_pass(const SortPassArgs& a, int variant, hipStream_t s);
 uint32_t sort_tile(int variant);      // words per radix tile of a sort variant
 constexpr int kSortVariants = 5;
-hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
+hipError_t launch_scan(const ScanArgs& a, int variant, hipStream_t s);
+uint32_t scan_tile(int variant);      // words per scan tile of a scan variant
+constexpr int kScanVariants = 2;
 hipError_t launch_count(const CountArgs& a, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
 hipError_t launch_group_update(const GroupUpdateArgs& a, uint64_t max_seg, hipStream_t s);
@@ -216,5 +234,6 @@ hipError_t launch_group_read(const GroupState& g, uint8_t* verdict, uint64_t* co
                              hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, uint64_t n, uint8_t v, hipStream_t s);
+hipError_t launch_batch_out(const BatchOutArgs& a, hipStream_t s);
 
 }  // namespace ltl4c

@@ -161,12 +161,12 @@ __global__ __launch_bounds__(256) void k_zero(ZeroArgs a) {
 // classify: record -> (binding key, class) word + radix histograms
 // ---------------------------------------------------------------------------
 template <int RDW>
-__device__ __forceinline__ void load_record(const ClassifyArgs& a, uint64_t i, uint32_t* dw) {
+__device__ __forceinline__ void load_record(const uint8_t* rec, uint32_t* dw) {
     if constexpr (RDW == 4) {
-        uint4 r = reinterpret_cast<const uint4*>(a.records)[i];
+        uint4 r = *reinterpret_cast<const uint4*>(rec);
         dw[0] = r.x; dw[1] = r.y; dw[2] = r.z; dw[3] = r.w;
     } else if constexpr (RDW == 3) {
-        const uint32_t* p = reinterpret_cast<const uint32_t*>(a.records) + 3 * i;
+        const uint32_t* p = reinterpret_cast<const uint32_t*>(rec);
         dw[0] = p[0]; dw[1] = p[1]; dw[2] = p[2];
     }
 }
@@ -192,15 +192,28 @@ __global__ __launch_bounds__(1024) void k_classify(ClassifyArgs a) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
         uint32_t t, f[kMaxLevels];
+        uint32_t chunk = 0;
+        const uint8_t* rec_ptr = a.records + i * a.record_bytes;
+        if constexpr (GROUP) {
+            // chunk c with s_coff[c] <= i < s_coff[c+1]
+            uint32_t lo = 0, hi = a.n_chunks;
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (s_coff[mid] <= (uint32_t)i) lo = mid; else hi = mid;
+            }
+            chunk = lo;
+            if (a.chunk_ptr)
+                rec_ptr = reinterpret_cast<const uint8_t*>(a.chunk_ptr[lo]) + (i - s_coff[lo]) * a.record_bytes;
+        }
         if constexpr (RDW > 0) {
             uint32_t dw[RDW];
-            load_record<RDW>(a, i, dw);
+            load_record<RDW>(rec_ptr, dw);
             t = (dw[a.type_dw] >> a.type_shift) & a.type_mask;
 #pragma unroll
             for (int m = 0; m < kMaxLevels; ++m)
                 f[m] = m < (int)a.n_keys ? (dw[a.key_dw[m]] >> a.key_shift[m]) & a.key_mask[m] : 0u;
         } else {
-            const uint32_t* rec = reinterpret_cast<const uint32_t*>(a.records + i * a.record_bytes);
+            const uint32_t* rec = reinterpret_cast<const uint32_t*>(rec_ptr);
             t = (rec[a.type_dw] >> a.type_shift) & a.type_mask;
 #pragma unroll
             for (int m = 0; m < kMaxLevels; ++m)
@@ -220,15 +233,7 @@ __global__ __launch_bounds__(1024) void k_classify(ClassifyArgs a) {
             }
         }
         if (ok && over) err |= kErrRange;
-        if constexpr (GROUP) {
-            // chunk c with s_coff[c] <= i < s_coff[c+1]
-            uint32_t lo = 0, hi = a.n_chunks;
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (s_coff[mid] <= (uint32_t)i) lo = mid; else hi = mid;
-            }
-            key |= (uint64_t)s_cstream[lo] << a.stream_shift;
-        }
+        if constexpr (GROUP) key |= (uint64_t)s_cstream[chunk] << a.stream_shift;
         const uint64_t word = ok ? ((key << a.cbits) | s_cls[t8]) : (1ull << a.excl_shift);
         a.words[i] = word;
         for (uint32_t p = 0; p < a.n_pass; ++p)
@@ -371,22 +376,25 @@ __global__ __launch_bounds__(THREADS) void k_sort_pass(SortPassArgs a) {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t pad_idx(uint32_t i) { return i + (i >> 4); }
 
-template <int PMAX>
-__global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
+template <int PMAX, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_scan(ScanArgs a) {
+    constexpr int kScanThreads = THREADS;
+    constexpr int kScanTile = THREADS * kScanItems;
+    constexpr int WAVES = THREADS / 64;
     __shared__ uint64_t s_w[kScanTile + kScanTile / 16 + 1];
     __shared__ uint8_t s_delta[PMAX][kStates * 16];
     __shared__ uint8_t s_label[PMAX][kStates];
     __shared__ uint64_t s_colmap[PMAX][16];
     __shared__ uint32_t s_q0[PMAX];
-    __shared__ uint64_t s_wtot[PMAX][4];
-    __shared__ uint32_t s_ctot[4][4];
+    __shared__ uint64_t s_wtot[PMAX][WAVES];
+    __shared__ uint32_t s_ctot[4][WAVES];
     __shared__ uint64_t s_tprefix[PMAX];
     __shared__ uint64_t s_tagg[PMAX];
     __shared__ uint32_t s_cagg[4];
     __shared__ uint32_t s_tcnt[4];
     __shared__ uint64_t s_prev, s_next;
     __shared__ uint32_t s_tile;
-    __shared__ uint32_t s_red[2][4];
+    __shared__ uint32_t s_red[2][WAVES];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const uint32_t P = a.n_props;
@@ -507,12 +515,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
     // tile aggregates: thread p composes property p, threads 32..35 sum counts
     if (tid < (int)P) {
         uint64_t t = kIdentityMap;
-        for (int i = 0; i < 4; ++i) t = map_compose(s_wtot[tid][i], t);
+        for (int i = 0; i < WAVES; ++i) t = map_compose(s_wtot[tid][i], t);
         s_tagg[tid] = t;
     }
     if (tid >= 32 && tid < 36) {
         const int k = tid - 32;
-        s_cagg[k] = s_ctot[k][0] + s_ctot[k][1] + s_ctot[k][2] + s_ctot[k][3];
+        uint32_t sum = 0;
+        for (int i = 0; i < WAVES; ++i) sum += s_ctot[k][i];
+        s_cagg[k] = sum;
     }
     __syncthreads();
 
@@ -675,8 +685,354 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
             s_red[1][w] = my_hi;
         }
         __syncthreads();
-        const uint32_t lo = min(min(s_red[0][0], s_red[0][1]), min(s_red[0][2], s_red[0][3]));
-        const uint32_t hi = max(max(s_red[1][0], s_red[1][1]), max(s_red[1][2], s_red[1][3]));
+        uint32_t lo = s_red[0][0], hi = s_red[1][0];
+        for (int i = 1; i < WAVES; ++i) {
+            lo = min(lo, s_red[0][i]);
+            hi = max(hi, s_red[1][i]);
+        }
+        if (lo < hi) {
+            const uint32_t cnt_iv = hi - lo, slot0 = lo + 1u - id_base;
+            for (uint32_t p = 0; p < P; ++p)
+                for (uint32_t i = tid; i < cnt_iv; i += kScanThreads)
+                    a.inst_verdict[p * a.inst_stride + lo + i] = s_iv[p * kIvStride + slot0 + i];
+        }
+    }
+    // the thread holding the last event publishes the totals
+    const uint64_t my0 = base + (uint64_t)tid * kScanItems;
+    if (my0 <= a.n - 1 && a.n - 1 < my0 + kScanItems) {
+#pragma unroll
+        for (int m = 0; m < kMaxLevels; ++m) {
+            if (m >= (int)L) break;
+            const uint32_t tot = s_tcnt[m] + cexcl[m] + cnt[m];
+            a.sizes[m] = tot;
+            a.sizes32[m] = tot;
+        }
+    }
+}
+
+// The same scan for up to 16 properties with compact code: property loops
+// that compose maps are not unrolled, per-property run summaries live in LDS
+// (in the word buffer, free once the words are in registers) and the states
+// of all properties are nibbles of one 64-bit register.
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_scan_wide(ScanArgs a) {
+    constexpr int PMAX = kMaxProps;
+    constexpr int kScanThreads = THREADS;
+    constexpr int kScanTile = THREADS * kScanItems;
+    constexpr int WAVES = THREADS / 64;
+    __shared__ uint64_t s_w[kScanTile + kScanTile / 16 + 1];
+    __shared__ uint8_t s_delta[PMAX][kStates * 16];
+    __shared__ uint8_t s_label[PMAX][kStates];
+    __shared__ uint64_t s_colmap[PMAX][16];
+    __shared__ uint32_t s_q0[PMAX];
+    __shared__ uint64_t s_wtot[PMAX][WAVES];
+    __shared__ uint32_t s_ctot[4][WAVES];
+    __shared__ uint64_t s_tprefix[PMAX];
+    __shared__ uint64_t s_tagg[PMAX];
+    __shared__ uint32_t s_cagg[4];
+    __shared__ uint32_t s_tcnt[4];
+    __shared__ uint64_t s_prev, s_next;
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_red[2][WAVES];
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t P = a.n_props;
+    if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
+    for (uint32_t i = tid; i < P * kStates * 16; i += kScanThreads)
+        s_delta[i / (kStates * 16)][i % (kStates * 16)] = a.plan->prop[i / (kStates * 16)].delta[i % (kStates * 16)];
+    if (tid < (int)(P * 16)) {
+        s_label[tid / 16][tid % 16] = a.plan->prop[tid / 16].label[tid % 16];
+        s_colmap[tid / 16][tid % 16] = a.plan->prop[tid / 16].colmap[tid % 16];
+    }
+    if (tid < (int)P) s_q0[tid] = a.plan->prop[tid].q0;
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint64_t base = (uint64_t)tile * kScanTile;
+    const uint64_t kInvalid = ~0ull;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        const uint64_t idx = base + r * kScanThreads + tid;
+        s_w[pad_idx(r * kScanThreads + tid)] = idx < a.n ? a.words[idx] : kInvalid;
+    }
+    if (tid == 0) s_prev = base > 0 ? a.words[base - 1] : kInvalid;
+    if (tid == 1) s_next = base + kScanTile < a.n ? a.words[base + kScanTile] : kInvalid;
+    __syncthreads();
+
+    uint64_t wv[kScanItems];
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) wv[j] = s_w[pad_idx(tid * kScanItems + j)];
+    const uint64_t wp = tid == 0 ? s_prev : s_w[pad_idx(tid * kScanItems - 1)];
+    const uint64_t wn = tid == kScanThreads - 1 ? s_next : s_w[pad_idx(tid * kScanItems + kScanItems)];
+    const bool has_prev = base + (uint64_t)tid * kScanItems > 0;
+    const uint32_t cb = a.cbits, vs = a.valid_shift, L = a.n_levels;
+    const uint32_t cmask = (1u << cb) - 1u;
+
+    // per-event flags as bit masks
+    uint32_t m_valid = 0, m_head = 0, m_end = 0, m_lvl[kMaxLevels] = {0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const uint64_t x = wv[j];
+        if ((x >> vs) != 0) continue;
+        m_valid |= 1u << j;
+        const uint64_t prv = j == 0 ? wp : wv[j - 1];
+        const bool first = (j == 0 && !has_prev);
+        const uint64_t nxt = j == kScanItems - 1 ? wn : wv[j + 1];
+        if (first || (prv >> cb) != (x >> cb)) m_head |= 1u << j;
+        if ((nxt >> vs) != 0 || (nxt >> cb) != (x >> cb)) m_end |= 1u << j;
+#pragma unroll
+        for (int m = 1; m < kMaxLevels; ++m) {
+            if (m >= (int)L) break;
+            const uint32_t sh = a.prefix_shift[m];
+            if (first || (prv >> sh) != (x >> sh)) m_lvl[m] |= 1u << j;
+        }
+    }
+    uint32_t cnt[4];
+    cnt[0] = __popc(m_head);
+#pragma unroll
+    for (int m = 1; m < 4; ++m) cnt[m] = (uint32_t)m < L ? __popc(m_lvl[m]) : 0u;
+
+    // summaries: the map from the state before this run to the state after
+    // it, per property, kept in s_map[p][tid] (the word buffer is free now)
+    __syncthreads();
+    uint64_t* s_map = s_w;                                   // [PMAX][kScanThreads]
+#pragma unroll 1
+    for (int p = 0; p < (int)P; ++p) {
+        uint64_t f = kIdentityMap;
+        bool cst = false;
+        uint32_t st = 0;
+        for (int j = 0; j < kScanItems; ++j) {
+            if (!((m_valid >> j) & 1u)) break;
+            const uint32_t c = (uint32_t)wv[j] & cmask;
+            if ((m_head >> j) & 1u) {
+                cst = true;
+                st = s_delta[p][s_q0[p] * 16 + c];
+            } else if (cst) {
+                st = s_delta[p][st * 16 + c];
+            } else {
+                f = map_compose_full(s_colmap[p][c], f);
+            }
+        }
+        uint64_t v = cst ? map_const(st) : f;
+        // wave-level inclusive composition scan
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint64_t o = shfl_up64(v, off);
+            if (lane >= off) v = map_compose(v, o);
+        }
+        const uint64_t e = shfl_up64(v, 1);
+        s_map[p * kScanThreads + tid] = lane == 0 ? kIdentityMap : e;
+        if (lane == 63) s_wtot[p][w] = v;
+    }
+    uint32_t cexcl[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t incl = wave_incl_scan_u32(cnt[k]);
+        cexcl[k] = incl - cnt[k];
+        if (lane == 63) s_ctot[k][w] = incl;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int p = 0; p < (int)P; ++p) {
+        uint64_t pre = kIdentityMap;
+        for (int i = 0; i < w; ++i) pre = map_compose(s_wtot[p][i], pre);
+        s_map[p * kScanThreads + tid] = map_compose(s_map[p * kScanThreads + tid], pre);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        uint32_t pre = 0;
+        for (int i = 0; i < w; ++i) pre += s_ctot[k][i];
+        cexcl[k] += pre;
+    }
+    // tile aggregates: thread p composes property p, threads 32..35 sum counts
+    if (tid < (int)P) {
+        uint64_t t = kIdentityMap;
+        for (int i = 0; i < WAVES; ++i) t = map_compose(s_wtot[tid][i], t);
+        s_tagg[tid] = t;
+    }
+    if (tid >= 32 && tid < 36) {
+        const int k = tid - 32;
+        uint32_t sum = 0;
+        for (int i = 0; i < WAVES; ++i) sum += s_ctot[k][i];
+        s_cagg[k] = sum;
+    }
+    __syncthreads();
+
+    // publish this tile's aggregate, then look back (wave 0).  Lane p < P
+    // owns property p's map (two status words), lanes 32..35 the counts.
+    ScanTileStatus* st = a.status + tile;
+    const uint64_t kValid = 1ull << 32;
+    if (w == 0) {
+        if (lane < (int)P) {
+            const uint64_t m = s_tagg[lane];
+            __hip_atomic_store(&st->agg[2 * lane], kValid | (m & 0xFFFFFFFFull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&st->agg[2 * lane + 1], kValid | (m >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (lane >= 32 && lane < 36)
+            __hip_atomic_store(&st->agg[2 * kMaxProps + lane - 32], kValid | s_cagg[lane - 32], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        const bool owns = lane < (int)P || (lane >= 32 && lane < 36);
+        const int w0 = lane < 32 ? 2 * lane : 2 * kMaxProps + lane - 32;   // first word of this lane
+        const int nw = lane < 32 ? 2 : 1;
+        uint64_t acc = kIdentityMap;
+        uint32_t accc = 0;
+        if (tile > 0) {
+            // windowed look-back: every owning lane fetches the aggregate and
+            // inclusive words of kScanLookWindow predecessors in one round trip,
+            // then folds them nearest first until an inclusive tile
+            int64_t j = (int64_t)tile - 1;
+            uint32_t spins = 0;
+            bool done = false;
+            while (!done) {
+                uint64_t ia[kScanLookWindow], ib[kScanLookWindow], aa[kScanLookWindow], ab[kScanLookWindow];
+#pragma unroll
+                for (int k = 0; k < kScanLookWindow; ++k) {
+                    ia[k] = ib[k] = aa[k] = ab[k] = kValid;
+                    if (owns && j - k >= 0) {
+                        const ScanTileStatus* sj = a.status + (j - k);
+                        ia[k] = __hip_atomic_load(&sj->inc[w0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        aa[k] = __hip_atomic_load(&sj->agg[w0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (nw == 2) {
+                            ib[k] = __hip_atomic_load(&sj->inc[w0 + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            ab[k] = __hip_atomic_load(&sj->agg[w0 + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                    }
+                }
+                int used = 0;
+                bool stop = false;
+#pragma unroll
+                for (int k = 0; k < kScanLookWindow; ++k) {
+                    if (stop || done) continue;
+                    if (j - k < 0) { done = true; continue; }
+                    const bool inc_ok = __all(((ia[k] & kValid) != 0) && ((ib[k] & kValid) != 0));
+                    const bool agg_ok = __all(((aa[k] & kValid) != 0) && ((ab[k] & kValid) != 0));
+                    if (!inc_ok && !agg_ok) { stop = true; continue; }
+                    const uint64_t v0 = inc_ok ? ia[k] : aa[k], v1 = inc_ok ? ib[k] : ab[k];
+                    if (lane < (int)P) acc = map_compose(acc, (v0 & 0xFFFFFFFFull) | ((v1 & 0xFFFFFFFFull) << 32));
+                    if (lane >= 32 && lane < 36) accc += (uint32_t)v0;
+                    used = k + 1;
+                    if (inc_ok) done = true;
+                }
+                j -= used;
+                if (!done && j < 0) done = true;
+                if (!done && used == 0) {
+                    if (++spins > kSpinLimit) {
+                        if (lane == 0) atomicOr(a.err, kErrSpin);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+        }
+        // publish the inclusive value
+        if (lane < (int)P) {
+            const uint64_t m = tile > 0 ? map_compose(s_tagg[lane], acc) : s_tagg[lane];
+            __hip_atomic_store(&st->inc[2 * lane], kValid | (m & 0xFFFFFFFFull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&st->inc[2 * lane + 1], kValid | (m >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_tprefix[lane] = acc;
+        }
+        if (lane >= 32 && lane < 36) {
+            __hip_atomic_store(&st->inc[2 * kMaxProps + lane - 32], kValid | (accc + s_cagg[lane - 32]),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_tcnt[lane - 32] = accc;
+        }
+    }
+    __syncthreads();
+
+    // second walk: final state at every instance end; numbering of nodes.
+    // States of all properties are nibbles of curp.
+    uint64_t curp = 0, q0p = 0;
+#pragma unroll 1
+    for (int p = 0; p < (int)P; ++p) {
+        curp |= (uint64_t)map_at(map_compose(s_map[p * kScanThreads + tid], s_tprefix[p]), 0) << (4 * p);
+        q0p |= (uint64_t)s_q0[p] << (4 * p);
+    }
+    __syncthreads();                                          // s_map no longer needed
+    uint32_t inst = s_tcnt[0] + cexcl[0];
+    uint32_t lvl[4];
+#pragma unroll
+    for (int m = 1; m < 4; ++m) lvl[m] = s_tcnt[m] + cexcl[m];
+    // Instance verdicts are staged in LDS (the word buffer is free now) and
+    // written out contiguously: the instances ending in this tile have the
+    // consecutive ids [s_ilo, s_ihi], all >= s_tcnt[0] - 1.
+    const bool stage = P <= 8;
+    uint8_t* s_iv = reinterpret_cast<uint8_t*>(s_w);
+    constexpr uint32_t kIvStride = kScanTile + 1;
+    const uint32_t id_base = s_tcnt[0];             // slot of id = id + 1 - id_base
+    uint32_t my_lo = 0xFFFFFFFFu, my_hi = 0u;       // ids [my_lo, my_hi) this thread staged
+    uint32_t err = 0;
+    for (int j = 0; j < kScanItems; ++j) {
+        if (!((m_valid >> j) & 1u)) break;
+        const uint64_t x = wv[j];
+        const uint32_t c = (uint32_t)x & cmask;
+        if ((m_head >> j) & 1u) {
+            ++inst;
+            curp = q0p;
+#pragma unroll
+            for (int m = kMaxLevels - 1; m >= 1; --m) {
+                if (m >= (int)L || !((m_lvl[m] >> j) & 1u)) continue;
+                ++lvl[m];
+                const uint64_t id = lvl[m] - 1;
+                const uint32_t child = m == (int)L - 1 ? inst - 1 : lvl[m < 3 ? m + 1 : 3] - 1;
+                if (id < a.node_limit[m]) {
+                    a.node_start[m][id] = child;
+                    if (a.node_keys[m]) a.node_keys[m][id] = x >> a.prefix_shift[m];
+                } else {
+                    err |= kErrCapacity;
+                }
+            }
+        }
+        {
+            uint64_t nxt = 0;
+#pragma unroll
+            for (int p = 0; p < PMAX; ++p)
+                if (p < (int)P) nxt |= (uint64_t)s_delta[p][((curp >> (4 * p)) & 15u) * 16 + c] << (4 * p);
+            curp = nxt;
+        }
+        if ((m_end >> j) & 1u) {
+            const uint64_t id = inst - 1;
+            if (id < a.inst_limit) {
+                if (stage) {
+                    const uint32_t slot = (uint32_t)id + 1u - id_base;
+#pragma unroll
+                    for (int p = 0; p < 8; ++p)
+                        if (p < (int)P) {
+                            const uint32_t q = (uint32_t)(curp >> (4 * p)) & 15u;
+                            s_iv[p * kIvStride + slot] = a.emit_state ? q : s_label[p][q];
+                        }
+                    my_lo = min(my_lo, (uint32_t)id);
+                    my_hi = max(my_hi, (uint32_t)id + 1u);
+                } else {
+#pragma unroll
+                    for (int p = 0; p < PMAX; ++p)
+                        if (p < (int)P) {
+                            const uint32_t q = (uint32_t)(curp >> (4 * p)) & 15u;
+                            a.inst_verdict[p * a.inst_stride + id] = a.emit_state ? q : s_label[p][q];
+                        }
+                }
+                if (a.inst_keys) a.inst_keys[id] = x >> cb;
+            } else {
+                err |= kErrCapacity;
+            }
+        }
+    }
+    if (err) atomicOr(a.err, err);
+    if (stage) {
+        // block min / max of the staged id range
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            my_lo = min(my_lo, (uint32_t)__shfl_xor(my_lo, off, 64));
+            my_hi = max(my_hi, (uint32_t)__shfl_xor(my_hi, off, 64));
+        }
+        if (lane == 0) {
+            s_red[0][w] = my_lo;
+            s_red[1][w] = my_hi;
+        }
+        __syncthreads();
+        uint32_t lo = s_red[0][0], hi = s_red[1][0];
+        for (int i = 1; i < WAVES; ++i) {
+            lo = min(lo, s_red[0][i]);
+            hi = max(hi, s_red[1][i]);
+        }
         if (lo < hi) {
             const uint32_t cnt_iv = hi - lo, slot0 = lo + 1u - id_base;
             for (uint32_t p = 0; p < P; ++p)
@@ -948,6 +1304,26 @@ __global__ __launch_bounds__(256) void k_group_read(GroupState g, uint8_t* verdi
     }
 }
 
+// One thread per trace of a batch.
+__global__ __launch_bounds__(256) void k_batch_out(BatchOutArgs a) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.n_traces) return;
+    const uint32_t nn = min<uint64_t>(*a.n_nodes, a.stride);
+    uint32_t lo = 0, hi = nn;                 // first node with key >= t
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a.node_keys[mid] < t) lo = mid + 1; else hi = mid;
+    }
+    const bool has = lo < nn && a.node_keys[lo] == t;
+    const uint32_t zero[6] = {0, 0, 0, 0, 0, 0};
+    for (uint32_t p = 0; p < a.n_props; ++p) {
+        const uint32_t* c = has ? a.node_counts + ((uint64_t)p * a.stride + lo) * 6 : zero;
+        a.verdict[(uint64_t)t * a.n_props + p] =
+            has ? a.node_verdict[(uint64_t)p * a.stride + lo] : (uint8_t)valuate(a.plan->prop[p], 1, zero);
+        for (int b = 0; b < 6; ++b) a.counts[((uint64_t)t * a.n_props + p) * 6 + b] = c[b];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -970,7 +1346,7 @@ hipError_t launch_classify(const ClassifyArgs& a, hipStream_t s) {
     const uint64_t want = (a.n + 1023) / 1024;
     const uint32_t blocks = (uint32_t)(want < 512 ? (want ? want : 1) : 512);
     const bool group = a.chunk_off != nullptr;
-    if (a.record_bytes == 16 && (reinterpret_cast<uintptr_t>(a.records) & 15) == 0) {
+    if (a.record_bytes == 16 && (reinterpret_cast<uintptr_t>(a.records) & 15) == 0 && a.vec_ok) {
         if (group) hipLaunchKernelGGL((k_classify<4, true>), dim3(blocks), dim3(1024), 0, s, a);
         else hipLaunchKernelGGL((k_classify<4, false>), dim3(blocks), dim3(1024), 0, s, a);
     } else if (a.record_bytes == 12) {
@@ -1006,18 +1382,24 @@ hipError_t launch_sort_pass(const SortPassArgs& a, int variant, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_scan(const ScanArgs& a, hipStream_t s) {
-    const uint32_t tiles = (a.n + kScanTile - 1) / kScanTile;
+template <int T>
+static void launch_scan_t(const ScanArgs& a, hipStream_t s) {
+    const uint32_t tiles = (a.n + T * kScanItems - 1) / (T * kScanItems);
     if (a.n_props <= 1)
-        hipLaunchKernelGGL(k_scan<1>, dim3(tiles), dim3(kScanThreads), 0, s, a);
+        hipLaunchKernelGGL((k_scan<1, T>), dim3(tiles), dim3(T), 0, s, a);
     else if (a.n_props <= 2)
-        hipLaunchKernelGGL(k_scan<2>, dim3(tiles), dim3(kScanThreads), 0, s, a);
+        hipLaunchKernelGGL((k_scan<2, T>), dim3(tiles), dim3(T), 0, s, a);
     else if (a.n_props <= 4)
-        hipLaunchKernelGGL(k_scan<4>, dim3(tiles), dim3(kScanThreads), 0, s, a);
-    else if (a.n_props <= 8)
-        hipLaunchKernelGGL(k_scan<8>, dim3(tiles), dim3(kScanThreads), 0, s, a);
+        hipLaunchKernelGGL((k_scan<4, T>), dim3(tiles), dim3(T), 0, s, a);
     else
-        hipLaunchKernelGGL(k_scan<16>, dim3(tiles), dim3(kScanThreads), 0, s, a);
+        hipLaunchKernelGGL(k_scan_wide<T>, dim3(tiles), dim3(T), 0, s, a);
+}
+
+uint32_t scan_tile(int variant) { return (variant == 1 ? 512u : 256u) * kScanItems; }
+
+hipError_t launch_scan(const ScanArgs& a, int variant, hipStream_t s) {
+    if (variant == 1) launch_scan_t<512>(a, s);
+    else launch_scan_t<256>(a, s);
     return hipGetLastError();
 }
 
@@ -1067,6 +1449,15 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
 
 hipError_t launch_fill_u8(uint8_t* p, uint64_t n, uint8_t v, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u8, dim3(1024), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace ltl4c
+
+namespace ltl4c {
+
+hipError_t launch_batch_out(const BatchOutArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_out, dim3((a.n_traces + 255) / 256), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -65,7 +65,11 @@ struct ltl4c_ctx {
     std::map<std::vector<int32_t>, Plan*> plans;
     uint32_t* err_dev = nullptr;
     int sort_variant = 1;
+    int scan_variant = 0;
     uint64_t budget = ~0ull, used = 0;
+    uint32_t* batch_chunk_dev = nullptr;      // trace table of ltl4c_eval_batch
+    uint32_t* batch_chunk_host = nullptr;     // pinned staging for it
+    hipEvent_t batch_ev = nullptr;
     std::vector<struct GroupHost*> groups;
     bool prof = false;
     std::vector<Timed> timed;
@@ -78,18 +82,24 @@ namespace {
 // Derived quantities of a layout shared by the workspace query and eval.
 struct Geometry {
     uint32_t cbits, key_bits_total, sort_bits, n_pass;
-    uint32_t stream_bits;                   // stream id above the keys (stream groups)
+    uint32_t stream_bits;                   // stream / trace id above the keys
+    uint32_t n_levels;                      // levels of the monitor tree (quantifier nodes 0..n_levels-1)
     bool excl;
-    uint32_t prefix_bits[kMaxLevels];       // bits of the stream id and keys 0..m-1
+    uint32_t prefix_bits[kMaxLevels];       // bits of the packed prefix that identifies a level-m node
 };
 
-Geometry geometry(const ltl4c_layout& L, uint32_t stream_bits = 0) {
+// stream_is_level: the id above the keys is a tree level of its own (batches
+// of traces: one subtree per trace); otherwise it only separates streams.
+Geometry geometry(const ltl4c_layout& L, uint32_t stream_bits = 0, bool stream_is_level = false) {
     Geometry g{};
     g.cbits = bits_for(L.n_classes);
     g.stream_bits = stream_bits;
+    g.n_levels = L.n_keys + (stream_is_level ? 1u : 0u);
     uint32_t kb = stream_bits;
+    const uint32_t shift = stream_is_level ? 1u : 0u;
+    if (stream_is_level) g.prefix_bits[0] = 0;
     for (uint32_t m = 0; m < L.n_keys; ++m) {
-        g.prefix_bits[m] = kb;
+        if (m + shift < kMaxLevels) g.prefix_bits[m + shift] = kb;
         kb += L.key_bits[m];
     }
     g.key_bits_total = kb;
@@ -113,11 +123,13 @@ struct WsLayout {
     uint32_t tiles_sort, tiles_scan;
 };
 
-WsLayout plan_workspace(const ltl4c_layout& L, const Geometry& g, uint64_t n, uint32_t P, int sort_variant) {
+WsLayout plan_workspace(const ltl4c_layout& L, const Geometry& g, uint64_t n, uint32_t P, int sort_variant,
+                        int scan_variant) {
     WsLayout w{};
     const uint64_t st = sort_tile(sort_variant);
     w.tiles_sort = (uint32_t)((n + st - 1) / st);
-    w.tiles_scan = (uint32_t)((n + kScanTile - 1) / kScanTile);
+    const uint64_t sct = scan_tile(scan_variant);
+    w.tiles_scan = (uint32_t)((n + sct - 1) / sct);
     // zero block, in 32-bit words
     uint64_t z = 0;
     w.hist_off = z;        z += (uint64_t)g.n_pass * kRadix;
@@ -136,7 +148,8 @@ WsLayout plan_workspace(const ltl4c_layout& L, const Geometry& g, uint64_t n, ui
     w.words_a_off = off;   off = align256(off + n * 8);
     w.words_b_off = off;   off = align256(off + n * 8);
     w.inst_verdict_off = off; off = align256(off + (uint64_t)P * n);
-    for (uint32_t m = 1; m < L.n_keys; ++m) {
+    (void)L;
+    for (uint32_t m = 1; m < g.n_levels; ++m) {
         uint64_t cap = n;
         if (g.prefix_bits[m] < 40) cap = std::min<uint64_t>(cap, 1ull << g.prefix_bits[m]);
         w.cap_node[m] = cap;
@@ -171,7 +184,9 @@ int32_t check_layout(const ltl4c_layout* L) {
     return LTL4C_OK;
 }
 
-PropDev make_prop(const MonitorHost& M, const ltl4c_property& p) {
+// shift = 1 places the quantifiers one level down (level 0 gets a dummy
+// E>=0): used when a batch adds a per-trace level above the quantifiers.
+PropDev make_prop(const MonitorHost& M, const ltl4c_property& p, uint32_t shift = 0) {
     PropDev d;
     std::memset(&d, 0, sizeof d);
     for (uint32_t q = 0; q < M.n_states; ++q)
@@ -187,17 +202,24 @@ PropDev make_prop(const MonitorHost& M, const ltl4c_property& p) {
     }
     d.q0 = M.q0;
     d.n_states = M.n_states;
-    for (uint32_t l = 0; l < p.n_levels; ++l) {
-        d.kind[l] = p.q[l].kind;
-        d.op[l] = p.q[l].op;
-        d.num[l] = p.q[l].num;
-        d.den[l] = p.q[l].kind == LTL4C_Q_PERCENT ? p.q[l].den : 1u;
+    if (shift) {
+        d.kind[0] = LTL4C_Q_COUNT;
+        d.op[0] = LTL4C_GE;
+        d.num[0] = 0;
+        d.den[0] = 1;
+    }
+    for (uint32_t l = 0; l < p.n_levels && l + shift < (uint32_t)kMaxLevels; ++l) {
+        d.kind[l + shift] = p.q[l].kind;
+        d.op[l + shift] = p.q[l].op;
+        d.num[l + shift] = p.q[l].num;
+        d.den[l + shift] = p.q[l].kind == LTL4C_Q_PERCENT ? p.q[l].den : 1u;
     }
     return d;
 }
 
-int32_t get_plan(ltl4c_ctx* ctx, const int32_t* props, int32_t n_props, Plan** out) {
+int32_t get_plan(ltl4c_ctx* ctx, const int32_t* props, int32_t n_props, Plan** out, uint32_t shift = 0) {
     std::vector<int32_t> key(props, props + n_props);
+    if (shift) key.insert(key.begin(), -1);
     auto it = ctx->plans.find(key);
     if (it != ctx->plans.end()) {
         *out = it->second;
@@ -207,7 +229,7 @@ int32_t get_plan(ltl4c_ctx* ctx, const int32_t* props, int32_t n_props, Plan** o
     std::memset(&host, 0, sizeof host);
     for (int32_t i = 0; i < n_props; ++i) {
         const ltl4c_property& p = ctx->props[props[i]];
-        host.prop[i] = make_prop(ctx->monitors[p.monitor], p);
+        host.prop[i] = make_prop(ctx->monitors[p.monitor], p, shift);
     }
     std::memcpy(host.class_of_type, ctx->layout.class_of_type, 256);
     std::memcpy(host.key_present, ctx->layout.key_present, 256);
@@ -293,7 +315,8 @@ int32_t drain_profile(ltl4c_ctx* ctx) {
 // passes; *sorted receives the buffer holding the sorted words.
 int32_t enqueue_front(ltl4c_ctx* ctx, const ltl4c_layout& L, const Geometry& g, const WsLayout& w, uint8_t* ws,
                       const void* d_records, uint64_t n, const Plan* plan, const uint32_t* chunk_off,
-                      const uint32_t* chunk_stream, uint32_t n_chunks, uint64_t** sorted) {
+                      const uint32_t* chunk_stream, const uint64_t* chunk_ptr, uint32_t n_chunks, bool vec_ok,
+                      uint64_t** sorted, int sort_variant) {
     const uint32_t NL = L.n_keys;
     uint32_t* z = reinterpret_cast<uint32_t*>(ws);
     uint32_t* hist = z + w.hist_off;
@@ -329,7 +352,9 @@ int32_t enqueue_front(ltl4c_ctx* ctx, const ltl4c_layout& L, const Geometry& g, 
     ca.err = ctx->err_dev;
     ca.chunk_off = chunk_off;
     ca.chunk_stream = chunk_stream;
+    ca.chunk_ptr = chunk_ptr;
     ca.n_chunks = n_chunks;
+    ca.vec_ok = vec_ok ? 1u : 0u;
     ca.stream_shift = g.key_bits_total - g.stream_bits;
     s = launch(ctx, "classify", [&] { return launch_classify(ca, st); });
     if (s) return s;
@@ -346,7 +371,7 @@ int32_t enqueue_front(ltl4c_ctx* ctx, const ltl4c_layout& L, const Geometry& g, 
         sa.status = sort_status + (uint64_t)p * w.tiles_sort * kRadix;
         sa.ticket = sort_ticket + p;
         sa.err = ctx->err_dev;
-        s = launch(ctx, "sort_pass", [&] { return launch_sort_pass(sa, ctx->sort_variant, st); });
+        s = launch(ctx, "sort_pass", [&] { return launch_sort_pass(sa, sort_variant, st); });
         if (s) return s;
         std::swap(in, outw);
     }
@@ -360,6 +385,7 @@ int32_t enqueue_front(ltl4c_ctx* ctx, const ltl4c_layout& L, const Geometry& g, 
 // A stream group: the resident monitor tree of up to max_streams streams.
 struct GroupHost {
     std::vector<int32_t> props;
+    int sort_variant = 0, scan_variant = 0;   // schedules fixed when the group opens
     uint32_t P = 0, V = 0, S = 0, max_bindings = 0;
     uint64_t max_batch = 0;
     Geometry g{};
@@ -383,7 +409,7 @@ struct GroupHost {
 namespace {
 
 constexpr int kChunkRing = 4;
-constexpr uint64_t kChunkTableWords = 2 * kMaxChunks + 1;
+constexpr uint64_t kChunkTableWords = 4 * kMaxChunks + 4;   // offsets, streams, pointers
 
 uint64_t pow2_at_least(uint64_t x) {
     uint64_t p = 1024;
@@ -466,9 +492,13 @@ int32_t group_configure(ltl4c_ctx* ctx, GroupHost& G, const int32_t* props, int3
     G.g = geometry(L, sb);
     if (G.g.cbits + G.g.key_bits_total + (G.g.excl ? 1 : 0) > 63)
         return fail(LTL4C_EUNSUPPORTED, "stream id, keys and class bits exceed 63 bits");
+    G.sort_variant = ctx->sort_variant;
+    G.scan_variant = ctx->scan_variant;
     G.lay_ws = L;
     G.lay_ws.n_keys = 1;
-    G.w = plan_workspace(G.lay_ws, G.g, max_batch, G.V, ctx->sort_variant);
+    Geometry g1 = G.g;
+    g1.n_levels = 1;                    // the scan of a push numbers segments only
+    G.w = plan_workspace(G.lay_ws, g1, max_batch, G.V, ctx->sort_variant, ctx->scan_variant);
     G.seg_keys_off = align256(G.w.total);
     G.ws_bytes = G.seg_keys_off + 8 * max_batch;
     G.state_bytes = group_state_layout(G, L.n_keys, nullptr, nullptr);
@@ -542,6 +572,9 @@ int32_t ltl4c_destroy(ltl4c_ctx* ctx) {
     drop_plans(ctx);
     for (auto* G : ctx->groups) group_free(G);
     ctx->groups.clear();
+    (void)hipFree(ctx->batch_chunk_dev);
+    (void)hipHostFree(ctx->batch_chunk_host);
+    if (ctx->batch_ev) (void)hipEventDestroy(ctx->batch_ev);
     for (auto& t : ctx->timed) {
         (void)hipEventDestroy(t.start);
         (void)hipEventDestroy(t.stop);
@@ -618,43 +651,19 @@ int32_t ltl4c_workspace_bytes(ltl4c_ctx* ctx, uint64_t n_events, const int32_t* 
     if (!bytes) return fail(LTL4C_EINVAL, "bytes is NULL");
     if (n_events > LTL4C_MAX_EVENTS) return fail(LTL4C_EUNSUPPORTED, "too many events for one call");
     Geometry g = geometry(ctx->layout);
-    *bytes = plan_workspace(ctx->layout, g, n_events, (uint32_t)n_props, ctx->sort_variant).total;
+    *bytes = plan_workspace(ctx->layout, g, n_events, (uint32_t)n_props, ctx->sort_variant, ctx->scan_variant).total;
     return LTL4C_OK;
 }
 
-int32_t ltl4c_eval(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int32_t* props, int32_t n_props,
-                   void* d_ws, uint64_t ws_bytes, const ltl4c_result* out) {
-    int32_t s = check_props(ctx, props, n_props);
-    if (s) return s;
-    if (n > LTL4C_MAX_EVENTS) return fail(LTL4C_EUNSUPPORTED, "too many events for one call");
-    if (n > 0 && !d_records) return fail(LTL4C_EINVAL, "records is NULL");
-    if (!out || !out->root_verdict || !out->root_counts || !out->sizes)
-        return fail(LTL4C_EINVAL, "root_verdict, root_counts and sizes are required");
-    if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) & 255)) return fail(LTL4C_EINVAL, "workspace must be 256-byte aligned");
+// The evaluation pipeline after validation: zero, classify, radix passes,
+// scan, counting per level, finalize.  g.n_levels tree levels; when a chunk
+// table is given the chunk index (a trace id) is the top key.
+static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, void* d_ws, const void* d_records,
+                         uint64_t n, const Plan* plan, uint32_t P, const uint32_t* chunk_off,
+                         const uint32_t* chunk_stream, uint32_t n_chunks, const ltl4c_result* out) {
     const ltl4c_layout& L = ctx->layout;
-    const uint32_t P = (uint32_t)n_props, NL = L.n_keys;
-    if (n > 0 && (reinterpret_cast<uintptr_t>(d_records) & 3))
-        return fail(LTL4C_EINVAL, "records must be 4-byte aligned");
-    Geometry g = geometry(L);
-    WsLayout w = plan_workspace(L, g, n, P, ctx->sort_variant);
-    if (ws_bytes < w.total) return fail(LTL4C_ENOMEM, "workspace smaller than ltl4c_workspace_bytes()");
-    if ((out->inst_keys != nullptr) != (out->inst_verdict != nullptr))
-        return fail(LTL4C_EINVAL, "inst_keys and inst_verdict are given together or not at all");
-    bool any_optional = out->inst_verdict != nullptr;
-    for (uint32_t m = 1; m < L.n_keys; ++m) {
-        const bool k = out->node_keys[m] != nullptr, c = out->node_counts[m] != nullptr,
-                   v = out->node_verdict[m] != nullptr;
-        if (k != c || c != v)
-            return fail(LTL4C_EINVAL, "node_keys, node_counts and node_verdict of a level go together");
-        any_optional = any_optional || c;
-    }
-    if (any_optional && out->capacity == 0)
-        return fail(LTL4C_EINVAL, "capacity must be > 0 when optional outputs are given");
-    Plan* plan = nullptr;
-    s = get_plan(ctx, props, n_props, &plan);
-    if (s) return s;
-    HIP_TRY(hipSetDevice(ctx->device));
-
+    const uint32_t NL = g.n_levels;
+    int32_t s = LTL4C_OK;
     uint8_t* ws = static_cast<uint8_t*>(d_ws);
     uint32_t* z = reinterpret_cast<uint32_t*>(ws);
     uint32_t* scan_ticket = z + w.scan_ticket_off;
@@ -673,7 +682,8 @@ int32_t ltl4c_eval(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int3
     }
     uint64_t* sorted = words_a;
     if (n > 0) {
-        s = enqueue_front(ctx, L, g, w, ws, d_records, n, plan, nullptr, nullptr, 0, &sorted);
+        s = enqueue_front(ctx, L, g, w, ws, d_records, n, plan, chunk_off, chunk_stream, nullptr, n_chunks, true,
+                          &sorted, ctx->sort_variant);
         if (s) return s;
     }
 
@@ -721,7 +731,7 @@ int32_t ltl4c_eval(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int3
         sa.sizes = sizes64;
         sa.sizes32 = sizes32;
         sa.err = ctx->err_dev;
-        s = launch(ctx, "scan", [&] { return launch_scan(sa, st); });
+        s = launch(ctx, "scan", [&] { return launch_scan(sa, ctx->scan_variant, st); });
         if (s) return s;
 
         for (int m = (int)NL - 1; m >= 0; --m) {
@@ -774,6 +784,150 @@ int32_t ltl4c_eval(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int3
     fa.sizes_out = out->sizes;
     fa.n_levels = NL;
     s = launch(ctx, "finalize", [&] { return launch_finalize(fa, st); });
+    return s;
+}
+
+int32_t ltl4c_eval(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int32_t* props, int32_t n_props,
+                   void* d_ws, uint64_t ws_bytes, const ltl4c_result* out) {
+    int32_t s = check_props(ctx, props, n_props);
+    if (s) return s;
+    if (n > LTL4C_MAX_EVENTS) return fail(LTL4C_EUNSUPPORTED, "too many events for one call");
+    if (n > 0 && !d_records) return fail(LTL4C_EINVAL, "records is NULL");
+    if (!out || !out->root_verdict || !out->root_counts || !out->sizes)
+        return fail(LTL4C_EINVAL, "root_verdict, root_counts and sizes are required");
+    if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) & 255)) return fail(LTL4C_EINVAL, "workspace must be 256-byte aligned");
+    const ltl4c_layout& L = ctx->layout;
+    const uint32_t P = (uint32_t)n_props;
+    if (n > 0 && (reinterpret_cast<uintptr_t>(d_records) & 3))
+        return fail(LTL4C_EINVAL, "records must be 4-byte aligned");
+    Geometry g = geometry(L);
+    WsLayout w = plan_workspace(L, g, n, P, ctx->sort_variant, ctx->scan_variant);
+    if (ws_bytes < w.total) return fail(LTL4C_ENOMEM, "workspace smaller than ltl4c_workspace_bytes()");
+    if ((out->inst_keys != nullptr) != (out->inst_verdict != nullptr))
+        return fail(LTL4C_EINVAL, "inst_keys and inst_verdict are given together or not at all");
+    bool any_optional = out->inst_verdict != nullptr;
+    for (uint32_t m = 1; m < L.n_keys; ++m) {
+        const bool k = out->node_keys[m] != nullptr, c = out->node_counts[m] != nullptr,
+                   v = out->node_verdict[m] != nullptr;
+        if (k != c || c != v)
+            return fail(LTL4C_EINVAL, "node_keys, node_counts and node_verdict of a level go together");
+        any_optional = any_optional || c;
+    }
+    if (any_optional && out->capacity == 0)
+        return fail(LTL4C_EINVAL, "capacity must be > 0 when optional outputs are given");
+    Plan* plan = nullptr;
+    s = get_plan(ctx, props, n_props, &plan);
+    if (s) return s;
+    HIP_TRY(hipSetDevice(ctx->device));
+
+    return eval_core(ctx, g, w, d_ws, d_records, n, plan, P, nullptr, nullptr, 0, out);
+}
+
+
+// ---- batches of traces -----------------------------------------------------
+namespace {
+
+struct BatchLayout {
+    Geometry g;
+    WsLayout w;
+    uint64_t root_off, keys_off, counts_off, verdict_off, cap1, total;
+};
+
+int32_t batch_layout(ltl4c_ctx* ctx, uint64_t n, int32_t n_traces, uint32_t P, BatchLayout* b) {
+    const ltl4c_layout& L = ctx->layout;
+    if (n_traces < 1 || n_traces > (int32_t)kMaxChunks) return fail(LTL4C_EUNSUPPORTED, "n_traces must be 1..4096");
+    if (L.n_keys + 1 > (uint32_t)kMaxLevels)
+        return fail(LTL4C_EUNSUPPORTED, "a batch takes properties with at most 3 quantifiers");
+    if (n > LTL4C_MAX_EVENTS) return fail(LTL4C_EUNSUPPORTED, "too many events for one call");
+    b->g = geometry(L, std::max<uint32_t>(1, bits_for((uint32_t)n_traces)), true);
+    if (b->g.cbits + b->g.key_bits_total + (b->g.excl ? 1 : 0) > 63)
+        return fail(LTL4C_EUNSUPPORTED, "trace id, keys and class bits exceed 63 bits");
+    b->w = plan_workspace(L, b->g, n, P, ctx->sort_variant, ctx->scan_variant);
+    b->cap1 = b->w.cap_node[1];
+    uint64_t off = align256(b->w.total);
+    b->root_off = off;    off = align256(off + 2048);     // outputs of the artificial root
+    b->keys_off = off;    off = align256(off + 8 * b->cap1);
+    b->counts_off = off;  off = align256(off + 24ull * P * b->cap1);
+    b->verdict_off = off; off = align256(off + (uint64_t)P * b->cap1);
+    b->total = off;
+    return LTL4C_OK;
+}
+
+}  // namespace
+
+int32_t ltl4c_batch_workspace_bytes(ltl4c_ctx* ctx, uint64_t n_events, int32_t n_traces, const int32_t* props,
+                                    int32_t n_props, uint64_t* bytes) {
+    int32_t s = check_props(ctx, props, n_props);
+    if (s) return s;
+    if (!bytes) return fail(LTL4C_EINVAL, "bytes is NULL");
+    BatchLayout b;
+    s = batch_layout(ctx, n_events, n_traces, (uint32_t)n_props, &b);
+    if (s) return s;
+    *bytes = b.total;
+    return LTL4C_OK;
+}
+
+int32_t ltl4c_eval_batch(ltl4c_ctx* ctx, const void* d_records, const uint64_t* offsets, int32_t n_traces,
+                         const int32_t* props, int32_t n_props, void* d_ws, uint64_t ws_bytes,
+                         uint8_t* d_root_verdict, uint64_t* d_root_counts) {
+    int32_t s = check_props(ctx, props, n_props);
+    if (s) return s;
+    if (!offsets || !d_root_verdict || !d_root_counts) return fail(LTL4C_EINVAL, "NULL argument");
+    if (n_traces < 1 || n_traces > (int32_t)kMaxChunks) return fail(LTL4C_EUNSUPPORTED, "n_traces must be 1..4096");
+    if (offsets[0] != 0) return fail(LTL4C_EINVAL, "offsets[0] must be 0");
+    for (int32_t t = 0; t < n_traces; ++t)
+        if (offsets[t + 1] < offsets[t]) return fail(LTL4C_EINVAL, "offsets must be non-decreasing");
+    const uint64_t n = offsets[n_traces];
+    const uint32_t P = (uint32_t)n_props;
+    BatchLayout b;
+    s = batch_layout(ctx, n, n_traces, P, &b);
+    if (s) return s;
+    if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) & 255)) return fail(LTL4C_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < b.total) return fail(LTL4C_ENOMEM, "workspace smaller than ltl4c_batch_workspace_bytes()");
+    if (n > 0 && (!d_records || (reinterpret_cast<uintptr_t>(d_records) & 3)))
+        return fail(LTL4C_EINVAL, "records must be non-NULL and 4-byte aligned");
+    Plan* plan = nullptr;
+    s = get_plan(ctx, props, n_props, &plan, 1);
+    if (s) return s;
+    HIP_TRY(hipSetDevice(ctx->device));
+    if (!ctx->batch_chunk_dev) {
+        HIP_TRY(hipMalloc(&ctx->batch_chunk_dev, 4 * (2 * kMaxChunks + 2)));
+        HIP_TRY(hipHostMalloc(&ctx->batch_chunk_host, 4 * (2 * kMaxChunks + 2), hipHostMallocDefault));
+        HIP_TRY(hipEventCreateWithFlags(&ctx->batch_ev, hipEventDisableTiming));
+    }
+    const hipStream_t st = ctx->stream;
+    // trace table: chunk t is trace t
+    HIP_TRY(hipEventSynchronize(ctx->batch_ev));
+    uint32_t* h = ctx->batch_chunk_host;
+    for (int32_t t = 0; t <= n_traces; ++t) h[t] = (uint32_t)offsets[t];
+    for (int32_t t = 0; t < n_traces; ++t) h[n_traces + 1 + t] = (uint32_t)t;
+    HIP_TRY(hipMemcpyAsync(ctx->batch_chunk_dev, h, 4ull * (2 * n_traces + 1), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(ctx->batch_ev, st));
+
+    uint8_t* ws = static_cast<uint8_t*>(d_ws);
+    ltl4c_result r{};
+    r.root_verdict = ws + b.root_off;                                   // artificial root: unused
+    r.root_counts = reinterpret_cast<uint64_t*>(ws + b.root_off + 256);
+    r.sizes = reinterpret_cast<uint64_t*>(ws + b.root_off + 1024);
+    r.capacity = b.cap1;
+    r.node_keys[1] = reinterpret_cast<uint64_t*>(ws + b.keys_off);
+    r.node_counts[1] = reinterpret_cast<uint32_t*>(ws + b.counts_off);
+    r.node_verdict[1] = ws + b.verdict_off;
+    s = eval_core(ctx, b.g, b.w, d_ws, d_records, n, plan, P, ctx->batch_chunk_dev,
+                  ctx->batch_chunk_dev + n_traces + 1, (uint32_t)n_traces, &r);
+    if (s) return s;
+    BatchOutArgs o{};
+    o.n_props = P;
+    o.n_traces = (uint32_t)n_traces;
+    o.plan = plan;
+    o.n_nodes = reinterpret_cast<uint32_t*>(ws) + b.w.sizes32_off + 1;
+    o.node_keys = r.node_keys[1];
+    o.node_counts = r.node_counts[1];
+    o.node_verdict = r.node_verdict[1];
+    o.stride = b.cap1;
+    o.verdict = d_root_verdict;
+    o.counts = d_root_counts;
+    s = launch(ctx, "batch_out", [&] { return launch_batch_out(o, st); });
     return s;
 }
 
@@ -912,31 +1066,51 @@ int32_t ltl4c_group_close(ltl4c_ctx* ctx, int32_t group) {
     return LTL4C_OK;
 }
 
-int32_t ltl4c_group_push(ltl4c_ctx* ctx, int32_t group, const void* d_records, const uint64_t* offsets,
-                         const uint32_t* streams, int32_t n_chunks) {
+// Shared by both push entry points: chunk i holds sizes[i] records at
+// chunk_ptr[i] (or at d_records + offset when chunk_ptr is NULL).
+static int32_t group_push_impl(ltl4c_ctx* ctx, int32_t group, const void* d_records, const void* const* chunk_ptr,
+                               const uint64_t* sizes, const uint32_t* streams, int32_t n_chunks) {
     GroupHost* G = nullptr;
     int32_t s = get_group(ctx, group, &G);
     if (s) return s;
     if (n_chunks < 1 || n_chunks > (int32_t)kMaxChunks) return fail(LTL4C_EINVAL, "n_chunks must be 1..4096");
-    if (!offsets || !streams) return fail(LTL4C_EINVAL, "offsets / streams are NULL");
-    if (offsets[0] != 0) return fail(LTL4C_EINVAL, "offsets[0] must be 0");
+    if (!sizes || !streams) return fail(LTL4C_EINVAL, "chunk sizes / streams are NULL");
+    uint64_t n = 0;
+    bool vec_ok = ctx->layout.record_bytes == 16;
     for (int32_t i = 0; i < n_chunks; ++i) {
-        if (offsets[i + 1] < offsets[i]) return fail(LTL4C_EINVAL, "offsets must be non-decreasing");
         if (streams[i] >= G->S) return fail(LTL4C_EINVAL, "stream id >= max_streams");
+        if (chunk_ptr && sizes[i] > 0) {
+            const uintptr_t a = reinterpret_cast<uintptr_t>(chunk_ptr[i]);
+            if (!a || (a & 3)) return fail(LTL4C_EINVAL, "chunk records must be non-NULL and 4-byte aligned");
+            if (a & 15) vec_ok = false;
+        }
+        n += sizes[i];
     }
-    const uint64_t n = offsets[n_chunks];
     if (n > G->max_batch) return fail(LTL4C_ECAPACITY, "batch larger than the group's max_batch");
-    if (n > 0 && (!d_records || (reinterpret_cast<uintptr_t>(d_records) & 3)))
+    if (!chunk_ptr && n > 0 && (!d_records || (reinterpret_cast<uintptr_t>(d_records) & 3)))
         return fail(LTL4C_EINVAL, "records must be non-NULL and 4-byte aligned");
     if (n == 0) return LTL4C_OK;
     HIP_TRY(hipSetDevice(ctx->device));
     const hipStream_t st = ctx->stream;
-    // chunk table through a pinned ring slot (reused only after its copy ran)
+    // packed chunk table [offsets n+1][streams n][pad][pointers n] through a
+    // pinned ring slot, reused only after its copy has run
     uint32_t* slot = G->chunk_host + (uint64_t)G->ring_i * kChunkTableWords;
     HIP_TRY(hipEventSynchronize(G->ring_ev[G->ring_i]));
-    for (int32_t i = 0; i <= n_chunks; ++i) slot[i] = (uint32_t)offsets[i];
-    for (int32_t i = 0; i < n_chunks; ++i) slot[kMaxChunks + 1 + i] = streams[i];
-    HIP_TRY(hipMemcpyAsync(G->chunk_dev, slot, 4 * kChunkTableWords, hipMemcpyHostToDevice, st));
+    uint64_t acc = 0;
+    for (int32_t i = 0; i < n_chunks; ++i) {
+        slot[i] = (uint32_t)acc;
+        acc += sizes[i];
+    }
+    slot[n_chunks] = (uint32_t)acc;
+    const uint64_t so = n_chunks + 1, po = (so + n_chunks + 1) & ~1ull;
+    for (int32_t i = 0; i < n_chunks; ++i) slot[so + i] = streams[i];
+    uint64_t words = so + n_chunks;
+    if (chunk_ptr) {
+        uint64_t* pp = reinterpret_cast<uint64_t*>(slot + po);
+        for (int32_t i = 0; i < n_chunks; ++i) pp[i] = reinterpret_cast<uint64_t>(chunk_ptr[i]);
+        words = po + 2ull * n_chunks;
+    }
+    HIP_TRY(hipMemcpyAsync(G->chunk_dev, slot, 4 * words, hipMemcpyHostToDevice, st));
     HIP_TRY(hipEventRecord(G->ring_ev[G->ring_i], st));
     G->ring_i = (G->ring_i + 1) % kChunkRing;
 
@@ -954,8 +1128,9 @@ int32_t ltl4c_group_push(ltl4c_ctx* ctx, int32_t group, const void* d_records, c
         if (s) return s;
     }
     uint64_t* sorted = nullptr;
-    s = enqueue_front(ctx, L, G->g, w, ws, d_records, n, G->vplan, G->chunk_dev, G->chunk_dev + kMaxChunks + 1,
-                      (uint32_t)n_chunks, &sorted);
+    s = enqueue_front(ctx, L, G->g, w, ws, d_records, n, G->vplan, G->chunk_dev, G->chunk_dev + so,
+                      chunk_ptr ? reinterpret_cast<const uint64_t*>(G->chunk_dev + po) : nullptr,
+                      (uint32_t)n_chunks, chunk_ptr ? vec_ok : true, &sorted, G->sort_variant);
     if (s) return s;
     uint64_t* seg_keys = reinterpret_cast<uint64_t*>(ws + G->seg_keys_off);
     uint8_t* seg_state = ws + w.inst_verdict_off;
@@ -979,7 +1154,7 @@ int32_t ltl4c_group_push(ltl4c_ctx* ctx, int32_t group, const void* d_records, c
         sa.sizes32 = sizes32;
         sa.err = ctx->err_dev;
         sa.emit_state = 1;
-        s = launch(ctx, "scan", [&] { return launch_scan(sa, st); });
+        s = launch(ctx, "scan", [&] { return launch_scan(sa, G->scan_variant, st); });
         if (s) return s;
     }
     GroupUpdateArgs ua{};
@@ -995,6 +1170,25 @@ int32_t ltl4c_group_push(ltl4c_ctx* ctx, int32_t group, const void* d_records, c
         if (s) return s;
     }
     return launch(ctx, "group_roots", [&] { return launch_group_roots(G->gs, false, st); });
+}
+
+int32_t ltl4c_group_push(ltl4c_ctx* ctx, int32_t group, const void* d_records, const uint64_t* offsets,
+                         const uint32_t* streams, int32_t n_chunks) {
+    if (!offsets) return fail(LTL4C_EINVAL, "offsets is NULL");
+    if (n_chunks < 1 || n_chunks > (int32_t)kMaxChunks) return fail(LTL4C_EINVAL, "n_chunks must be 1..4096");
+    if (offsets[0] != 0) return fail(LTL4C_EINVAL, "offsets[0] must be 0");
+    std::vector<uint64_t> sizes(n_chunks);
+    for (int32_t i = 0; i < n_chunks; ++i) {
+        if (offsets[i + 1] < offsets[i]) return fail(LTL4C_EINVAL, "offsets must be non-decreasing");
+        sizes[i] = offsets[i + 1] - offsets[i];
+    }
+    return group_push_impl(ctx, group, d_records, nullptr, sizes.data(), streams, n_chunks);
+}
+
+int32_t ltl4c_group_push_chunks(ltl4c_ctx* ctx, int32_t group, const void* const* d_chunks, const uint64_t* sizes,
+                                const uint32_t* streams, int32_t n_chunks) {
+    if (!d_chunks) return fail(LTL4C_EINVAL, "chunk pointers are NULL");
+    return group_push_impl(ctx, group, nullptr, d_chunks, sizes, streams, n_chunks);
 }
 
 int32_t ltl4c_group_read(ltl4c_ctx* ctx, int32_t group, uint8_t* d_root_verdict, uint64_t* d_root_counts,
@@ -1042,6 +1236,10 @@ int32_t ltl4c_set_option(ltl4c_ctx* ctx, int32_t option, int64_t value) {
         case LTL4C_OPT_SORT_TILE:
             if (value < 0 || value >= kSortVariants) return fail(LTL4C_EINVAL, "sort tile variant out of range");
             ctx->sort_variant = (int)value;
+            return LTL4C_OK;
+        case LTL4C_OPT_SCAN_TILE:
+            if (value < 0 || value >= kScanVariants) return fail(LTL4C_EINVAL, "scan tile variant out of range");
+            ctx->scan_variant = (int)value;
             return LTL4C_OK;
         default:
             return fail(LTL4C_EINVAL, "unknown option");

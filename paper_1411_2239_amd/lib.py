@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(HERE, "libltl4c.so")
 OK, EINVAL, ENOMEM, ECAPACITY, EDEVICE, EADMIT, ESEQ, EUNSUPPORTED, ERANGE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 BOT, BOT_C, BOT_P, TOP_P, TOP_C, TOP = range(6)
 OPT_SORT_TILE = 0
+OPT_SCAN_TILE = 1
 VERDICT_NAMES = ["F", "Fc", "Fp", "Tp", "Tc", "T"]
 KIND = {"A": 0, "E": 1}
 OP = {"<": 0, "<=": 1, ">": 2, ">=": 3, "=": 4}
@@ -76,6 +77,11 @@ SIGNATURES = [
     ("ltl4c_eval", C.c_int32,
      [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(C.c_int32), C.c_int32, C.c_void_p, C.c_uint64,
       C.POINTER(Result)]),
+    ("ltl4c_batch_workspace_bytes", C.c_int32, [C.c_void_p, C.c_uint64, C.c_int32, C.POINTER(C.c_int32), C.c_int32,
+                                                C.POINTER(C.c_uint64)]),
+    ("ltl4c_eval_batch", C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_uint64), C.c_int32,
+                                     C.POINTER(C.c_int32), C.c_int32, C.c_void_p, C.c_uint64, C.c_void_p,
+                                     C.c_void_p]),
     ("ltl4c_wait", C.c_int32, [C.c_void_p]),
     ("ltl4c_set_memory_budget", C.c_int32, [C.c_void_p, C.c_uint64]),
     ("ltl4c_group_bytes", C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32, C.c_uint32, C.c_uint32,
@@ -85,6 +91,8 @@ SIGNATURES = [
     ("ltl4c_group_close", C.c_int32, [C.c_void_p, C.c_int32]),
     ("ltl4c_group_push", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_uint64),
                                      C.POINTER(C.c_uint32), C.c_int32]),
+    ("ltl4c_group_push_chunks", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_uint64),
+                                            C.POINTER(C.c_uint32), C.c_int32]),
     ("ltl4c_group_read", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("ltl4c_group_snapshot", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_uint64)]),
     ("ltl4c_group_restore", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_uint64]),
@@ -295,6 +303,39 @@ class Context:
         _check(self.lib.ltl4c_set_option(self.h, option, value), "ltl4c_set_option")
         self._workspace = None
 
+    def batch_workspace(self, n_events, n_traces, props):
+        arr = (C.c_int32 * len(props))(*props)
+        b = C.c_uint64()
+        _check(self.lib.ltl4c_batch_workspace_bytes(self.h, n_events, n_traces, arr, len(props), C.byref(b)),
+               "ltl4c_batch_workspace_bytes")
+        need = max(b.value, 256)
+        ws = self._workspace
+        if ws is None or ws.numel() < need:
+            ws = self.torch.empty(need, dtype=self.torch.uint8, device=f"cuda:{self.device}")
+            self._workspace = ws
+        return ws
+
+    def eval_batch_into(self, records, offsets, props, verdict, counts, workspace):
+        """Enqueue a batch: trace t = records [offsets[t], offsets[t+1])."""
+        self._bind_stream()
+        nt = len(offsets) - 1
+        off = (C.c_uint64 * (nt + 1))(*[int(x) for x in offsets])
+        arr = (C.c_int32 * len(props))(*props)
+        _check(self.lib.ltl4c_eval_batch(self.h, C.c_void_p(records.data_ptr() if int(offsets[-1]) else 0), off, nt,
+                                         arr, len(props), C.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                         C.c_void_p(verdict.data_ptr()), C.c_void_p(counts.data_ptr())),
+               "ltl4c_eval_batch")
+
+    def eval_batch(self, records, offsets, props):
+        """Evaluate and wait: (verdict [T, P], counts [T, P, 6]) as numpy."""
+        t, dev = self.torch, f"cuda:{self.device}"
+        nt = len(offsets) - 1
+        v = t.empty(nt * len(props), dtype=t.uint8, device=dev)
+        c = t.empty(nt * len(props) * 6, dtype=t.int64, device=dev)
+        self.eval_batch_into(records, offsets, props, v, c, self.batch_workspace(int(offsets[-1]), nt, props))
+        self.wait()
+        return v.cpu().numpy().reshape(nt, len(props)), c.cpu().numpy().reshape(nt, len(props), 6)
+
     def set_memory_budget(self, nbytes):
         _check(self.lib.ltl4c_set_memory_budget(self.h, nbytes), "ltl4c_set_memory_budget")
 
@@ -350,6 +391,15 @@ class StreamGroup:
         st = (C.c_uint32 * n)(*[int(x) for x in streams])
         _check(self.lib.ltl4c_group_push(self.ctx.h, self.id, C.c_void_p(records.data_ptr()), off, st, n),
                "ltl4c_group_push")
+
+    def push_chunks(self, ptrs, sizes, streams):
+        """Enqueue chunks held in separate device buffers (addresses in ptrs)."""
+        self.ctx._bind_stream()
+        n = len(streams)
+        p = (C.c_void_p * n)(*[int(x) for x in ptrs])
+        sz = (C.c_uint64 * n)(*[int(x) for x in sizes])
+        st = (C.c_uint32 * n)(*[int(x) for x in streams])
+        _check(self.lib.ltl4c_group_push_chunks(self.ctx.h, self.id, p, sz, st, n), "ltl4c_group_push_chunks")
 
     def read(self):
         """(verdict [S, P], counts [S, P, 6], bindings [S]) as numpy, after a wait."""

@@ -190,12 +190,12 @@ def prop_layout(n_props=3, n_levels=1, key_bits=None):
                   [{names[i] for i in range(n_props) if (c >> i) & 1} for c in range(n_cls)])
 
 
-def zipf_ranks(rng, n, n_ranks, s):
+def zipf_ranks(rng, n, n_ranks, s, dtype=np.float64):
     """Draw n ranks in [0, n_ranks) with P(r) proportional to (r+1)^-s."""
     w = np.arange(1, n_ranks + 1, dtype=np.float64) ** (-s)
     cdf = np.cumsum(w)
     cdf /= cdf[-1]
-    return np.minimum(np.searchsorted(cdf, rng.random(n), side="right"), n_ranks - 1)
+    return np.minimum(np.searchsorted(cdf.astype(dtype), rng.random(n, dtype=dtype), side="right"), n_ranks - 1)
 
 
 def gen_prop_trace(n_events, n_keys, zipf_s, p_props=(0.02, 0.9, 0.5), seed=0, key_space_bits=32,
@@ -220,3 +220,167 @@ def gen_prop_trace(n_events, n_keys, zipf_s, p_props=(0.02, 0.9, 0.5), seed=0, k
     rec["k0"] = key_of_rank[ranks]
     lay = prop_layout(len(p_props), 1, [key_space_bits])
     return Workload(name, rec, lay, props or [])
+
+
+def serving_layout(n_streams=64, users=1000, bindings=100_000):
+    cot, kp = _type_table(4, [0, 1, 2, 3], 0b11)
+    return Layout(16, 4, 1, [8, 12], [4, 4],
+                  [max(1, int(users - 1).bit_length()), max(1, int(bindings - 1).bit_length())], cot, kp,
+                  [{"issue"}, set(), {"done"}, set()],
+                  {0: "issue", 1: "progress", 2: "done", 3: "other"})
+
+
+def gen_serving_pool(stream, events, users=1000, bindings=100_000, zipf_s=1.2, seed=0x14112239 + 5):
+    """Event pool of one log stream: `bindings` (user, req) pairs whose users
+    follow Zipf(zipf_s) shares over `users` users; every event picks a
+    binding uniformly; types issue/progress/done/other with probabilities
+    0.3/0.3/0.35/0.05.  16-byte records in stream order."""
+    rng = np.random.Generator(np.random.PCG64(seed + 7919 * stream))
+    user_of = zipf_ranks(rng, bindings, users, zipf_s).astype(np.uint32)
+    req_ids = rng.permutation(bindings).astype(np.uint32)
+    b = rng.integers(0, bindings, size=events)
+    rec = np.zeros(events, dtype=REC16)
+    rec["ts"] = np.arange(events, dtype=np.uint32)
+    rec["type"] = rng.choice(4, size=events, p=[0.3, 0.3, 0.35, 0.05]).astype(np.uint32)
+    rec["k0"] = user_of[b]
+    rec["k1"] = req_ids[b]
+    return rec
+
+
+def serving_schedule(n_chunks, n_streams=64, offered_events_per_s=2e9, min_chunk=4096, max_chunk=262_144,
+                     seed=0x14112239 + 6):
+    """Open-loop arrivals: chunk sizes log-uniform in [min_chunk, max_chunk],
+    streams uniform, Poisson arrivals at the offered aggregate event rate.
+    Returns (arrival seconds, stream, size) arrays."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sizes = np.floor(np.exp(rng.uniform(np.log(min_chunk), np.log(max_chunk), size=n_chunks))).astype(np.int64)
+    mean = (max_chunk - min_chunk) / (np.log(max_chunk) - np.log(min_chunk))
+    gaps = rng.exponential(mean / offered_events_per_s, size=n_chunks)
+    return np.cumsum(gaps), rng.integers(0, n_streams, size=n_chunks), sizes
+
+
+# Sixteen LTL bodies over {a, b, c} of nesting depth <= 4, drawn by a seeded
+# random search so that their minimal monitors over the 8 event classes have
+# 3 to 16 states (3, 4, 5, ..., 16, plus a second 3- and 5-state one).
+BATCH_FORMULAS = [
+    "G(a -> X b)",
+    "a U (b U c)",
+    "G(a -> X X b)",
+    "X X X a",
+    "(!(X(G(b)))) & ((G(X(c))) -> (c))",
+    "G((X(X(c))) U (G(G(b))))",
+    "(X(X(a))) -> ((X(!(a))) -> (((c) -> (a)) U (G(a))))",
+    "((b) U (((a) U (a)) U (G(a)))) | ((F((c) | (b))) & ((true) & ((c) U (a))))",
+    "(!(X(X(a)))) | (((G(a)) | (F(b))) U (X(G(a))))",
+    "(((X(b)) & (F(a))) | (G((c) -> (b)))) | ((G(X(b))) | (X(G(a))))",
+    "((X(X(c))) -> (G((true) -> (a)))) -> (G(c))",
+    "((!(a)) U (X(!(b)))) U ((G((c) U (c))) | (((c) U (b)) -> (G(b))))",
+    "(((!(a)) U ((a) & (c))) -> ((X(a)) & ((b) U (a)))) U (X(X(b)))",
+    "(!(G(a) | c)) U (X(X(b)))",
+    "F(a & X F a)",
+    "G a | (b U c)",
+]
+BATCH_QUANTS = [("A", ">=", "9/10"), ("E", ">=", 10), ("A", "=", 1), ("E", "<=", 5),
+                ("A", ">", "1/2"), ("E", "=", 3), ("A", "<", "1/4"), ("E", ">", 100)]
+
+
+def batch_properties(n=16):
+    return [PropertySpec(BATCH_FORMULAS[i], [BATCH_QUANTS[i % len(BATCH_QUANTS)]], f"batch{i}") for i in range(n)]
+
+
+def gen_batch(n_traces=4096, min_len=1000, max_len=1_000_000, p_prop=0.3, zipf_s=1.1, seed=0x14112239 + 4,
+              n_props=16):
+    """Many independent traces: lengths log-uniform in [min_len, max_len];
+    three proposition bits, each Bernoulli(p_prop); keys Zipf(zipf_s) over
+    max(16, length // 256) ranks mapped to a permutation of 0..K-1.
+    Returns (Workload of the concatenated records, offsets)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lengths = np.floor(np.exp(rng.uniform(np.log(min_len), np.log(max_len), size=n_traces))).astype(np.int64)
+    offsets = np.concatenate([[0], np.cumsum(lengths)])
+    rec = np.zeros(int(offsets[-1]), dtype=REC16)
+    kmax = 16
+    for t in range(n_traces):
+        L = int(lengths[t])
+        a, b = int(offsets[t]), int(offsets[t + 1])
+        K = max(16, L // 256)
+        kmax = max(kmax, K)
+        ranks = zipf_ranks(rng, L, K, zipf_s, dtype=np.float32)
+        perm = rng.permutation(K).astype(np.uint32)
+        bits = (rng.random((3, L), dtype=np.float32) < p_prop).astype(np.uint32)
+        rec["type"][a:b] = bits[0] | (bits[1] << 1) | (bits[2] << 2)
+        rec["k0"][a:b] = perm[ranks]
+        rec["ts"][a:b] = np.arange(L, dtype=np.uint32)
+    lay = prop_layout(3, 1, [max(1, int(kmax - 1).bit_length())])
+    lay.type_bytes = 1          # the type values fit one byte: no exclusion bit in the sort key
+    return Workload("batch", rec, lay, batch_properties(n_props)), offsets
+
+
+# One long trace, three properties evaluated in one pass; the monitors have 3,
+# 8 and 16 states (the last two bodies come from the same seeded search).
+LARGE_PROPERTIES = [
+    PropertySpec("G(a -> X b)", [("A", ">=", "99/100")], "large-3"),
+    PropertySpec("G((X(X(c))) U (G(G(b))))", [("E", ">=", 100_000)], "large-8"),
+    PropertySpec("(!(G(a) | c)) U (X(X(b)))", [("A", ">", "1/4")], "large-16"),
+]
+
+
+def gen_large_trace(n_events=500_000_000, n_keys=1_000_000, zipf_s=1.1, p_props=(0.02, 0.9, 0.5),
+                    seed=0x14112239 + 3, block=1 << 24):
+    """A single long trace of 16-byte records: proposition bits a, b, c drawn
+    independently; keys Zipf(zipf_s) over n_keys ranks, each rank mapped to a
+    distinct random 32-bit value.  Generated in blocks to bound memory."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    vals = np.unique(rng.integers(0, 1 << 32, size=int(n_keys * 1.1) + 64, dtype=np.uint64))
+    while vals.size < n_keys:
+        vals = np.unique(np.concatenate([vals, rng.integers(0, 1 << 32, size=n_keys, dtype=np.uint64)]))
+    key_of_rank = rng.permutation(vals)[:n_keys].astype(np.uint32)
+    w = np.arange(1, n_keys + 1, dtype=np.float64) ** (-zipf_s)
+    cdf = (np.cumsum(w) / w.sum()).astype(np.float32)
+    rec = np.zeros(n_events, dtype=REC16)
+    for a in range(0, n_events, block):
+        b = min(n_events, a + block)
+        L = b - a
+        ranks = np.minimum(np.searchsorted(cdf, rng.random(L, dtype=np.float32), side="right"), n_keys - 1)
+        t = np.zeros(L, dtype=np.uint32)
+        for i, p in enumerate(p_props):
+            t |= (rng.random(L, dtype=np.float32) < p).astype(np.uint32) << i
+        rec["type"][a:b] = t
+        rec["k0"][a:b] = key_of_rank[ranks]
+        rec["ts"][a:b] = np.arange(a, b, dtype=np.uint64).astype(np.uint32)
+    lay = prop_layout(3, 1, [32])
+    lay.type_bytes = 1
+    return Workload("large", rec, lay, list(LARGE_PROPERTIES))
+
+
+def gen_large_trace_device(n_events=500_000_000, n_keys=1_000_000, zipf_s=1.1, p_props=(0.02, 0.9, 0.5),
+                           seed=0x14112239 + 3, device="cuda:0", block=1 << 26):
+    """The gen_large_trace workload drawn directly in device memory with
+    torch's seeded generator (for sizes where host generation is slow).
+    Returns (Workload with records=None, device uint8 tensor of the records)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    vals = torch.unique(torch.randint(0, 1 << 32, (int(n_keys * 1.1) + 64,), generator=g, device=device,
+                                      dtype=torch.int64))
+    while vals.numel() < n_keys:
+        more = torch.randint(0, 1 << 32, (n_keys,), generator=g, device=device, dtype=torch.int64)
+        vals = torch.unique(torch.cat([vals, more]))
+    key_of_rank = vals[torch.randperm(vals.numel(), generator=g, device=device)[:n_keys]]
+    w = torch.arange(1, n_keys + 1, dtype=torch.float64, device=device) ** (-zipf_s)
+    cdf = torch.cumsum(w, 0) / w.sum()
+    rec = torch.empty((n_events, 4), dtype=torch.int32, device=device)
+    for a in range(0, n_events, block):
+        b = min(n_events, a + block)
+        L = b - a
+        ranks = torch.clamp(torch.searchsorted(cdf, torch.rand(L, generator=g, device=device, dtype=torch.float64),
+                                               right=True), max=n_keys - 1)
+        t = torch.zeros(L, dtype=torch.int32, device=device)
+        for i, p in enumerate(p_props):
+            t |= (torch.rand(L, generator=g, device=device) < p).to(torch.int32) << i
+        rec[a:b, 0] = torch.arange(a, b, device=device, dtype=torch.int64).to(torch.int32)
+        rec[a:b, 1] = t
+        rec[a:b, 2] = key_of_rank[ranks].to(torch.int64).to(torch.int32)
+        rec[a:b, 3] = 0
+    lay = prop_layout(3, 1, [32])
+    lay.type_bytes = 1
+    return Workload("large", None, lay, list(LARGE_PROPERTIES)), rec.view(torch.uint8).reshape(-1)

@@ -119,3 +119,23 @@ def test_sort_tile_variants(variant):
     torch.cuda.synchronize()
     ctx.close()
     compare_full(r, evaluate_workload(wl), len(ids), 2)
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("case", ["users", "one_cluster", "wide"])
+def test_scan_tile_variants(variant, case):
+    import torch
+    from paper_1411_2239_amd import lib
+    if case == "users":
+        wl = W.gen_user_requests(n_events=500_000, n_users=900, seed=41)
+    elif case == "one_cluster":
+        wl = prop_workload(70_000, 1, [1], seed=42, n_props=3)
+    else:
+        wl = prop_workload(90_000, 2, [30, 40], seed=43, n_props=11)
+    print(f"[case] scan variant {variant} {case}", flush=True)
+    ctx, ids, rec = lib.open_workload(wl)
+    ctx.set_option(lib.OPT_SCAN_TILE, variant)
+    r = ctx.eval(rec, ids, instances=True, nodes=True)
+    torch.cuda.synchronize()
+    ctx.close()
+    compare_full(r, evaluate_workload(wl), len(ids), wl.layout.n_keys)

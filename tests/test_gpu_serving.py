@@ -157,3 +157,31 @@ def test_binding_capacity_is_reported():
     assert e.value.status == lib.ECAPACITY
     grp.close()
     ctx.close()
+
+
+def test_push_chunks_from_separate_buffers():
+    import torch
+    traces = _stream_traces("users", 4, 3000, 300)
+    ctx, ids, _ = lib.open_workload(traces[0])
+    rb = traces[0].layout.record_bytes
+    grp = lib.StreamGroup(ctx, ids, max_streams=4, max_bindings=4096, max_batch=12000)
+    dev = [torch.from_numpy(np.ascontiguousarray(t.raw())).to("cuda:0") for t in traces]
+    rng = np.random.default_rng(1)
+    pos = [0] * 4
+    for k in range(5):
+        ptrs, sizes, streams = [], [], []
+        for _ in range(6):
+            s = int(rng.integers(0, 4))
+            size = min(int(rng.integers(1, 900)), 3000 - pos[s])
+            ptrs.append(dev[s].data_ptr() + pos[s] * rb)
+            sizes.append(size)
+            streams.append(s)
+            pos[s] += size
+        grp.push_chunks(ptrs, sizes, streams)
+        verdict, counts, bindings = grp.read()
+        for s in range(4):
+            o = evaluate_workload(traces[s], records=traces[s].records[:pos[s]])
+            assert np.array_equal(verdict[s], o.root_verdict) and np.array_equal(counts[s], o.root_counts.astype(np.int64))
+            assert bindings[s] == o.inst_keys.shape[0]
+    grp.close()
+    ctx.close()
