@@ -283,8 +283,8 @@ int32_t ltl4c_group_restore(ltl4c_ctx *ctx, int32_t group, const void *host, uin
  * 0 = 256 threads x 16 words, 1 = 512 x 16 (default), 2 = 256 x 24,
  * 3 = 256 x 8, 4 = 512 x 8. */
 enum { LTL4C_OPT_SORT_TILE = 0, LTL4C_OPT_SCAN_TILE = 1 };
-/* LTL4C_OPT_SCAN_TILE: map-scan tile of 0 = 256 threads x 16 words (default)
- * or 1 = 512 x 16. */
+/* LTL4C_OPT_SCAN_TILE: map-scan tile of 0 = 256 threads x 16 words or
+ * 1 = 512 x 16 (default). */
 int32_t ltl4c_set_option(ltl4c_ctx *ctx, int32_t option, int64_t value);
 
 /* ---- profiling: per-kernel time of the enqueued work ------------------- */

@@ -43,7 +43,7 @@ def test_large_trace_full_size_sampled():
         assert np.array_equal(np.bincount(iv[p], minlength=6), rc[p])
     assert np.all(np.diff(keys.astype(np.int64)) > 0)
     # a key partition, evaluated by the oracle on exactly its events
-    rv = rec.view(-1, 4)
+    rv = rec.view(torch.int32).view(-1, 4)
     sel = (rv[:, 2].to(torch.int64) & 0xFFFFFFFF) % 128 == 0
     part = rv[sel].cpu().numpy().view(np.uint8).reshape(-1)
     o = evaluate_workload(wl, records=part)
