@@ -18,8 +18,6 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;     // 4096 words per tile
 constexpr int kCountThreads = 256;
-constexpr int kCountItems = 16;
-constexpr int kCountTile = kCountThreads * kCountItems;
 constexpr int kCountWindow = 64;     // nodes kept in LDS per counting tile
 constexpr uint64_t kIdentityMap = 0xFEDCBA9876543210ull;
 constexpr uint32_t kSpinLimit = 1u << 22;   // bounded waits in decoupled look-back
@@ -33,6 +31,8 @@ struct PropDev {
     uint8_t delta[kStates * 16];     // delta[q * 16 + c]
     uint8_t label[kStates];
     uint64_t colmap[16];             // class c -> packed map q -> delta(q, c); lanes >= n_states identity
+    uint64_t bcolmap[16];            // the same with one byte per state (monitors of at most 8 states)
+    uint32_t blabel;                 // label of state q in bits 4q..4q+3 (at most 8 states)
     uint32_t q0, n_states;
     uint32_t kind[kMaxLevels], op[kMaxLevels], num[kMaxLevels], den[kMaxLevels];
 };
@@ -108,10 +108,14 @@ struct ScanArgs {
     uint64_t inst_limit;                 // instances with an id below this are written
     uint64_t* inst_keys;                 // optional [inst_limit]
     uint32_t* node_start[kMaxLevels];    // level m: first child of node j
+    uint32_t* node_counts[kMaxLevels];   // level m: [p][node_stride][6], zeroed when node j is created
+    uint64_t node_stride[kMaxLevels];
+    uint32_t* inst_parent;               // optional [inst_limit]: level n_levels-1 node of each instance
     uint64_t* node_keys[kMaxLevels];     // optional
     uint64_t node_limit[kMaxLevels];     // nodes with an id below this are written
     ScanTileStatus* status;              // [tiles], zeroed before the launch
     uint32_t emit_state;                 // write final states instead of verdicts
+    uint32_t max_states;                 // largest monitor among the properties
     uint32_t* ticket;
     uint64_t* sizes;                     // [1 + n_levels] written by the last tile
     uint32_t* sizes32;                   // same, 32-bit, for the counting kernels
@@ -125,6 +129,8 @@ struct CountArgs {
     const Plan* plan;
     // children
     const uint32_t* n_children;          // device count of children
+    const uint32_t* child_parent;        // optional: parent node of every child (else found in node_start)
+    uint32_t items;                      // children per thread and tile: 16 (leaves) or 2
     uint64_t child_limit;                // children beyond this were not recorded
     const uint8_t* child_verdict;        // level m+1 == n_levels: instance verdicts [p][child_stride]
     const uint32_t* child_counts;        // otherwise: counts of level m+1 [p][child_stride][6]

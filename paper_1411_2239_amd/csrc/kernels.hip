@@ -251,15 +251,20 @@ __global__ __launch_bounds__(1024) void k_classify(ClassifyArgs a) {
 // one stable radix pass (onesweep: rank in-tile, look back across tiles)
 // ---------------------------------------------------------------------------
 constexpr uint32_t kFlagAgg = 1u << 30, kFlagInc = 2u << 30, kValMask = (1u << 30) - 1;
-constexpr int kSortLookWindow = 1;
+constexpr int kSortLookWindow = 8;
 constexpr int kScanLookWindow = 4;
 
+// 16-item tiles are held to 128 VGPRs (two 512-thread blocks per CU), 8-item
+// tiles to 80 (three)
 template <int THREADS, int ITEMS>
-__global__ __launch_bounds__(THREADS) void k_sort_pass(SortPassArgs a) {
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(ITEMS <= 8 ? 6 : ITEMS <= 16 ? 4 : 2)))
+void k_sort_pass(SortPassArgs a) {
     constexpr int TILE = THREADS * ITEMS;
     constexpr int WAVES = THREADS / 64;
+    static_assert(THREADS >= kRadix, "one thread per bucket");
     __shared__ uint64_t s_keys[TILE];
     __shared__ uint32_t s_wcnt[WAVES][kRadix];
+    __shared__ uint32_t s_hist[kRadix];
     __shared__ uint32_t s_lstart[kRadix];
     __shared__ uint32_t s_gbase[kRadix];
     __shared__ uint32_t s_tmp[2][4];
@@ -267,41 +272,56 @@ __global__ __launch_bounds__(THREADS) void k_sort_pass(SortPassArgs a) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
     for (int i = tid; i < WAVES * kRadix; i += THREADS) (&s_wcnt[0][0])[i] = 0;
+    if (tid < kRadix) s_hist[tid] = 0;
     __syncthreads();
     const uint32_t tile = s_tile;
     const uint64_t base = (uint64_t)tile * TILE;
+    const uint64_t wbase = base + (uint64_t)w * (ITEMS * 64) + lane;   // item r of this lane: wbase + 64 r
+    // items r with 64 r < rem are inside the array
+    const uint32_t rem = wbase < a.n ? (uint32_t)min<uint64_t>(a.n - wbase, ITEMS * 64) : 0u;
     const uint32_t dmask = (1u << a.nbits) - 1u;
     const uint64_t lt = (1ull << lane) - 1ull;
 
     uint64_t key[ITEMS];
-    uint32_t dig[ITEMS];
-    uint32_t rank[ITEMS];
+    uint32_t dr[ITEMS];   // digit in bits 0..7; rank inside the wave from bit 8 on
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
-        const uint64_t idx = base + (uint64_t)w * (ITEMS * 64) + r * 64 + lane;
-        key[r] = idx < a.n ? a.in[idx] : 0ull;
-        dig[r] = (uint32_t)(key[r] >> a.shift) & dmask;
+        key[r] = (uint32_t)r * 64 < rem ? a.in[wbase + (uint64_t)r * 64] : 0ull;
+    }
+    uint32_t h = 0;
+    if (tid < kRadix) h = a.hist[tid];
+    // the tile's bucket counts first: they are published before the ranking,
+    // so that later tiles looking back find them early
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        dr[r] = (uint32_t)(key[r] >> a.shift) & dmask;
+        if ((uint32_t)r * 64 < rem) atomicAdd(&s_hist[dr[r]], 1u);
+    }
+    __syncthreads();
+    uint32_t tot = 0;
+    if (tid < kRadix) {
+        tot = s_hist[tid];
+        st_flag(a.status + (uint64_t)tile * kRadix + tid, (tile == 0 ? kFlagInc : kFlagAgg) | tot);
     }
     // rank inside the wave: lanes with the same digit found by one ballot per
     // digit bit; per-wave counters in LDS carry the count across rounds
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
-        const uint64_t idx = base + (uint64_t)w * (ITEMS * 64) + r * 64 + lane;
-        const bool valid = idx < a.n;
+        const bool valid = (uint32_t)r * 64 < rem;
+        const uint32_t d = dr[r];
         uint64_t m = __ballot(valid);
         for (uint32_t b = 0; b < a.nbits; ++b) {
-            const bool bit = (dig[r] >> b) & 1u;
+            const bool bit = (d >> b) & 1u;
             const uint64_t bb = __ballot(bit);
             m &= bit ? bb : ~bb;
         }
         const uint32_t below = (uint32_t)__popcll(m & lt);
-        const uint32_t prev = s_wcnt[w][dig[r]];
-        rank[r] = prev + below;
-        if (valid && below == 0) s_wcnt[w][dig[r]] = prev + (uint32_t)__popcll(m);
+        const uint32_t prev = s_wcnt[w][d];
+        dr[r] = d | ((prev + below) << 8);
+        if (valid && below == 0) s_wcnt[w][d] = prev + (uint32_t)__popcll(m);
     }
     __syncthreads();
-    // per bucket (threads 0..255): wave offsets, tile count, aggregate, look-back
-    uint32_t tot = 0, h = 0;
+    // per bucket (threads 0..255): wave offsets, tile offset, look-back
     if (tid < kRadix) {
         uint32_t run = 0;
 #pragma unroll
@@ -310,9 +330,6 @@ __global__ __launch_bounds__(THREADS) void k_sort_pass(SortPassArgs a) {
             s_wcnt[ww][tid] = run;
             run += c;
         }
-        tot = run;
-        st_flag(a.status + (uint64_t)tile * kRadix + tid, (tile == 0 ? kFlagInc : kFlagAgg) | tot);
-        h = a.hist[tid];
     }
     uint32_t dummy;
     const uint32_t lstart = block256_excl_scan(tot, s_tmp[0], &dummy);
@@ -320,7 +337,8 @@ __global__ __launch_bounds__(THREADS) void k_sort_pass(SortPassArgs a) {
     if (tid < kRadix) {
         uint32_t prefix = 0;
         if (tile > 0) {
-            // windowed look-back: one round trip fetches kSortLookWindow predecessors
+            // windowed look-back: one round trip fetches kSortLookWindow
+            // predecessors of this bucket (consecutive buckets: coalesced)
             int64_t j = (int64_t)tile - 1;
             uint32_t spins = 0;
             bool done = false;
@@ -330,10 +348,11 @@ __global__ __launch_bounds__(THREADS) void k_sort_pass(SortPassArgs a) {
                 for (int k = 0; k < kSortLookWindow; ++k)
                     sv[k] = j - k >= 0 ? ld_acquire_flag(a.status + (uint64_t)(j - k) * kRadix + tid) : kFlagInc;
                 int used = 0;
+                bool stop = false;
 #pragma unroll
                 for (int k = 0; k < kSortLookWindow; ++k) {
-                    if (done || used < k) continue;          // stop at the first gap
-                    if ((sv[k] >> 30) == 0u) continue;       // not published yet: poll again from here
+                    if (done || stop) continue;
+                    if ((sv[k] >> 30) == 0u) { stop = true; continue; }   // not published yet: poll again from here
                     prefix += sv[k] & kValMask;
                     used = k + 1;
                     if ((sv[k] & ~kValMask) == kFlagInc) done = true;
@@ -356,9 +375,9 @@ __global__ __launch_bounds__(THREADS) void k_sort_pass(SortPassArgs a) {
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
-        const uint64_t idx = base + (uint64_t)w * (ITEMS * 64) + r * 64 + lane;
-        const uint32_t pos = s_lstart[dig[r]] + s_wcnt[w][dig[r]] + rank[r];
-        if (idx < a.n && pos < (uint32_t)TILE) s_keys[pos] = key[r];
+        const uint32_t d = dr[r] & 0xFFu;
+        const uint32_t pos = s_lstart[d] + s_wcnt[w][d] + (dr[r] >> 8);
+        if ((uint32_t)r * 64 < rem && pos < (uint32_t)TILE) s_keys[pos] = key[r];
     }
     __syncthreads();
     const uint32_t tile_n = (uint32_t)min<uint64_t>(TILE, a.n - base);
@@ -375,6 +394,18 @@ __global__ __launch_bounds__(THREADS) void k_sort_pass(SortPassArgs a) {
 // segmented transition-map scan
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t pad_idx(uint32_t i) { return i + (i >> 4); }
+
+// A new level-m node starts with empty counts (its counting runs later).
+__device__ __forceinline__ void zero_node_counts(const ScanArgs& a, int m, uint64_t id) {
+    uint32_t* c = a.node_counts[m];
+    if (!c) return;
+    for (uint32_t p = 0; p < a.n_props; ++p) {
+        uint2* q = reinterpret_cast<uint2*>(c + (p * a.node_stride[m] + id) * 6);
+        q[0] = make_uint2(0u, 0u);
+        q[1] = make_uint2(0u, 0u);
+        q[2] = make_uint2(0u, 0u);
+    }
+}
 
 template <int PMAX, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_scan(ScanArgs a) {
@@ -642,6 +673,7 @@ __global__ __launch_bounds__(THREADS) void k_scan(ScanArgs a) {
                 if (id < a.node_limit[m]) {
                     a.node_start[m][id] = child;
                     if (a.node_keys[m]) a.node_keys[m][id] = x >> a.prefix_shift[m];
+                    zero_node_counts(a, m, id);
                 } else {
                     err |= kErrCapacity;
                 }
@@ -667,6 +699,7 @@ __global__ __launch_bounds__(THREADS) void k_scan(ScanArgs a) {
                             a.inst_verdict[p * a.inst_stride + id] = a.emit_state ? cur[p] : s_label[p][cur[p]];
                 }
                 if (a.inst_keys) a.inst_keys[id] = x >> cb;
+                if (a.inst_parent) a.inst_parent[id] = (L >= 4 ? lvl[3] : L == 3 ? lvl[2] : lvl[1]) - 1u;
             } else {
                 err |= kErrCapacity;
             }
@@ -976,6 +1009,7 @@ __global__ __launch_bounds__(THREADS) void k_scan_wide(ScanArgs a) {
                 if (id < a.node_limit[m]) {
                     a.node_start[m][id] = child;
                     if (a.node_keys[m]) a.node_keys[m][id] = x >> a.prefix_shift[m];
+                    zero_node_counts(a, m, id);
                 } else {
                     err |= kErrCapacity;
                 }
@@ -1010,6 +1044,7 @@ __global__ __launch_bounds__(THREADS) void k_scan_wide(ScanArgs a) {
                         }
                 }
                 if (a.inst_keys) a.inst_keys[id] = x >> cb;
+                if (a.inst_parent) a.inst_parent[id] = (L >= 4 ? lvl[3] : L == 3 ? lvl[2] : lvl[1]) - 1u;
             } else {
                 err |= kErrCapacity;
             }
@@ -1054,6 +1089,367 @@ __global__ __launch_bounds__(THREADS) void k_scan_wide(ScanArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// segmented transition-map scan for monitors of at most 8 states
+// ---------------------------------------------------------------------------
+// A map over at most 8 states is a uint64 whose byte q holds the image of q.
+// The composition g∘f (f applied first) picks, for every byte of f, the byte
+// of g it names: two byte permutes, with no constant-map special cases.  A
+// state steps through one permute as well.
+constexpr uint64_t kByteIdentity = 0x0706050403020100ull;
+
+__device__ __forceinline__ uint64_t bmap_compose(uint64_t g, uint64_t f) {
+    const uint32_t g0 = (uint32_t)g, g1 = (uint32_t)(g >> 32);
+    return (uint64_t)__builtin_amdgcn_perm(g1, g0, (uint32_t)f) |
+           ((uint64_t)__builtin_amdgcn_perm(g1, g0, (uint32_t)(f >> 32)) << 32);
+}
+__device__ __forceinline__ uint32_t bmap_at(uint64_t g, uint32_t q) {
+    return __builtin_amdgcn_perm((uint32_t)(g >> 32), (uint32_t)g, q) & 0xFFu;
+}
+__device__ __forceinline__ uint64_t bmap_const(uint32_t s) { return (uint64_t)s * 0x0101010101010101ull; }
+
+// Look-back records in structure-of-arrays form: row r of the aggregates of
+// tile t is st[r * tiles + t], row r of the inclusive values
+// st[(kScanStatusWords + r) * tiles + t].  Rows 0..3 are the instance / node
+// counts, rows 4 + 2p and 5 + 2p the halves of property p's map, so that the
+// lanes of one wave reading one row of 64 consecutive tiles read one
+// contiguous 512-byte span.  Every word is a 32-bit payload under the
+// validity bit 32, as in the other scan.
+template <int PMAX, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_scan8(ScanArgs a) {
+    constexpr int TILE = THREADS * kScanItems;
+    constexpr int WAVES = THREADS / 64;
+    constexpr int NW = 4 + 2 * PMAX;          // record words in use (at most)
+    __shared__ uint64_t s_w[TILE + TILE / 16 + 1];
+    __shared__ uint64_t s_cm[PMAX][16];
+    __shared__ uint32_t s_q0[PMAX], s_lab[PMAX];
+    __shared__ uint64_t s_wtot[PMAX][WAVES];
+    __shared__ uint32_t s_ctot[4][WAVES];
+    __shared__ uint64_t s_tprefix[PMAX];
+    __shared__ uint64_t s_tagg[PMAX];
+    __shared__ uint32_t s_cagg[4];
+    __shared__ uint32_t s_tcnt[4];
+    __shared__ uint64_t s_prev, s_next;
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_red[2][WAVES];
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const uint32_t P = a.n_props;
+    if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
+    if (tid < (int)(P * 16)) s_cm[tid / 16][tid % 16] = a.plan->prop[tid / 16].bcolmap[tid % 16];
+    if (tid < (int)P) {
+        s_q0[tid] = a.plan->prop[tid].q0;
+        s_lab[tid] = a.plan->prop[tid].blabel;
+    }
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint64_t base = (uint64_t)tile * TILE;
+    const uint64_t kInvalid = ~0ull;
+#pragma unroll
+    for (int r = 0; r < kScanItems; ++r) {
+        const uint64_t idx = base + r * THREADS + tid;
+        s_w[pad_idx(r * THREADS + tid)] = idx < a.n ? a.words[idx] : kInvalid;
+    }
+    if (tid == 0) s_prev = base > 0 ? a.words[base - 1] : kInvalid;
+    if (tid == 1) s_next = base + TILE < a.n ? a.words[base + TILE] : kInvalid;
+    __syncthreads();
+
+    uint64_t wv[kScanItems];
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) wv[j] = s_w[pad_idx(tid * kScanItems + j)];
+    const uint64_t wp = tid == 0 ? s_prev : s_w[pad_idx(tid * kScanItems - 1)];
+    const uint64_t wn = tid == THREADS - 1 ? s_next : s_w[pad_idx(tid * kScanItems + kScanItems)];
+    const bool has_prev = base + (uint64_t)tid * kScanItems > 0;
+    const uint32_t cb = a.cbits, vs = a.valid_shift, L = a.n_levels;
+    const uint32_t cmask = (1u << cb) - 1u;
+
+    // per-event flags as bit masks (excluded events sort last, so the valid
+    // events of a thread are a prefix of its run)
+    uint32_t m_valid = 0, m_head = 0, m_end = 0, m_lvl[kMaxLevels] = {0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const uint64_t x = wv[j];
+        if ((x >> vs) != 0) continue;
+        m_valid |= 1u << j;
+        const uint64_t prv = j == 0 ? wp : wv[j - 1];
+        const bool first = (j == 0 && !has_prev);
+        const uint64_t nxt = j == kScanItems - 1 ? wn : wv[j + 1];
+        if (first || ((prv ^ x) >> cb) != 0) m_head |= 1u << j;
+        if ((nxt >> vs) != 0 || ((nxt ^ x) >> cb) != 0) m_end |= 1u << j;
+#pragma unroll
+        for (int m = 1; m < kMaxLevels; ++m) {
+            if (m >= (int)L) break;
+            if (first || ((prv ^ x) >> a.prefix_shift[m]) != 0) m_lvl[m] |= 1u << j;
+        }
+    }
+    const int n_valid = __popc(m_valid);
+    uint32_t cnt[4];
+    cnt[0] = __popc(m_head);
+#pragma unroll
+    for (int m = 1; m < 4; ++m) cnt[m] = (uint32_t)m < L ? __popc(m_lvl[m]) : 0u;
+
+    // run summaries: a head restarts the monitor from q0
+    uint64_t excl[PMAX];
+#pragma unroll
+    for (int p = 0; p < PMAX; ++p) {
+        uint64_t f = kByteIdentity;
+        if (p < (int)P) {
+            const uint64_t start = bmap_const(s_q0[p]);
+#pragma unroll
+            for (int j = 0; j < kScanItems; ++j) {
+                if (j >= n_valid) break;
+                const uint64_t cm = s_cm[p][(uint32_t)wv[j] & cmask];
+                f = bmap_compose(cm, ((m_head >> j) & 1u) ? start : f);
+            }
+        }
+        // wave-inclusive scan of the summaries in lane order
+        uint64_t v = f;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint64_t o = shfl_up64(v, off);
+            if (lane >= off) v = bmap_compose(v, o);
+        }
+        const uint64_t e = shfl_up64(v, 1);
+        excl[p] = lane == 0 ? kByteIdentity : e;
+        if (lane == 63) s_wtot[p][w] = v;
+    }
+    uint32_t cexcl[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t incl = wave_incl_scan_u32(cnt[k]);
+        cexcl[k] = incl - cnt[k];
+        if (lane == 63) s_ctot[k][w] = incl;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < PMAX; ++p) {
+        if (p >= (int)P) continue;
+        uint64_t pre = kByteIdentity;
+        for (int i = 0; i < w; ++i) pre = bmap_compose(s_wtot[p][i], pre);
+        excl[p] = bmap_compose(excl[p], pre);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        uint32_t pre = 0;
+        for (int i = 0; i < w; ++i) pre += s_ctot[k][i];
+        cexcl[k] += pre;
+    }
+    if (tid < (int)P) {
+        uint64_t t = kByteIdentity;
+        for (int i = 0; i < WAVES; ++i) t = bmap_compose(s_wtot[tid][i], t);
+        s_tagg[tid] = t;
+    }
+    if (tid >= 32 && tid < 36) {
+        const int k = tid - 32;
+        uint32_t sum = 0;
+        for (int i = 0; i < WAVES; ++i) sum += s_ctot[k][i];
+        s_cagg[k] = sum;
+    }
+    __syncthreads();
+
+    // publish the aggregate (tile 0: the inclusive value), then look back
+    // with one lane per predecessor tile (wave 0)
+    if (w == 0) {
+        const uint32_t n_tiles = (uint32_t)((a.n + TILE - 1) / TILE);
+        uint64_t* st = reinterpret_cast<uint64_t*>(a.status);
+        const uint32_t nw = 4 + 2 * P;
+        const uint64_t kValid = 1ull << 32;
+        auto payload = [&](uint32_t r, const uint64_t* maps, const uint32_t* cnts) -> uint32_t {
+            if (r < 4) return cnts[r];
+            const uint64_t m = maps[(r - 4) >> 1];
+            return (r & 1u) ? (uint32_t)(m >> 32) : (uint32_t)m;
+        };
+        if (lane < (int)nw) {
+            const uint32_t row = (tile == 0 ? kScanStatusWords : 0) + lane;
+            __hip_atomic_store(st + (uint64_t)row * n_tiles + tile, kValid | payload(lane, s_tagg, s_cagg),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        uint64_t acc[PMAX];
+        uint32_t accc[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int p = 0; p < PMAX; ++p) acc[p] = kByteIdentity;
+        int64_t j = (int64_t)tile - 1;
+        uint32_t spins = 0;
+        while (j >= 0) {
+            const int64_t t = j - lane;
+            uint64_t vi[NW], va[NW];
+            bool inc_ok = true, agg_ok = true;
+#pragma unroll
+            for (int r = 0; r < NW; ++r) {
+                vi[r] = va[r] = kValid;
+                if (r < (int)nw && t >= 0) {
+                    vi[r] = __hip_atomic_load(st + (uint64_t)(kScanStatusWords + r) * n_tiles + t, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                    va[r] = __hip_atomic_load(st + (uint64_t)r * n_tiles + t, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+                }
+                inc_ok = inc_ok && (vi[r] & kValid);
+                agg_ok = agg_ok && (va[r] & kValid);
+            }
+            // lanes past tile 0 read as inclusive identities; tile 0 itself
+            // only ever publishes an inclusive record
+            const uint64_t incm = __ballot(inc_ok);
+            const uint64_t nrm = __ballot(!inc_ok && !agg_ok);
+            const int first_inc = incm ? __ffsll((unsigned long long)incm) - 1 : 64;
+            const int first_nr = nrm ? __ffsll((unsigned long long)nrm) - 1 : 64;
+            const bool done = first_inc < first_nr;
+            const int take = done ? first_inc + 1 : first_nr;
+            const bool mine = lane < take;
+            // fold lanes [0, take): nearest tile last applied
+            uint64_t m[PMAX];
+#pragma unroll
+            for (int p = 0; p < PMAX; ++p) {
+                const uint32_t lo = (uint32_t)(inc_ok ? vi[4 + 2 * p] : va[4 + 2 * p]);
+                const uint32_t hi = (uint32_t)(inc_ok ? vi[5 + 2 * p] : va[5 + 2 * p]);
+                m[p] = (mine && p < (int)P) ? ((uint64_t)lo | ((uint64_t)hi << 32)) : kByteIdentity;
+            }
+            uint32_t c[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) c[k] = mine ? (uint32_t)(inc_ok ? vi[k] : va[k]) : 0u;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+#pragma unroll
+                for (int p = 0; p < PMAX; ++p) {
+                    const uint64_t o = __shfl_down(m[p], off, 64);
+                    if (lane + off < 64) m[p] = bmap_compose(m[p], o);
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t o = __shfl_down(c[k], off, 64);
+                    if (lane + off < 64) c[k] += o;
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < PMAX; ++p) acc[p] = bmap_compose(acc[p], __shfl(m[p], 0, 64));
+#pragma unroll
+            for (int k = 0; k < 4; ++k) accc[k] += __shfl(c[k], 0, 64);
+            j -= take;
+            if (done) break;
+            if (take == 0) {
+                if (++spins > kSpinLimit) {
+                    if (lane == 0) atomicOr(a.err, kErrSpin);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        if (tile > 0) {
+            uint64_t incl[PMAX];
+            uint32_t inclc[4];
+#pragma unroll
+            for (int p = 0; p < PMAX; ++p) incl[p] = p < (int)P ? bmap_compose(s_tagg[p], acc[p]) : kByteIdentity;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) inclc[k] = accc[k] + s_cagg[k];
+            if (lane < (int)nw)
+                __hip_atomic_store(st + (uint64_t)(kScanStatusWords + lane) * n_tiles + tile,
+                                   kValid | payload(lane, incl, inclc), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (lane < (int)P) s_tprefix[lane] = acc[lane];
+        if (lane < 4) s_tcnt[lane] = accc[lane];
+    }
+    __syncthreads();
+
+    // second walk: final state at every instance end; numbering of nodes
+    uint32_t cur[PMAX];
+#pragma unroll
+    for (int p = 0; p < PMAX; ++p)
+        cur[p] = p < (int)P ? bmap_at(bmap_compose(excl[p], s_tprefix[p]), 0) : 0u;
+    uint32_t inst = s_tcnt[0] + cexcl[0];
+    uint32_t lvl[4];
+#pragma unroll
+    for (int m = 1; m < 4; ++m) lvl[m] = s_tcnt[m] + cexcl[m];
+    // staging in the word buffer (free now): verdict bytes [P][TILE + 1],
+    // then parent ids [TILE + 1]
+    uint8_t* s_iv = reinterpret_cast<uint8_t*>(s_w);
+    constexpr uint32_t kIvStride = TILE + 1;
+    static_assert(PMAX * kIvStride + 4 * kIvStride + 4 <= sizeof(s_w), "staging fits the word buffer");
+    uint32_t* s_par = reinterpret_cast<uint32_t*>(s_iv + ((PMAX * kIvStride + 3) & ~3u));
+    const uint32_t id_base = s_tcnt[0];
+    uint32_t my_lo = 0xFFFFFFFFu, my_hi = 0u;
+    uint32_t err = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        if (j >= n_valid) break;
+        const uint64_t x = wv[j];
+        const uint32_t c = (uint32_t)x & cmask;
+        if ((m_head >> j) & 1u) {
+            ++inst;
+#pragma unroll
+            for (int p = 0; p < PMAX; ++p) cur[p] = p < (int)P ? s_q0[p] : 0u;
+#pragma unroll
+            for (int m = kMaxLevels - 1; m >= 1; --m) {
+                if (m >= (int)L || !((m_lvl[m] >> j) & 1u)) continue;
+                ++lvl[m];
+                const uint64_t id = lvl[m] - 1;
+                const uint32_t child = m == (int)L - 1 ? inst - 1 : lvl[m < 3 ? m + 1 : 3] - 1;
+                if (id < a.node_limit[m]) {
+                    a.node_start[m][id] = child;
+                    if (a.node_keys[m]) a.node_keys[m][id] = x >> a.prefix_shift[m];
+                    zero_node_counts(a, m, id);
+                } else {
+                    err |= kErrCapacity;
+                }
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < PMAX; ++p)
+            if (p < (int)P) cur[p] = bmap_at(s_cm[p][c], cur[p]);
+        if ((m_end >> j) & 1u) {
+            const uint64_t id = inst - 1;
+            if (id < a.inst_limit) {
+                const uint32_t slot = (uint32_t)id + 1u - id_base;
+#pragma unroll
+                for (int p = 0; p < PMAX; ++p)
+                    if (p < (int)P)
+                        s_iv[p * kIvStride + slot] = a.emit_state ? cur[p] : (s_lab[p] >> (4 * cur[p])) & 15u;
+                if (L >= 2) s_par[slot] = (L >= 4 ? lvl[3] : L == 3 ? lvl[2] : lvl[1]) - 1u;
+                my_lo = min(my_lo, (uint32_t)id);
+                my_hi = max(my_hi, (uint32_t)id + 1u);
+                if (a.inst_keys) a.inst_keys[id] = x >> cb;
+            } else {
+                err |= kErrCapacity;
+            }
+        }
+    }
+    if (err) atomicOr(a.err, err);
+    // the instances ending in this tile have consecutive ids: write their
+    // verdicts contiguously from LDS
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        my_lo = min(my_lo, (uint32_t)__shfl_xor(my_lo, off, 64));
+        my_hi = max(my_hi, (uint32_t)__shfl_xor(my_hi, off, 64));
+    }
+    if (lane == 0) {
+        s_red[0][w] = my_lo;
+        s_red[1][w] = my_hi;
+    }
+    __syncthreads();
+    uint32_t lo = s_red[0][0], hi = s_red[1][0];
+    for (int i = 1; i < WAVES; ++i) {
+        lo = min(lo, s_red[0][i]);
+        hi = max(hi, s_red[1][i]);
+    }
+    if (lo < hi) {
+        const uint32_t cnt_iv = hi - lo, slot0 = lo + 1u - id_base;
+        for (uint32_t p = 0; p < P; ++p)
+            for (uint32_t i = tid; i < cnt_iv; i += THREADS)
+                a.inst_verdict[p * a.inst_stride + lo + i] = s_iv[p * kIvStride + slot0 + i];
+        if (a.inst_parent)
+            for (uint32_t i = tid; i < cnt_iv; i += THREADS) a.inst_parent[lo + i] = s_par[slot0 + i];
+    }
+    // the thread holding the last event publishes the totals
+    const uint64_t my0 = base + (uint64_t)tid * kScanItems;
+    if (my0 <= a.n - 1 && a.n - 1 < my0 + kScanItems) {
+#pragma unroll
+        for (int m = 0; m < kMaxLevels; ++m) {
+            if (m >= (int)L) break;
+            const uint32_t tot = s_tcnt[m] + cexcl[m] + cnt[m];
+            a.sizes[m] = tot;
+            a.sizes32[m] = tot;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // counting for one level
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t node_of(const uint32_t* start, uint32_t nn, uint32_t c) {
@@ -1066,6 +1462,41 @@ __device__ __forceinline__ uint32_t node_of(const uint32_t* start, uint32_t nn, 
     return lo;
 }
 
+// Children are read in strided order (consecutive threads take consecutive
+// children; all loads of a tile are issued before any is used) and counted
+// into an LDS window of kCountWindow parents; a wave whose children all have
+// one parent (always true at the root) counts by six ballots instead of
+// per-child atomics.
+__device__ __forceinline__ void count_child(const CountArgs& a, uint32_t* s_cnt, uint32_t p, uint32_t lo, uint32_t nn,
+                                            bool valid, uint32_t node, uint32_t b) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t vm = __ballot(valid);
+    if (vm == 0) return;
+    const uint32_t node0 = __shfl(node, __ffsll((unsigned long long)vm) - 1, 64);
+    if (__all(!valid || node == node0)) {
+        uint32_t mine = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < 6; ++q) {
+            const uint32_t nq = (uint32_t)__popcll(__ballot(valid && b == q));
+            if (lane == (int)q) mine = nq;
+        }
+        if (lane < 6 && mine) {
+            const uint32_t slot = node0 - lo;
+            if (slot < (uint32_t)kCountWindow)
+                atomicAdd(&s_cnt[(p * kCountWindow + slot) * 6 + lane], mine);
+            else if (node0 < nn)
+                atomicAdd(&a.counts[((uint64_t)p * a.stride + node0) * 6 + lane], mine);
+        }
+    } else if (valid && b < 6u) {
+        const uint32_t slot = node - lo;
+        if (slot < (uint32_t)kCountWindow)
+            atomicAdd(&s_cnt[(p * kCountWindow + slot) * 6 + b], 1u);
+        else if (node < nn)
+            atomicAdd(&a.counts[((uint64_t)p * a.stride + node) * 6 + b], 1u);
+    }
+}
+
+template <int ITEMS>
 __global__ __launch_bounds__(kCountThreads) void k_count(CountArgs a) {
     __shared__ uint32_t s_cnt[kMaxProps * kCountWindow * 6];
     __shared__ uint32_t s_lo;
@@ -1076,39 +1507,47 @@ __global__ __launch_bounds__(kCountThreads) void k_count(CountArgs a) {
     const uint32_t nch = (uint32_t)min<uint64_t>(nch_all, a.child_limit);
     const uint32_t nn = (uint32_t)min<uint64_t>(nn_all, a.level == 0 ? 1ull : a.node_limit);
     const bool leaves = a.level + 1 == a.n_levels;
-    const uint32_t ntiles = (nch + kCountTile - 1) / kCountTile;
+    constexpr uint32_t kTile = kCountThreads * ITEMS;
+    const uint32_t ntiles = (nch + kTile - 1) / kTile;
     if (blockIdx.x == 0 && tid == 0 && (nch < nch_all || nn < nn_all)) atomicOr(a.err, kErrCapacity);
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint32_t c0 = tile * kCountTile;
+        const uint32_t c0 = tile * kTile;
         for (uint32_t i = tid; i < P * kCountWindow * 6; i += kCountThreads) s_cnt[i] = 0;
-        if (tid == 0) s_lo = a.level == 0 ? 0u : node_of(a.node_start, nn, c0);
+        if (tid == 0)
+            s_lo = a.level == 0 ? 0u : a.child_parent ? a.child_parent[c0] : node_of(a.node_start, nn, c0);
+        uint32_t node[ITEMS];
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            const uint32_t c = c0 + k * kCountThreads + tid;
+            node[k] = 0;
+            if (c < nch && a.level > 0) node[k] = a.child_parent ? a.child_parent[c] : node_of(a.node_start, nn, c);
+        }
         __syncthreads();
         const uint32_t lo = s_lo;
-        const uint32_t cbeg = c0 + tid * kCountItems;
-        if (cbeg < nch) {
-            const uint32_t cend = min(cbeg + kCountItems, nch);
-            uint32_t node = a.level == 0 ? 0u : node_of(a.node_start, nn, cbeg);
-            for (uint32_t c = cbeg; c < cend; ++c) {
-                if (a.level > 0)
-                    while (node + 1 < nn && a.node_start[node + 1] <= c) ++node;
-                for (uint32_t p = 0; p < P; ++p) {
-                    uint32_t b;
+        for (uint32_t p = 0; p < P; ++p) {
+            uint32_t b[ITEMS];
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) {
+                const uint32_t c = c0 + k * kCountThreads + tid;
+                b[k] = 6u;
+                if (c < nch) {
                     if (leaves) {
-                        b = a.child_verdict[p * a.child_stride + c];
+                        b[k] = a.child_verdict[p * a.child_stride + c];
                     } else {
-                        b = valuate(a.plan->prop[p], (int)a.level + 1, a.child_counts + (p * a.child_stride + c) * 6);
-                        if (a.child_verdict_out) a.child_verdict_out[p * a.child_stride + c] = (uint8_t)b;
+                        b[k] = valuate(a.plan->prop[p], (int)a.level + 1, a.child_counts + (p * a.child_stride + c) * 6);
+                        if (a.child_verdict_out) a.child_verdict_out[p * a.child_stride + c] = (uint8_t)b[k];
                     }
-                    if (b > 5u) {
-                        atomicOr(a.err, kErrSpin);
-                        continue;
-                    }
-                    const uint32_t slot = node - lo;
-                    if (slot < (uint32_t)kCountWindow)
-                        atomicAdd(&s_cnt[(p * kCountWindow + slot) * 6 + b], 1u);
-                    else if (node < nn)
-                        atomicAdd(&a.counts[((uint64_t)p * a.stride + node) * 6 + b], 1u);
                 }
+            }
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) {
+                const uint32_t c = c0 + k * kCountThreads + tid;
+                const bool valid = c < nch;
+                if (valid && b[k] > 5u) {
+                    atomicOr(a.err, kErrSpin);
+                    b[k] = 6u;
+                }
+                count_child(a, s_cnt, p, lo, nn, valid, node[k], b[k]);
             }
         }
         __syncthreads();
@@ -1122,7 +1561,6 @@ __global__ __launch_bounds__(kCountThreads) void k_count(CountArgs a) {
         __syncthreads();
     }
 }
-
 __global__ void k_finalize(FinalizeArgs a) {
     const uint32_t p = threadIdx.x;
     if (p <= a.n_levels) a.sizes_out[p] = p < a.n_levels ? a.sizes_ws[p] : 0ull;
@@ -1385,6 +1823,15 @@ hipError_t launch_sort_pass(const SortPassArgs& a, int variant, hipStream_t s) {
 template <int T>
 static void launch_scan_t(const ScanArgs& a, hipStream_t s) {
     const uint32_t tiles = (a.n + T * kScanItems - 1) / (T * kScanItems);
+    if (a.max_states <= 8 && a.n_props <= 4) {
+        if (a.n_props <= 1)
+            hipLaunchKernelGGL((k_scan8<1, T>), dim3(tiles), dim3(T), 0, s, a);
+        else if (a.n_props <= 2)
+            hipLaunchKernelGGL((k_scan8<2, T>), dim3(tiles), dim3(T), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_scan8<4, T>), dim3(tiles), dim3(T), 0, s, a);
+        return;
+    }
     if (a.n_props <= 1)
         hipLaunchKernelGGL((k_scan<1, T>), dim3(tiles), dim3(T), 0, s, a);
     else if (a.n_props <= 2)
@@ -1404,9 +1851,13 @@ hipError_t launch_scan(const ScanArgs& a, int variant, hipStream_t s) {
 }
 
 hipError_t launch_count(const CountArgs& a, hipStream_t s) {
-    const uint64_t want = (a.child_limit + kCountTile - 1) / kCountTile;
-    const uint32_t blocks = (uint32_t)(want < 1024 ? (want ? want : 1) : 1024);
-    hipLaunchKernelGGL(k_count, dim3(blocks), dim3(kCountThreads), 0, s, a);
+    const uint64_t tile = (uint64_t)kCountThreads * (a.items >= 16 ? 16 : 2);
+    const uint64_t want = (a.child_limit + tile - 1) / tile;
+    const uint32_t blocks = (uint32_t)(want < 2048 ? (want ? want : 1) : 2048);
+    if (a.items >= 16)
+        hipLaunchKernelGGL(k_count<16>, dim3(blocks), dim3(kCountThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_count<2>, dim3(blocks), dim3(kCountThreads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -117,7 +117,7 @@ struct WsLayout {
     uint64_t zero_off, zero_words;
     uint64_t hist_off, sort_ticket_off, scan_ticket_off, root_counts_off, sizes32_off, sizes64_off;
     uint64_t sort_status_off, scan_status_off;
-    uint64_t words_a_off, words_b_off, inst_verdict_off;
+    uint64_t words_a_off, words_b_off, inst_verdict_off, inst_parent_off;
     uint64_t node_start_off[kMaxLevels], counts_off[kMaxLevels];
     uint64_t cap_node[kMaxLevels];
     uint32_t tiles_sort, tiles_scan;
@@ -148,6 +148,11 @@ WsLayout plan_workspace(const ltl4c_layout& L, const Geometry& g, uint64_t n, ui
     w.words_a_off = off;   off = align256(off + n * 8);
     w.words_b_off = off;   off = align256(off + n * 8);
     w.inst_verdict_off = off; off = align256(off + (uint64_t)P * n);
+    w.inst_parent_off = 0;
+    if (g.n_levels >= 2) {
+        w.inst_parent_off = off;
+        off = align256(off + 4 * n);
+    }
     (void)L;
     for (uint32_t m = 1; m < g.n_levels; ++m) {
         uint64_t cap = n;
@@ -199,7 +204,14 @@ PropDev make_prop(const MonitorHost& M, const ltl4c_property& p, uint32_t shift 
             m |= to << (4 * q);
         }
         d.colmap[c] = m;
+        uint64_t b = 0;
+        for (uint32_t q = 0; q < 8; ++q) {
+            uint64_t to = (c < M.n_classes && q < M.n_states) ? M.delta[q * M.n_classes + c] : q;
+            b |= (to & 0xFF) << (8 * q);
+        }
+        d.bcolmap[c] = b;
     }
+    for (uint32_t q = 0; q < M.n_states && q < 8; ++q) d.blabel |= (uint32_t)(M.label[q] & 15) << (4 * q);
     d.q0 = M.q0;
     d.n_states = M.n_states;
     if (shift) {
@@ -658,8 +670,15 @@ int32_t ltl4c_workspace_bytes(ltl4c_ctx* ctx, uint64_t n_events, const int32_t* 
 // The evaluation pipeline after validation: zero, classify, radix passes,
 // scan, counting per level, finalize.  g.n_levels tree levels; when a chunk
 // table is given the chunk index (a trace id) is the top key.
+static uint32_t max_states_of(const ltl4c_ctx* ctx, const int32_t* props, int32_t n_props) {
+    uint32_t m = 0;
+    for (int32_t i = 0; i < n_props; ++i)
+        m = std::max(m, ctx->monitors[ctx->props[props[i]].monitor].n_states);
+    return m;
+}
+
 static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, void* d_ws, const void* d_records,
-                         uint64_t n, const Plan* plan, uint32_t P, const uint32_t* chunk_off,
+                         uint64_t n, const Plan* plan, uint32_t P, uint32_t max_states, const uint32_t* chunk_off,
                          const uint32_t* chunk_stream, uint32_t n_chunks, const ltl4c_result* out) {
     const ltl4c_layout& L = ctx->layout;
     const uint32_t NL = g.n_levels;
@@ -716,6 +735,7 @@ static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, v
         for (uint32_t m = 1; m < NL; ++m) sa.prefix_shift[m] = g.cbits + (g.key_bits_total - g.prefix_bits[m]);
         sa.valid_shift = g.cbits + g.key_bits_total;
         sa.n_props = P;
+        sa.max_states = max_states;
         sa.plan = plan;
         sa.inst_verdict = inst_verdict;
         sa.inst_stride = inst_stride;
@@ -725,7 +745,11 @@ static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, v
             sa.node_start[m] = node_start[m];
             sa.node_keys[m] = out->node_keys[m];
             sa.node_limit[m] = node_limit[m];
+            sa.node_counts[m] = node_counts[m];
+            sa.node_stride[m] = node_stride[m];
         }
+        uint32_t* inst_parent = NL >= 2 ? reinterpret_cast<uint32_t*>(ws + w.inst_parent_off) : nullptr;
+        sa.inst_parent = inst_parent;
         sa.status = scan_status;
         sa.ticket = scan_ticket;
         sa.sizes = sizes64;
@@ -743,10 +767,13 @@ static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, v
             c.err = ctx->err_dev;
             if ((uint32_t)m + 1 == NL) {
                 c.n_children = sizes32 + 0;
-                c.child_limit = inst_stride;
+                c.child_limit = std::min<uint64_t>(inst_stride, n);
                 c.child_verdict = inst_verdict;
                 c.child_stride = inst_stride;
+                c.child_parent = inst_parent;                 // null at the root
+                c.items = 16;
             } else {
+                c.items = 2;
                 c.n_children = sizes32 + (m + 1);
                 c.child_limit = node_limit[m + 1];
                 c.child_counts = node_counts[m + 1];
@@ -761,14 +788,8 @@ static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, v
                 c.node_start = node_start[m];
                 c.n_nodes = sizes32 + m;
                 c.node_limit = node_limit[m];
-                c.counts = node_counts[m];
+                c.counts = node_counts[m];                    // zeroed by the scan as nodes appear
                 c.stride = node_stride[m];
-                // zero the used part of this level's counts: P segments of nodes*6 words
-                for (uint32_t p = 0; p < P; ++p) {
-                    ZeroArgs za{node_counts[m] + (uint64_t)p * node_stride[m] * 6, sizes32 + m, 6, 0, node_limit[m]};
-                    s = launch(ctx, "zero", [&] { return launch_zero(za, 512, st); });
-                    if (s) return s;
-                }
             }
             s = launch(ctx, "count", [&] { return launch_count(c, st); });
             if (s) return s;
@@ -820,7 +841,8 @@ int32_t ltl4c_eval(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int3
     if (s) return s;
     HIP_TRY(hipSetDevice(ctx->device));
 
-    return eval_core(ctx, g, w, d_ws, d_records, n, plan, P, nullptr, nullptr, 0, out);
+    return eval_core(ctx, g, w, d_ws, d_records, n, plan, P, max_states_of(ctx, props, n_props), nullptr, nullptr,
+                     0, out);
 }
 
 
@@ -913,7 +935,7 @@ int32_t ltl4c_eval_batch(ltl4c_ctx* ctx, const void* d_records, const uint64_t* 
     r.node_keys[1] = reinterpret_cast<uint64_t*>(ws + b.keys_off);
     r.node_counts[1] = reinterpret_cast<uint32_t*>(ws + b.counts_off);
     r.node_verdict[1] = ws + b.verdict_off;
-    s = eval_core(ctx, b.g, b.w, d_ws, d_records, n, plan, P, ctx->batch_chunk_dev,
+    s = eval_core(ctx, b.g, b.w, d_ws, d_records, n, plan, P, max_states_of(ctx, props, n_props), ctx->batch_chunk_dev,
                   ctx->batch_chunk_dev + n_traces + 1, (uint32_t)n_traces, &r);
     if (s) return s;
     BatchOutArgs o{};
@@ -1143,6 +1165,7 @@ static int32_t group_push_impl(ltl4c_ctx* ctx, int32_t group, const void* d_reco
         sa.n_levels = 1;
         sa.valid_shift = G->g.cbits + G->g.key_bits_total;
         sa.n_props = G->V;
+        sa.max_states = max_states_of(ctx, G->props.data(), (int32_t)G->P);
         sa.plan = G->vplan;
         sa.inst_verdict = seg_state;
         sa.inst_stride = G->max_batch;

@@ -139,3 +139,27 @@ def test_scan_tile_variants(variant, case):
     torch.cuda.synchronize()
     ctx.close()
     compare_full(r, evaluate_workload(wl), len(ids), wl.layout.n_keys)
+
+
+def test_repeated_evaluations_share_one_workspace():
+    """Evaluations that reuse one workspace must not see each other's look-back
+    words: alternate traces with equal keys and different event types on one
+    context and check every result against the oracle."""
+    import torch
+    from paper_1411_2239_amd import lib
+    a = W.gen_user_requests(n_events=400_000, n_users=500, seed=11)
+    rng = np.random.default_rng(5)
+    b_rec = a.records.copy()
+    b_rec["type"] = rng.permutation(b_rec["type"])
+    c_rec = a.records[: 150_001].copy()
+    ctx, ids, _ = lib.open_workload(a)
+    rb = a.layout.record_bytes
+    for name, recs in (("a", a.records), ("b", b_rec), ("a", a.records), ("c", c_rec), ("b", b_rec)):
+        print(f"[case] repeated evaluation {name} n={recs.shape[0]}", flush=True)
+        dev = torch.from_numpy(recs.view(np.uint8).reshape(-1).copy()).to("cuda:0")
+        r = ctx.eval(dev, ids, instances=True, nodes=True)
+        torch.cuda.synchronize()
+        o = evaluate_workload(a, records=recs)
+        compare_full(r, o, len(ids), a.layout.n_keys)
+        assert dev.numel() == recs.shape[0] * rb
+    ctx.close()
