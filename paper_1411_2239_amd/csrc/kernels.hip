@@ -1464,35 +1464,46 @@ __device__ __forceinline__ uint32_t node_of(const uint32_t* start, uint32_t nn, 
 
 // Children are read in strided order (consecutive threads take consecutive
 // children; all loads of a tile are issued before any is used) and counted
-// into an LDS window of kCountWindow parents; a wave whose children all have
-// one parent (always true at the root) counts by six ballots instead of
-// per-child atomics.
+// into an LDS window of kCountWindow parents.  Children are in parent order,
+// so the lanes of one wave with one parent form a run: six ballots give every
+// run's bin counts and the first lane of each run adds them.
+__device__ __forceinline__ void count_add(const CountArgs& a, uint32_t* s_cnt, uint32_t p, uint32_t lo, uint32_t nn,
+                                          uint32_t node, uint32_t q, uint32_t v) {
+    const uint32_t slot = node - lo;
+    if (slot < (uint32_t)kCountWindow)
+        atomicAdd(&s_cnt[(p * kCountWindow + slot) * 6 + q], v);
+    else if (node < nn)
+        atomicAdd(&a.counts[((uint64_t)p * a.stride + node) * 6 + q], v);
+}
+
 __device__ __forceinline__ void count_child(const CountArgs& a, uint32_t* s_cnt, uint32_t p, uint32_t lo, uint32_t nn,
                                             bool valid, uint32_t node, uint32_t b) {
     const int lane = threadIdx.x & 63;
     const uint64_t vm = __ballot(valid);
     if (vm == 0) return;
-    const uint32_t node0 = __shfl(node, __ffsll((unsigned long long)vm) - 1, 64);
-    if (__all(!valid || node == node0)) {
+    uint64_t bq[6];
+#pragma unroll
+    for (uint32_t q = 0; q < 6; ++q) bq[q] = __ballot(valid && b == q);
+    const uint32_t pn = __shfl_up(node, 1, 64);
+    const bool head = valid && (lane == 0 || pn != node);
+    const uint64_t heads = __ballot(head);
+    if (__popcll(heads) == 1) {
+        // one parent for the whole wave: lanes 0..5 add one bin each
+        const uint32_t node0 = __shfl(node, __ffsll((unsigned long long)heads) - 1, 64);
         uint32_t mine = 0;
 #pragma unroll
+        for (uint32_t q = 0; q < 6; ++q)
+            if (lane == (int)q) mine = (uint32_t)__popcll(bq[q]);
+        if (lane < 6 && mine) count_add(a, s_cnt, p, lo, nn, node0, (uint32_t)lane, mine);
+    } else if (head) {
+        const uint64_t later = heads & ~((2ull << lane) - 1ull);
+        const int end = later ? __ffsll((unsigned long long)later) - 1 : 64;
+        const uint64_t run = (end == 64 ? ~0ull : ((1ull << end) - 1ull)) & ~((1ull << lane) - 1ull);
+#pragma unroll
         for (uint32_t q = 0; q < 6; ++q) {
-            const uint32_t nq = (uint32_t)__popcll(__ballot(valid && b == q));
-            if (lane == (int)q) mine = nq;
+            const uint32_t cnt = (uint32_t)__popcll(bq[q] & run);
+            if (cnt) count_add(a, s_cnt, p, lo, nn, node, q, cnt);
         }
-        if (lane < 6 && mine) {
-            const uint32_t slot = node0 - lo;
-            if (slot < (uint32_t)kCountWindow)
-                atomicAdd(&s_cnt[(p * kCountWindow + slot) * 6 + lane], mine);
-            else if (node0 < nn)
-                atomicAdd(&a.counts[((uint64_t)p * a.stride + node0) * 6 + lane], mine);
-        }
-    } else if (valid && b < 6u) {
-        const uint32_t slot = node - lo;
-        if (slot < (uint32_t)kCountWindow)
-            atomicAdd(&s_cnt[(p * kCountWindow + slot) * 6 + b], 1u);
-        else if (node < nn)
-            atomicAdd(&a.counts[((uint64_t)p * a.stride + node) * 6 + b], 1u);
     }
 }
 
@@ -1561,6 +1572,107 @@ __global__ __launch_bounds__(kCountThreads) void k_count(CountArgs a) {
         __syncthreads();
     }
 }
+// Counting of leaf verdicts: every thread takes 16 consecutive children (the
+// verdict bytes and parent ids are read as 16-byte vectors where aligned),
+// accumulates each run of children with one parent in a packed register of
+// six 5-bit bins and adds the run once, into the LDS window of kCountWindow
+// parents or, beyond it, to global memory.
+__device__ __forceinline__ void leaf_flush(const CountArgs& a, uint32_t* s_cnt, uint32_t p, uint32_t lo, uint32_t nn,
+                                           uint32_t node, uint32_t acc) {
+    if (!acc) return;
+    const uint32_t slot = node - lo;
+#pragma unroll
+    for (uint32_t q = 0; q < 6; ++q) {
+        const uint32_t v = (acc >> (5 * q)) & 31u;
+        if (!v) continue;
+        if (slot < (uint32_t)kCountWindow)
+            atomicAdd(&s_cnt[(p * kCountWindow + slot) * 6 + q], v);
+        else if (node < nn)
+            atomicAdd(&a.counts[((uint64_t)p * a.stride + node) * 6 + q], v);
+    }
+}
+
+__global__ __launch_bounds__(kCountThreads) void k_count_leaves(CountArgs a) {
+    __shared__ uint32_t s_cnt[kMaxProps * kCountWindow * 6];
+    __shared__ uint32_t s_lo;
+    const int tid = threadIdx.x;
+    const uint32_t P = a.n_props;
+    const uint32_t nch_all = *a.n_children;
+    const uint32_t nn_all = a.level == 0 ? 1u : *a.n_nodes;
+    const uint32_t nch = (uint32_t)min<uint64_t>(nch_all, a.child_limit);
+    const uint32_t nn = (uint32_t)min<uint64_t>(nn_all, a.level == 0 ? 1ull : a.node_limit);
+    constexpr uint32_t kItems = 16, kTile = kCountThreads * kItems;
+    const uint32_t ntiles = (nch + kTile - 1) / kTile;
+    if (blockIdx.x == 0 && tid == 0 && (nch < nch_all || nn < nn_all)) atomicOr(a.err, kErrCapacity);
+    uint32_t err = 0;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t c0 = tile * kTile;
+        for (uint32_t i = tid; i < P * kCountWindow * 6; i += kCountThreads) s_cnt[i] = 0;
+        if (tid == 0) s_lo = a.level == 0 ? 0u : a.child_parent[c0];
+        const uint32_t cb = c0 + tid * kItems;
+        const uint32_t cnt = cb < nch ? min(kItems, nch - cb) : 0u;
+        uint32_t par[kItems];
+        if (a.level == 0) {
+#pragma unroll
+            for (uint32_t k = 0; k < kItems; ++k) par[k] = 0;
+        } else if (cnt == kItems) {
+            const uint4* pv = reinterpret_cast<const uint4*>(a.child_parent + cb);   // cb is a multiple of 16
+#pragma unroll
+            for (uint32_t k = 0; k < kItems / 4; ++k) {
+                const uint4 x = pv[k];
+                par[4 * k] = x.x;
+                par[4 * k + 1] = x.y;
+                par[4 * k + 2] = x.z;
+                par[4 * k + 3] = x.w;
+            }
+        } else {
+#pragma unroll
+            for (uint32_t k = 0; k < kItems; ++k) par[k] = k < cnt ? a.child_parent[cb + k] : 0u;
+        }
+        __syncthreads();
+        const uint32_t lo = s_lo;
+        for (uint32_t p = 0; p < P && cnt > 0; ++p) {
+            const uint8_t* vp = a.child_verdict + p * a.child_stride + cb;
+            uint32_t vw[kItems / 4];
+            if (cnt == kItems && (reinterpret_cast<uintptr_t>(vp) & 15u) == 0) {
+                const uint4 x = *reinterpret_cast<const uint4*>(vp);
+                vw[0] = x.x;
+                vw[1] = x.y;
+                vw[2] = x.z;
+                vw[3] = x.w;
+            } else {
+#pragma unroll
+                for (uint32_t k = 0; k < kItems / 4; ++k) vw[k] = 0;
+                for (uint32_t k = 0; k < cnt; ++k) vw[k >> 2] |= (uint32_t)vp[k] << (8 * (k & 3));
+            }
+            uint32_t cur = par[0], acc = 0;
+#pragma unroll
+            for (uint32_t k = 0; k < kItems; ++k) {
+                if (k >= cnt) break;
+                if (par[k] != cur) {
+                    leaf_flush(a, s_cnt, p, lo, nn, cur, acc);
+                    cur = par[k];
+                    acc = 0;
+                }
+                const uint32_t b = (vw[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+                if (b > 5u) err |= kErrSpin;
+                else acc += 1u << (5 * b);
+            }
+            leaf_flush(a, s_cnt, p, lo, nn, cur, acc);
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < P * kCountWindow * 6; i += kCountThreads) {
+            const uint32_t v = s_cnt[i];
+            if (!v) continue;
+            const uint32_t p = i / (kCountWindow * 6), slot = (i / 6) % kCountWindow, b = i % 6;
+            const uint32_t node = lo + slot;
+            if (node < nn) atomicAdd(&a.counts[((uint64_t)p * a.stride + node) * 6 + b], v);
+        }
+        __syncthreads();
+    }
+    if (err) atomicOr(a.err, err);
+}
+
 __global__ void k_finalize(FinalizeArgs a) {
     const uint32_t p = threadIdx.x;
     if (p <= a.n_levels) a.sizes_out[p] = p < a.n_levels ? a.sizes_ws[p] : 0ull;
@@ -1855,7 +1967,7 @@ hipError_t launch_count(const CountArgs& a, hipStream_t s) {
     const uint64_t want = (a.child_limit + tile - 1) / tile;
     const uint32_t blocks = (uint32_t)(want < 2048 ? (want ? want : 1) : 2048);
     if (a.items >= 16)
-        hipLaunchKernelGGL(k_count<16>, dim3(blocks), dim3(kCountThreads), 0, s, a);
+        hipLaunchKernelGGL(k_count_leaves, dim3(blocks), dim3(kCountThreads), 0, s, a);
     else
         hipLaunchKernelGGL(k_count<2>, dim3(blocks), dim3(kCountThreads), 0, s, a);
     return hipGetLastError();
