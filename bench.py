@@ -111,10 +111,13 @@ def serving_bench(n_chunks=3000, pool_events=1_000_000, n_streams=64, plain_chun
     ptrs = chunk_ptrs()
     torch.cuda.synchronize()
 
+    pushes = [0]
+
     def run_batched(grp, count):
         lat = np.zeros(count)
         inflight = collections.deque()
         i, done_events = 0, 0
+        pushes[0] = 0
         t0 = time.perf_counter()
         t_last = t0
         while i < count or inflight:
@@ -130,6 +133,7 @@ def serving_bench(n_chunks=3000, pool_events=1_000_000, n_streams=64, plain_chun
                     tot += int(sizes[j])
                     j += 1
                 grp.push_chunks(ptrs[i:j], sizes[i:j], streams[i:j])
+                pushes[0] += 1
                 ev = torch.cuda.Event()
                 ev.record()
                 inflight.append((ev, i, j))
@@ -161,7 +165,17 @@ def serving_bench(n_chunks=3000, pool_events=1_000_000, n_streams=64, plain_chun
     v, c, b = grp.read()
     batched = {"events_per_s": ev / el, "chunks": n_chunks, "events": ev, "seconds": el,
                "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-               "live_bindings": int(b.sum())}
+               "live_bindings": int(b.sum()), "pushes": pushes[0]}
+    grp.close()
+    # per-kernel time of the same batched schedule, in a separate profiled run
+    grp = lib.StreamGroup(ctx, [pid], n_streams, 100_000, max_batch)
+    ctx.profile(True)
+    ctx.profile_reset()
+    run_batched(grp, n_chunks)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    batched["kernel_ms"] = {k: round(x[0], 3) for k, x in prof.items()}
+    batched["profiled_pushes"] = pushes[0]
     grp.close()
     grp = lib.StreamGroup(ctx, [pid], n_streams, 100_000, max_batch)
     log(f"[bench] serving: plain, {plain_chunks} chunks")
@@ -234,6 +248,46 @@ def batching_bench(n_traces=4096, reps=3, log=print):
             "batched_kernel_ms": {k: round(x[0], 3) for k, x in prof.items()}}
 
 
+def large_bench(n_events=500_000_000, reps=3, log=print):
+    """One long trace (16-byte records, 1M Zipf(1.1) keys) with three
+    properties whose monitors have 3, 8 and 16 states, evaluated in one pass."""
+    import torch
+    from paper_1411_2239_amd import lib, workloads
+
+    log(f"[bench] large trace: drawing {n_events} events on the device")
+    wl, rec = workloads.gen_large_trace_device(n_events=n_events)
+    ctx = lib.Context(0)
+    ctx.set_layout(wl.layout)
+    ids = [ctx.add_spec(p) for p in wl.props]
+    ws = ctx.workspace(n_events, ids)
+    res = ctx.alloc_result(len(ids))
+    ctx.eval_into(rec, n_events, ids, res, ws)
+    ctx.wait()
+    torch.cuda.synchronize()
+    log(f"[bench] large trace: {reps} evaluations")
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.eval_into(rec, n_events, ids, res, ws)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    ctx.wait()
+    ctx.profile(True)
+    ctx.profile_reset()
+    ctx.eval_into(rec, n_events, ids, res, ws)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ctx.wait()
+    out = {"workload": f"{n_events} events, 1M keys Zipf(1.1), 3 properties (3/8/16-state monitors)",
+           "events": n_events, "events_per_s": n_events / el, "ms": el * 1e3,
+           "instances": int(res.sizes[0].item()),
+           "root_verdict": [lib.VERDICT_NAMES[v] for v in res.root_verdict.cpu().numpy().tolist()],
+           "kernel_ms": {k: round(x[0], 3) for k, x in prof.items()}}
+    ctx.close()
+    del rec, ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,6 +300,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the online-monitoring section")
     ap.add_argument("--no-batching", action="store_true", help="skip the batched-traces section")
     ap.add_argument("--batch-traces", type=int, default=4096)
+    ap.add_argument("--no-large", action="store_true", help="skip the 500M-event single-trace section")
+    ap.add_argument("--large-events", type=int, default=500_000_000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -324,6 +380,10 @@ def main():
     if not args.no_batching:
         batching = batching_bench(args.batch_traces, log=log)
 
+    large = None
+    if not args.no_large:
+        large = large_bench(args.large_events, log=log)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (C oracle)")
@@ -348,6 +408,7 @@ def main():
         "root_verdict": [lib.VERDICT_NAMES[v] for v in root], "root_counts": counts,
         "serving": serving,
         "batching": batching,
+        "large_trace": large,
         "batched_vs_plain_speedup": batching["batched_vs_plain"] if batching else None,
         "p99_chunk_latency_ms": serving["batched"]["p99_ms"] if serving else None,
         "cpu_baseline": cpu,

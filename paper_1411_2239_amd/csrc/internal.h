@@ -178,10 +178,9 @@ struct GroupState {
     uint32_t stream_shift;               // key >> stream_shift = stream
     uint32_t max_streams, max_bindings;
     // bindings
-    uint64_t* bkeys;                     // [bcap]
+    uint64_t* bslot;                     // [bcap][2]: key, then parent | states of properties 0..3 << 32
     uint64_t bmask;
-    uint8_t* bstate;                     // [P][bcap]
-    uint32_t* bparent;                   // [bcap]
+    uint8_t* bstate;                     // [P - 4][bcap]: states of properties 4..
     uint32_t* stream_bindings;           // [max_streams]
     // quantifier nodes of levels 1..n_levels-1
     uint64_t* nkeys[kMaxLevels];         // [ncap]

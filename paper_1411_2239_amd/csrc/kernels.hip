@@ -255,14 +255,18 @@ constexpr int kSortLookWindow = 8;
 constexpr int kScanLookWindow = 4;
 
 // 16-item tiles are held to 128 VGPRs (two 512-thread blocks per CU), 8-item
-// tiles to 80 (three)
+// tiles to 80 (three).  Tiles above 8192 words are written out in PHASES
+// parts through an LDS buffer of CHUNK words.
 template <int THREADS, int ITEMS>
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(ITEMS <= 8 ? 6 : ITEMS <= 16 ? 4 : 2)))
 void k_sort_pass(SortPassArgs a) {
     constexpr int TILE = THREADS * ITEMS;
     constexpr int WAVES = THREADS / 64;
+    constexpr int PHASES = (TILE + 8191) / 8192;
+    constexpr int CHUNK = TILE / PHASES;
     static_assert(THREADS >= kRadix, "one thread per bucket");
-    __shared__ uint64_t s_keys[TILE];
+    static_assert(CHUNK * PHASES == TILE, "phases split the tile evenly");
+    __shared__ uint64_t s_keys[CHUNK];
     __shared__ uint32_t s_wcnt[WAVES][kRadix];
     __shared__ uint32_t s_hist[kRadix];
     __shared__ uint32_t s_lstart[kRadix];
@@ -373,20 +377,31 @@ void k_sort_pass(SortPassArgs a) {
         s_gbase[tid] = gexcl + prefix;
     }
     __syncthreads();
+    // local position of every key in the bucket-ordered tile
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
         const uint32_t d = dr[r] & 0xFFu;
-        const uint32_t pos = s_lstart[d] + s_wcnt[w][d] + (dr[r] >> 8);
-        if ((uint32_t)r * 64 < rem && pos < (uint32_t)TILE) s_keys[pos] = key[r];
+        dr[r] = d | ((s_lstart[d] + s_wcnt[w][d] + (dr[r] >> 8)) << 8);
     }
-    __syncthreads();
     const uint32_t tile_n = (uint32_t)min<uint64_t>(TILE, a.n - base);
-    for (uint32_t i = tid; i < tile_n; i += THREADS) {
-        const uint64_t k = s_keys[i];
-        const uint32_t d = (uint32_t)(k >> a.shift) & dmask;
-        const uint64_t dst = (uint64_t)s_gbase[d] + (i - s_lstart[d]);
-        if (dst < a.n) a.out[dst] = k;
-        else atomicOr(a.err, kErrSpin);
+#pragma unroll
+    for (int ph = 0; ph < PHASES; ++ph) {
+        const uint32_t lo_pos = (uint32_t)ph * CHUNK;
+        if (ph > 0) __syncthreads();
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) {
+            const uint32_t rel = (dr[r] >> 8) - lo_pos;
+            if ((uint32_t)r * 64 < rem && rel < (uint32_t)CHUNK) s_keys[rel] = key[r];
+        }
+        __syncthreads();
+        const uint32_t hi_pos = min<uint32_t>(tile_n, lo_pos + CHUNK);
+        for (uint32_t i = lo_pos + tid; i < hi_pos; i += THREADS) {
+            const uint64_t k = s_keys[i - lo_pos];
+            const uint32_t d = (uint32_t)(k >> a.shift) & dmask;
+            const uint64_t dst = (uint64_t)s_gbase[d] + (i - s_lstart[d]);
+            if (dst < a.n) a.out[dst] = k;
+            else atomicOr(a.err, kErrSpin);
+        }
     }
 }
 
@@ -1697,17 +1712,21 @@ __device__ __forceinline__ uint64_t mix64(uint64_t x) {
 }
 
 // Insert-or-find `key` in an open-addressing table; returns its slot and
-// whether this call inserted it, or ~0 when the table is full.
-__device__ uint64_t table_slot(uint64_t* keys, uint64_t mask, uint64_t key, bool* fresh) {
+// whether this call inserted it, or ~0 when the table is full.  A slot only
+// ever changes from empty to a key, so probes read through the caches: a
+// stale copy can only show "empty", and the compare-and-swap that follows
+// returns the slot's real content.
+// Keys sit `stride` words apart (a slot may carry data after its key).
+__device__ uint64_t table_slot(uint64_t* keys, uint32_t stride, uint64_t mask, uint64_t key, bool* fresh) {
     uint64_t h = mix64(key) & mask;
     for (uint64_t probe = 0; probe <= mask; ++probe) {
-        const uint64_t k = __hip_atomic_load(keys + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t k = __hip_atomic_load(keys + h * stride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (k == key) {
             *fresh = false;
             return h;
         }
         if (k == kEmptyKey) {
-            const uint64_t prev = atomicCAS(reinterpret_cast<unsigned long long*>(keys + h), kEmptyKey, key);
+            const uint64_t prev = atomicCAS(reinterpret_cast<unsigned long long*>(keys + h * stride), kEmptyKey, key);
             if (prev == kEmptyKey) {
                 *fresh = true;
                 return h;
@@ -1723,12 +1742,25 @@ __device__ uint64_t table_slot(uint64_t* keys, uint64_t mask, uint64_t key, bool
     return ~0ull;
 }
 
-__device__ __forceinline__ void mark_node(const GroupState& g, uint32_t level, uint32_t slot) {
-    if (level == 0) {
-        if (atomicExch(g.rdirty + slot, 1u) == 0u) g.rlist[atomicAdd(g.list_cnt + 0, 1u)] = slot;
-    } else {
-        if (atomicExch(g.ndirty[level] + slot, 1u) == 0u) g.nlist[level][atomicAdd(g.list_cnt + level, 1u)] = slot;
-    }
+// Put node `slot` of `level` on the level's dirty list once.  Called by every
+// lane of a wave (want: this lane has a node to mark); the appends of a wave
+// share one atomic on the list length.  A dirty flag only goes from 0 to 1
+// within a kernel, so a cached read of 1 is final and skips the exchange.
+__device__ __forceinline__ void mark_nodes(const GroupState& g, uint32_t level, bool want, uint32_t slot) {
+    const int lane = threadIdx.x & 63;
+    uint32_t* dirty = level == 0 ? g.rdirty : g.ndirty[level];
+    uint32_t* list = level == 0 ? g.rlist : g.nlist[level];
+    bool mine = false;
+    if (want)
+        mine = __hip_atomic_load(dirty + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == 0u &&
+               atomicExch(dirty + slot, 1u) == 0u;
+    const uint64_t m = __ballot(mine);
+    if (m == 0) return;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(g.list_cnt + level, (uint32_t)__popcll(m));
+    base = __shfl(base, leader, 64);
+    if (mine) list[base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = slot;
 }
 
 __device__ __forceinline__ uint32_t* counts_of(const GroupState& g, uint32_t level, uint32_t slot, uint32_t p) {
@@ -1736,100 +1768,157 @@ __device__ __forceinline__ uint32_t* counts_of(const GroupState& g, uint32_t lev
     return g.ncounts[level] + ((uint64_t)p * (g.nmask + 1) + slot) * 6;
 }
 
-// One thread per binding segment of the pushed chunks.
+// One thread per binding segment of the pushed chunks.  Segments are in key
+// order, so the lanes of a wave whose bindings share a parent node form a
+// run: its count changes are summed by ballots and applied once per run.
 __global__ __launch_bounds__(256) void k_group_update(GroupUpdateArgs a) {
     const GroupState& g = a.g;
     const uint32_t nseg = *a.n_seg;
     const uint32_t L = g.n_levels;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nseg; i += gridDim.x * blockDim.x) {
-        const uint64_t key = a.seg_key[i];
-        const uint32_t stream = (uint32_t)(key >> g.stream_shift);
+    const uint32_t plevel = L - 1;
+    const int lane = threadIdx.x & 63;
+    for (uint32_t base = blockIdx.x * blockDim.x; base < nseg; base += gridDim.x * blockDim.x) {
+        const uint32_t i = base + threadIdx.x;
+        bool ok = i < nseg;
+        uint64_t b = 0, aux = 0;                                 // aux: parent | states of properties 0..3
         bool fresh = false;
-        const uint64_t b = table_slot(g.bkeys, g.bmask, key, &fresh);
-        if (b == ~0ull || stream >= g.max_streams) {
-            atomicOr(g.err, kErrCapacity);
-            continue;
-        }
-        uint32_t parent;
-        if (fresh) {
-            if (atomicAdd(g.stream_bindings + stream, 1u) >= g.max_bindings) atomicOr(g.err, kErrCapacity);
-            if (L == 1) {
-                parent = stream;
-            } else {
-                // find or create the chain of quantifier nodes above this binding
-                bool nf = false;
-                uint64_t slot = table_slot(g.nkeys[L - 1], g.nmask, key >> g.level_shift[L - 1], &nf);
-                if (slot == ~0ull) {
-                    atomicOr(g.err, kErrCapacity);
-                    continue;
-                }
-                parent = (uint32_t)slot;
-                for (uint32_t m = L - 1; nf && m >= 1; --m) {
-                    if (m == 1) {
-                        g.nparent[1][slot] = stream;
-                        break;
-                    }
-                    bool pf = false;
-                    const uint64_t ps = table_slot(g.nkeys[m - 1], g.nmask, key >> g.level_shift[m - 1], &pf);
-                    if (ps == ~0ull) {
+        uint32_t parent = 0;
+        if (ok) {
+            const uint64_t key = a.seg_key[i];
+            const uint32_t stream = (uint32_t)(key >> g.stream_shift);
+            b = table_slot(g.bslot, 2, g.bmask, key, &fresh);
+            if (b == ~0ull || stream >= g.max_streams) {
+                atomicOr(g.err, kErrCapacity);
+                ok = false;
+            } else if (fresh) {
+                if (L == 1) {
+                    parent = stream;
+                } else {
+                    // find or create the chain of quantifier nodes above this binding
+                    bool nf = false;
+                    uint64_t slot = table_slot(g.nkeys[L - 1], 1, g.nmask, key >> g.level_shift[L - 1], &nf);
+                    if (slot == ~0ull) {
                         atomicOr(g.err, kErrCapacity);
-                        break;
+                        ok = false;
+                    } else {
+                        parent = (uint32_t)slot;
+                        for (uint32_t m = L - 1; nf && m >= 1; --m) {
+                            if (m == 1) {
+                                g.nparent[1][slot] = stream;
+                                break;
+                            }
+                            bool pf = false;
+                            const uint64_t ps = table_slot(g.nkeys[m - 1], 1, g.nmask, key >> g.level_shift[m - 1], &pf);
+                            if (ps == ~0ull) {
+                                atomicOr(g.err, kErrCapacity);
+                                break;
+                            }
+                            g.nparent[m][slot] = (uint32_t)ps;
+                            slot = ps;
+                            nf = pf;
+                        }
                     }
-                    g.nparent[m][slot] = (uint32_t)ps;
-                    slot = ps;
-                    nf = pf;
                 }
+            } else {
+                aux = g.bslot[2 * b + 1];
+                parent = (uint32_t)aux;
             }
-            g.bparent[b] = parent;
-        } else {
-            parent = g.bparent[b];
         }
-        const uint32_t plevel = L - 1;
-        bool touched = false;
+        const uint64_t okm = __ballot(ok);
+        {
+            // new bindings per stream: one atomic per run of lanes with one stream
+            const uint32_t stream = ok ? (uint32_t)(a.seg_key[i] >> g.stream_shift) : 0u;
+            const uint32_t ps = __shfl_up(stream, 1, 64);
+            const bool sprev = lane > 0 && ((okm >> (lane - 1)) & 1ull);
+            const bool shead = ok && (!sprev || ps != stream);
+            const uint64_t sheads = __ballot(shead);
+            const uint64_t freshm = __ballot(ok && fresh);
+            if (shead && freshm) {
+                const uint64_t later = sheads & ~((2ull << lane) - 1ull);
+                const int end = later ? __ffsll((unsigned long long)later) - 1 : 64;
+                const uint64_t srun = (end == 64 ? ~0ull : ((1ull << end) - 1ull)) & ~((1ull << lane) - 1ull);
+                const uint32_t nf = (uint32_t)__popcll(freshm & srun);
+                if (nf && atomicAdd(g.stream_bindings + stream, nf) + nf > g.max_bindings) atomicOr(g.err, kErrCapacity);
+            }
+        }
+        // runs of lanes with one parent (all lanes take part in the ballots)
+        const uint32_t pn = __shfl_up(parent, 1, 64);
+        const bool prev_ok = lane > 0 && ((okm >> (lane - 1)) & 1ull);
+        const bool head = ok && (!prev_ok || pn != parent);
+        const uint64_t heads = __ballot(head);
+        uint64_t run = 0;
+        if (head) {
+            const uint64_t later = heads & ~((2ull << lane) - 1ull);
+            const int end = later ? __ffsll((unsigned long long)later) - 1 : 64;
+            run = (end == 64 ? ~0ull : ((1ull << end) - 1ull)) & ~((1ull << lane) - 1ull) & okm;
+        }
+        bool touched_run = false;
+        uint64_t aux_new = (uint64_t)parent;
         for (uint32_t p = 0; p < g.n_props; ++p) {
             const PropDev& P = g.plan->prop[p];
-            uint8_t* sp = g.bstate + (uint64_t)p * (g.bmask + 1) + b;
-            const uint32_t s_old = fresh ? P.q0 : *sp;
-            const uint32_t s_new = a.seg_state[(uint64_t)(g.vbase[p] + s_old) * a.seg_stride + i];
-            *sp = (uint8_t)s_new;
-            const uint32_t v_new = P.label[s_new];
-            uint32_t* c = counts_of(g, plevel, parent, p);
-            if (fresh) {
-                atomicAdd(c + v_new, 1u);
-                touched = true;
-            } else {
-                const uint32_t v_old = P.label[s_old];
-                if (v_old != v_new) {
-                    atomicSub(c + v_old, 1u);
-                    atomicAdd(c + v_new, 1u);
-                    touched = true;
+            uint32_t v_old = 6u, v_new = 6u;                       // 6: no change in this lane
+            if (ok) {
+                uint8_t* sp = p >= 4 ? g.bstate + (uint64_t)(p - 4) * (g.bmask + 1) + b : nullptr;
+                const uint32_t s_old = fresh ? P.q0 : p < 4 ? (uint32_t)(aux >> (32 + 8 * p)) & 0xFFu : *sp;
+                const uint32_t s_new = a.seg_state[(uint64_t)(g.vbase[p] + s_old) * a.seg_stride + i];
+                if (p < 4) aux_new |= (uint64_t)s_new << (32 + 8 * p);
+                else *sp = (uint8_t)s_new;
+                const uint32_t vn = P.label[s_new];
+                if (fresh) {
+                    v_new = vn;
+                } else {
+                    const uint32_t vo = P.label[s_old];
+                    if (vo != vn) {
+                        v_old = vo;
+                        v_new = vn;
+                    }
                 }
             }
+            uint32_t delta[6];
+#pragma unroll
+            for (uint32_t q = 0; q < 6; ++q) {
+                const uint64_t plus = __ballot(v_new == q), minus = __ballot(v_old == q);
+                delta[q] = (uint32_t)__popcll(plus & run) - (uint32_t)__popcll(minus & run);
+            }
+            if (head) {
+                uint32_t* c = counts_of(g, plevel, parent, p);
+#pragma unroll
+                for (uint32_t q = 0; q < 6; ++q)
+                    if (delta[q]) {
+                        atomicAdd(c + q, delta[q]);                // two's complement: a negative delta subtracts
+                        touched_run = true;
+                    }
+            }
         }
-        if (touched) mark_node(g, plevel, parent);
+        if (ok) g.bslot[2 * b + 1] = aux_new;
+        mark_nodes(g, plevel, head && touched_run, parent);
     }
 }
 
 // Re-valuate the dirty nodes of one level (>= 1) and pass changed verdicts up.
 __global__ __launch_bounds__(256) void k_group_level(GroupState g, uint32_t level) {
     const uint32_t n = g.list_cnt[level];
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint32_t slot = g.nlist[level][i];
-        g.ndirty[level][slot] = 0u;
-        const uint32_t parent = g.nparent[level][slot];
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const uint32_t i = base + threadIdx.x;
         bool touched = false;
-        for (uint32_t p = 0; p < g.n_props; ++p) {
-            const uint32_t v = valuate(g.plan->prop[p], (int)level, counts_of(g, level, slot, p));
-            uint8_t* vp = g.nverdict[level] + (uint64_t)p * (g.nmask + 1) + slot;
-            const uint32_t v_old = *vp;
-            if (v_old == v) continue;
-            *vp = (uint8_t)v;
-            uint32_t* c = counts_of(g, level - 1, parent, p);
-            if (v_old != kNoVerdict) atomicSub(c + v_old, 1u);
-            atomicAdd(c + v, 1u);
-            touched = true;
+        uint32_t parent = 0;
+        if (i < n) {
+            const uint32_t slot = g.nlist[level][i];
+            g.ndirty[level][slot] = 0u;
+            parent = g.nparent[level][slot];
+            for (uint32_t p = 0; p < g.n_props; ++p) {
+                const uint32_t v = valuate(g.plan->prop[p], (int)level, counts_of(g, level, slot, p));
+                uint8_t* vp = g.nverdict[level] + (uint64_t)p * (g.nmask + 1) + slot;
+                const uint32_t v_old = *vp;
+                if (v_old == v) continue;
+                *vp = (uint8_t)v;
+                uint32_t* c = counts_of(g, level - 1, parent, p);
+                if (v_old != kNoVerdict) atomicSub(c + v_old, 1u);
+                atomicAdd(c + v, 1u);
+                touched = true;
+            }
         }
-        if (touched) mark_node(g, level - 1, parent);
+        mark_nodes(g, level - 1, touched, parent);
     }
 }
 

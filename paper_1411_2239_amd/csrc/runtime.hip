@@ -439,9 +439,8 @@ uint64_t group_state_layout(const GroupHost& G, uint32_t L, uint8_t* base, Group
         off = align256(off + bytes);
         return base ? base + o : nullptr;
     };
-    uint8_t* bkeys = take(8 * bcap);
-    uint8_t* bstate = take((uint64_t)G.P * bcap);
-    uint8_t* bparent = take(4 * bcap);
+    uint8_t* bslot = take(16 * bcap);
+    uint8_t* bstate = take((uint64_t)(G.P > 4 ? G.P - 4 : 0) * bcap);
     uint8_t* sb = take(4ull * G.S);
     uint8_t* nk[kMaxLevels] = {}, *nc[kMaxLevels] = {}, *nv[kMaxLevels] = {}, *np[kMaxLevels] = {},
              *nd[kMaxLevels] = {}, *nl[kMaxLevels] = {};
@@ -459,10 +458,9 @@ uint64_t group_state_layout(const GroupHost& G, uint32_t L, uint8_t* base, Group
     uint8_t* rl = take(4ull * G.S);
     uint8_t* lc = take(4 * kMaxLevels);
     if (gs) {
-        gs->bkeys = reinterpret_cast<uint64_t*>(bkeys);
+        gs->bslot = reinterpret_cast<uint64_t*>(bslot);
         gs->bmask = bcap - 1;
         gs->bstate = bstate;
-        gs->bparent = reinterpret_cast<uint32_t*>(bparent);
         gs->stream_bindings = reinterpret_cast<uint32_t*>(sb);
         gs->nmask = ncap - 1;
         for (uint32_t m = 1; m < L; ++m) {
@@ -1049,7 +1047,7 @@ int32_t ltl4c_group_open(ltl4c_ctx* ctx, const int32_t* props, int32_t n_props, 
     // empty tree: no keys, no verdicts yet, zero counts; then value every root
     const hipStream_t st = ctx->stream;
     e = hipMemsetAsync(G->state, 0, G->state_bytes, st);
-    if (e == hipSuccess) e = launch_fill_u64(gs.bkeys, gs.bmask + 1, kEmptyKey, st);
+    if (e == hipSuccess) e = launch_fill_u64(gs.bslot, 2 * (gs.bmask + 1), kEmptyKey, st);
     for (uint32_t m = 1; m < L && e == hipSuccess; ++m) {
         e = launch_fill_u64(gs.nkeys[m], gs.nmask + 1, kEmptyKey, st);
         if (e == hipSuccess) e = launch_fill_u8(gs.nverdict[m], (uint64_t)G->P * (gs.nmask + 1), kNoVerdict, st);
