@@ -113,7 +113,8 @@ def serving_bench(n_chunks=3000, pool_events=1_000_000, n_streams=64, plain_chun
 
     pushes = [0]
 
-    def run_batched(grp, count):
+    def run_batched(grp, count, arrivals=None):
+        arr_ = arr if arrivals is None else arrivals
         lat = np.zeros(count)
         inflight = collections.deque()
         i, done_events = 0, 0
@@ -125,11 +126,11 @@ def serving_bench(n_chunks=3000, pool_events=1_000_000, n_streams=64, plain_chun
             while inflight and inflight[0][0].query():
                 ev, a, b = inflight.popleft()
                 t_done = time.perf_counter() - t0
-                lat[a:b] = t_done - arr[a:b]
+                lat[a:b] = t_done - arr_[a:b]
                 t_last = t_done
-            if i < count and len(inflight) < 2 and arr[i] <= now:
+            if i < count and len(inflight) < 2 and arr_[i] <= now:
                 j, tot = i, 0
-                while j < count and arr[j] <= now and j - i < 4096 and tot + sizes[j] <= max_batch:
+                while j < count and arr_[j] <= now and j - i < 4096 and tot + sizes[j] <= max_batch:
                     tot += int(sizes[j])
                     j += 1
                 grp.push_chunks(ptrs[i:j], sizes[i:j], streams[i:j])
@@ -177,6 +178,12 @@ def serving_bench(n_chunks=3000, pool_events=1_000_000, n_streams=64, plain_chun
     batched["kernel_ms"] = {k: round(x[0], 3) for k, x in prof.items()}
     batched["profiled_pushes"] = pushes[0]
     grp.close()
+    # capacity: every chunk available at once (closed loop), same pushes
+    grp = lib.StreamGroup(ctx, [pid], n_streams, 100_000, max_batch)
+    _, ev_c, el_c = run_batched(grp, n_chunks, np.zeros(n_chunks))
+    batched["capacity_events_per_s"] = ev_c / el_c
+    batched["capacity_pushes"] = pushes[0]
+    grp.close()
     grp = lib.StreamGroup(ctx, [pid], n_streams, 100_000, max_batch)
     log(f"[bench] serving: plain, {plain_chunks} chunks")
     lat_p, ev_p, el_p = run_plain(grp, plain_chunks)
@@ -188,7 +195,8 @@ def serving_bench(n_chunks=3000, pool_events=1_000_000, n_streams=64, plain_chun
     return {"workload": f"{n_streams} streams, 100k bindings each, chunks 4k-256k log-uniform, Poisson arrivals, "
                         f"device-resident chunk pools",
             "offered_events_per_s": offered, "batched": batched, "plain_per_chunk": plain,
-            "batched_vs_plain_throughput": batched["events_per_s"] / plain["events_per_s"]}
+            "batched_vs_plain_throughput": batched["events_per_s"] / plain["events_per_s"],
+            "capacity_vs_plain_throughput": batched["capacity_events_per_s"] / plain["events_per_s"]}
 
 
 def batching_bench(n_traces=4096, reps=3, log=print):
