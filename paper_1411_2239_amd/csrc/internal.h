@@ -19,7 +19,6 @@ constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;     // 4096 words per tile
 constexpr int kCountThreads = 256;
 constexpr int kCountWindow = 64;     // nodes kept in LDS per counting tile
-constexpr uint64_t kIdentityMap = 0xFEDCBA9876543210ull;
 constexpr uint32_t kSpinLimit = 1u << 22;   // bounded waits in decoupled look-back
 constexpr uint32_t kMaxChunks = 4096;        // chunks in one stream-group push
 
@@ -28,11 +27,9 @@ enum : uint32_t { kErrRange = 1u, kErrCapacity = 2u, kErrSpin = 4u };
 
 // One property as the kernels see it (lives in device memory).
 struct PropDev {
-    uint8_t delta[kStates * 16];     // delta[q * 16 + c]
     uint8_t label[kStates];
-    uint64_t colmap[16];             // class c -> packed map q -> delta(q, c); lanes >= n_states identity
-    uint64_t bcolmap[16];            // the same with one byte per state (monitors of at most 8 states)
-    uint32_t blabel;                 // label of state q in bits 4q..4q+3 (at most 8 states)
+    uint32_t bmap[16][4];            // class c -> map q -> delta(q, c), byte q of the 16 (identity for q >= n_states)
+    uint32_t blabel[2];              // label of state q in bits 4(q mod 8).. of word q / 8
     uint32_t q0, n_states;
     uint32_t kind[kMaxLevels], op[kMaxLevels], num[kMaxLevels], den[kMaxLevels];
 };
@@ -43,17 +40,11 @@ struct Plan {
     uint8_t key_present[256];
 };
 
-// Look-back record of one scan tile.  Every 64-bit word carries its own
-// validity bit (bit 32) above a 32-bit payload, so readers need no memory
-// fence: a word is either zero (not yet published) or complete.  Words
-// [0, 2*kMaxProps) are the low/high halves of the property maps, words
-// [2*kMaxProps, 2*kMaxProps+4) the instance / node counts.  Aggregate and
-// inclusive values are kept apart.
-constexpr int kScanStatusWords = 2 * kMaxProps + 4;
-struct ScanTileStatus {
-    uint64_t agg[kScanStatusWords];
-    uint64_t inc[kScanStatusWords];
-};
+// Look-back rows of one scan launch, per kind (aggregate / inclusive): the
+// four instance / node counts and up to 16 map dwords.  The rows of a launch
+// occupy 2 * kScanRows * tiles 32-bit words.
+constexpr int kScanRows = 20;
+constexpr int kScanGroupProps = 8;      // properties of one scan launch, at most
 
 struct ClassifyArgs {
     const uint8_t* records;
@@ -101,9 +92,12 @@ struct ScanArgs {
     uint32_t n_levels;
     uint32_t prefix_shift[kMaxLevels];   // word >> prefix_shift[m] = packed keys 0..m-1 (m>=1)
     uint32_t valid_shift;                // word >> valid_shift != 0 means excluded
-    uint32_t n_props;
+    uint32_t n_props;                    // properties of this launch: plan->prop[prop_idx[0 ..]]
+    uint8_t prop_idx[kScanGroupProps];
+    uint32_t n_props_all;                // properties of the evaluation (node counts to zero)
+    uint32_t structure;                  // this launch writes the numbering, parents, keys and sizes
     const Plan* plan;
-    uint8_t* inst_verdict;               // [n_props][inst_stride]
+    uint8_t* inst_verdict;               // [n_props_all][inst_stride]
     uint64_t inst_stride;
     uint64_t inst_limit;                 // instances with an id below this are written
     uint64_t* inst_keys;                 // optional [inst_limit]
@@ -113,9 +107,9 @@ struct ScanArgs {
     uint32_t* inst_parent;               // optional [inst_limit]: level n_levels-1 node of each instance
     uint64_t* node_keys[kMaxLevels];     // optional
     uint64_t node_limit[kMaxLevels];     // nodes with an id below this are written
-    ScanTileStatus* status;              // [tiles], zeroed before the launch
+    uint32_t* status;                    // look-back rows [2 * kScanRows][tiles], zeroed before the launch
     uint32_t emit_state;                 // write final states instead of verdicts
-    uint32_t max_states;                 // largest monitor among the properties
+    uint32_t max_states;                 // largest monitor among the properties of this launch
     uint32_t* ticket;
     uint64_t* sizes;                     // [1 + n_levels] written by the last tile
     uint32_t* sizes32;                   // same, 32-bit, for the counting kernels

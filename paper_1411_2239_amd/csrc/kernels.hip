@@ -31,36 +31,6 @@ __device__ __forceinline__ void st_flag(uint32_t* p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ uint64_t map_const(uint32_t s) { return (uint64_t)s * 0x1111111111111111ull; }
-__device__ __forceinline__ bool map_is_const(uint64_t f) { return f == (f & 15ull) * 0x1111111111111111ull; }
-__device__ __forceinline__ uint32_t map_at(uint64_t f, uint32_t q) { return (uint32_t)(f >> (4u * q)) & 15u; }
-
-// (g o f)[q] = g[f[q]] over all 16 lanes.  Kept out of line: it is the rare
-// path (runs with no segment head) and inlining it everywhere blows the
-// kernel past the instruction cache.
-__device__ __noinline__ uint64_t map_compose_full(uint64_t g, uint64_t f) {
-    uint64_t r = 0;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        uint32_t fq = (uint32_t)(f >> (4 * q)) & 15u;
-        r |= ((g >> (4u * fq)) & 15ull) << (4 * q);
-    }
-    return r;
-}
-
-// g after f, with the constant-map shortcuts.
-__device__ __forceinline__ uint64_t map_compose(uint64_t g, uint64_t f) {
-    if (map_is_const(g)) return g;
-    if (map_is_const(f)) return map_const(map_at(g, (uint32_t)(f & 15u)));
-    return map_compose_full(g, f);
-}
-
-__device__ __forceinline__ uint64_t shfl_up64(uint64_t v, int off) {
-    uint32_t lo = __shfl_up((uint32_t)v, off, 64);
-    uint32_t hi = __shfl_up((uint32_t)(v >> 32), off, 64);
-    return ((uint64_t)hi << 32) | lo;
-}
-
 __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
     const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -414,7 +384,7 @@ __device__ __forceinline__ uint32_t pad_idx(uint32_t i) { return i + (i >> 4); }
 __device__ __forceinline__ void zero_node_counts(const ScanArgs& a, int m, uint64_t id) {
     uint32_t* c = a.node_counts[m];
     if (!c) return;
-    for (uint32_t p = 0; p < a.n_props; ++p) {
+    for (uint32_t p = 0; p < a.n_props_all; ++p) {
         uint2* q = reinterpret_cast<uint2*>(c + (p * a.node_stride[m] + id) * 6);
         q[0] = make_uint2(0u, 0u);
         q[1] = make_uint2(0u, 0u);
@@ -422,725 +392,113 @@ __device__ __forceinline__ void zero_node_counts(const ScanArgs& a, int m, uint6
     }
 }
 
-template <int PMAX, int THREADS>
+// Maps over at most 8 (MW = 2) or 16 (MW = 4) states: MW dwords whose byte q
+// holds the image of state q.  The composition g∘f (f applied first) picks,
+// for every byte of f, the byte of g it names: one byte permute per dword for
+// 8 states; for 16 states two permutes (the low and the high half of g) and a
+// per-byte select on bit 3 of the selector.  No constant-map special cases
+// are needed.
+template <int MW>
+struct BMap {
+    uint32_t d[MW];
+};
+
+template <int MW>
+__device__ __forceinline__ BMap<MW> bm_identity() {
+    BMap<MW> r;
+#pragma unroll
+    for (int i = 0; i < MW; ++i) r.d[i] = 0x03020100u + 0x04040404u * (uint32_t)i;
+    return r;
+}
+template <int MW>
+__device__ __forceinline__ BMap<MW> bm_const(uint32_t s) {
+    BMap<MW> r;
+#pragma unroll
+    for (int i = 0; i < MW; ++i) r.d[i] = s * 0x01010101u;
+    return r;
+}
+template <int MW>
+__device__ __forceinline__ BMap<MW> bm_compose(const BMap<MW>& g, const BMap<MW>& f) {
+    BMap<MW> r;
+#pragma unroll
+    for (int i = 0; i < MW; ++i) {
+        if constexpr (MW == 2) {
+            r.d[i] = __builtin_amdgcn_perm(g.d[1], g.d[0], f.d[i]);
+        } else {
+            const uint32_t sel = f.d[i], s7 = sel & 0x07070707u;
+            const uint32_t lo = __builtin_amdgcn_perm(g.d[1], g.d[0], s7);
+            const uint32_t hi = __builtin_amdgcn_perm(g.d[3], g.d[2], s7);
+            const uint32_t t = (sel >> 3) & 0x01010101u, m = (t << 8) - t;   // 0xFF where the state is >= 8
+            r.d[i] = (hi & m) | (lo & ~m);
+        }
+    }
+    return r;
+}
+template <int MW>
+__device__ __forceinline__ uint32_t bm_at(const BMap<MW>& g, uint32_t q) {
+    if constexpr (MW == 2) {
+        return __builtin_amdgcn_perm(g.d[1], g.d[0], q) & 0xFFu;
+    } else {
+        const uint32_t lo = __builtin_amdgcn_perm(g.d[1], g.d[0], q & 7u);
+        const uint32_t hi = __builtin_amdgcn_perm(g.d[3], g.d[2], q & 7u);
+        return ((q & 8u) ? hi : lo) & 0xFFu;
+    }
+}
+template <int MW>
+__device__ __forceinline__ BMap<MW> bm_shfl_up(const BMap<MW>& v, int off) {
+    BMap<MW> r;
+#pragma unroll
+    for (int i = 0; i < MW; ++i) r.d[i] = __shfl_up(v.d[i], off, 64);
+    return r;
+}
+template <int MW>
+__device__ __forceinline__ BMap<MW> bm_shfl_down(const BMap<MW>& v, int off) {
+    BMap<MW> r;
+#pragma unroll
+    for (int i = 0; i < MW; ++i) r.d[i] = __shfl_down(v.d[i], off, 64);
+    return r;
+}
+template <int MW>
+__device__ __forceinline__ BMap<MW> bm_bcast(const BMap<MW>& v, int src) {
+    BMap<MW> r;
+#pragma unroll
+    for (int i = 0; i < MW; ++i) r.d[i] = __shfl(v.d[i], src, 64);
+    return r;
+}
+template <int MW>
+__device__ __forceinline__ BMap<MW> bm_load(const uint32_t* p) {
+    BMap<MW> r;
+#pragma unroll
+    for (int i = 0; i < MW; ++i) r.d[i] = p[i];
+    return r;
+}
+
+// One launch scans a group of up to PMAX properties whose monitors have at
+// most 4 MW states (PMAX * MW <= 16); the structure outputs (instance and node
+// numbering, parent ids, node-count zeroing, keys, sizes) come from one
+// launch with at most 4 properties.
+//
+// Look-back records are structure-of-arrays: row r of the aggregates of tile
+// t is st[r * tiles + t], row r of the inclusive values st[(kScanRows + r) *
+// tiles + t].  Rows 0..3 are the instance / node counts, row 4 + MW p + k the
+// dword k of property p's map, so that the lanes of one wave reading one row
+// of 64 consecutive tiles read one contiguous 256-byte span.  Every word
+// carries its own validity bit 31 (counts stay below 2^30 and map bytes below
+// 16): readers need no fence.
+template <int PMAX, int MW, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_scan(ScanArgs a) {
-    constexpr int kScanThreads = THREADS;
-    constexpr int kScanTile = THREADS * kScanItems;
-    constexpr int WAVES = THREADS / 64;
-    __shared__ uint64_t s_w[kScanTile + kScanTile / 16 + 1];
-    __shared__ uint8_t s_delta[PMAX][kStates * 16];
-    __shared__ uint8_t s_label[PMAX][kStates];
-    __shared__ uint64_t s_colmap[PMAX][16];
-    __shared__ uint32_t s_q0[PMAX];
-    __shared__ uint64_t s_wtot[PMAX][WAVES];
-    __shared__ uint32_t s_ctot[4][WAVES];
-    __shared__ uint64_t s_tprefix[PMAX];
-    __shared__ uint64_t s_tagg[PMAX];
-    __shared__ uint32_t s_cagg[4];
-    __shared__ uint32_t s_tcnt[4];
-    __shared__ uint64_t s_prev, s_next;
-    __shared__ uint32_t s_tile;
-    __shared__ uint32_t s_red[2][WAVES];
-
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const uint32_t P = a.n_props;
-    if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
-    for (uint32_t i = tid; i < P * kStates * 16; i += kScanThreads)
-        s_delta[i / (kStates * 16)][i % (kStates * 16)] = a.plan->prop[i / (kStates * 16)].delta[i % (kStates * 16)];
-    if (tid < (int)(P * 16)) {
-        s_label[tid / 16][tid % 16] = a.plan->prop[tid / 16].label[tid % 16];
-        s_colmap[tid / 16][tid % 16] = a.plan->prop[tid / 16].colmap[tid % 16];
-    }
-    if (tid < (int)P) s_q0[tid] = a.plan->prop[tid].q0;
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    const uint64_t base = (uint64_t)tile * kScanTile;
-    const uint64_t kInvalid = ~0ull;
-#pragma unroll
-    for (int r = 0; r < kScanItems; ++r) {
-        const uint64_t idx = base + r * kScanThreads + tid;
-        s_w[pad_idx(r * kScanThreads + tid)] = idx < a.n ? a.words[idx] : kInvalid;
-    }
-    if (tid == 0) s_prev = base > 0 ? a.words[base - 1] : kInvalid;
-    if (tid == 1) s_next = base + kScanTile < a.n ? a.words[base + kScanTile] : kInvalid;
-    __syncthreads();
-
-    uint64_t wv[kScanItems];
-#pragma unroll
-    for (int j = 0; j < kScanItems; ++j) wv[j] = s_w[pad_idx(tid * kScanItems + j)];
-    const uint64_t wp = tid == 0 ? s_prev : s_w[pad_idx(tid * kScanItems - 1)];
-    const uint64_t wn = tid == kScanThreads - 1 ? s_next : s_w[pad_idx(tid * kScanItems + kScanItems)];
-    const bool has_prev = base + (uint64_t)tid * kScanItems > 0;
-    const uint32_t cb = a.cbits, vs = a.valid_shift, L = a.n_levels;
-    const uint32_t cmask = (1u << cb) - 1u;
-
-    // per-event flags as bit masks
-    uint32_t m_valid = 0, m_head = 0, m_end = 0, m_lvl[kMaxLevels] = {0, 0, 0, 0};
-#pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        const uint64_t x = wv[j];
-        if ((x >> vs) != 0) continue;
-        m_valid |= 1u << j;
-        const uint64_t prv = j == 0 ? wp : wv[j - 1];
-        const bool first = (j == 0 && !has_prev);
-        const uint64_t nxt = j == kScanItems - 1 ? wn : wv[j + 1];
-        if (first || (prv >> cb) != (x >> cb)) m_head |= 1u << j;
-        if ((nxt >> vs) != 0 || (nxt >> cb) != (x >> cb)) m_end |= 1u << j;
-#pragma unroll
-        for (int m = 1; m < kMaxLevels; ++m) {
-            if (m >= (int)L) break;
-            const uint32_t sh = a.prefix_shift[m];
-            if (first || (prv >> sh) != (x >> sh)) m_lvl[m] |= 1u << j;
-        }
-    }
-    uint32_t cnt[4];
-    cnt[0] = __popc(m_head);
-#pragma unroll
-    for (int m = 1; m < 4; ++m) cnt[m] = (uint32_t)m < L ? __popc(m_lvl[m]) : 0u;
-
-    // summaries: the map from the state before this run to the state after it
-    uint64_t summ[PMAX];
-#pragma unroll
-    for (int p = 0; p < PMAX; ++p) {
-        summ[p] = kIdentityMap;
-        if (p >= (int)P) continue;
-        uint64_t f = kIdentityMap;
-        bool cst = false;
-        uint32_t s = 0;
-        for (int j = 0; j < kScanItems; ++j) {
-            if (!((m_valid >> j) & 1u)) break;
-            const uint32_t c = (uint32_t)wv[j] & cmask;
-            if ((m_head >> j) & 1u) {
-                cst = true;
-                s = s_delta[p][s_q0[p] * 16 + c];
-            } else if (cst) {
-                s = s_delta[p][s * 16 + c];
-            } else {
-                f = map_compose_full(s_colmap[p][c], f);
-            }
-        }
-        summ[p] = cst ? map_const(s) : f;
-    }
-
-    // block-wide exclusive scan of the summaries (composition) and counts
-    uint64_t excl[PMAX];
-#pragma unroll
-    for (int p = 0; p < PMAX; ++p) {
-        if (p >= (int)P) { excl[p] = kIdentityMap; continue; }
-        uint64_t v = summ[p];
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint64_t o = shfl_up64(v, off);
-            if (lane >= off) v = map_compose(v, o);
-        }
-        const uint64_t e = shfl_up64(v, 1);
-        excl[p] = lane == 0 ? kIdentityMap : e;
-        if (lane == 63) s_wtot[p][w] = v;
-    }
-    uint32_t cexcl[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint32_t incl = wave_incl_scan_u32(cnt[k]);
-        cexcl[k] = incl - cnt[k];
-        if (lane == 63) s_ctot[k][w] = incl;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < PMAX; ++p) {
-        if (p >= (int)P) continue;
-        uint64_t pre = kIdentityMap;
-        for (int i = 0; i < w; ++i) pre = map_compose(s_wtot[p][i], pre);
-        excl[p] = map_compose(excl[p], pre);
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        uint32_t pre = 0;
-        for (int i = 0; i < w; ++i) pre += s_ctot[k][i];
-        cexcl[k] += pre;
-    }
-    // tile aggregates: thread p composes property p, threads 32..35 sum counts
-    if (tid < (int)P) {
-        uint64_t t = kIdentityMap;
-        for (int i = 0; i < WAVES; ++i) t = map_compose(s_wtot[tid][i], t);
-        s_tagg[tid] = t;
-    }
-    if (tid >= 32 && tid < 36) {
-        const int k = tid - 32;
-        uint32_t sum = 0;
-        for (int i = 0; i < WAVES; ++i) sum += s_ctot[k][i];
-        s_cagg[k] = sum;
-    }
-    __syncthreads();
-
-    // publish this tile's aggregate, then look back (wave 0).  Lane p < P
-    // owns property p's map (two status words), lanes 32..35 the counts.
-    ScanTileStatus* st = a.status + tile;
-    const uint64_t kValid = 1ull << 32;
-    if (w == 0) {
-        if (lane < (int)P) {
-            const uint64_t m = s_tagg[lane];
-            __hip_atomic_store(&st->agg[2 * lane], kValid | (m & 0xFFFFFFFFull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&st->agg[2 * lane + 1], kValid | (m >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (lane >= 32 && lane < 36)
-            __hip_atomic_store(&st->agg[2 * kMaxProps + lane - 32], kValid | s_cagg[lane - 32], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        const bool owns = lane < (int)P || (lane >= 32 && lane < 36);
-        const int w0 = lane < 32 ? 2 * lane : 2 * kMaxProps + lane - 32;   // first word of this lane
-        const int nw = lane < 32 ? 2 : 1;
-        uint64_t acc = kIdentityMap;
-        uint32_t accc = 0;
-        if (tile > 0) {
-            // windowed look-back: every owning lane fetches the aggregate and
-            // inclusive words of kScanLookWindow predecessors in one round trip,
-            // then folds them nearest first until an inclusive tile
-            int64_t j = (int64_t)tile - 1;
-            uint32_t spins = 0;
-            bool done = false;
-            while (!done) {
-                uint64_t ia[kScanLookWindow], ib[kScanLookWindow], aa[kScanLookWindow], ab[kScanLookWindow];
-#pragma unroll
-                for (int k = 0; k < kScanLookWindow; ++k) {
-                    ia[k] = ib[k] = aa[k] = ab[k] = kValid;
-                    if (owns && j - k >= 0) {
-                        const ScanTileStatus* sj = a.status + (j - k);
-                        ia[k] = __hip_atomic_load(&sj->inc[w0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        aa[k] = __hip_atomic_load(&sj->agg[w0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        if (nw == 2) {
-                            ib[k] = __hip_atomic_load(&sj->inc[w0 + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            ab[k] = __hip_atomic_load(&sj->agg[w0 + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        }
-                    }
-                }
-                int used = 0;
-                bool stop = false;
-#pragma unroll
-                for (int k = 0; k < kScanLookWindow; ++k) {
-                    if (stop || done) continue;
-                    if (j - k < 0) { done = true; continue; }
-                    const bool inc_ok = __all(((ia[k] & kValid) != 0) && ((ib[k] & kValid) != 0));
-                    const bool agg_ok = __all(((aa[k] & kValid) != 0) && ((ab[k] & kValid) != 0));
-                    if (!inc_ok && !agg_ok) { stop = true; continue; }
-                    const uint64_t v0 = inc_ok ? ia[k] : aa[k], v1 = inc_ok ? ib[k] : ab[k];
-                    if (lane < (int)P) acc = map_compose(acc, (v0 & 0xFFFFFFFFull) | ((v1 & 0xFFFFFFFFull) << 32));
-                    if (lane >= 32 && lane < 36) accc += (uint32_t)v0;
-                    used = k + 1;
-                    if (inc_ok) done = true;
-                }
-                j -= used;
-                if (!done && j < 0) done = true;
-                if (!done && used == 0) {
-                    if (++spins > kSpinLimit) {
-                        if (lane == 0) atomicOr(a.err, kErrSpin);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-            }
-        }
-        // publish the inclusive value
-        if (lane < (int)P) {
-            const uint64_t m = tile > 0 ? map_compose(s_tagg[lane], acc) : s_tagg[lane];
-            __hip_atomic_store(&st->inc[2 * lane], kValid | (m & 0xFFFFFFFFull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&st->inc[2 * lane + 1], kValid | (m >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_tprefix[lane] = acc;
-        }
-        if (lane >= 32 && lane < 36) {
-            __hip_atomic_store(&st->inc[2 * kMaxProps + lane - 32], kValid | (accc + s_cagg[lane - 32]),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_tcnt[lane - 32] = accc;
-        }
-    }
-    __syncthreads();
-
-    // second walk: final state at every instance end; numbering of nodes
-    uint32_t cur[PMAX];
-#pragma unroll
-    for (int p = 0; p < PMAX; ++p)
-        cur[p] = p < (int)P ? map_at(map_compose(excl[p], s_tprefix[p]), 0) : 0u;
-    uint32_t inst = s_tcnt[0] + cexcl[0];
-    uint32_t lvl[4];
-#pragma unroll
-    for (int m = 1; m < 4; ++m) lvl[m] = s_tcnt[m] + cexcl[m];
-    // Instance verdicts are staged in LDS (the word buffer is free now) and
-    // written out contiguously: the instances ending in this tile have the
-    // consecutive ids [s_ilo, s_ihi], all >= s_tcnt[0] - 1.
-    const bool stage = P <= 8;
-    uint8_t* s_iv = reinterpret_cast<uint8_t*>(s_w);
-    constexpr uint32_t kIvStride = kScanTile + 1;
-    const uint32_t id_base = s_tcnt[0];             // slot of id = id + 1 - id_base
-    uint32_t my_lo = 0xFFFFFFFFu, my_hi = 0u;       // ids [my_lo, my_hi) this thread staged
-    uint32_t err = 0;
-    for (int j = 0; j < kScanItems; ++j) {
-        if (!((m_valid >> j) & 1u)) break;
-        const uint64_t x = wv[j];
-        const uint32_t c = (uint32_t)x & cmask;
-        if ((m_head >> j) & 1u) {
-            ++inst;
-#pragma unroll
-            for (int p = 0; p < PMAX; ++p) cur[p] = p < (int)P ? s_q0[p] : 0u;
-#pragma unroll
-            for (int m = kMaxLevels - 1; m >= 1; --m) {
-                if (m >= (int)L || !((m_lvl[m] >> j) & 1u)) continue;
-                ++lvl[m];
-                const uint64_t id = lvl[m] - 1;
-                const uint32_t child = m == (int)L - 1 ? inst - 1 : lvl[m < 3 ? m + 1 : 3] - 1;
-                if (id < a.node_limit[m]) {
-                    a.node_start[m][id] = child;
-                    if (a.node_keys[m]) a.node_keys[m][id] = x >> a.prefix_shift[m];
-                    zero_node_counts(a, m, id);
-                } else {
-                    err |= kErrCapacity;
-                }
-            }
-        }
-#pragma unroll
-        for (int p = 0; p < PMAX; ++p)
-            if (p < (int)P) cur[p] = s_delta[p][cur[p] * 16 + c];
-        if ((m_end >> j) & 1u) {
-            const uint64_t id = inst - 1;
-            if (id < a.inst_limit) {
-                if (stage) {
-                    const uint32_t slot = (uint32_t)id + 1u - id_base;
-#pragma unroll
-                    for (int p = 0; p < (PMAX < 8 ? PMAX : 8); ++p)
-                        if (p < (int)P) s_iv[p * kIvStride + slot] = a.emit_state ? cur[p] : s_label[p][cur[p]];
-                    my_lo = min(my_lo, (uint32_t)id);
-                    my_hi = max(my_hi, (uint32_t)id + 1u);
-                } else {
-#pragma unroll
-                    for (int p = 0; p < PMAX; ++p)
-                        if (p < (int)P)
-                            a.inst_verdict[p * a.inst_stride + id] = a.emit_state ? cur[p] : s_label[p][cur[p]];
-                }
-                if (a.inst_keys) a.inst_keys[id] = x >> cb;
-                if (a.inst_parent) a.inst_parent[id] = (L >= 4 ? lvl[3] : L == 3 ? lvl[2] : lvl[1]) - 1u;
-            } else {
-                err |= kErrCapacity;
-            }
-        }
-    }
-    if (err) atomicOr(a.err, err);
-    if (stage) {
-        // block min / max of the staged id range
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            my_lo = min(my_lo, (uint32_t)__shfl_xor(my_lo, off, 64));
-            my_hi = max(my_hi, (uint32_t)__shfl_xor(my_hi, off, 64));
-        }
-        if (lane == 0) {
-            s_red[0][w] = my_lo;
-            s_red[1][w] = my_hi;
-        }
-        __syncthreads();
-        uint32_t lo = s_red[0][0], hi = s_red[1][0];
-        for (int i = 1; i < WAVES; ++i) {
-            lo = min(lo, s_red[0][i]);
-            hi = max(hi, s_red[1][i]);
-        }
-        if (lo < hi) {
-            const uint32_t cnt_iv = hi - lo, slot0 = lo + 1u - id_base;
-            for (uint32_t p = 0; p < P; ++p)
-                for (uint32_t i = tid; i < cnt_iv; i += kScanThreads)
-                    a.inst_verdict[p * a.inst_stride + lo + i] = s_iv[p * kIvStride + slot0 + i];
-        }
-    }
-    // the thread holding the last event publishes the totals
-    const uint64_t my0 = base + (uint64_t)tid * kScanItems;
-    if (my0 <= a.n - 1 && a.n - 1 < my0 + kScanItems) {
-#pragma unroll
-        for (int m = 0; m < kMaxLevels; ++m) {
-            if (m >= (int)L) break;
-            const uint32_t tot = s_tcnt[m] + cexcl[m] + cnt[m];
-            a.sizes[m] = tot;
-            a.sizes32[m] = tot;
-        }
-    }
-}
-
-// The same scan for up to 16 properties with compact code: property loops
-// that compose maps are not unrolled, per-property run summaries live in LDS
-// (in the word buffer, free once the words are in registers) and the states
-// of all properties are nibbles of one 64-bit register.
-template <int THREADS>
-__global__ __launch_bounds__(THREADS) void k_scan_wide(ScanArgs a) {
-    constexpr int PMAX = kMaxProps;
-    constexpr int kScanThreads = THREADS;
-    constexpr int kScanTile = THREADS * kScanItems;
-    constexpr int WAVES = THREADS / 64;
-    __shared__ uint64_t s_w[kScanTile + kScanTile / 16 + 1];
-    __shared__ uint8_t s_delta[PMAX][kStates * 16];
-    __shared__ uint8_t s_label[PMAX][kStates];
-    __shared__ uint64_t s_colmap[PMAX][16];
-    __shared__ uint32_t s_q0[PMAX];
-    __shared__ uint64_t s_wtot[PMAX][WAVES];
-    __shared__ uint32_t s_ctot[4][WAVES];
-    __shared__ uint64_t s_tprefix[PMAX];
-    __shared__ uint64_t s_tagg[PMAX];
-    __shared__ uint32_t s_cagg[4];
-    __shared__ uint32_t s_tcnt[4];
-    __shared__ uint64_t s_prev, s_next;
-    __shared__ uint32_t s_tile;
-    __shared__ uint32_t s_red[2][WAVES];
-
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const uint32_t P = a.n_props;
-    if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
-    for (uint32_t i = tid; i < P * kStates * 16; i += kScanThreads)
-        s_delta[i / (kStates * 16)][i % (kStates * 16)] = a.plan->prop[i / (kStates * 16)].delta[i % (kStates * 16)];
-    if (tid < (int)(P * 16)) {
-        s_label[tid / 16][tid % 16] = a.plan->prop[tid / 16].label[tid % 16];
-        s_colmap[tid / 16][tid % 16] = a.plan->prop[tid / 16].colmap[tid % 16];
-    }
-    if (tid < (int)P) s_q0[tid] = a.plan->prop[tid].q0;
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    const uint64_t base = (uint64_t)tile * kScanTile;
-    const uint64_t kInvalid = ~0ull;
-#pragma unroll
-    for (int r = 0; r < kScanItems; ++r) {
-        const uint64_t idx = base + r * kScanThreads + tid;
-        s_w[pad_idx(r * kScanThreads + tid)] = idx < a.n ? a.words[idx] : kInvalid;
-    }
-    if (tid == 0) s_prev = base > 0 ? a.words[base - 1] : kInvalid;
-    if (tid == 1) s_next = base + kScanTile < a.n ? a.words[base + kScanTile] : kInvalid;
-    __syncthreads();
-
-    uint64_t wv[kScanItems];
-#pragma unroll
-    for (int j = 0; j < kScanItems; ++j) wv[j] = s_w[pad_idx(tid * kScanItems + j)];
-    const uint64_t wp = tid == 0 ? s_prev : s_w[pad_idx(tid * kScanItems - 1)];
-    const uint64_t wn = tid == kScanThreads - 1 ? s_next : s_w[pad_idx(tid * kScanItems + kScanItems)];
-    const bool has_prev = base + (uint64_t)tid * kScanItems > 0;
-    const uint32_t cb = a.cbits, vs = a.valid_shift, L = a.n_levels;
-    const uint32_t cmask = (1u << cb) - 1u;
-
-    // per-event flags as bit masks
-    uint32_t m_valid = 0, m_head = 0, m_end = 0, m_lvl[kMaxLevels] = {0, 0, 0, 0};
-#pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        const uint64_t x = wv[j];
-        if ((x >> vs) != 0) continue;
-        m_valid |= 1u << j;
-        const uint64_t prv = j == 0 ? wp : wv[j - 1];
-        const bool first = (j == 0 && !has_prev);
-        const uint64_t nxt = j == kScanItems - 1 ? wn : wv[j + 1];
-        if (first || (prv >> cb) != (x >> cb)) m_head |= 1u << j;
-        if ((nxt >> vs) != 0 || (nxt >> cb) != (x >> cb)) m_end |= 1u << j;
-#pragma unroll
-        for (int m = 1; m < kMaxLevels; ++m) {
-            if (m >= (int)L) break;
-            const uint32_t sh = a.prefix_shift[m];
-            if (first || (prv >> sh) != (x >> sh)) m_lvl[m] |= 1u << j;
-        }
-    }
-    uint32_t cnt[4];
-    cnt[0] = __popc(m_head);
-#pragma unroll
-    for (int m = 1; m < 4; ++m) cnt[m] = (uint32_t)m < L ? __popc(m_lvl[m]) : 0u;
-
-    // summaries: the map from the state before this run to the state after
-    // it, per property, kept in s_map[p][tid] (the word buffer is free now)
-    __syncthreads();
-    uint64_t* s_map = s_w;                                   // [PMAX][kScanThreads]
-#pragma unroll 1
-    for (int p = 0; p < (int)P; ++p) {
-        uint64_t f = kIdentityMap;
-        bool cst = false;
-        uint32_t st = 0;
-        for (int j = 0; j < kScanItems; ++j) {
-            if (!((m_valid >> j) & 1u)) break;
-            const uint32_t c = (uint32_t)wv[j] & cmask;
-            if ((m_head >> j) & 1u) {
-                cst = true;
-                st = s_delta[p][s_q0[p] * 16 + c];
-            } else if (cst) {
-                st = s_delta[p][st * 16 + c];
-            } else {
-                f = map_compose_full(s_colmap[p][c], f);
-            }
-        }
-        uint64_t v = cst ? map_const(st) : f;
-        // wave-level inclusive composition scan
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint64_t o = shfl_up64(v, off);
-            if (lane >= off) v = map_compose(v, o);
-        }
-        const uint64_t e = shfl_up64(v, 1);
-        s_map[p * kScanThreads + tid] = lane == 0 ? kIdentityMap : e;
-        if (lane == 63) s_wtot[p][w] = v;
-    }
-    uint32_t cexcl[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint32_t incl = wave_incl_scan_u32(cnt[k]);
-        cexcl[k] = incl - cnt[k];
-        if (lane == 63) s_ctot[k][w] = incl;
-    }
-    __syncthreads();
-#pragma unroll 1
-    for (int p = 0; p < (int)P; ++p) {
-        uint64_t pre = kIdentityMap;
-        for (int i = 0; i < w; ++i) pre = map_compose(s_wtot[p][i], pre);
-        s_map[p * kScanThreads + tid] = map_compose(s_map[p * kScanThreads + tid], pre);
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        uint32_t pre = 0;
-        for (int i = 0; i < w; ++i) pre += s_ctot[k][i];
-        cexcl[k] += pre;
-    }
-    // tile aggregates: thread p composes property p, threads 32..35 sum counts
-    if (tid < (int)P) {
-        uint64_t t = kIdentityMap;
-        for (int i = 0; i < WAVES; ++i) t = map_compose(s_wtot[tid][i], t);
-        s_tagg[tid] = t;
-    }
-    if (tid >= 32 && tid < 36) {
-        const int k = tid - 32;
-        uint32_t sum = 0;
-        for (int i = 0; i < WAVES; ++i) sum += s_ctot[k][i];
-        s_cagg[k] = sum;
-    }
-    __syncthreads();
-
-    // publish this tile's aggregate, then look back (wave 0).  Lane p < P
-    // owns property p's map (two status words), lanes 32..35 the counts.
-    ScanTileStatus* st = a.status + tile;
-    const uint64_t kValid = 1ull << 32;
-    if (w == 0) {
-        if (lane < (int)P) {
-            const uint64_t m = s_tagg[lane];
-            __hip_atomic_store(&st->agg[2 * lane], kValid | (m & 0xFFFFFFFFull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&st->agg[2 * lane + 1], kValid | (m >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (lane >= 32 && lane < 36)
-            __hip_atomic_store(&st->agg[2 * kMaxProps + lane - 32], kValid | s_cagg[lane - 32], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        const bool owns = lane < (int)P || (lane >= 32 && lane < 36);
-        const int w0 = lane < 32 ? 2 * lane : 2 * kMaxProps + lane - 32;   // first word of this lane
-        const int nw = lane < 32 ? 2 : 1;
-        uint64_t acc = kIdentityMap;
-        uint32_t accc = 0;
-        if (tile > 0) {
-            // windowed look-back: every owning lane fetches the aggregate and
-            // inclusive words of kScanLookWindow predecessors in one round trip,
-            // then folds them nearest first until an inclusive tile
-            int64_t j = (int64_t)tile - 1;
-            uint32_t spins = 0;
-            bool done = false;
-            while (!done) {
-                uint64_t ia[kScanLookWindow], ib[kScanLookWindow], aa[kScanLookWindow], ab[kScanLookWindow];
-#pragma unroll
-                for (int k = 0; k < kScanLookWindow; ++k) {
-                    ia[k] = ib[k] = aa[k] = ab[k] = kValid;
-                    if (owns && j - k >= 0) {
-                        const ScanTileStatus* sj = a.status + (j - k);
-                        ia[k] = __hip_atomic_load(&sj->inc[w0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        aa[k] = __hip_atomic_load(&sj->agg[w0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        if (nw == 2) {
-                            ib[k] = __hip_atomic_load(&sj->inc[w0 + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            ab[k] = __hip_atomic_load(&sj->agg[w0 + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        }
-                    }
-                }
-                int used = 0;
-                bool stop = false;
-#pragma unroll
-                for (int k = 0; k < kScanLookWindow; ++k) {
-                    if (stop || done) continue;
-                    if (j - k < 0) { done = true; continue; }
-                    const bool inc_ok = __all(((ia[k] & kValid) != 0) && ((ib[k] & kValid) != 0));
-                    const bool agg_ok = __all(((aa[k] & kValid) != 0) && ((ab[k] & kValid) != 0));
-                    if (!inc_ok && !agg_ok) { stop = true; continue; }
-                    const uint64_t v0 = inc_ok ? ia[k] : aa[k], v1 = inc_ok ? ib[k] : ab[k];
-                    if (lane < (int)P) acc = map_compose(acc, (v0 & 0xFFFFFFFFull) | ((v1 & 0xFFFFFFFFull) << 32));
-                    if (lane >= 32 && lane < 36) accc += (uint32_t)v0;
-                    used = k + 1;
-                    if (inc_ok) done = true;
-                }
-                j -= used;
-                if (!done && j < 0) done = true;
-                if (!done && used == 0) {
-                    if (++spins > kSpinLimit) {
-                        if (lane == 0) atomicOr(a.err, kErrSpin);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-            }
-        }
-        // publish the inclusive value
-        if (lane < (int)P) {
-            const uint64_t m = tile > 0 ? map_compose(s_tagg[lane], acc) : s_tagg[lane];
-            __hip_atomic_store(&st->inc[2 * lane], kValid | (m & 0xFFFFFFFFull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&st->inc[2 * lane + 1], kValid | (m >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_tprefix[lane] = acc;
-        }
-        if (lane >= 32 && lane < 36) {
-            __hip_atomic_store(&st->inc[2 * kMaxProps + lane - 32], kValid | (accc + s_cagg[lane - 32]),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_tcnt[lane - 32] = accc;
-        }
-    }
-    __syncthreads();
-
-    // second walk: final state at every instance end; numbering of nodes.
-    // States of all properties are nibbles of curp.
-    uint64_t curp = 0, q0p = 0;
-#pragma unroll 1
-    for (int p = 0; p < (int)P; ++p) {
-        curp |= (uint64_t)map_at(map_compose(s_map[p * kScanThreads + tid], s_tprefix[p]), 0) << (4 * p);
-        q0p |= (uint64_t)s_q0[p] << (4 * p);
-    }
-    __syncthreads();                                          // s_map no longer needed
-    uint32_t inst = s_tcnt[0] + cexcl[0];
-    uint32_t lvl[4];
-#pragma unroll
-    for (int m = 1; m < 4; ++m) lvl[m] = s_tcnt[m] + cexcl[m];
-    // Instance verdicts are staged in LDS (the word buffer is free now) and
-    // written out contiguously: the instances ending in this tile have the
-    // consecutive ids [s_ilo, s_ihi], all >= s_tcnt[0] - 1.
-    const bool stage = P <= 8;
-    uint8_t* s_iv = reinterpret_cast<uint8_t*>(s_w);
-    constexpr uint32_t kIvStride = kScanTile + 1;
-    const uint32_t id_base = s_tcnt[0];             // slot of id = id + 1 - id_base
-    uint32_t my_lo = 0xFFFFFFFFu, my_hi = 0u;       // ids [my_lo, my_hi) this thread staged
-    uint32_t err = 0;
-    for (int j = 0; j < kScanItems; ++j) {
-        if (!((m_valid >> j) & 1u)) break;
-        const uint64_t x = wv[j];
-        const uint32_t c = (uint32_t)x & cmask;
-        if ((m_head >> j) & 1u) {
-            ++inst;
-            curp = q0p;
-#pragma unroll
-            for (int m = kMaxLevels - 1; m >= 1; --m) {
-                if (m >= (int)L || !((m_lvl[m] >> j) & 1u)) continue;
-                ++lvl[m];
-                const uint64_t id = lvl[m] - 1;
-                const uint32_t child = m == (int)L - 1 ? inst - 1 : lvl[m < 3 ? m + 1 : 3] - 1;
-                if (id < a.node_limit[m]) {
-                    a.node_start[m][id] = child;
-                    if (a.node_keys[m]) a.node_keys[m][id] = x >> a.prefix_shift[m];
-                    zero_node_counts(a, m, id);
-                } else {
-                    err |= kErrCapacity;
-                }
-            }
-        }
-        {
-            uint64_t nxt = 0;
-#pragma unroll
-            for (int p = 0; p < PMAX; ++p)
-                if (p < (int)P) nxt |= (uint64_t)s_delta[p][((curp >> (4 * p)) & 15u) * 16 + c] << (4 * p);
-            curp = nxt;
-        }
-        if ((m_end >> j) & 1u) {
-            const uint64_t id = inst - 1;
-            if (id < a.inst_limit) {
-                if (stage) {
-                    const uint32_t slot = (uint32_t)id + 1u - id_base;
-#pragma unroll
-                    for (int p = 0; p < 8; ++p)
-                        if (p < (int)P) {
-                            const uint32_t q = (uint32_t)(curp >> (4 * p)) & 15u;
-                            s_iv[p * kIvStride + slot] = a.emit_state ? q : s_label[p][q];
-                        }
-                    my_lo = min(my_lo, (uint32_t)id);
-                    my_hi = max(my_hi, (uint32_t)id + 1u);
-                } else {
-#pragma unroll
-                    for (int p = 0; p < PMAX; ++p)
-                        if (p < (int)P) {
-                            const uint32_t q = (uint32_t)(curp >> (4 * p)) & 15u;
-                            a.inst_verdict[p * a.inst_stride + id] = a.emit_state ? q : s_label[p][q];
-                        }
-                }
-                if (a.inst_keys) a.inst_keys[id] = x >> cb;
-                if (a.inst_parent) a.inst_parent[id] = (L >= 4 ? lvl[3] : L == 3 ? lvl[2] : lvl[1]) - 1u;
-            } else {
-                err |= kErrCapacity;
-            }
-        }
-    }
-    if (err) atomicOr(a.err, err);
-    if (stage) {
-        // block min / max of the staged id range
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            my_lo = min(my_lo, (uint32_t)__shfl_xor(my_lo, off, 64));
-            my_hi = max(my_hi, (uint32_t)__shfl_xor(my_hi, off, 64));
-        }
-        if (lane == 0) {
-            s_red[0][w] = my_lo;
-            s_red[1][w] = my_hi;
-        }
-        __syncthreads();
-        uint32_t lo = s_red[0][0], hi = s_red[1][0];
-        for (int i = 1; i < WAVES; ++i) {
-            lo = min(lo, s_red[0][i]);
-            hi = max(hi, s_red[1][i]);
-        }
-        if (lo < hi) {
-            const uint32_t cnt_iv = hi - lo, slot0 = lo + 1u - id_base;
-            for (uint32_t p = 0; p < P; ++p)
-                for (uint32_t i = tid; i < cnt_iv; i += kScanThreads)
-                    a.inst_verdict[p * a.inst_stride + lo + i] = s_iv[p * kIvStride + slot0 + i];
-        }
-    }
-    // the thread holding the last event publishes the totals
-    const uint64_t my0 = base + (uint64_t)tid * kScanItems;
-    if (my0 <= a.n - 1 && a.n - 1 < my0 + kScanItems) {
-#pragma unroll
-        for (int m = 0; m < kMaxLevels; ++m) {
-            if (m >= (int)L) break;
-            const uint32_t tot = s_tcnt[m] + cexcl[m] + cnt[m];
-            a.sizes[m] = tot;
-            a.sizes32[m] = tot;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// segmented transition-map scan for monitors of at most 8 states
-// ---------------------------------------------------------------------------
-// A map over at most 8 states is a uint64 whose byte q holds the image of q.
-// The composition g∘f (f applied first) picks, for every byte of f, the byte
-// of g it names: two byte permutes, with no constant-map special cases.  A
-// state steps through one permute as well.
-constexpr uint64_t kByteIdentity = 0x0706050403020100ull;
-
-__device__ __forceinline__ uint64_t bmap_compose(uint64_t g, uint64_t f) {
-    const uint32_t g0 = (uint32_t)g, g1 = (uint32_t)(g >> 32);
-    return (uint64_t)__builtin_amdgcn_perm(g1, g0, (uint32_t)f) |
-           ((uint64_t)__builtin_amdgcn_perm(g1, g0, (uint32_t)(f >> 32)) << 32);
-}
-__device__ __forceinline__ uint32_t bmap_at(uint64_t g, uint32_t q) {
-    return __builtin_amdgcn_perm((uint32_t)(g >> 32), (uint32_t)g, q) & 0xFFu;
-}
-__device__ __forceinline__ uint64_t bmap_const(uint32_t s) { return (uint64_t)s * 0x0101010101010101ull; }
-
-// Look-back records in structure-of-arrays form: row r of the aggregates of
-// tile t is st[r * tiles + t], row r of the inclusive values
-// st[(kScanStatusWords + r) * tiles + t].  Rows 0..3 are the instance / node
-// counts, rows 4 + 2p and 5 + 2p the halves of property p's map, so that the
-// lanes of one wave reading one row of 64 consecutive tiles read one
-// contiguous 512-byte span.  Every word is a 32-bit payload under the
-// validity bit 32, as in the other scan.
-template <int PMAX, int THREADS>
-__global__ __launch_bounds__(THREADS) void k_scan8(ScanArgs a) {
+    static_assert(PMAX * MW <= 16 && 4 + PMAX * MW <= kScanRows, "look-back record of at most 20 words");
+    constexpr bool kParents = PMAX <= 4;       // LDS room to stage parent ids
     constexpr int TILE = THREADS * kScanItems;
     constexpr int WAVES = THREADS / 64;
-    constexpr int NW = 4 + 2 * PMAX;          // record words in use (at most)
+    constexpr int NW = 4 + MW * PMAX;          // record words in use (at most)
     __shared__ uint64_t s_w[TILE + TILE / 16 + 1];
-    __shared__ uint64_t s_cm[PMAX][16];
-    __shared__ uint32_t s_q0[PMAX], s_lab[PMAX];
-    __shared__ uint64_t s_wtot[PMAX][WAVES];
+    __shared__ uint32_t s_cm[PMAX][16][MW];
+    __shared__ uint32_t s_q0[PMAX], s_lab[PMAX][2];
+    __shared__ uint32_t s_wtot[PMAX][WAVES][MW];
     __shared__ uint32_t s_ctot[4][WAVES];
-    __shared__ uint64_t s_tprefix[PMAX];
-    __shared__ uint64_t s_tagg[PMAX];
+    __shared__ uint32_t s_tprefix[PMAX][MW];
+    __shared__ uint32_t s_tagg[PMAX][MW];
     __shared__ uint32_t s_cagg[4];
     __shared__ uint32_t s_tcnt[4];
     __shared__ uint64_t s_prev, s_next;
@@ -1148,12 +506,18 @@ __global__ __launch_bounds__(THREADS) void k_scan8(ScanArgs a) {
     __shared__ uint32_t s_red[2][WAVES];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const uint32_t P = a.n_props;
+    const uint32_t P = a.n_props;               // properties of this launch
+    const bool structure = kParents && a.structure != 0;
     if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
-    if (tid < (int)(P * 16)) s_cm[tid / 16][tid % 16] = a.plan->prop[tid / 16].bcolmap[tid % 16];
+    for (uint32_t i = tid; i < P * 16 * MW; i += THREADS) {
+        const uint32_t p = i / (16 * MW), c = (i / MW) % 16, k = i % MW;
+        s_cm[p][c][k] = a.plan->prop[a.prop_idx[p]].bmap[c][k];
+    }
     if (tid < (int)P) {
-        s_q0[tid] = a.plan->prop[tid].q0;
-        s_lab[tid] = a.plan->prop[tid].blabel;
+        const PropDev& pd = a.plan->prop[a.prop_idx[tid]];
+        s_q0[tid] = pd.q0;
+        s_lab[tid][0] = pd.blabel[0];
+        s_lab[tid][1] = pd.blabel[1];
     }
     __syncthreads();
     const uint32_t tile = s_tile;
@@ -1202,30 +566,32 @@ __global__ __launch_bounds__(THREADS) void k_scan8(ScanArgs a) {
 #pragma unroll
     for (int m = 1; m < 4; ++m) cnt[m] = (uint32_t)m < L ? __popc(m_lvl[m]) : 0u;
 
-    // run summaries: a head restarts the monitor from q0
-    uint64_t excl[PMAX];
+    // run summaries (a head restarts the monitor from q0), then a
+    // wave-inclusive scan of them in lane order
+    BMap<MW> excl[PMAX];
 #pragma unroll
     for (int p = 0; p < PMAX; ++p) {
-        uint64_t f = kByteIdentity;
+        BMap<MW> f = bm_identity<MW>();
         if (p < (int)P) {
-            const uint64_t start = bmap_const(s_q0[p]);
+            const BMap<MW> start = bm_const<MW>(s_q0[p]);
 #pragma unroll
             for (int j = 0; j < kScanItems; ++j) {
                 if (j >= n_valid) break;
-                const uint64_t cm = s_cm[p][(uint32_t)wv[j] & cmask];
-                f = bmap_compose(cm, ((m_head >> j) & 1u) ? start : f);
+                const BMap<MW> cm = bm_load<MW>(s_cm[p][(uint32_t)wv[j] & cmask]);
+                f = bm_compose<MW>(cm, ((m_head >> j) & 1u) ? start : f);
             }
         }
-        // wave-inclusive scan of the summaries in lane order
-        uint64_t v = f;
+        BMap<MW> v = f;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
-            const uint64_t o = shfl_up64(v, off);
-            if (lane >= off) v = bmap_compose(v, o);
+            const BMap<MW> o = bm_shfl_up<MW>(v, off);
+            if (lane >= off) v = bm_compose<MW>(v, o);
         }
-        const uint64_t e = shfl_up64(v, 1);
-        excl[p] = lane == 0 ? kByteIdentity : e;
-        if (lane == 63) s_wtot[p][w] = v;
+        const BMap<MW> e = bm_shfl_up<MW>(v, 1);
+        excl[p] = lane == 0 ? bm_identity<MW>() : e;
+        if (lane == 63)
+#pragma unroll
+            for (int k = 0; k < MW; ++k) s_wtot[p][w][k] = v.d[k];
     }
     uint32_t cexcl[4];
 #pragma unroll
@@ -1238,9 +604,9 @@ __global__ __launch_bounds__(THREADS) void k_scan8(ScanArgs a) {
 #pragma unroll
     for (int p = 0; p < PMAX; ++p) {
         if (p >= (int)P) continue;
-        uint64_t pre = kByteIdentity;
-        for (int i = 0; i < w; ++i) pre = bmap_compose(s_wtot[p][i], pre);
-        excl[p] = bmap_compose(excl[p], pre);
+        BMap<MW> pre = bm_identity<MW>();
+        for (int i = 0; i < w; ++i) pre = bm_compose<MW>(bm_load<MW>(s_wtot[p][i]), pre);
+        excl[p] = bm_compose<MW>(excl[p], pre);
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -1249,9 +615,10 @@ __global__ __launch_bounds__(THREADS) void k_scan8(ScanArgs a) {
         cexcl[k] += pre;
     }
     if (tid < (int)P) {
-        uint64_t t = kByteIdentity;
-        for (int i = 0; i < WAVES; ++i) t = bmap_compose(s_wtot[tid][i], t);
-        s_tagg[tid] = t;
+        BMap<MW> t = bm_identity<MW>();
+        for (int i = 0; i < WAVES; ++i) t = bm_compose<MW>(bm_load<MW>(s_wtot[tid][i]), t);
+#pragma unroll
+        for (int k = 0; k < MW; ++k) s_tagg[tid][k] = t.d[k];
     }
     if (tid >= 32 && tid < 36) {
         const int k = tid - 32;
@@ -1265,34 +632,30 @@ __global__ __launch_bounds__(THREADS) void k_scan8(ScanArgs a) {
     // with one lane per predecessor tile (wave 0)
     if (w == 0) {
         const uint32_t n_tiles = (uint32_t)((a.n + TILE - 1) / TILE);
-        uint64_t* st = reinterpret_cast<uint64_t*>(a.status);
-        const uint32_t nw = 4 + 2 * P;
-        const uint64_t kValid = 1ull << 32;
-        auto payload = [&](uint32_t r, const uint64_t* maps, const uint32_t* cnts) -> uint32_t {
-            if (r < 4) return cnts[r];
-            const uint64_t m = maps[(r - 4) >> 1];
-            return (r & 1u) ? (uint32_t)(m >> 32) : (uint32_t)m;
-        };
+        uint32_t* st = a.status;
+        const uint32_t nw = 4 + MW * P;
+        const uint32_t kValid = 1u << 31;
         if (lane < (int)nw) {
-            const uint32_t row = (tile == 0 ? kScanStatusWords : 0) + lane;
-            __hip_atomic_store(st + (uint64_t)row * n_tiles + tile, kValid | payload(lane, s_tagg, s_cagg),
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t pay = lane < 4 ? s_cagg[lane] : s_tagg[(lane - 4) / MW][(lane - 4) % MW];
+            const uint32_t row = (tile == 0 ? kScanRows : 0) + lane;
+            __hip_atomic_store(st + (uint64_t)row * n_tiles + tile, kValid | pay, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         }
-        uint64_t acc[PMAX];
+        BMap<MW> acc[PMAX];
         uint32_t accc[4] = {0, 0, 0, 0};
 #pragma unroll
-        for (int p = 0; p < PMAX; ++p) acc[p] = kByteIdentity;
+        for (int p = 0; p < PMAX; ++p) acc[p] = bm_identity<MW>();
         int64_t j = (int64_t)tile - 1;
         uint32_t spins = 0;
         while (j >= 0) {
             const int64_t t = j - lane;
-            uint64_t vi[NW], va[NW];
+            uint32_t vi[NW], va[NW];
             bool inc_ok = true, agg_ok = true;
 #pragma unroll
             for (int r = 0; r < NW; ++r) {
                 vi[r] = va[r] = kValid;
                 if (r < (int)nw && t >= 0) {
-                    vi[r] = __hip_atomic_load(st + (uint64_t)(kScanStatusWords + r) * n_tiles + t, __ATOMIC_RELAXED,
+                    vi[r] = __hip_atomic_load(st + (uint64_t)(kScanRows + r) * n_tiles + t, __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT);
                     va[r] = __hip_atomic_load(st + (uint64_t)r * n_tiles + t, __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT);
@@ -1309,23 +672,24 @@ __global__ __launch_bounds__(THREADS) void k_scan8(ScanArgs a) {
             const bool done = first_inc < first_nr;
             const int take = done ? first_inc + 1 : first_nr;
             const bool mine = lane < take;
-            // fold lanes [0, take): nearest tile last applied
-            uint64_t m[PMAX];
+            // fold lanes [0, take): the nearest tile is applied last
+            BMap<MW> m[PMAX];
 #pragma unroll
-            for (int p = 0; p < PMAX; ++p) {
-                const uint32_t lo = (uint32_t)(inc_ok ? vi[4 + 2 * p] : va[4 + 2 * p]);
-                const uint32_t hi = (uint32_t)(inc_ok ? vi[5 + 2 * p] : va[5 + 2 * p]);
-                m[p] = (mine && p < (int)P) ? ((uint64_t)lo | ((uint64_t)hi << 32)) : kByteIdentity;
-            }
+            for (int p = 0; p < PMAX; ++p)
+#pragma unroll
+                for (int k = 0; k < MW; ++k) {
+                    const uint32_t x = (inc_ok ? vi[4 + MW * p + k] : va[4 + MW * p + k]) & ~kValid;
+                    m[p].d[k] = (mine && p < (int)P) ? x : 0x03020100u + 0x04040404u * (uint32_t)k;
+                }
             uint32_t c[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) c[k] = mine ? (uint32_t)(inc_ok ? vi[k] : va[k]) : 0u;
+            for (int k = 0; k < 4; ++k) c[k] = mine ? (inc_ok ? vi[k] : va[k]) & ~kValid : 0u;
 #pragma unroll
             for (int off = 1; off < 64; off <<= 1) {
 #pragma unroll
                 for (int p = 0; p < PMAX; ++p) {
-                    const uint64_t o = __shfl_down(m[p], off, 64);
-                    if (lane + off < 64) m[p] = bmap_compose(m[p], o);
+                    const BMap<MW> o = bm_shfl_down<MW>(m[p], off);
+                    if (lane + off < 64) m[p] = bm_compose<MW>(m[p], o);
                 }
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
@@ -1334,7 +698,7 @@ __global__ __launch_bounds__(THREADS) void k_scan8(ScanArgs a) {
                 }
             }
 #pragma unroll
-            for (int p = 0; p < PMAX; ++p) acc[p] = bmap_compose(acc[p], __shfl(m[p], 0, 64));
+            for (int p = 0; p < PMAX; ++p) acc[p] = bm_compose<MW>(acc[p], bm_bcast<MW>(m[p], 0));
 #pragma unroll
             for (int k = 0; k < 4; ++k) accc[k] += __shfl(c[k], 0, 64);
             j -= take;
@@ -1347,18 +711,30 @@ __global__ __launch_bounds__(THREADS) void k_scan8(ScanArgs a) {
                 __builtin_amdgcn_s_sleep(1);
             }
         }
-        if (tile > 0) {
-            uint64_t incl[PMAX];
-            uint32_t inclc[4];
+        if (tile > 0 && lane < (int)nw) {
+            uint32_t pay;
+            if (lane < 4) {
+                pay = accc[lane] + s_cagg[lane];
+            } else {
+                const int p = (lane - 4) / MW, k = (lane - 4) % MW;
+                BMap<MW> incl = bm_identity<MW>();
 #pragma unroll
-            for (int p = 0; p < PMAX; ++p) incl[p] = p < (int)P ? bmap_compose(s_tagg[p], acc[p]) : kByteIdentity;
+                for (int q = 0; q < PMAX; ++q)
+                    if (q == p) incl = bm_compose<MW>(bm_load<MW>(s_tagg[q]), acc[q]);
+                pay = incl.d[0];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) inclc[k] = accc[k] + s_cagg[k];
-            if (lane < (int)nw)
-                __hip_atomic_store(st + (uint64_t)(kScanStatusWords + lane) * n_tiles + tile,
-                                   kValid | payload(lane, incl, inclc), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (int i = 1; i < MW; ++i)
+                    if (i == k) pay = incl.d[i];
+            }
+            __hip_atomic_store(st + (uint64_t)(kScanRows + lane) * n_tiles + tile, kValid | pay, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         }
-        if (lane < (int)P) s_tprefix[lane] = acc[lane];
+        if (lane < (int)P)
+#pragma unroll
+            for (int q = 0; q < PMAX; ++q)
+                if (q == lane)
+#pragma unroll
+                    for (int k = 0; k < MW; ++k) s_tprefix[q][k] = acc[q].d[k];
         if (lane < 4) s_tcnt[lane] = accc[lane];
     }
     __syncthreads();
@@ -1367,7 +743,7 @@ __global__ __launch_bounds__(THREADS) void k_scan8(ScanArgs a) {
     uint32_t cur[PMAX];
 #pragma unroll
     for (int p = 0; p < PMAX; ++p)
-        cur[p] = p < (int)P ? bmap_at(bmap_compose(excl[p], s_tprefix[p]), 0) : 0u;
+        cur[p] = p < (int)P ? bm_at<MW>(bm_compose<MW>(excl[p], bm_load<MW>(s_tprefix[p])), 0) : 0u;
     uint32_t inst = s_tcnt[0] + cexcl[0];
     uint32_t lvl[4];
 #pragma unroll
@@ -1376,7 +752,7 @@ __global__ __launch_bounds__(THREADS) void k_scan8(ScanArgs a) {
     // then parent ids [TILE + 1]
     uint8_t* s_iv = reinterpret_cast<uint8_t*>(s_w);
     constexpr uint32_t kIvStride = TILE + 1;
-    static_assert(PMAX * kIvStride + 4 * kIvStride + 4 <= sizeof(s_w), "staging fits the word buffer");
+    static_assert(PMAX * kIvStride + (kParents ? 4 * kIvStride + 4 : 0) <= sizeof(s_w), "staging fits the word buffer");
     uint32_t* s_par = reinterpret_cast<uint32_t*>(s_iv + ((PMAX * kIvStride + 3) & ~3u));
     const uint32_t id_base = s_tcnt[0];
     uint32_t my_lo = 0xFFFFFFFFu, my_hi = 0u;
@@ -1394,6 +770,7 @@ __global__ __launch_bounds__(THREADS) void k_scan8(ScanArgs a) {
             for (int m = kMaxLevels - 1; m >= 1; --m) {
                 if (m >= (int)L || !((m_lvl[m] >> j) & 1u)) continue;
                 ++lvl[m];
+                if (!structure) continue;
                 const uint64_t id = lvl[m] - 1;
                 const uint32_t child = m == (int)L - 1 ? inst - 1 : lvl[m < 3 ? m + 1 : 3] - 1;
                 if (id < a.node_limit[m]) {
@@ -1407,7 +784,7 @@ __global__ __launch_bounds__(THREADS) void k_scan8(ScanArgs a) {
         }
 #pragma unroll
         for (int p = 0; p < PMAX; ++p)
-            if (p < (int)P) cur[p] = bmap_at(s_cm[p][c], cur[p]);
+            if (p < (int)P) cur[p] = bm_at<MW>(bm_load<MW>(s_cm[p][c]), cur[p]);
         if ((m_end >> j) & 1u) {
             const uint64_t id = inst - 1;
             if (id < a.inst_limit) {
@@ -1415,11 +792,12 @@ __global__ __launch_bounds__(THREADS) void k_scan8(ScanArgs a) {
 #pragma unroll
                 for (int p = 0; p < PMAX; ++p)
                     if (p < (int)P)
-                        s_iv[p * kIvStride + slot] = a.emit_state ? cur[p] : (s_lab[p] >> (4 * cur[p])) & 15u;
-                if (L >= 2) s_par[slot] = (L >= 4 ? lvl[3] : L == 3 ? lvl[2] : lvl[1]) - 1u;
+                        s_iv[p * kIvStride + slot] =
+                            a.emit_state ? cur[p] : (s_lab[p][cur[p] >> 3] >> (4 * (cur[p] & 7u))) & 15u;
+                if (kParents && L >= 2) s_par[slot] = (L >= 4 ? lvl[3] : L == 3 ? lvl[2] : lvl[1]) - 1u;
                 my_lo = min(my_lo, (uint32_t)id);
                 my_hi = max(my_hi, (uint32_t)id + 1u);
-                if (a.inst_keys) a.inst_keys[id] = x >> cb;
+                if (structure && a.inst_keys) a.inst_keys[id] = x >> cb;
             } else {
                 err |= kErrCapacity;
             }
@@ -1427,7 +805,7 @@ __global__ __launch_bounds__(THREADS) void k_scan8(ScanArgs a) {
     }
     if (err) atomicOr(a.err, err);
     // the instances ending in this tile have consecutive ids: write their
-    // verdicts contiguously from LDS
+    // verdicts (and parents) contiguously from LDS
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         my_lo = min(my_lo, (uint32_t)__shfl_xor(my_lo, off, 64));
@@ -1447,13 +825,13 @@ __global__ __launch_bounds__(THREADS) void k_scan8(ScanArgs a) {
         const uint32_t cnt_iv = hi - lo, slot0 = lo + 1u - id_base;
         for (uint32_t p = 0; p < P; ++p)
             for (uint32_t i = tid; i < cnt_iv; i += THREADS)
-                a.inst_verdict[p * a.inst_stride + lo + i] = s_iv[p * kIvStride + slot0 + i];
-        if (a.inst_parent)
+                a.inst_verdict[a.prop_idx[p] * a.inst_stride + lo + i] = s_iv[p * kIvStride + slot0 + i];
+        if (structure && a.inst_parent)
             for (uint32_t i = tid; i < cnt_iv; i += THREADS) a.inst_parent[lo + i] = s_par[slot0 + i];
     }
     // the thread holding the last event publishes the totals
     const uint64_t my0 = base + (uint64_t)tid * kScanItems;
-    if (my0 <= a.n - 1 && a.n - 1 < my0 + kScanItems) {
+    if (structure && my0 <= a.n - 1 && a.n - 1 < my0 + kScanItems) {
 #pragma unroll
         for (int m = 0; m < kMaxLevels; ++m) {
             if (m >= (int)L) break;
@@ -2024,28 +1402,30 @@ hipError_t launch_sort_pass(const SortPassArgs& a, int variant, hipStream_t s) {
 template <int T>
 static void launch_scan_t(const ScanArgs& a, hipStream_t s) {
     const uint32_t tiles = (a.n + T * kScanItems - 1) / (T * kScanItems);
-    if (a.max_states <= 8 && a.n_props <= 4) {
+    if (a.max_states <= 8) {
         if (a.n_props <= 1)
-            hipLaunchKernelGGL((k_scan8<1, T>), dim3(tiles), dim3(T), 0, s, a);
+            hipLaunchKernelGGL((k_scan<1, 2, T>), dim3(tiles), dim3(T), 0, s, a);
         else if (a.n_props <= 2)
-            hipLaunchKernelGGL((k_scan8<2, T>), dim3(tiles), dim3(T), 0, s, a);
+            hipLaunchKernelGGL((k_scan<2, 2, T>), dim3(tiles), dim3(T), 0, s, a);
+        else if (a.n_props <= 4)
+            hipLaunchKernelGGL((k_scan<4, 2, T>), dim3(tiles), dim3(T), 0, s, a);
         else
-            hipLaunchKernelGGL((k_scan8<4, T>), dim3(tiles), dim3(T), 0, s, a);
-        return;
+            hipLaunchKernelGGL((k_scan<8, 2, T>), dim3(tiles), dim3(T), 0, s, a);
+    } else {
+        if (a.n_props <= 1)
+            hipLaunchKernelGGL((k_scan<1, 4, T>), dim3(tiles), dim3(T), 0, s, a);
+        else if (a.n_props <= 2)
+            hipLaunchKernelGGL((k_scan<2, 4, T>), dim3(tiles), dim3(T), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_scan<4, 4, T>), dim3(tiles), dim3(T), 0, s, a);
     }
-    if (a.n_props <= 1)
-        hipLaunchKernelGGL((k_scan<1, T>), dim3(tiles), dim3(T), 0, s, a);
-    else if (a.n_props <= 2)
-        hipLaunchKernelGGL((k_scan<2, T>), dim3(tiles), dim3(T), 0, s, a);
-    else if (a.n_props <= 4)
-        hipLaunchKernelGGL((k_scan<4, T>), dim3(tiles), dim3(T), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_scan_wide<T>, dim3(tiles), dim3(T), 0, s, a);
 }
 
 uint32_t scan_tile(int variant) { return (variant == 1 ? 512u : 256u) * kScanItems; }
 
 hipError_t launch_scan(const ScanArgs& a, int variant, hipStream_t s) {
+    if (a.n_props < 1 || a.n_props > (a.max_states <= 8 ? 8u : 4u) || (a.structure && a.n_props > 4))
+        return hipErrorInvalidValue;
     if (variant == 1) launch_scan_t<512>(a, s);
     else launch_scan_t<256>(a, s);
     return hipGetLastError();

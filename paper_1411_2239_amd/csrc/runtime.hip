@@ -123,8 +123,57 @@ struct WsLayout {
     uint32_t tiles_sort, tiles_scan;
 };
 
-WsLayout plan_workspace(const ltl4c_layout& L, const Geometry& g, uint64_t n, uint32_t P, int sort_variant,
-                        int scan_variant) {
+// Properties share scan launches by monitor size: up to 8 whose monitors have
+// at most 8 states (two-dword maps), up to 4 of larger ones (four dwords).
+// The numbering (instances, nodes, parents, sizes) comes from a launch of at
+// most 4 properties, which runs first.
+struct ScanGroup {
+    uint32_t cnt, states;
+    uint8_t idx[kScanGroupProps];
+    bool structure;
+};
+
+std::vector<ScanGroup> scan_groups(const std::vector<uint32_t>& states) {
+    std::vector<uint32_t> small, big;
+    for (uint32_t i = 0; i < states.size(); ++i) (states[i] <= 8 ? small : big).push_back(i);
+    std::vector<ScanGroup> out;
+    auto emit = [&](const std::vector<uint32_t>& v, uint32_t per) {
+        for (size_t i = 0; i < v.size(); i += per) {
+            ScanGroup gr{};
+            gr.cnt = (uint32_t)std::min<size_t>(per, v.size() - i);
+            for (uint32_t k = 0; k < gr.cnt; ++k) {
+                gr.idx[k] = (uint8_t)v[i + k];
+                gr.states = std::max(gr.states, states[v[i + k]]);
+            }
+            out.push_back(gr);
+        }
+    };
+    emit(big, 4);
+    emit(small, kScanGroupProps);
+    if (out.empty()) return out;
+    size_t sg = 0;
+    while (sg < out.size() && out[sg].cnt > 4) ++sg;
+    if (sg == out.size()) {                 // only groups of 8: split the first one
+        ScanGroup rest = out[0];
+        rest.cnt = out[0].cnt - 4;
+        for (uint32_t k = 0; k < rest.cnt; ++k) rest.idx[k] = out[0].idx[4 + k];
+        out[0].cnt = 4;
+        out.insert(out.begin() + 1, rest);
+        sg = 0;
+    }
+    std::swap(out[0], out[sg]);
+    out[0].structure = true;
+    return out;
+}
+
+std::vector<uint32_t> monitor_states(const ltl4c_ctx* ctx, const int32_t* props, int32_t n_props) {
+    std::vector<uint32_t> st;
+    for (int32_t i = 0; i < n_props; ++i) st.push_back(ctx->monitors[ctx->props[props[i]].monitor].n_states);
+    return st;
+}
+
+WsLayout plan_workspace(const ltl4c_layout& L, const Geometry& g, uint64_t n, uint32_t P, uint32_t n_scan_groups,
+                        int sort_variant, int scan_variant) {
     WsLayout w{};
     const uint64_t st = sort_tile(sort_variant);
     w.tiles_sort = (uint32_t)((n + st - 1) / st);
@@ -140,7 +189,7 @@ WsLayout plan_workspace(const ltl4c_layout& L, const Geometry& g, uint64_t n, ui
     w.sizes64_off = z;     z += 64;                      // 32 x uint64
     w.sort_status_off = z; z += (uint64_t)g.n_pass * w.tiles_sort * kRadix;
     z = (z + 63) & ~63ull;
-    w.scan_status_off = z; z += (uint64_t)w.tiles_scan * (sizeof(ScanTileStatus) / 4);
+    w.scan_status_off = z; z += (uint64_t)n_scan_groups * w.tiles_scan * (2 * kScanRows);   // 2 kinds x 32-bit words
     z = (z + 63) & ~63ull;
     w.zero_off = 0;
     w.zero_words = z;
@@ -194,24 +243,13 @@ int32_t check_layout(const ltl4c_layout* L) {
 PropDev make_prop(const MonitorHost& M, const ltl4c_property& p, uint32_t shift = 0) {
     PropDev d;
     std::memset(&d, 0, sizeof d);
-    for (uint32_t q = 0; q < M.n_states; ++q)
-        for (uint32_t c = 0; c < M.n_classes; ++c) d.delta[q * 16 + c] = M.delta[q * M.n_classes + c];
     for (uint32_t q = 0; q < M.n_states; ++q) d.label[q] = M.label[q];
-    for (uint32_t c = 0; c < 16; ++c) {
-        uint64_t m = 0;
+    for (uint32_t c = 0; c < 16; ++c)
         for (uint32_t q = 0; q < 16; ++q) {
-            uint64_t to = (c < M.n_classes && q < M.n_states) ? M.delta[q * M.n_classes + c] : q;
-            m |= to << (4 * q);
+            const uint32_t to = (c < M.n_classes && q < M.n_states) ? M.delta[q * M.n_classes + c] : q;
+            d.bmap[c][q / 4] |= to << (8 * (q % 4));
         }
-        d.colmap[c] = m;
-        uint64_t b = 0;
-        for (uint32_t q = 0; q < 8; ++q) {
-            uint64_t to = (c < M.n_classes && q < M.n_states) ? M.delta[q * M.n_classes + c] : q;
-            b |= (to & 0xFF) << (8 * q);
-        }
-        d.bcolmap[c] = b;
-    }
-    for (uint32_t q = 0; q < M.n_states && q < 8; ++q) d.blabel |= (uint32_t)(M.label[q] & 15) << (4 * q);
+    for (uint32_t q = 0; q < M.n_states; ++q) d.blabel[q / 8] |= (uint32_t)(M.label[q] & 15) << (4 * (q % 8));
     d.q0 = M.q0;
     d.n_states = M.n_states;
     if (shift) {
@@ -397,6 +435,7 @@ int32_t enqueue_front(ltl4c_ctx* ctx, const ltl4c_layout& L, const Geometry& g, 
 // A stream group: the resident monitor tree of up to max_streams streams.
 struct GroupHost {
     std::vector<int32_t> props;
+    std::vector<ScanGroup> sgroups;    // scan launches over the virtual properties
     int sort_variant = 0, scan_variant = 0;   // schedules fixed when the group opens
     uint32_t P = 0, V = 0, S = 0, max_bindings = 0;
     uint64_t max_batch = 0;
@@ -508,7 +547,13 @@ int32_t group_configure(ltl4c_ctx* ctx, GroupHost& G, const int32_t* props, int3
     G.lay_ws.n_keys = 1;
     Geometry g1 = G.g;
     g1.n_levels = 1;                    // the scan of a push numbers segments only
-    G.w = plan_workspace(G.lay_ws, g1, max_batch, G.V, ctx->sort_variant, ctx->scan_variant);
+    std::vector<uint32_t> vstates;
+    for (int32_t i = 0; i < n_props; ++i) {
+        const uint32_t ns = ctx->monitors[ctx->props[props[i]].monitor].n_states;
+        vstates.insert(vstates.end(), ns, ns);
+    }
+    G.sgroups = scan_groups(vstates);
+    G.w = plan_workspace(G.lay_ws, g1, max_batch, G.V, (uint32_t)G.sgroups.size(), ctx->sort_variant, ctx->scan_variant);
     G.seg_keys_off = align256(G.w.total);
     G.ws_bytes = G.seg_keys_off + 8 * max_batch;
     G.state_bytes = group_state_layout(G, L.n_keys, nullptr, nullptr);
@@ -661,22 +706,19 @@ int32_t ltl4c_workspace_bytes(ltl4c_ctx* ctx, uint64_t n_events, const int32_t* 
     if (!bytes) return fail(LTL4C_EINVAL, "bytes is NULL");
     if (n_events > LTL4C_MAX_EVENTS) return fail(LTL4C_EUNSUPPORTED, "too many events for one call");
     Geometry g = geometry(ctx->layout);
-    *bytes = plan_workspace(ctx->layout, g, n_events, (uint32_t)n_props, ctx->sort_variant, ctx->scan_variant).total;
+    *bytes = plan_workspace(ctx->layout, g, n_events, (uint32_t)n_props,
+                            (uint32_t)scan_groups(monitor_states(ctx, props, n_props)).size(), ctx->sort_variant,
+                            ctx->scan_variant)
+                 .total;
     return LTL4C_OK;
 }
 
 // The evaluation pipeline after validation: zero, classify, radix passes,
 // scan, counting per level, finalize.  g.n_levels tree levels; when a chunk
 // table is given the chunk index (a trace id) is the top key.
-static uint32_t max_states_of(const ltl4c_ctx* ctx, const int32_t* props, int32_t n_props) {
-    uint32_t m = 0;
-    for (int32_t i = 0; i < n_props; ++i)
-        m = std::max(m, ctx->monitors[ctx->props[props[i]].monitor].n_states);
-    return m;
-}
-
 static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, void* d_ws, const void* d_records,
-                         uint64_t n, const Plan* plan, uint32_t P, uint32_t max_states, const uint32_t* chunk_off,
+                         uint64_t n, const Plan* plan, uint32_t P, const std::vector<ScanGroup>& groups,
+                         const uint32_t* chunk_off,
                          const uint32_t* chunk_stream, uint32_t n_chunks, const ltl4c_result* out) {
     const ltl4c_layout& L = ctx->layout;
     const uint32_t NL = g.n_levels;
@@ -688,7 +730,7 @@ static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, v
     uint32_t* sizes32 = z + w.sizes32_off;
     uint64_t* sizes64 = reinterpret_cast<uint64_t*>(z + w.sizes64_off);
     uint64_t* words_a = reinterpret_cast<uint64_t*>(ws + w.words_a_off);
-    ScanTileStatus* scan_status = reinterpret_cast<ScanTileStatus*>(z + w.scan_status_off);
+    uint32_t* scan_status = z + w.scan_status_off;
     const hipStream_t st = ctx->stream;
 
     {
@@ -732,8 +774,7 @@ static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, v
         sa.n_levels = NL;
         for (uint32_t m = 1; m < NL; ++m) sa.prefix_shift[m] = g.cbits + (g.key_bits_total - g.prefix_bits[m]);
         sa.valid_shift = g.cbits + g.key_bits_total;
-        sa.n_props = P;
-        sa.max_states = max_states;
+        sa.n_props_all = P;
         sa.plan = plan;
         sa.inst_verdict = inst_verdict;
         sa.inst_stride = inst_stride;
@@ -748,13 +789,21 @@ static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, v
         }
         uint32_t* inst_parent = NL >= 2 ? reinterpret_cast<uint32_t*>(ws + w.inst_parent_off) : nullptr;
         sa.inst_parent = inst_parent;
-        sa.status = scan_status;
-        sa.ticket = scan_ticket;
         sa.sizes = sizes64;
         sa.sizes32 = sizes32;
         sa.err = ctx->err_dev;
-        s = launch(ctx, "scan", [&] { return launch_scan(sa, ctx->scan_variant, st); });
-        if (s) return s;
+        // one launch per property group, each with its own look-back rows and
+        // ticket; the first one also writes the numbering
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            sa.n_props = groups[gi].cnt;
+            std::memcpy(sa.prop_idx, groups[gi].idx, sizeof sa.prop_idx);
+            sa.max_states = groups[gi].states;
+            sa.structure = groups[gi].structure ? 1u : 0u;
+            sa.status = scan_status + gi * 2ull * kScanRows * w.tiles_scan;
+            sa.ticket = scan_ticket + gi;
+            s = launch(ctx, "scan", [&] { return launch_scan(sa, ctx->scan_variant, st); });
+            if (s) return s;
+        }
 
         for (int m = (int)NL - 1; m >= 0; --m) {
             CountArgs c{};
@@ -820,7 +869,8 @@ int32_t ltl4c_eval(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int3
     if (n > 0 && (reinterpret_cast<uintptr_t>(d_records) & 3))
         return fail(LTL4C_EINVAL, "records must be 4-byte aligned");
     Geometry g = geometry(L);
-    WsLayout w = plan_workspace(L, g, n, P, ctx->sort_variant, ctx->scan_variant);
+    const std::vector<ScanGroup> groups = scan_groups(monitor_states(ctx, props, n_props));
+    WsLayout w = plan_workspace(L, g, n, P, (uint32_t)groups.size(), ctx->sort_variant, ctx->scan_variant);
     if (ws_bytes < w.total) return fail(LTL4C_ENOMEM, "workspace smaller than ltl4c_workspace_bytes()");
     if ((out->inst_keys != nullptr) != (out->inst_verdict != nullptr))
         return fail(LTL4C_EINVAL, "inst_keys and inst_verdict are given together or not at all");
@@ -839,8 +889,7 @@ int32_t ltl4c_eval(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int3
     if (s) return s;
     HIP_TRY(hipSetDevice(ctx->device));
 
-    return eval_core(ctx, g, w, d_ws, d_records, n, plan, P, max_states_of(ctx, props, n_props), nullptr, nullptr,
-                     0, out);
+    return eval_core(ctx, g, w, d_ws, d_records, n, plan, P, groups, nullptr, nullptr, 0, out);
 }
 
 
@@ -853,7 +902,8 @@ struct BatchLayout {
     uint64_t root_off, keys_off, counts_off, verdict_off, cap1, total;
 };
 
-int32_t batch_layout(ltl4c_ctx* ctx, uint64_t n, int32_t n_traces, uint32_t P, BatchLayout* b) {
+int32_t batch_layout(ltl4c_ctx* ctx, uint64_t n, int32_t n_traces, uint32_t P, uint32_t n_scan_groups,
+                     BatchLayout* b) {
     const ltl4c_layout& L = ctx->layout;
     if (n_traces < 1 || n_traces > (int32_t)kMaxChunks) return fail(LTL4C_EUNSUPPORTED, "n_traces must be 1..4096");
     if (L.n_keys + 1 > (uint32_t)kMaxLevels)
@@ -862,7 +912,7 @@ int32_t batch_layout(ltl4c_ctx* ctx, uint64_t n, int32_t n_traces, uint32_t P, B
     b->g = geometry(L, std::max<uint32_t>(1, bits_for((uint32_t)n_traces)), true);
     if (b->g.cbits + b->g.key_bits_total + (b->g.excl ? 1 : 0) > 63)
         return fail(LTL4C_EUNSUPPORTED, "trace id, keys and class bits exceed 63 bits");
-    b->w = plan_workspace(L, b->g, n, P, ctx->sort_variant, ctx->scan_variant);
+    b->w = plan_workspace(L, b->g, n, P, n_scan_groups, ctx->sort_variant, ctx->scan_variant);
     b->cap1 = b->w.cap_node[1];
     uint64_t off = align256(b->w.total);
     b->root_off = off;    off = align256(off + 2048);     // outputs of the artificial root
@@ -881,7 +931,8 @@ int32_t ltl4c_batch_workspace_bytes(ltl4c_ctx* ctx, uint64_t n_events, int32_t n
     if (s) return s;
     if (!bytes) return fail(LTL4C_EINVAL, "bytes is NULL");
     BatchLayout b;
-    s = batch_layout(ctx, n_events, n_traces, (uint32_t)n_props, &b);
+    s = batch_layout(ctx, n_events, n_traces, (uint32_t)n_props,
+                     (uint32_t)scan_groups(monitor_states(ctx, props, n_props)).size(), &b);
     if (s) return s;
     *bytes = b.total;
     return LTL4C_OK;
@@ -899,8 +950,9 @@ int32_t ltl4c_eval_batch(ltl4c_ctx* ctx, const void* d_records, const uint64_t* 
         if (offsets[t + 1] < offsets[t]) return fail(LTL4C_EINVAL, "offsets must be non-decreasing");
     const uint64_t n = offsets[n_traces];
     const uint32_t P = (uint32_t)n_props;
+    const std::vector<ScanGroup> groups = scan_groups(monitor_states(ctx, props, n_props));
     BatchLayout b;
-    s = batch_layout(ctx, n, n_traces, P, &b);
+    s = batch_layout(ctx, n, n_traces, P, (uint32_t)groups.size(), &b);
     if (s) return s;
     if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) & 255)) return fail(LTL4C_EINVAL, "workspace must be 256-byte aligned");
     if (ws_bytes < b.total) return fail(LTL4C_ENOMEM, "workspace smaller than ltl4c_batch_workspace_bytes()");
@@ -933,7 +985,7 @@ int32_t ltl4c_eval_batch(ltl4c_ctx* ctx, const void* d_records, const uint64_t* 
     r.node_keys[1] = reinterpret_cast<uint64_t*>(ws + b.keys_off);
     r.node_counts[1] = reinterpret_cast<uint32_t*>(ws + b.counts_off);
     r.node_verdict[1] = ws + b.verdict_off;
-    s = eval_core(ctx, b.g, b.w, d_ws, d_records, n, plan, P, max_states_of(ctx, props, n_props), ctx->batch_chunk_dev,
+    s = eval_core(ctx, b.g, b.w, d_ws, d_records, n, plan, P, groups, ctx->batch_chunk_dev,
                   ctx->batch_chunk_dev + n_traces + 1, (uint32_t)n_traces, &r);
     if (s) return s;
     BatchOutArgs o{};
@@ -1162,21 +1214,27 @@ static int32_t group_push_impl(ltl4c_ctx* ctx, int32_t group, const void* d_reco
         sa.cbits = G->g.cbits;
         sa.n_levels = 1;
         sa.valid_shift = G->g.cbits + G->g.key_bits_total;
-        sa.n_props = G->V;
-        sa.max_states = max_states_of(ctx, G->props.data(), (int32_t)G->P);
+        sa.n_props_all = G->V;
         sa.plan = G->vplan;
         sa.inst_verdict = seg_state;
         sa.inst_stride = G->max_batch;
         sa.inst_limit = G->max_batch;
         sa.inst_keys = seg_keys;
-        sa.status = reinterpret_cast<ScanTileStatus*>(z + w.scan_status_off);
-        sa.ticket = z + w.scan_ticket_off;
         sa.sizes = reinterpret_cast<uint64_t*>(z + w.sizes64_off);
         sa.sizes32 = sizes32;
         sa.err = ctx->err_dev;
         sa.emit_state = 1;
-        s = launch(ctx, "scan", [&] { return launch_scan(sa, G->scan_variant, st); });
-        if (s) return s;
+        uint32_t* scan_status = z + w.scan_status_off;
+        for (size_t gi = 0; gi < G->sgroups.size(); ++gi) {
+            sa.n_props = G->sgroups[gi].cnt;
+            std::memcpy(sa.prop_idx, G->sgroups[gi].idx, sizeof sa.prop_idx);
+            sa.max_states = G->sgroups[gi].states;
+            sa.structure = G->sgroups[gi].structure ? 1u : 0u;
+            sa.status = scan_status + gi * 2ull * kScanRows * w.tiles_scan;
+            sa.ticket = z + w.scan_ticket_off + gi;
+            s = launch(ctx, "scan", [&] { return launch_scan(sa, G->scan_variant, st); });
+            if (s) return s;
+        }
     }
     GroupUpdateArgs ua{};
     ua.g = G->gs;
