@@ -220,7 +220,7 @@ hipError_t launch_zero(const ZeroArgs& a, uint32_t blocks, hipStream_t s);
 hipError_t launch_classify(const ClassifyArgs& a, hipStream_t s);
 hipError_t launch_sort_pass(const SortPassArgs& a, int variant, hipStream_t s);
 uint32_t sort_tile(int variant);      // words per radix tile of a sort variant
-constexpr int kSortVariants = 5;
+constexpr int kSortVariants = 6;
 hipError_t launch_scan(const ScanArgs& a, int variant, hipStream_t s);
 uint32_t scan_tile(int variant);      // words per scan tile of a scan variant
 constexpr int kScanVariants = 2;

@@ -55,6 +55,25 @@ __device__ __forceinline__ uint32_t block256_excl_scan(uint32_t v, uint32_t* s_t
     return pre + incl - v;
 }
 
+// Exclusive scans of two values over threads 0..255 in one pass (threads
+// 256.. contribute zeros); two barriers.
+__device__ __forceinline__ uint2 block256_excl_scan2(uint32_t v0, uint32_t v1, uint32_t* s_tmp /*[8]*/) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t i0 = wave_incl_scan_u32(v0), i1 = wave_incl_scan_u32(v1);
+    if (lane == 63 && w < 4) {
+        s_tmp[w] = i0;
+        s_tmp[4 + w] = i1;
+    }
+    __syncthreads();
+    uint32_t p0 = 0, p1 = 0;
+    for (int i = 0; i < w && i < 4; ++i) {
+        p0 += s_tmp[i];
+        p1 += s_tmp[4 + i];
+    }
+    __syncthreads();
+    return make_uint2(p0 + i0 - v0, p1 + i1 - v1);
+}
+
 // Eq. 6 and Def. 7 (device restatement; exact integers).
 __device__ __forceinline__ bool cmp_op(uint64_t a, uint32_t op, uint64_t b) {
     switch (op) {
@@ -221,14 +240,15 @@ __global__ __launch_bounds__(1024) void k_classify(ClassifyArgs a) {
 // one stable radix pass (onesweep: rank in-tile, look back across tiles)
 // ---------------------------------------------------------------------------
 constexpr uint32_t kFlagAgg = 1u << 30, kFlagInc = 2u << 30, kValMask = (1u << 30) - 1;
-constexpr int kSortLookWindow = 8;
+constexpr int kSortLookWindow = 4;
+constexpr bool kSortSpinSleep = true;    // back off while a predecessor has not published
 constexpr int kScanLookWindow = 4;
 
 // 16-item tiles are held to 128 VGPRs (two 512-thread blocks per CU), 8-item
 // tiles to 80 (three).  Tiles above 8192 words are written out in PHASES
 // parts through an LDS buffer of CHUNK words.
 template <int THREADS, int ITEMS>
-__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(ITEMS <= 8 ? 6 : ITEMS <= 16 ? 4 : 2)))
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(ITEMS <= 8 ? 6 : ITEMS <= 12 ? 5 : ITEMS <= 16 ? 4 : 2)))
 void k_sort_pass(SortPassArgs a) {
     constexpr int TILE = THREADS * ITEMS;
     constexpr int WAVES = THREADS / 64;
@@ -238,7 +258,6 @@ void k_sort_pass(SortPassArgs a) {
     static_assert(CHUNK * PHASES == TILE, "phases split the tile evenly");
     __shared__ uint64_t s_keys[CHUNK];
     __shared__ uint32_t s_wcnt[WAVES][kRadix];
-    __shared__ uint32_t s_hist[kRadix];
     __shared__ uint32_t s_lstart[kRadix];
     __shared__ uint32_t s_gbase[kRadix];
     __shared__ uint32_t s_tmp[2][4];
@@ -246,7 +265,6 @@ void k_sort_pass(SortPassArgs a) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
     for (int i = tid; i < WAVES * kRadix; i += THREADS) (&s_wcnt[0][0])[i] = 0;
-    if (tid < kRadix) s_hist[tid] = 0;
     __syncthreads();
     const uint32_t tile = s_tile;
     const uint64_t base = (uint64_t)tile * TILE;
@@ -264,19 +282,9 @@ void k_sort_pass(SortPassArgs a) {
     }
     uint32_t h = 0;
     if (tid < kRadix) h = a.hist[tid];
-    // the tile's bucket counts first: they are published before the ranking,
-    // so that later tiles looking back find them early
 #pragma unroll
-    for (int r = 0; r < ITEMS; ++r) {
-        dr[r] = (uint32_t)(key[r] >> a.shift) & dmask;
-        if ((uint32_t)r * 64 < rem) atomicAdd(&s_hist[dr[r]], 1u);
-    }
-    __syncthreads();
+    for (int r = 0; r < ITEMS; ++r) dr[r] = (uint32_t)(key[r] >> a.shift) & dmask;
     uint32_t tot = 0;
-    if (tid < kRadix) {
-        tot = s_hist[tid];
-        st_flag(a.status + (uint64_t)tile * kRadix + tid, (tile == 0 ? kFlagInc : kFlagAgg) | tot);
-    }
     // rank inside the wave: lanes with the same digit found by one ballot per
     // digit bit; per-wave counters in LDS carry the count across rounds
 #pragma unroll
@@ -304,10 +312,12 @@ void k_sort_pass(SortPassArgs a) {
             s_wcnt[ww][tid] = run;
             run += c;
         }
+        // publish this tile's bucket count
+        tot = run;
+        st_flag(a.status + (uint64_t)tile * kRadix + tid, (tile == 0 ? kFlagInc : kFlagAgg) | tot);
     }
-    uint32_t dummy;
-    const uint32_t lstart = block256_excl_scan(tot, s_tmp[0], &dummy);
-    const uint32_t gexcl = block256_excl_scan(h, s_tmp[1], &dummy);
+    const uint2 ex = block256_excl_scan2(tot, h, &s_tmp[0][0]);
+    const uint32_t lstart = ex.x, gexcl = ex.y;
     if (tid < kRadix) {
         uint32_t prefix = 0;
         if (tile > 0) {
@@ -338,13 +348,13 @@ void k_sort_pass(SortPassArgs a) {
                         atomicOr(a.err, kErrSpin);
                         break;
                     }
-                    __builtin_amdgcn_s_sleep(1);
+                    if (kSortSpinSleep) __builtin_amdgcn_s_sleep(1);
                 }
             }
             st_flag(a.status + (uint64_t)tile * kRadix + tid, kFlagInc | (prefix + tot));
         }
         s_lstart[tid] = lstart;
-        s_gbase[tid] = gexcl + prefix;
+        s_gbase[tid] = gexcl + prefix - lstart;     // destination of tile position i of bucket d: s_gbase[d] + i
     }
     __syncthreads();
     // local position of every key in the bucket-ordered tile
@@ -368,7 +378,7 @@ void k_sort_pass(SortPassArgs a) {
         for (uint32_t i = lo_pos + tid; i < hi_pos; i += THREADS) {
             const uint64_t k = s_keys[i - lo_pos];
             const uint32_t d = (uint32_t)(k >> a.shift) & dmask;
-            const uint64_t dst = (uint64_t)s_gbase[d] + (i - s_lstart[d]);
+            const uint64_t dst = (uint64_t)(uint32_t)(s_gbase[d] + i);
             if (dst < a.n) a.out[dst] = k;
             else atomicOr(a.err, kErrSpin);
         }
@@ -1382,6 +1392,7 @@ uint32_t sort_tile(int variant) {
         case 2: return 256 * 24;
         case 3: return 256 * 8;
         case 4: return 512 * 8;
+        case 5: return 512 * 12;
         default: return 256 * 16;
     }
 }
@@ -1394,6 +1405,7 @@ hipError_t launch_sort_pass(const SortPassArgs& a, int variant, hipStream_t s) {
         case 2: hipLaunchKernelGGL((k_sort_pass<256, 24>), dim3(tiles), dim3(256), 0, s, a); break;
         case 3: hipLaunchKernelGGL((k_sort_pass<256, 8>), dim3(tiles), dim3(256), 0, s, a); break;
         case 4: hipLaunchKernelGGL((k_sort_pass<512, 8>), dim3(tiles), dim3(512), 0, s, a); break;
+        case 5: hipLaunchKernelGGL((k_sort_pass<512, 12>), dim3(tiles), dim3(512), 0, s, a); break;
         default: hipLaunchKernelGGL((k_sort_pass<256, 16>), dim3(tiles), dim3(256), 0, s, a); break;
     }
     return hipGetLastError();
