@@ -56,7 +56,8 @@ __device__ __forceinline__ uint32_t block256_excl_scan(uint32_t v, uint32_t* s_t
 }
 
 // Exclusive scans of two values over threads 0..255 in one pass (threads
-// 256.. contribute zeros); two barriers.
+// 256.. contribute zeros).  One barrier: the caller must not write s_tmp
+// again before its next barrier.
 __device__ __forceinline__ uint2 block256_excl_scan2(uint32_t v0, uint32_t v1, uint32_t* s_tmp /*[8]*/) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t i0 = wave_incl_scan_u32(v0), i1 = wave_incl_scan_u32(v1);
@@ -70,7 +71,6 @@ __device__ __forceinline__ uint2 block256_excl_scan2(uint32_t v0, uint32_t v1, u
         p0 += s_tmp[i];
         p1 += s_tmp[4 + i];
     }
-    __syncthreads();
     return make_uint2(p0 + i0 - v0, p1 + i1 - v1);
 }
 
@@ -318,6 +318,17 @@ void k_sort_pass(SortPassArgs a) {
     }
     const uint2 ex = block256_excl_scan2(tot, h, &s_tmp[0][0]);
     const uint32_t lstart = ex.x, gexcl = ex.y;
+    if (tid < kRadix) s_lstart[tid] = lstart;
+    __syncthreads();
+    // local position of every key in the bucket-ordered tile; a tile that fits
+    // the LDS buffer is ordered there before the look-back, so that the waves
+    // without a bucket do it while the others wait on their predecessors
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+        const uint32_t d = dr[r] & 0xFFu;
+        dr[r] = d | ((s_lstart[d] + s_wcnt[w][d] + (dr[r] >> 8)) << 8);
+        if (PHASES == 1 && (uint32_t)r * 64 < rem && (dr[r] >> 8) < (uint32_t)CHUNK) s_keys[dr[r] >> 8] = key[r];
+    }
     if (tid < kRadix) {
         uint32_t prefix = 0;
         if (tile > 0) {
@@ -353,27 +364,22 @@ void k_sort_pass(SortPassArgs a) {
             }
             st_flag(a.status + (uint64_t)tile * kRadix + tid, kFlagInc | (prefix + tot));
         }
-        s_lstart[tid] = lstart;
         s_gbase[tid] = gexcl + prefix - lstart;     // destination of tile position i of bucket d: s_gbase[d] + i
     }
     __syncthreads();
-    // local position of every key in the bucket-ordered tile
-#pragma unroll
-    for (int r = 0; r < ITEMS; ++r) {
-        const uint32_t d = dr[r] & 0xFFu;
-        dr[r] = d | ((s_lstart[d] + s_wcnt[w][d] + (dr[r] >> 8)) << 8);
-    }
     const uint32_t tile_n = (uint32_t)min<uint64_t>(TILE, a.n - base);
 #pragma unroll
     for (int ph = 0; ph < PHASES; ++ph) {
         const uint32_t lo_pos = (uint32_t)ph * CHUNK;
-        if (ph > 0) __syncthreads();
+        if (PHASES > 1) {
+            if (ph > 0) __syncthreads();
 #pragma unroll
-        for (int r = 0; r < ITEMS; ++r) {
-            const uint32_t rel = (dr[r] >> 8) - lo_pos;
-            if ((uint32_t)r * 64 < rem && rel < (uint32_t)CHUNK) s_keys[rel] = key[r];
+            for (int r = 0; r < ITEMS; ++r) {
+                const uint32_t rel = (dr[r] >> 8) - lo_pos;
+                if ((uint32_t)r * 64 < rem && rel < (uint32_t)CHUNK) s_keys[rel] = key[r];
+            }
+            __syncthreads();
         }
-        __syncthreads();
         const uint32_t hi_pos = min<uint32_t>(tile_n, lo_pos + CHUNK);
         for (uint32_t i = lo_pos + tid; i < hi_pos; i += THREADS) {
             const uint64_t k = s_keys[i - lo_pos];
