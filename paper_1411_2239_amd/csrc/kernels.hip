@@ -161,7 +161,7 @@ __device__ __forceinline__ void load_record(const uint8_t* rec, uint32_t* dw) {
 }
 
 template <int RDW, bool GROUP>
-__global__ __launch_bounds__(1024) void k_classify(ClassifyArgs a) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_classify(ClassifyArgs a) {
     __shared__ uint8_t s_cls[256];
     __shared__ uint8_t s_kp[256];
     __shared__ uint32_t s_hist[8][256];
@@ -179,35 +179,11 @@ __global__ __launch_bounds__(1024) void k_classify(ClassifyArgs a) {
     __syncthreads();
     uint32_t err = 0;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
-        uint32_t t, f[kMaxLevels];
-        uint32_t chunk = 0;
-        const uint8_t* rec_ptr = a.records + i * a.record_bytes;
-        if constexpr (GROUP) {
-            // chunk c with s_coff[c] <= i < s_coff[c+1]
-            uint32_t lo = 0, hi = a.n_chunks;
-            while (hi - lo > 1) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (s_coff[mid] <= (uint32_t)i) lo = mid; else hi = mid;
-            }
-            chunk = lo;
-            if (a.chunk_ptr)
-                rec_ptr = reinterpret_cast<const uint8_t*>(a.chunk_ptr[lo]) + (i - s_coff[lo]) * a.record_bytes;
-        }
-        if constexpr (RDW > 0) {
-            uint32_t dw[RDW];
-            load_record<RDW>(rec_ptr, dw);
-            t = (dw[a.type_dw] >> a.type_shift) & a.type_mask;
-#pragma unroll
-            for (int m = 0; m < kMaxLevels; ++m)
-                f[m] = m < (int)a.n_keys ? (dw[a.key_dw[m]] >> a.key_shift[m]) & a.key_mask[m] : 0u;
-        } else {
-            const uint32_t* rec = reinterpret_cast<const uint32_t*>(rec_ptr);
-            t = (rec[a.type_dw] >> a.type_shift) & a.type_mask;
-#pragma unroll
-            for (int m = 0; m < kMaxLevels; ++m)
-                f[m] = m < (int)a.n_keys ? (rec[a.key_dw[m]] >> a.key_shift[m]) & a.key_mask[m] : 0u;
-        }
+    // Records of one grid-stride step are loaded before any is processed, so
+    // that each thread keeps U loads in flight.
+    constexpr int U = (RDW > 0 && !GROUP) ? 4 : 1;
+    constexpr int NDW = RDW > 0 ? RDW : 1;
+    auto process = [&](uint64_t i, uint32_t t, const uint32_t* f, uint32_t chunk) {
         bool ok = !(a.check_type_range && t > 255u);
         const uint32_t t8 = t & 255u;
         ok = ok && ((s_kp[t8] & a.need_mask) == a.need_mask);
@@ -227,6 +203,49 @@ __global__ __launch_bounds__(1024) void k_classify(ClassifyArgs a) {
         a.words[i] = word;
         for (uint32_t p = 0; p < a.n_pass; ++p)
             atomicAdd(&s_hist[p][(uint32_t)(word >> (a.sort_shift + kRadixBits * p)) & (kRadix - 1)], 1u);
+    };
+    for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < a.n; i0 += U * stride) {
+        uint32_t dw[U][NDW];
+        uint32_t chunk[U];
+        const uint8_t* rec_ptr[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = i0 + u * stride;
+            chunk[u] = 0;
+            rec_ptr[u] = a.records + i * a.record_bytes;
+            if (i >= a.n) continue;
+            if constexpr (GROUP) {
+                // chunk c with s_coff[c] <= i < s_coff[c+1]
+                uint32_t lo = 0, hi = a.n_chunks;
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (s_coff[mid] <= (uint32_t)i) lo = mid; else hi = mid;
+                }
+                chunk[u] = lo;
+                if (a.chunk_ptr)
+                    rec_ptr[u] = reinterpret_cast<const uint8_t*>(a.chunk_ptr[lo]) + (i - s_coff[lo]) * a.record_bytes;
+            }
+            if constexpr (RDW > 0) load_record<RDW>(rec_ptr[u], dw[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = i0 + u * stride;
+            if (i >= a.n) continue;
+            uint32_t t, f[kMaxLevels];
+            if constexpr (RDW > 0) {
+                t = (dw[u][a.type_dw] >> a.type_shift) & a.type_mask;
+#pragma unroll
+                for (int m = 0; m < kMaxLevels; ++m)
+                    f[m] = m < (int)a.n_keys ? (dw[u][a.key_dw[m]] >> a.key_shift[m]) & a.key_mask[m] : 0u;
+            } else {
+                const uint32_t* rec = reinterpret_cast<const uint32_t*>(rec_ptr[u]);
+                t = (rec[a.type_dw] >> a.type_shift) & a.type_mask;
+#pragma unroll
+                for (int m = 0; m < kMaxLevels; ++m)
+                    f[m] = m < (int)a.n_keys ? (rec[a.key_dw[m]] >> a.key_shift[m]) & a.key_mask[m] : 0u;
+            }
+            process(i, t, f, chunk[u]);
+        }
     }
     if (err) atomicOr(a.err, err);
     __syncthreads();
