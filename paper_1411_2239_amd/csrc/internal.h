@@ -116,6 +116,17 @@ struct ScanArgs {
     uint32_t* err;
 };
 
+struct FinalizeArgs {
+    uint32_t n_props;
+    const Plan* plan;
+    const uint32_t* root_counts;         // [p][6]
+    uint8_t* root_verdict;
+    uint64_t* root_counts_out;
+    const uint64_t* sizes_ws;            // [n_levels] from the scan
+    uint64_t* sizes_out;                 // [1 + n_levels]
+    uint32_t n_levels;
+};
+
 struct CountArgs {
     uint32_t level;                      // m: the parents' level (0 = root)
     uint32_t n_levels;
@@ -125,6 +136,8 @@ struct CountArgs {
     const uint32_t* n_children;          // device count of children
     const uint32_t* child_parent;        // optional: parent node of every child (else found in node_start)
     uint32_t items;                      // children per thread and tile: 16 (leaves) or 2
+    uint32_t* done;                      // non-null at the root: the last block to finish runs `fin`
+    FinalizeArgs fin;
     uint64_t child_limit;                // children beyond this were not recorded
     const uint8_t* child_verdict;        // level m+1 == n_levels: instance verdicts [p][child_stride]
     const uint32_t* child_counts;        // otherwise: counts of level m+1 [p][child_stride][6]
@@ -147,16 +160,6 @@ struct ZeroArgs {
     uint64_t limit;
 };
 
-struct FinalizeArgs {
-    uint32_t n_props;
-    const Plan* plan;
-    const uint32_t* root_counts;         // [p][6]
-    uint8_t* root_verdict;
-    uint64_t* root_counts_out;
-    const uint64_t* sizes_ws;            // [n_levels] from the scan
-    uint64_t* sizes_out;                 // [1 + n_levels]
-    uint32_t n_levels;
-};
 
 // Online monitoring: the resident monitor tree of a stream group.
 // Bindings and quantifier nodes live in open-addressing hash tables keyed by

@@ -890,6 +890,21 @@ __device__ __forceinline__ uint32_t node_of(const uint32_t* start, uint32_t nn, 
     return lo;
 }
 
+// Def. 7 at the root and the sizes, by threads 0..63; `counts` read coherently.
+__device__ __forceinline__ void finalize_root(const FinalizeArgs& a) {
+    const uint32_t p = threadIdx.x;
+    if (p <= a.n_levels) a.sizes_out[p] = p < a.n_levels ? a.sizes_ws[p] : 0ull;
+    if (p >= a.n_props) return;
+    uint32_t v[6];
+#pragma unroll
+    for (int b = 0; b < 6; ++b)
+        v[b] = __hip_atomic_load(a.root_counts + p * 6 + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    a.root_verdict[p] = (uint8_t)valuate(a.plan->prop[p], 0, v);
+    for (int b = 0; b < 6; ++b) a.root_counts_out[p * 6 + b] = v[b];
+}
+
+__global__ void k_finalize(FinalizeArgs a) { finalize_root(a); }
+
 // Children are read in strided order (consecutive threads take consecutive
 // children; all loads of a tile are issued before any is used) and counted
 // into an LDS window of kCountWindow parents.  Children are in parent order,
@@ -999,6 +1014,18 @@ __global__ __launch_bounds__(kCountThreads) void k_count(CountArgs a) {
         }
         __syncthreads();
     }
+    if (a.done) {
+        // the last block to finish values the root
+        __shared__ uint32_t s_last;
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) s_last = atomicAdd(a.done, 1u) == gridDim.x - 1 ? 1u : 0u;
+        __syncthreads();
+        if (s_last) {
+            __threadfence();
+            finalize_root(a.fin);
+        }
+    }
 }
 // Counting of leaf verdicts: every thread takes 16 consecutive children (the
 // verdict bytes and parent ids are read as 16-byte vectors where aligned),
@@ -1101,14 +1128,6 @@ __global__ __launch_bounds__(kCountThreads) void k_count_leaves(CountArgs a) {
     if (err) atomicOr(a.err, err);
 }
 
-__global__ void k_finalize(FinalizeArgs a) {
-    const uint32_t p = threadIdx.x;
-    if (p <= a.n_levels) a.sizes_out[p] = p < a.n_levels ? a.sizes_ws[p] : 0ull;
-    if (p >= a.n_props) return;
-    const uint32_t* v = a.root_counts + p * 6;
-    a.root_verdict[p] = (uint8_t)valuate(a.plan->prop[p], 0, v);
-    for (int b = 0; b < 6; ++b) a.root_counts_out[p * 6 + b] = v[b];
-}
 
 // ---------------------------------------------------------------------------
 // online monitoring: incremental update of a stream group's monitor tree

@@ -766,6 +766,16 @@ static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, v
         node_limit[m] = std::min(node_stride[m], w.cap_node[m]);
     }
 
+    FinalizeArgs fa{};
+    fa.n_props = P;
+    fa.plan = plan;
+    fa.root_counts = root_counts;
+    fa.root_verdict = out->root_verdict;
+    fa.root_counts_out = out->root_counts;
+    fa.sizes_ws = sizes64;
+    fa.sizes_out = out->sizes;
+    fa.n_levels = NL;
+    bool fused_finalize = false;
     if (n > 0) {
         ScanArgs sa{};
         sa.words = sorted;
@@ -805,6 +815,7 @@ static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, v
             if (s) return s;
         }
 
+        fused_finalize = NL >= 2;                             // the node-level root count ends with Def. 7
         for (int m = (int)NL - 1; m >= 0; --m) {
             CountArgs c{};
             c.level = (uint32_t)m;
@@ -831,6 +842,10 @@ static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, v
                 c.counts = root_counts;
                 c.stride = 1;
                 c.node_limit = 1;
+                if (fused_finalize) {
+                    c.done = sizes32 + 32;
+                    c.fin = fa;
+                }
             } else {
                 c.node_start = node_start[m];
                 c.n_nodes = sizes32 + m;
@@ -842,15 +857,7 @@ static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, v
             if (s) return s;
         }
     }
-    FinalizeArgs fa{};
-    fa.n_props = P;
-    fa.plan = plan;
-    fa.root_counts = root_counts;
-    fa.root_verdict = out->root_verdict;
-    fa.root_counts_out = out->root_counts;
-    fa.sizes_ws = sizes64;
-    fa.sizes_out = out->sizes;
-    fa.n_levels = NL;
+    if (fused_finalize) return LTL4C_OK;
     s = launch(ctx, "finalize", [&] { return launch_finalize(fa, st); });
     return s;
 }
