@@ -11,6 +11,8 @@ constexpr int kMaxLevels = 4;
 constexpr int kStates = 16;          // nibble-packed maps always carry 16 lanes
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
+constexpr int kRadixBitsWide = 9;        // digit of the passes of 512-thread tiles, when it saves a pass
+constexpr int kHistWords = 4096;         // classify's histograms: n_pass << digit bits, at most
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;     // 4096 words per tile
@@ -58,10 +60,12 @@ struct ClassifyArgs {
     uint32_t cbits;
     uint32_t excl_shift;             // bit set in the word of an excluded event
     uint32_t n_pass;                 // radix passes whose histograms are built here
+    uint32_t digit_bits;             // radix digit width (8 or 9)
     uint32_t sort_shift;             // lowest sorted bit
     const Plan* plan;
     uint64_t* words;
-    uint32_t* hist;                  // [n_pass][256]
+    uint32_t* hist;                  // [n_pass][1 << digit_bits]
+    uint32_t* n_valid;               // non-null: count of events kept; excluded events enter no histogram
     uint32_t* err;
     // stream groups: event i belongs to the chunk c with
     // chunk_off[c] <= i < chunk_off[c+1]; its stream id goes above the keys
@@ -76,18 +80,22 @@ struct ClassifyArgs {
 struct SortPassArgs {
     const uint64_t* in;
     uint64_t* out;
-    uint32_t n;
+    uint32_t n;                      // words in `in` (an upper bound when n_valid is set)
     uint32_t shift;                  // lowest bit of this pass's digit
-    uint32_t nbits;                  // digit width (<= 8)
-    const uint32_t* hist;            // this pass's global histogram [256]
-    uint32_t* status;                // [tiles][256] look-back words
+    uint32_t nbits;                  // digit width (<= the kernel's digit bits)
+    const uint32_t* hist;            // this pass's global histogram [buckets]
+    uint32_t* status;                // [tiles][buckets] look-back words
     uint32_t* ticket;
+    const uint32_t* n_valid;         // non-null: words kept by the first pass (device)
+    uint32_t drop_excl;              // first pass: words with bit excl_shift set are dropped
+    uint32_t excl_shift;
     uint32_t* err;
 };
 
 struct ScanArgs {
     const uint64_t* words;
     uint32_t n;
+    const uint32_t* n_dev;               // non-null: the word count lives on the device (n bounds it)
     uint32_t cbits;
     uint32_t n_levels;
     uint32_t prefix_shift[kMaxLevels];   // word >> prefix_shift[m] = packed keys 0..m-1 (m>=1)
@@ -221,7 +229,8 @@ struct BatchOutArgs {
 // Launchers (defined in kernels.hip).
 hipError_t launch_zero(const ZeroArgs& a, uint32_t blocks, hipStream_t s);
 hipError_t launch_classify(const ClassifyArgs& a, hipStream_t s);
-hipError_t launch_sort_pass(const SortPassArgs& a, int variant, hipStream_t s);
+hipError_t launch_sort_pass(const SortPassArgs& a, int variant, uint32_t digit_bits, hipStream_t s);
+uint32_t sort_threads(int variant);   // threads per block of a sort variant
 uint32_t sort_tile(int variant);      // words per radix tile of a sort variant
 constexpr int kSortVariants = 6;
 hipError_t launch_scan(const ScanArgs& a, int variant, hipStream_t s);

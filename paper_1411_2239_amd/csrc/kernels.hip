@@ -55,21 +55,23 @@ __device__ __forceinline__ uint32_t block256_excl_scan(uint32_t v, uint32_t* s_t
     return pre + incl - v;
 }
 
-// Exclusive scans of two values over threads 0..255 in one pass (threads
-// 256.. contribute zeros).  One barrier: the caller must not write s_tmp
-// again before its next barrier.
-__device__ __forceinline__ uint2 block256_excl_scan2(uint32_t v0, uint32_t v1, uint32_t* s_tmp /*[8]*/) {
+// Exclusive scans of two values over the threads of waves 0..NB-1 in one
+// pass (later waves contribute zeros).  One barrier: s_tmp[0..NB) then holds
+// the wave totals of v0 and s_tmp[NB..2NB) those of v1, and the caller must
+// not write s_tmp again before its next barrier.
+template <int NB>
+__device__ __forceinline__ uint2 block_excl_scan2(uint32_t v0, uint32_t v1, uint32_t* s_tmp /*[2 NB]*/) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint32_t i0 = wave_incl_scan_u32(v0), i1 = wave_incl_scan_u32(v1);
-    if (lane == 63 && w < 4) {
+    if (lane == 63 && w < NB) {
         s_tmp[w] = i0;
-        s_tmp[4 + w] = i1;
+        s_tmp[NB + w] = i1;
     }
     __syncthreads();
     uint32_t p0 = 0, p1 = 0;
-    for (int i = 0; i < w && i < 4; ++i) {
+    for (int i = 0; i < w && i < NB; ++i) {
         p0 += s_tmp[i];
-        p1 += s_tmp[4 + i];
+        p1 += s_tmp[NB + i];
     }
     return make_uint2(p0 + i0 - v0, p1 + i1 - v1);
 }
@@ -164,20 +166,23 @@ template <int RDW, bool GROUP>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_classify(ClassifyArgs a) {
     __shared__ uint8_t s_cls[256];
     __shared__ uint8_t s_kp[256];
-    __shared__ uint32_t s_hist[8][256];
+    __shared__ uint32_t s_hist[kHistWords];     // [n_pass][1 << digit_bits]
+    __shared__ uint32_t s_nvalid;
     __shared__ uint32_t s_coff[GROUP ? kMaxChunks + 1 : 1];
     __shared__ uint32_t s_cstream[GROUP ? kMaxChunks : 1];
     for (int i = threadIdx.x; i < 256; i += blockDim.x) {
         s_cls[i] = a.plan->class_of_type[i];
         s_kp[i] = a.plan->key_present[i];
     }
-    for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) (&s_hist[0][0])[i] = 0;
+    const uint32_t n_hist = a.n_pass << a.digit_bits, dmask = (1u << a.digit_bits) - 1u;
+    for (uint32_t i = threadIdx.x; i < n_hist; i += blockDim.x) s_hist[i] = 0;
+    if (threadIdx.x == 0) s_nvalid = 0;
     if constexpr (GROUP) {
         for (uint32_t i = threadIdx.x; i <= a.n_chunks; i += blockDim.x) s_coff[i] = a.chunk_off[i];
         for (uint32_t i = threadIdx.x; i < a.n_chunks; i += blockDim.x) s_cstream[i] = a.chunk_stream[i];
     }
     __syncthreads();
-    uint32_t err = 0;
+    uint32_t err = 0, kept = 0;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     // Records of one grid-stride step are loaded before any is processed, so
     // that each thread keeps U loads in flight.
@@ -201,8 +206,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         if constexpr (GROUP) key |= (uint64_t)s_cstream[chunk] << a.stream_shift;
         const uint64_t word = ok ? ((key << a.cbits) | s_cls[t8]) : (1ull << a.excl_shift);
         a.words[i] = word;
-        for (uint32_t p = 0; p < a.n_pass; ++p)
-            atomicAdd(&s_hist[p][(uint32_t)(word >> (a.sort_shift + kRadixBits * p)) & (kRadix - 1)], 1u);
+        // with n_valid set the first radix pass drops excluded events, so
+        // they enter no histogram
+        if (ok || !a.n_valid) {
+            kept += ok;
+            for (uint32_t p = 0; p < a.n_pass; ++p)
+                atomicAdd(&s_hist[(p << a.digit_bits) + ((uint32_t)(word >> (a.sort_shift + a.digit_bits * p)) & dmask)], 1u);
+        }
     };
     for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < a.n; i0 += U * stride) {
         uint32_t dw[U][NDW];
@@ -248,11 +258,17 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         }
     }
     if (err) atomicOr(a.err, err);
+    if (a.n_valid) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) kept += __shfl_xor(kept, off, 64);
+        if ((threadIdx.x & 63) == 0 && kept) atomicAdd(&s_nvalid, kept);
+    }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < a.n_pass * 256u; i += blockDim.x) {
-        const uint32_t v = (&s_hist[0][0])[i];
+    for (uint32_t i = threadIdx.x; i < n_hist; i += blockDim.x) {
+        const uint32_t v = s_hist[i];
         if (v) atomicAdd(a.hist + i, v);
     }
+    if (a.n_valid && threadIdx.x == 0 && s_nvalid) atomicAdd(a.n_valid, s_nvalid);
 }
 
 // ---------------------------------------------------------------------------
@@ -265,50 +281,67 @@ constexpr int kScanLookWindow = 4;
 
 // 16-item tiles are held to 128 VGPRs (two 512-thread blocks per CU), 8-item
 // tiles to 80 (three).  Tiles above 8192 words are written out in PHASES
-// parts through an LDS buffer of CHUNK words.
-template <int THREADS, int ITEMS>
+// parts through an LDS buffer of CHUNK words.  RB is the digit width of the
+// kernel (8: 256 buckets, 9: 512); one thread owns each bucket.
+template <int THREADS, int ITEMS, int RB>
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(ITEMS <= 8 ? 6 : ITEMS <= 12 ? 5 : ITEMS <= 16 ? 4 : 2)))
 void k_sort_pass(SortPassArgs a) {
+    constexpr int B = 1 << RB;
+    constexpr int NB = B / 64;                 // waves whose threads own a bucket
     constexpr int TILE = THREADS * ITEMS;
     constexpr int WAVES = THREADS / 64;
     constexpr int PHASES = (TILE + 8191) / 8192;
     constexpr int CHUNK = TILE / PHASES;
-    static_assert(THREADS >= kRadix, "one thread per bucket");
+    // 512 buckets: the per-wave counters and the key buffer share LDS (keys
+    // are placed once every position is known), which keeps two 512 x 16
+    // blocks on a CU
+    constexpr bool kShare = RB > 8;
+    constexpr int CNT64 = WAVES * B / 2;       // per-wave counters, in 64-bit words
+    static_assert(THREADS >= B, "one thread per bucket");
     static_assert(CHUNK * PHASES == TILE, "phases split the tile evenly");
-    __shared__ uint64_t s_keys[CHUNK];
-    __shared__ uint32_t s_wcnt[WAVES][kRadix];
-    __shared__ uint32_t s_lstart[kRadix];
-    __shared__ uint32_t s_gbase[kRadix];
-    __shared__ uint32_t s_tmp[2][4];
+    static_assert(!kShare || PHASES == 1, "shared counters need the whole tile in LDS");
+    __shared__ uint64_t s_buf[kShare ? (CHUNK > CNT64 ? CHUNK : CNT64) : CHUNK + CNT64];
+    uint64_t* s_keys = s_buf;
+    uint32_t* s_wcnt = reinterpret_cast<uint32_t*>(s_buf + (kShare ? 0 : CHUNK));   // [WAVES][B]
+    __shared__ uint32_t s_gbase[B];
+    __shared__ uint32_t s_tmp[2 * NB];
     __shared__ uint32_t s_tile;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
-    for (int i = tid; i < WAVES * kRadix; i += THREADS) (&s_wcnt[0][0])[i] = 0;
+    for (int i = tid; i < WAVES * B; i += THREADS) s_wcnt[i] = 0;
     __syncthreads();
     const uint32_t tile = s_tile;
     const uint64_t base = (uint64_t)tile * TILE;
+    // words read and written: the first pass of a dropping sort reads all n
+    // and keeps n_valid; the later passes read and write n_valid
+    const uint32_t n_out = a.n_valid ? *a.n_valid : a.n;
+    const uint32_t n_in = a.drop_excl ? a.n : n_out;
+    if (base >= n_in) return;                  // the whole block: no word of this tile
     const uint64_t wbase = base + (uint64_t)w * (ITEMS * 64) + lane;   // item r of this lane: wbase + 64 r
     // items r with 64 r < rem are inside the array
-    const uint32_t rem = wbase < a.n ? (uint32_t)min<uint64_t>(a.n - wbase, ITEMS * 64) : 0u;
+    const uint32_t rem = wbase < n_in ? (uint32_t)min<uint64_t>(n_in - wbase, ITEMS * 64) : 0u;
     const uint32_t dmask = (1u << a.nbits) - 1u;
     const uint64_t lt = (1ull << lane) - 1ull;
 
     uint64_t key[ITEMS];
-    uint32_t dr[ITEMS];   // digit in bits 0..7; rank inside the wave from bit 8 on
+    uint32_t dr[ITEMS];   // digit in bits 0..RB-1; rank inside the wave, later the tile position, from bit RB on
+    uint32_t vm = 0;      // items this lane keeps
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
         key[r] = (uint32_t)r * 64 < rem ? a.in[wbase + (uint64_t)r * 64] : 0ull;
     }
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r)
+        if ((uint32_t)r * 64 < rem && !(a.drop_excl && (key[r] >> a.excl_shift) != 0)) vm |= 1u << r;
     uint32_t h = 0;
-    if (tid < kRadix) h = a.hist[tid];
+    if (tid < B) h = a.hist[tid];
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) dr[r] = (uint32_t)(key[r] >> a.shift) & dmask;
-    uint32_t tot = 0;
     // rank inside the wave: lanes with the same digit found by one ballot per
     // digit bit; per-wave counters in LDS carry the count across rounds
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
-        const bool valid = (uint32_t)r * 64 < rem;
+        const bool valid = (vm >> r) & 1u;
         const uint32_t d = dr[r];
         uint64_t m = __ballot(valid);
         for (uint32_t b = 0; b < a.nbits; ++b) {
@@ -317,38 +350,52 @@ void k_sort_pass(SortPassArgs a) {
             m &= bit ? bb : ~bb;
         }
         const uint32_t below = (uint32_t)__popcll(m & lt);
-        const uint32_t prev = s_wcnt[w][d];
-        dr[r] = d | ((prev + below) << 8);
-        if (valid && below == 0) s_wcnt[w][d] = prev + (uint32_t)__popcll(m);
+        const uint32_t prev = s_wcnt[w * B + d];
+        dr[r] = d | ((prev + below) << RB);
+        if (valid && below == 0) s_wcnt[w * B + d] = prev + (uint32_t)__popcll(m);
     }
     __syncthreads();
-    // per bucket (threads 0..255): wave offsets, tile offset, look-back
-    if (tid < kRadix) {
-        uint32_t run = 0;
+    // per bucket: publish this tile's count, then tile and global offsets
+    uint32_t cw[WAVES];
+    uint32_t tot = 0;
+    if (tid < B) {
 #pragma unroll
         for (int ww = 0; ww < WAVES; ++ww) {
-            const uint32_t c = s_wcnt[ww][tid];
-            s_wcnt[ww][tid] = run;
-            run += c;
+            cw[ww] = s_wcnt[ww * B + tid];
+            tot += cw[ww];
         }
-        // publish this tile's bucket count
-        tot = run;
-        st_flag(a.status + (uint64_t)tile * kRadix + tid, (tile == 0 ? kFlagInc : kFlagAgg) | tot);
+        st_flag(a.status + (uint64_t)tile * B + tid, (tile == 0 ? kFlagInc : kFlagAgg) | tot);
     }
-    const uint2 ex = block256_excl_scan2(tot, h, &s_tmp[0][0]);
+    const uint2 ex = block_excl_scan2<NB>(tot, h, s_tmp);
     const uint32_t lstart = ex.x, gexcl = ex.y;
-    if (tid < kRadix) s_lstart[tid] = lstart;
+    uint32_t tile_n = 0;                       // words this tile keeps
+#pragma unroll
+    for (int i = 0; i < NB; ++i) tile_n += s_tmp[i];
+    if (tid < B) {
+        // each thread rewrites only its own bucket's column
+        uint32_t run = lstart;
+#pragma unroll
+        for (int ww = 0; ww < WAVES; ++ww) {
+            s_wcnt[ww * B + tid] = run;
+            run += cw[ww];
+        }
+    }
     __syncthreads();
-    // local position of every key in the bucket-ordered tile; a tile that fits
-    // the LDS buffer is ordered there before the look-back, so that the waves
-    // without a bucket do it while the others wait on their predecessors
+    // tile position of every kept key; a tile that fits the LDS buffer is
+    // ordered there before the look-back, so that the waves without a bucket
+    // do it while the others wait on their predecessors
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
-        const uint32_t d = dr[r] & 0xFFu;
-        dr[r] = d | ((s_lstart[d] + s_wcnt[w][d] + (dr[r] >> 8)) << 8);
-        if (PHASES == 1 && (uint32_t)r * 64 < rem && (dr[r] >> 8) < (uint32_t)CHUNK) s_keys[dr[r] >> 8] = key[r];
+        const uint32_t d = dr[r] & (B - 1);
+        dr[r] = d | ((s_wcnt[w * B + d] + (dr[r] >> RB)) << RB);
     }
-    if (tid < kRadix) {
+    if (kShare) __syncthreads();               // the counters' LDS becomes the key buffer
+    if (PHASES == 1) {
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r)
+            if (((vm >> r) & 1u) && (dr[r] >> RB) < (uint32_t)CHUNK) s_keys[dr[r] >> RB] = key[r];
+    }
+    if (tid < B) {
         uint32_t prefix = 0;
         if (tile > 0) {
             // windowed look-back: one round trip fetches kSortLookWindow
@@ -360,7 +407,7 @@ void k_sort_pass(SortPassArgs a) {
                 uint32_t sv[kSortLookWindow];
 #pragma unroll
                 for (int k = 0; k < kSortLookWindow; ++k)
-                    sv[k] = j - k >= 0 ? ld_acquire_flag(a.status + (uint64_t)(j - k) * kRadix + tid) : kFlagInc;
+                    sv[k] = j - k >= 0 ? ld_acquire_flag(a.status + (uint64_t)(j - k) * B + tid) : kFlagInc;
                 int used = 0;
                 bool stop = false;
 #pragma unroll
@@ -381,12 +428,11 @@ void k_sort_pass(SortPassArgs a) {
                     if (kSortSpinSleep) __builtin_amdgcn_s_sleep(1);
                 }
             }
-            st_flag(a.status + (uint64_t)tile * kRadix + tid, kFlagInc | (prefix + tot));
+            st_flag(a.status + (uint64_t)tile * B + tid, kFlagInc | (prefix + tot));
         }
         s_gbase[tid] = gexcl + prefix - lstart;     // destination of tile position i of bucket d: s_gbase[d] + i
     }
     __syncthreads();
-    const uint32_t tile_n = (uint32_t)min<uint64_t>(TILE, a.n - base);
 #pragma unroll
     for (int ph = 0; ph < PHASES; ++ph) {
         const uint32_t lo_pos = (uint32_t)ph * CHUNK;
@@ -394,8 +440,8 @@ void k_sort_pass(SortPassArgs a) {
             if (ph > 0) __syncthreads();
 #pragma unroll
             for (int r = 0; r < ITEMS; ++r) {
-                const uint32_t rel = (dr[r] >> 8) - lo_pos;
-                if ((uint32_t)r * 64 < rem && rel < (uint32_t)CHUNK) s_keys[rel] = key[r];
+                const uint32_t rel = (dr[r] >> RB) - lo_pos;
+                if (((vm >> r) & 1u) && rel < (uint32_t)CHUNK) s_keys[rel] = key[r];
             }
             __syncthreads();
         }
@@ -404,7 +450,7 @@ void k_sort_pass(SortPassArgs a) {
             const uint64_t k = s_keys[i - lo_pos];
             const uint32_t d = (uint32_t)(k >> a.shift) & dmask;
             const uint64_t dst = (uint64_t)(uint32_t)(s_gbase[d] + i);
-            if (dst < a.n) a.out[dst] = k;
+            if (dst < n_out) a.out[dst] = k;
             else atomicOr(a.err, kErrSpin);
         }
     }
@@ -558,13 +604,15 @@ __global__ __launch_bounds__(THREADS) void k_scan(ScanArgs a) {
     const uint32_t tile = s_tile;
     const uint64_t base = (uint64_t)tile * TILE;
     const uint64_t kInvalid = ~0ull;
+    const uint32_t n = a.n_dev ? *a.n_dev : a.n;    // the look-back rows stay laid out for a.n
+    if (base >= n) return;                         // the whole block: no word of this tile
 #pragma unroll
     for (int r = 0; r < kScanItems; ++r) {
         const uint64_t idx = base + r * THREADS + tid;
-        s_w[pad_idx(r * THREADS + tid)] = idx < a.n ? a.words[idx] : kInvalid;
+        s_w[pad_idx(r * THREADS + tid)] = idx < n ? a.words[idx] : kInvalid;
     }
     if (tid == 0) s_prev = base > 0 ? a.words[base - 1] : kInvalid;
-    if (tid == 1) s_next = base + TILE < a.n ? a.words[base + TILE] : kInvalid;
+    if (tid == 1) s_next = base + TILE < n ? a.words[base + TILE] : kInvalid;
     __syncthreads();
 
     uint64_t wv[kScanItems];
@@ -866,7 +914,7 @@ __global__ __launch_bounds__(THREADS) void k_scan(ScanArgs a) {
     }
     // the thread holding the last event publishes the totals
     const uint64_t my0 = base + (uint64_t)tid * kScanItems;
-    if (structure && my0 <= a.n - 1 && a.n - 1 < my0 + kScanItems) {
+    if (structure && my0 <= n - 1 && n - 1 < my0 + kScanItems) {
 #pragma unroll
         for (int m = 0; m < kMaxLevels; ++m) {
             if (m >= (int)L) break;
@@ -1441,16 +1489,28 @@ uint32_t sort_tile(int variant) {
     }
 }
 
-hipError_t launch_sort_pass(const SortPassArgs& a, int variant, hipStream_t s) {
+uint32_t sort_threads(int variant) { return variant == 1 || variant == 4 || variant == 5 ? 512u : 256u; }
+
+hipError_t launch_sort_pass(const SortPassArgs& a, int variant, uint32_t digit_bits, hipStream_t s) {
     const uint32_t tile = sort_tile(variant);
     const uint32_t tiles = (a.n + tile - 1) / tile;
+    if (digit_bits == 9) {
+        switch (variant) {
+            case 1: hipLaunchKernelGGL((k_sort_pass<512, 16, 9>), dim3(tiles), dim3(512), 0, s, a); break;
+            case 4: hipLaunchKernelGGL((k_sort_pass<512, 8, 9>), dim3(tiles), dim3(512), 0, s, a); break;
+            case 5: hipLaunchKernelGGL((k_sort_pass<512, 12, 9>), dim3(tiles), dim3(512), 0, s, a); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    if (digit_bits != 8) return hipErrorInvalidValue;
     switch (variant) {
-        case 1: hipLaunchKernelGGL((k_sort_pass<512, 16>), dim3(tiles), dim3(512), 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_sort_pass<256, 24>), dim3(tiles), dim3(256), 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_sort_pass<256, 8>), dim3(tiles), dim3(256), 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_sort_pass<512, 8>), dim3(tiles), dim3(512), 0, s, a); break;
-        case 5: hipLaunchKernelGGL((k_sort_pass<512, 12>), dim3(tiles), dim3(512), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_sort_pass<256, 16>), dim3(tiles), dim3(256), 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_sort_pass<512, 16, 8>), dim3(tiles), dim3(512), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_sort_pass<256, 24, 8>), dim3(tiles), dim3(256), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_sort_pass<256, 8, 8>), dim3(tiles), dim3(256), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_sort_pass<512, 8, 8>), dim3(tiles), dim3(512), 0, s, a); break;
+        case 5: hipLaunchKernelGGL((k_sort_pass<512, 12, 8>), dim3(tiles), dim3(512), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_sort_pass<256, 16, 8>), dim3(tiles), dim3(256), 0, s, a); break;
     }
     return hipGetLastError();
 }

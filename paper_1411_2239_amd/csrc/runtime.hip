@@ -82,6 +82,8 @@ namespace {
 // Derived quantities of a layout shared by the workspace query and eval.
 struct Geometry {
     uint32_t cbits, key_bits_total, sort_bits, n_pass;
+    uint32_t digit_bits;                    // radix digit width: 8, or 9 when that saves a pass
+    bool compact;                           // the first radix pass drops excluded events
     uint32_t stream_bits;                   // stream / trace id above the keys
     uint32_t n_levels;                      // levels of the monitor tree (quantifier nodes 0..n_levels-1)
     bool excl;
@@ -90,7 +92,12 @@ struct Geometry {
 
 // stream_is_level: the id above the keys is a tree level of its own (batches
 // of traces: one subtree per trace); otherwise it only separates streams.
-Geometry geometry(const ltl4c_layout& L, uint32_t stream_bits = 0, bool stream_is_level = false) {
+// compact: excluded events are dropped by the first radix pass instead of
+// being sorted behind the others on an extra key bit (the consumers then read
+// the kept count on the device).  wide: the sort variant has a thread per
+// bucket for 9-bit digits.
+Geometry geometry(const ltl4c_layout& L, uint32_t stream_bits = 0, bool stream_is_level = false,
+                  bool compact = false, bool wide = false) {
     Geometry g{};
     g.cbits = bits_for(L.n_classes);
     g.stream_bits = stream_bits;
@@ -107,15 +114,19 @@ Geometry geometry(const ltl4c_layout& L, uint32_t stream_bits = 0, bool stream_i
     g.excl = L.type_bytes > 1;
     for (int t = 0; t < 256 && !g.excl; ++t)
         if ((L.key_present[t] & need) != need) g.excl = true;
-    g.sort_bits = kb + (g.excl ? 1u : 0u);
-    g.n_pass = (g.sort_bits + kRadixBits - 1) / kRadixBits;
+    g.compact = compact && g.excl && kb > 0;
+    g.sort_bits = kb + (g.excl && !g.compact ? 1u : 0u);
+    const uint32_t p8 = (g.sort_bits + kRadixBits - 1) / kRadixBits;
+    const uint32_t p9 = (g.sort_bits + kRadixBitsWide - 1) / kRadixBitsWide;
+    g.digit_bits = wide && p9 < p8 && (p9 << kRadixBitsWide) <= (uint32_t)kHistWords ? kRadixBitsWide : kRadixBits;
+    g.n_pass = (g.sort_bits + g.digit_bits - 1) / g.digit_bits;
     return g;
 }
 
 struct WsLayout {
     uint64_t total;
     uint64_t zero_off, zero_words;
-    uint64_t hist_off, sort_ticket_off, scan_ticket_off, root_counts_off, sizes32_off, sizes64_off;
+    uint64_t hist_off, n_valid_off, sort_ticket_off, scan_ticket_off, root_counts_off, sizes32_off, sizes64_off;
     uint64_t sort_status_off, scan_status_off;
     uint64_t words_a_off, words_b_off, inst_verdict_off, inst_parent_off;
     uint64_t node_start_off[kMaxLevels], counts_off[kMaxLevels];
@@ -181,13 +192,14 @@ WsLayout plan_workspace(const ltl4c_layout& L, const Geometry& g, uint64_t n, ui
     w.tiles_scan = (uint32_t)((n + sct - 1) / sct);
     // zero block, in 32-bit words
     uint64_t z = 0;
-    w.hist_off = z;        z += (uint64_t)g.n_pass * kRadix;
+    w.hist_off = z;        z += (uint64_t)g.n_pass << g.digit_bits;
+    w.n_valid_off = z;     z += 64;
     w.sort_ticket_off = z; z += 64;
     w.scan_ticket_off = z; z += 64;
     w.root_counts_off = z; z += kMaxProps * 6;
     w.sizes32_off = z;     z += 64;
     w.sizes64_off = z;     z += 64;                      // 32 x uint64
-    w.sort_status_off = z; z += (uint64_t)g.n_pass * w.tiles_sort * kRadix;
+    w.sort_status_off = z; z += ((uint64_t)g.n_pass * w.tiles_sort) << g.digit_bits;
     z = (z + 63) & ~63ull;
     w.scan_status_off = z; z += (uint64_t)n_scan_groups * w.tiles_scan * (2 * kScanRows);   // 2 kinds x 32-bit words
     z = (z + 63) & ~63ull;
@@ -395,6 +407,8 @@ int32_t enqueue_front(ltl4c_ctx* ctx, const ltl4c_layout& L, const Geometry& g, 
     ca.cbits = g.cbits;
     ca.excl_shift = g.cbits + g.key_bits_total;
     ca.n_pass = g.n_pass;
+    ca.digit_bits = g.digit_bits;
+    ca.n_valid = g.compact ? z + w.n_valid_off : nullptr;
     ca.sort_shift = g.cbits;
     ca.plan = plan;
     ca.words = words_a;
@@ -415,13 +429,16 @@ int32_t enqueue_front(ltl4c_ctx* ctx, const ltl4c_layout& L, const Geometry& g, 
         sa.in = in;
         sa.out = outw;
         sa.n = (uint32_t)n;
-        sa.shift = g.cbits + kRadixBits * p;
-        sa.nbits = std::min<uint32_t>(kRadixBits, g.sort_bits - kRadixBits * p);
-        sa.hist = hist + (uint64_t)p * kRadix;
-        sa.status = sort_status + (uint64_t)p * w.tiles_sort * kRadix;
+        sa.shift = g.cbits + g.digit_bits * p;
+        sa.nbits = std::min<uint32_t>(g.digit_bits, g.sort_bits - g.digit_bits * p);
+        sa.hist = hist + ((uint64_t)p << g.digit_bits);
+        sa.status = sort_status + (((uint64_t)p * w.tiles_sort) << g.digit_bits);
         sa.ticket = sort_ticket + p;
+        sa.n_valid = ca.n_valid;
+        sa.drop_excl = g.compact && p == 0 ? 1u : 0u;
+        sa.excl_shift = ca.excl_shift;
         sa.err = ctx->err_dev;
-        s = launch(ctx, "sort_pass", [&] { return launch_sort_pass(sa, sort_variant, st); });
+        s = launch(ctx, "sort_pass", [&] { return launch_sort_pass(sa, sort_variant, g.digit_bits, st); });
         if (s) return s;
         std::swap(in, outw);
     }
@@ -538,7 +555,7 @@ int32_t group_configure(ltl4c_ctx* ctx, GroupHost& G, const int32_t* props, int3
     if (G.V > (uint32_t)kMaxProps)
         return fail(LTL4C_EUNSUPPORTED, "a stream group takes properties whose monitors have 16 states in total");
     const uint32_t sb = std::max<uint32_t>(1, bits_for(max_streams));
-    G.g = geometry(L, sb);
+    G.g = geometry(L, sb, false, false, sort_threads(ctx->sort_variant) >= 512);
     if (G.g.cbits + G.g.key_bits_total + (G.g.excl ? 1 : 0) > 63)
         return fail(LTL4C_EUNSUPPORTED, "stream id, keys and class bits exceed 63 bits");
     G.sort_variant = ctx->sort_variant;
@@ -705,7 +722,7 @@ int32_t ltl4c_workspace_bytes(ltl4c_ctx* ctx, uint64_t n_events, const int32_t* 
     if (s) return s;
     if (!bytes) return fail(LTL4C_EINVAL, "bytes is NULL");
     if (n_events > LTL4C_MAX_EVENTS) return fail(LTL4C_EUNSUPPORTED, "too many events for one call");
-    Geometry g = geometry(ctx->layout);
+    Geometry g = geometry(ctx->layout, 0, false, true, sort_threads(ctx->sort_variant) >= 512);
     *bytes = plan_workspace(ctx->layout, g, n_events, (uint32_t)n_props,
                             (uint32_t)scan_groups(monitor_states(ctx, props, n_props)).size(), ctx->sort_variant,
                             ctx->scan_variant)
@@ -780,6 +797,7 @@ static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, v
         ScanArgs sa{};
         sa.words = sorted;
         sa.n = (uint32_t)n;
+        sa.n_dev = g.compact ? z + w.n_valid_off : nullptr;   // the first radix pass dropped excluded events
         sa.cbits = g.cbits;
         sa.n_levels = NL;
         for (uint32_t m = 1; m < NL; ++m) sa.prefix_shift[m] = g.cbits + (g.key_bits_total - g.prefix_bits[m]);
@@ -875,7 +893,7 @@ int32_t ltl4c_eval(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int3
     const uint32_t P = (uint32_t)n_props;
     if (n > 0 && (reinterpret_cast<uintptr_t>(d_records) & 3))
         return fail(LTL4C_EINVAL, "records must be 4-byte aligned");
-    Geometry g = geometry(L);
+    Geometry g = geometry(L, 0, false, true, sort_threads(ctx->sort_variant) >= 512);
     const std::vector<ScanGroup> groups = scan_groups(monitor_states(ctx, props, n_props));
     WsLayout w = plan_workspace(L, g, n, P, (uint32_t)groups.size(), ctx->sort_variant, ctx->scan_variant);
     if (ws_bytes < w.total) return fail(LTL4C_ENOMEM, "workspace smaller than ltl4c_workspace_bytes()");
@@ -916,7 +934,8 @@ int32_t batch_layout(ltl4c_ctx* ctx, uint64_t n, int32_t n_traces, uint32_t P, u
     if (L.n_keys + 1 > (uint32_t)kMaxLevels)
         return fail(LTL4C_EUNSUPPORTED, "a batch takes properties with at most 3 quantifiers");
     if (n > LTL4C_MAX_EVENTS) return fail(LTL4C_EUNSUPPORTED, "too many events for one call");
-    b->g = geometry(L, std::max<uint32_t>(1, bits_for((uint32_t)n_traces)), true);
+    b->g = geometry(L, std::max<uint32_t>(1, bits_for((uint32_t)n_traces)), true, true,
+                    sort_threads(ctx->sort_variant) >= 512);
     if (b->g.cbits + b->g.key_bits_total + (b->g.excl ? 1 : 0) > 63)
         return fail(LTL4C_EUNSUPPORTED, "trace id, keys and class bits exceed 63 bits");
     b->w = plan_workspace(L, b->g, n, P, n_scan_groups, ctx->sort_variant, ctx->scan_variant);

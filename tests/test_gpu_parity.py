@@ -85,7 +85,7 @@ def test_nested_quantifiers(levels, keys):
 
 
 def test_wide_keys():
-    # 3 x 19-bit keys: a 57-bit binding key plus the exclusion bit, 8 radix passes
+    # 3 x 19-bit keys: a 57-bit binding key, 7 radix passes of 9-bit digits
     wl = prop_workload(50_000, 3, [1 << 19, 1 << 19, 1 << 19], seed=8, n_props=2, key_bits=[19, 19, 19])
     rng = np.random.default_rng(8)
     for m in range(3):
@@ -107,7 +107,40 @@ def test_excluded_events():
     _check(wl)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
+def _excluded_workload(n, seed, p_out):
+    # 27 key bits: three 9-bit or four 8-bit radix passes
+    wl = prop_workload(n, 2, [20, 30], seed=seed, n_props=3, key_bits=[14, 13])
+    rng = np.random.default_rng(seed)
+    t = wl.records["type"].copy()
+    t[rng.random(n) < p_out] = 300
+    wl.records["type"] = t
+    wl.layout.type_bytes = 2
+    return wl
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+def test_excluded_events_sort_variants(variant):
+    # the first radix pass drops excluded events (8- and 9-bit digit kernels);
+    # the later passes and the scan read the kept count on the device
+    import torch
+    from paper_1411_2239_amd import lib
+    wl = _excluded_workload(150_000, 60 + variant, 0.3)
+    print(f"[case] excluded events, sort variant {variant}", flush=True)
+    ctx, ids, rec = lib.open_workload(wl)
+    ctx.set_option(lib.OPT_SORT_TILE, variant)
+    r = ctx.eval(rec, ids, instances=True, nodes=True)
+    torch.cuda.synchronize()
+    ctx.close()
+    compare_full(r, evaluate_workload(wl), len(ids), 2)
+
+
+@pytest.mark.parametrize("p_out", [1.0, 0.9999])
+def test_all_or_nearly_all_events_excluded(p_out):
+    # nothing (or a handful of events) survives the first radix pass
+    _check(_excluded_workload(30_000, 71, p_out))
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
 def test_sort_tile_variants(variant):
     import torch
     from paper_1411_2239_amd import lib
