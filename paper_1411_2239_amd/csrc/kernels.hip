@@ -338,17 +338,28 @@ void k_sort_pass(SortPassArgs a) {
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) dr[r] = (uint32_t)(key[r] >> a.shift) & dmask;
     // rank inside the wave: lanes with the same digit found by one ballot per
-    // digit bit; per-wave counters in LDS carry the count across rounds
+    // digit bit (bits above nbits are zero in every lane and keep every lane);
+    // per-wave counters in LDS carry the count across rounds
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
         const bool valid = (vm >> r) & 1u;
         const uint32_t d = dr[r];
-        uint64_t m = __ballot(valid);
-        for (uint32_t b = 0; b < a.nbits; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bb = __ballot(bit);
-            m &= bit ? bb : ~bb;
+        const uint64_t vb = __ballot(valid);
+        uint32_t x_lo = 0, x_hi = 0;           // lanes whose digit differs from mine
+        uint32_t sb[RB];                       // bit b of d in all 32 bits
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+            sb[b] = (uint32_t)__builtin_amdgcn_sbfe((int32_t)d, b, 1);
+            asm("" : "+v"(sb[b]));             // ballot on sb itself, not on a second extract of the bit
         }
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+            const uint64_t bb = __ballot(sb[b] != 0u);
+            // x |= sb ^ bb, one three-input bit operation per half
+            x_lo = __builtin_amdgcn_bitop3_b32(x_lo, sb[b], (uint32_t)bb, 0xF6);
+            x_hi = __builtin_amdgcn_bitop3_b32(x_hi, sb[b], (uint32_t)(bb >> 32), 0xF6);
+        }
+        const uint64_t m = vb & ~(((uint64_t)x_hi << 32) | x_lo);
         const uint32_t below = (uint32_t)__popcll(m & lt);
         const uint32_t prev = s_wcnt[w * B + d];
         dr[r] = d | ((prev + below) << RB);
