@@ -145,7 +145,12 @@ __device__ __forceinline__ uint32_t valuate(const PropDev& P, int m, const uint3
 __global__ __launch_bounds__(256) void k_zero(ZeroArgs a) {
     const uint64_t n = a.n_dev ? min<uint64_t>(*a.n_dev, a.limit) * a.mult : a.n_words;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) a.ptr[i] = 0u;
+    const uint64_t t0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // 16-byte stores over the aligned part, then the last words one by one
+    const uint64_t head = (reinterpret_cast<uintptr_t>(a.ptr) & 15) == 0 ? n / 4 : 0;
+    uint4* p4 = reinterpret_cast<uint4*>(a.ptr);
+    for (uint64_t i = t0; i < head; i += stride) p4[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (uint64_t i = head * 4 + t0; i < n; i += stride) a.ptr[i] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -578,7 +583,7 @@ __device__ __forceinline__ BMap<MW> bm_load(const uint32_t* p) {
 // carries its own validity bit 31 (counts stay below 2^30 and map bytes below
 // 16): readers need no fence.
 template <int PMAX, int MW, int THREADS>
-__global__ __launch_bounds__(THREADS) void k_scan(ScanArgs a) {
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PMAX * MW <= 8 ? 4 : 1))) void k_scan(ScanArgs a) {
     static_assert(PMAX * MW <= 16 && 4 + PMAX * MW <= kScanRows, "look-back record of at most 20 words");
     constexpr bool kParents = PMAX <= 4;       // LDS room to stage parent ids
     constexpr int TILE = THREADS * kScanItems;
@@ -636,25 +641,37 @@ __global__ __launch_bounds__(THREADS) void k_scan(ScanArgs a) {
     const uint32_t cmask = (1u << cb) - 1u;
 
     // per-event flags as bit masks (excluded events sort last, so the valid
-    // events of a thread are a prefix of its run)
+    // events of a thread are a prefix of its run).  Branch-free: with d the
+    // previous word XOR this one, a change of the packed keys above bit s
+    // shows as d >= 2^s.
+    const uint64_t vlim = 1ull << vs, hlim = 1ull << cb;
+    uint64_t llim[kMaxLevels];
+#pragma unroll
+    for (int m = 1; m < kMaxLevels; ++m) llim[m] = (uint32_t)m < L ? 1ull << a.prefix_shift[m] : ~0ull;
     uint32_t m_valid = 0, m_head = 0, m_end = 0, m_lvl[kMaxLevels] = {0, 0, 0, 0};
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
         const uint64_t x = wv[j];
-        if ((x >> vs) != 0) continue;
-        m_valid |= 1u << j;
-        const uint64_t prv = j == 0 ? wp : wv[j - 1];
-        const bool first = (j == 0 && !has_prev);
-        const uint64_t nxt = j == kScanItems - 1 ? wn : wv[j + 1];
-        if (first || ((prv ^ x) >> cb) != 0) m_head |= 1u << j;
-        if ((nxt >> vs) != 0 || ((nxt ^ x) >> cb) != 0) m_end |= 1u << j;
+        const bool valid = x < vlim;
+        const bool first = j == 0 && !has_prev;
+        const uint64_t d = (j == 0 ? wp : wv[j - 1]) ^ x;
+        m_valid |= (uint32_t)valid << j;
+        m_head |= (uint32_t)(valid && (first || d >= hlim)) << j;
 #pragma unroll
-        for (int m = 1; m < kMaxLevels; ++m) {
-            if (m >= (int)L) break;
-            if (first || ((prv ^ x) >> a.prefix_shift[m]) != 0) m_lvl[m] |= 1u << j;
-        }
+        for (int m = 1; m < kMaxLevels; ++m)
+            if ((uint32_t)m < L) m_lvl[m] |= (uint32_t)(valid && (first || d >= llim[m])) << j;
     }
-    const int n_valid = __popc(m_valid);
+    {
+        // an instance ends where the next word is excluded, absent or of another key
+        const uint32_t cont = m_valid & ~m_head;             // valid words that continue the previous one
+        const bool cont_next = wn < vlim && (wn ^ wv[kScanItems - 1]) < hlim;
+        m_end = m_valid & ~((cont >> 1) | ((uint32_t)cont_next << (kScanItems - 1)));
+    }
+    // the class of each word, 4 bits apiece: the words themselves are not
+    // needed in registers after this point
+    uint64_t cls = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) cls |= (uint64_t)((uint32_t)wv[j] & cmask) << (4 * j);
     uint32_t cnt[4];
     cnt[0] = __popc(m_head);
 #pragma unroll
@@ -670,9 +687,10 @@ __global__ __launch_bounds__(THREADS) void k_scan(ScanArgs a) {
             const BMap<MW> start = bm_const<MW>(s_q0[p]);
 #pragma unroll
             for (int j = 0; j < kScanItems; ++j) {
-                if (j >= n_valid) break;
-                const BMap<MW> cm = bm_load<MW>(s_cm[p][(uint32_t)wv[j] & cmask]);
-                f = bm_compose<MW>(cm, ((m_head >> j) & 1u) ? start : f);
+                // excluded / absent words leave f alone
+                const BMap<MW> cm = bm_load<MW>(s_cm[p][(uint32_t)(cls >> (4 * j)) & 15u]);
+                const BMap<MW> g = bm_compose<MW>(cm, ((m_head >> j) & 1u) ? start : f);
+                if ((m_valid >> j) & 1u) f = g;
             }
         }
         BMap<MW> v = f;
@@ -838,10 +856,6 @@ __global__ __launch_bounds__(THREADS) void k_scan(ScanArgs a) {
 #pragma unroll
     for (int p = 0; p < PMAX; ++p)
         cur[p] = p < (int)P ? bm_at<MW>(bm_compose<MW>(excl[p], bm_load<MW>(s_tprefix[p])), 0) : 0u;
-    uint32_t inst = s_tcnt[0] + cexcl[0];
-    uint32_t lvl[4];
-#pragma unroll
-    for (int m = 1; m < 4; ++m) lvl[m] = s_tcnt[m] + cexcl[m];
     // staging in the word buffer (free now): verdict bytes [P][TILE + 1],
     // then parent ids [TILE + 1]
     uint8_t* s_iv = reinterpret_cast<uint8_t*>(s_w);
@@ -849,24 +863,53 @@ __global__ __launch_bounds__(THREADS) void k_scan(ScanArgs a) {
     static_assert(PMAX * kIvStride + (kParents ? 4 * kIvStride + 4 : 0) <= sizeof(s_w), "staging fits the word buffer");
     uint32_t* s_par = reinterpret_cast<uint32_t*>(s_iv + ((PMAX * kIvStride + 3) & ~3u));
     const uint32_t id_base = s_tcnt[0];
+    // parents are level-(L-1) nodes: their heads, and the id before this thread's first
+    const uint32_t m_par = L >= 4 ? m_lvl[3] : L == 3 ? m_lvl[2] : m_lvl[1];
+    const uint32_t par_base = (L >= 4 ? s_tcnt[3] + cexcl[3] : L == 3 ? s_tcnt[2] + cexcl[2] : s_tcnt[1] + cexcl[1]) - 1u;
     uint32_t my_lo = 0xFFFFFFFFu, my_hi = 0u;
     uint32_t err = 0;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
-        if (j >= n_valid) break;
-        const uint64_t x = wv[j];
-        const uint32_t c = (uint32_t)x & cmask;
-        if ((m_head >> j) & 1u) {
-            ++inst;
+        const uint32_t c = (uint32_t)(cls >> (4 * j)) & 15u;
+        const bool hd = (m_head >> j) & 1u;
 #pragma unroll
-            for (int p = 0; p < PMAX; ++p) cur[p] = p < (int)P ? s_q0[p] : 0u;
+        for (int p = 0; p < PMAX; ++p)
+            if (p < (int)P) cur[p] = bm_at<MW>(bm_load<MW>(s_cm[p][c]), hd ? s_q0[p] : cur[p]);
+        if ((m_end >> j) & 1u) {
+            // instances of this thread so far, from its head count
+            const uint32_t upto = (2u << j) - 1u;
+            const uint32_t slot = cexcl[0] + __popc(m_head & upto);
+            const uint64_t id = (uint64_t)id_base + slot - 1u;
+            if (id < a.inst_limit) {
+#pragma unroll
+                for (int p = 0; p < PMAX; ++p)
+                    if (p < (int)P)
+                        s_iv[p * kIvStride + slot] =
+                            a.emit_state ? cur[p] : (s_lab[p][cur[p] >> 3] >> (4 * (cur[p] & 7u))) & 15u;
+                if (kParents && L >= 2) s_par[slot] = par_base + __popc(m_par & upto);
+                my_lo = min(my_lo, (uint32_t)id);
+                my_hi = max(my_hi, (uint32_t)id + 1u);
+                if (structure && a.inst_keys) a.inst_keys[id] = a.words[base + (uint64_t)tid * kScanItems + j] >> cb;
+            } else {
+                err |= kErrCapacity;
+            }
+        }
+    }
+    // nodes of levels 1.. open at their first word; every such word is a
+    // level-(L-1) head, and a level-m head is also a level-(m+1) head
+    if (structure && L >= 2) {
+        // few words open nodes: loop over them, the word read again from memory
+        for (uint32_t rest = m_par; rest != 0u; rest &= rest - 1u) {
+            const int j = __ffs(rest) - 1;
+            const uint32_t upto = (2u << j) - 1u;
+            const uint64_t x = a.words[base + (uint64_t)tid * kScanItems + j];
 #pragma unroll
             for (int m = kMaxLevels - 1; m >= 1; --m) {
                 if (m >= (int)L || !((m_lvl[m] >> j) & 1u)) continue;
-                ++lvl[m];
-                if (!structure) continue;
-                const uint64_t id = lvl[m] - 1;
-                const uint32_t child = m == (int)L - 1 ? inst - 1 : lvl[m < 3 ? m + 1 : 3] - 1;
+                const uint64_t id = (uint64_t)s_tcnt[m] + cexcl[m] + __popc(m_lvl[m] & upto) - 1u;
+                const int mc = m < 3 ? m + 1 : 3;
+                const uint32_t child = m == (int)L - 1 ? s_tcnt[0] + cexcl[0] + __popc(m_head & upto) - 1u
+                                                       : s_tcnt[mc] + cexcl[mc] + __popc(m_lvl[mc] & upto) - 1u;
                 if (id < a.node_limit[m]) {
                     a.node_start[m][id] = child;
                     if (a.node_keys[m]) a.node_keys[m][id] = x >> a.prefix_shift[m];
@@ -874,26 +917,6 @@ __global__ __launch_bounds__(THREADS) void k_scan(ScanArgs a) {
                 } else {
                     err |= kErrCapacity;
                 }
-            }
-        }
-#pragma unroll
-        for (int p = 0; p < PMAX; ++p)
-            if (p < (int)P) cur[p] = bm_at<MW>(bm_load<MW>(s_cm[p][c]), cur[p]);
-        if ((m_end >> j) & 1u) {
-            const uint64_t id = inst - 1;
-            if (id < a.inst_limit) {
-                const uint32_t slot = (uint32_t)id + 1u - id_base;
-#pragma unroll
-                for (int p = 0; p < PMAX; ++p)
-                    if (p < (int)P)
-                        s_iv[p * kIvStride + slot] =
-                            a.emit_state ? cur[p] : (s_lab[p][cur[p] >> 3] >> (4 * (cur[p] & 7u))) & 15u;
-                if (kParents && L >= 2) s_par[slot] = (L >= 4 ? lvl[3] : L == 3 ? lvl[2] : lvl[1]) - 1u;
-                my_lo = min(my_lo, (uint32_t)id);
-                my_hi = max(my_hi, (uint32_t)id + 1u);
-                if (structure && a.inst_keys) a.inst_keys[id] = x >> cb;
-            } else {
-                err |= kErrCapacity;
             }
         }
     }
