@@ -583,7 +583,7 @@ __device__ __forceinline__ BMap<MW> bm_load(const uint32_t* p) {
 // carries its own validity bit 31 (counts stay below 2^30 and map bytes below
 // 16): readers need no fence.
 template <int PMAX, int MW, int THREADS>
-__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PMAX * MW <= 8 ? 4 : 1))) void k_scan(ScanArgs a) {
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(MW == 2 || PMAX <= 2 ? 4 : 1))) void k_scan(ScanArgs a) {
     static_assert(PMAX * MW <= 16 && 4 + PMAX * MW <= kScanRows, "look-back record of at most 20 words");
     constexpr bool kParents = PMAX <= 4;       // LDS room to stage parent ids
     constexpr int TILE = THREADS * kScanItems;
@@ -593,7 +593,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PMAX * 
     __shared__ uint32_t s_cm[PMAX][16][MW];
     __shared__ uint32_t s_q0[PMAX], s_lab[PMAX][2];
     __shared__ uint32_t s_wtot[PMAX][WAVES][MW];
-    __shared__ uint32_t s_ctot[4][WAVES];
+    __shared__ uint32_t s_ctot[2][WAVES];
     __shared__ uint32_t s_tprefix[PMAX][MW];
     __shared__ uint32_t s_tagg[PMAX][MW];
     __shared__ uint32_t s_cagg[4];
@@ -705,11 +705,16 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PMAX * 
 #pragma unroll
             for (int k = 0; k < MW; ++k) s_wtot[p][w][k] = v.d[k];
     }
+    // head counts two to a word in 16-bit fields (a tile holds at most 8192
+    // words, so no field carries into the next); levels 2-3 only when present
     uint32_t cexcl[4];
+    uint32_t pe[2] = {0u, 0u};
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint32_t incl = wave_incl_scan_u32(cnt[k]);
-        cexcl[k] = incl - cnt[k];
+    for (int k = 0; k < 2; ++k) {
+        if (k == 1 && L <= 2) break;
+        const uint32_t pk = cnt[2 * k] | (cnt[2 * k + 1] << 16);
+        const uint32_t incl = wave_incl_scan_u32(pk);
+        pe[k] = incl - pk;
         if (lane == 63) s_ctot[k][w] = incl;
     }
     __syncthreads();
@@ -721,22 +726,25 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(PMAX * 
         excl[p] = bm_compose<MW>(excl[p], pre);
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        uint32_t pre = 0;
-        for (int i = 0; i < w; ++i) pre += s_ctot[k][i];
-        cexcl[k] += pre;
+    for (int k = 0; k < 2; ++k) {
+        if (k == 1 && L <= 2) break;
+        for (int i = 0; i < w; ++i) pe[k] += s_ctot[k][i];
     }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cexcl[k] = (pe[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
     if (tid < (int)P) {
         BMap<MW> t = bm_identity<MW>();
         for (int i = 0; i < WAVES; ++i) t = bm_compose<MW>(bm_load<MW>(s_wtot[tid][i]), t);
 #pragma unroll
         for (int k = 0; k < MW; ++k) s_tagg[tid][k] = t.d[k];
     }
-    if (tid >= 32 && tid < 36) {
+    if (tid >= 32 && tid < 34) {
         const int k = tid - 32;
         uint32_t sum = 0;
-        for (int i = 0; i < WAVES; ++i) sum += s_ctot[k][i];
-        s_cagg[k] = sum;
+        if (k == 0 || L > 2)
+            for (int i = 0; i < WAVES; ++i) sum += s_ctot[k][i];
+        s_cagg[2 * k] = sum & 0xFFFFu;
+        s_cagg[2 * k + 1] = sum >> 16;
     }
     __syncthreads();
 
