@@ -582,8 +582,11 @@ __device__ __forceinline__ BMap<MW> bm_load(const uint32_t* p) {
 // of 64 consecutive tiles read one contiguous 256-byte span.  Every word
 // carries its own validity bit 31 (counts stay below 2^30 and map bytes below
 // 16): readers need no fence.
+//
+// Every instance is held to 128 VGPRs so that two 512-thread blocks share a
+// CU; the 4 x 16-state instance spills a few words, and still runs faster so.
 template <int PMAX, int MW, int THREADS>
-__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(MW == 2 || PMAX <= 2 ? 4 : 1))) void k_scan(ScanArgs a) {
+__global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_scan(ScanArgs a) {
     static_assert(PMAX * MW <= 16 && 4 + PMAX * MW <= kScanRows, "look-back record of at most 20 words");
     constexpr bool kParents = PMAX <= 4;       // LDS room to stage parent ids
     constexpr int TILE = THREADS * kScanItems;
