@@ -84,6 +84,13 @@ def test_nested_quantifiers(levels, keys):
     _check(prop_workload(80_000, levels, keys, seed=100 + levels, n_props=5))
 
 
+@pytest.mark.parametrize("n_outer", [900, 30_000])
+def test_root_level_counting(n_outer):
+    # few or many level-1 nodes under the root, whose count ends with Def. 7
+    # in the last block to finish
+    _check(prop_workload(200_000, 2, [n_outer, 7], seed=17, n_props=3))
+
+
 def test_wide_keys():
     # 3 x 19-bit keys: a 57-bit binding key, 7 radix passes of 9-bit digits
     wl = prop_workload(50_000, 3, [1 << 19, 1 << 19, 1 << 19], seed=8, n_props=2, key_bits=[19, 19, 19])
