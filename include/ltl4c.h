@@ -284,8 +284,10 @@ int32_t ltl4c_group_restore(ltl4c_ctx *ctx, int32_t group, const void *host, uin
  * 3 = 256 x 8, 4 = 512 x 8, 5 = 512 x 12.  The 512-thread shapes sort 9-bit
  * digits when that takes fewer passes than 8-bit ones. */
 enum { LTL4C_OPT_SORT_TILE = 0, LTL4C_OPT_SCAN_TILE = 1 };
-/* LTL4C_OPT_SCAN_TILE: map-scan tile of 0 = 256 threads x 16 words or
- * 1 = 512 x 16 (default). */
+/* LTL4C_OPT_SCAN_TILE: map-scan tile of 0 = 256 threads x 16 words,
+ * 1 = 512 x 16, 2 = 1024 x 16, or 3 = per launch (default): 1024 x 16 when a
+ * launch's maps take at most 4 dwords per event (one or two properties of at
+ * most 8 states, or one of at most 16), else 512 x 16. */
 int32_t ltl4c_set_option(ltl4c_ctx *ctx, int32_t option, int64_t value);
 
 /* ---- profiling: per-kernel time of the enqueued work ------------------- */

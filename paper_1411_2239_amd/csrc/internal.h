@@ -235,7 +235,7 @@ uint32_t sort_tile(int variant);      // words per radix tile of a sort variant
 constexpr int kSortVariants = 6;
 hipError_t launch_scan(const ScanArgs& a, int variant, hipStream_t s);
 uint32_t scan_tile(int variant);      // words per scan tile of a scan variant
-constexpr int kScanVariants = 2;
+constexpr int kScanVariants = 4;
 hipError_t launch_count(const CountArgs& a, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
 hipError_t launch_group_update(const GroupUpdateArgs& a, uint64_t max_seg, hipStream_t s);

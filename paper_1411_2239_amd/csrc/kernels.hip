@@ -1582,12 +1582,21 @@ static void launch_scan_t(const ScanArgs& a, hipStream_t s) {
     }
 }
 
-uint32_t scan_tile(int variant) { return (variant == 1 ? 512u : 256u) * kScanItems; }
+// Variant 3 picks per launch: 1024-thread tiles for launches whose maps take
+// at most 4 dwords per event (fewer tiles, a shorter look-back chain), 512
+// otherwise.  Workspace is sized for the smaller tile.
+uint32_t scan_tile(int variant) { return (variant == 2 ? 1024u : variant == 0 ? 256u : 512u) * kScanItems; }
 
 hipError_t launch_scan(const ScanArgs& a, int variant, hipStream_t s) {
     if (a.n_props < 1 || a.n_props > (a.max_states <= 8 ? 8u : 4u) || (a.structure && a.n_props > 4))
         return hipErrorInvalidValue;
-    if (variant == 1) launch_scan_t<512>(a, s);
+    if (variant == 3) {
+        const uint32_t mw = a.max_states <= 8 ? 2u : 4u;
+        const uint32_t pmax = a.n_props <= 1 ? 1u : a.n_props <= 2 ? 2u : a.n_props <= 4 ? 4u : 8u;
+        variant = mw * pmax <= 4 ? 2 : 1;
+    }
+    if (variant == 2) launch_scan_t<1024>(a, s);
+    else if (variant == 1) launch_scan_t<512>(a, s);
     else launch_scan_t<256>(a, s);
     return hipGetLastError();
 }

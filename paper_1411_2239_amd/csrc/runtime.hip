@@ -65,7 +65,7 @@ struct ltl4c_ctx {
     std::map<std::vector<int32_t>, Plan*> plans;
     uint32_t* err_dev = nullptr;
     int sort_variant = 1;
-    int scan_variant = 1;
+    int scan_variant = 3;
     uint64_t budget = ~0ull, used = 0;
     uint32_t* batch_chunk_dev = nullptr;      // trace table of ltl4c_eval_batch
     uint32_t* batch_chunk_host = nullptr;     // pinned staging for it
