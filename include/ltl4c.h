@@ -281,8 +281,9 @@ int32_t ltl4c_group_restore(ltl4c_ctx *ctx, int32_t group, const void *host, uin
 /* Kernel schedule options (set before ltl4c_workspace_bytes, which depends
  * on them).  LTL4C_OPT_SORT_TILE selects the radix-pass tile shape:
  * 0 = 256 threads x 16 words, 1 = 512 x 16 (default), 2 = 256 x 24,
- * 3 = 256 x 8, 4 = 512 x 8, 5 = 512 x 12.  The 512-thread shapes sort 9-bit
- * digits when that takes fewer passes than 8-bit ones. */
+ * 3 = 256 x 8, 4 = 512 x 8, 5 = 512 x 12, 6 = 1024 x 16.  The shapes of 512
+ * and more threads sort 9-bit digits when that takes fewer passes than 8-bit
+ * ones. */
 enum { LTL4C_OPT_SORT_TILE = 0, LTL4C_OPT_SCAN_TILE = 1 };
 /* LTL4C_OPT_SCAN_TILE: map-scan tile of 0 = 256 threads x 16 words,
  * 1 = 512 x 16, 2 = 1024 x 16, or 3 = per launch (default): 1024 x 16 when a

@@ -232,7 +232,7 @@ hipError_t launch_classify(const ClassifyArgs& a, hipStream_t s);
 hipError_t launch_sort_pass(const SortPassArgs& a, int variant, uint32_t digit_bits, hipStream_t s);
 uint32_t sort_threads(int variant);   // threads per block of a sort variant
 uint32_t sort_tile(int variant);      // words per radix tile of a sort variant
-constexpr int kSortVariants = 6;
+constexpr int kSortVariants = 7;
 hipError_t launch_scan(const ScanArgs& a, int variant, hipStream_t s);
 uint32_t scan_tile(int variant);      // words per scan tile of a scan variant
 constexpr int kScanVariants = 4;

@@ -295,7 +295,7 @@ void k_sort_pass(SortPassArgs a) {
     constexpr int NB = B / 64;                 // waves whose threads own a bucket
     constexpr int TILE = THREADS * ITEMS;
     constexpr int WAVES = THREADS / 64;
-    constexpr int PHASES = (TILE + 8191) / 8192;
+    constexpr int PHASES = TILE <= 16384 ? 1 : (TILE + 8191) / 8192;
     constexpr int CHUNK = TILE / PHASES;
     // 512 buckets: the per-wave counters and the key buffer share LDS (keys
     // are placed once every position is known), which keeps two 512 x 16
@@ -1530,11 +1530,12 @@ uint32_t sort_tile(int variant) {
         case 3: return 256 * 8;
         case 4: return 512 * 8;
         case 5: return 512 * 12;
+        case 6: return 1024 * 16;
         default: return 256 * 16;
     }
 }
 
-uint32_t sort_threads(int variant) { return variant == 1 || variant == 4 || variant == 5 ? 512u : 256u; }
+uint32_t sort_threads(int variant) { return variant == 6 ? 1024u : variant == 1 || variant == 4 || variant == 5 ? 512u : 256u; }
 
 hipError_t launch_sort_pass(const SortPassArgs& a, int variant, uint32_t digit_bits, hipStream_t s) {
     const uint32_t tile = sort_tile(variant);
@@ -1544,6 +1545,7 @@ hipError_t launch_sort_pass(const SortPassArgs& a, int variant, uint32_t digit_b
             case 1: hipLaunchKernelGGL((k_sort_pass<512, 16, 9>), dim3(tiles), dim3(512), 0, s, a); break;
             case 4: hipLaunchKernelGGL((k_sort_pass<512, 8, 9>), dim3(tiles), dim3(512), 0, s, a); break;
             case 5: hipLaunchKernelGGL((k_sort_pass<512, 12, 9>), dim3(tiles), dim3(512), 0, s, a); break;
+            case 6: hipLaunchKernelGGL((k_sort_pass<1024, 16, 9>), dim3(tiles), dim3(1024), 0, s, a); break;
             default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
@@ -1555,6 +1557,7 @@ hipError_t launch_sort_pass(const SortPassArgs& a, int variant, uint32_t digit_b
         case 3: hipLaunchKernelGGL((k_sort_pass<256, 8, 8>), dim3(tiles), dim3(256), 0, s, a); break;
         case 4: hipLaunchKernelGGL((k_sort_pass<512, 8, 8>), dim3(tiles), dim3(512), 0, s, a); break;
         case 5: hipLaunchKernelGGL((k_sort_pass<512, 12, 8>), dim3(tiles), dim3(512), 0, s, a); break;
+        case 6: hipLaunchKernelGGL((k_sort_pass<1024, 16, 8>), dim3(tiles), dim3(1024), 0, s, a); break;
         default: hipLaunchKernelGGL((k_sort_pass<256, 16, 8>), dim3(tiles), dim3(256), 0, s, a); break;
     }
     return hipGetLastError();

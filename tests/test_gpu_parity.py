@@ -125,7 +125,7 @@ def _excluded_workload(n, seed, p_out):
     return wl
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
 def test_excluded_events_sort_variants(variant):
     # the first radix pass drops excluded events (8- and 9-bit digit kernels);
     # the later passes and the scan read the kept count on the device
@@ -147,7 +147,7 @@ def test_all_or_nearly_all_events_excluded(p_out):
     _check(_excluded_workload(30_000, 71, p_out))
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
 def test_sort_tile_variants(variant):
     import torch
     from paper_1411_2239_amd import lib
