@@ -372,14 +372,10 @@ void k_sort_pass(SortPassArgs a) {
     }
     __syncthreads();
     // per bucket: publish this tile's count, then tile and global offsets
-    uint32_t cw[WAVES];
     uint32_t tot = 0;
     if (tid < B) {
 #pragma unroll
-        for (int ww = 0; ww < WAVES; ++ww) {
-            cw[ww] = s_wcnt[ww * B + tid];
-            tot += cw[ww];
-        }
+        for (int ww = 0; ww < WAVES; ++ww) tot += s_wcnt[ww * B + tid];
         st_flag(a.status + (uint64_t)tile * B + tid, (tile == 0 ? kFlagInc : kFlagAgg) | tot);
     }
     const uint2 ex = block_excl_scan2<NB>(tot, h, s_tmp);
@@ -388,12 +384,13 @@ void k_sort_pass(SortPassArgs a) {
 #pragma unroll
     for (int i = 0; i < NB; ++i) tile_n += s_tmp[i];
     if (tid < B) {
-        // each thread rewrites only its own bucket's column
+        // each thread reads and rewrites only its own bucket's column
         uint32_t run = lstart;
 #pragma unroll
         for (int ww = 0; ww < WAVES; ++ww) {
+            const uint32_t c = s_wcnt[ww * B + tid];
             s_wcnt[ww * B + tid] = run;
-            run += cw[ww];
+            run += c;
         }
     }
     __syncthreads();
