@@ -84,6 +84,26 @@ def test_nested_quantifiers(levels, keys):
     _check(prop_workload(80_000, levels, keys, seed=100 + levels, n_props=5))
 
 
+@pytest.mark.parametrize("instances", [True, False])
+@pytest.mark.parametrize("case", ["users", "two", "three", "four", "two_wide"])
+def test_without_node_outputs(case, instances):
+    # root results (and instance verdicts when asked) with the node counts
+    # kept in the workspace only
+    if case == "users":
+        wl = W.gen_user_requests(n_events=400_000, n_users=800, seed=51)
+    elif case == "two":
+        wl = prop_workload(120_000, 2, [40, 50], seed=52, n_props=3)
+    elif case == "three":
+        wl = prop_workload(120_000, 3, [5, 7, 9], seed=53, n_props=4)
+    elif case == "four":
+        wl = prop_workload(120_000, 4, [3, 4, 5, 6], seed=54, n_props=2)
+    else:
+        # parents spread far beyond the LDS window of a tile
+        wl = prop_workload(150_000, 2, [20_000, 3], seed=55, n_props=1)
+    r, P = _run(wl, instances=instances, nodes=False)
+    compare_full(r, evaluate_workload(wl), P, wl.layout.n_keys)
+
+
 @pytest.mark.parametrize("n_outer", [900, 30_000])
 def test_root_level_counting(n_outer):
     # few or many level-1 nodes under the root, whose count ends with Def. 7
