@@ -4,19 +4,22 @@
 //                step of SortTrace in Algorithm 1): record -> letter (event
 //                class) and packed binding key; builds the radix histograms
 //                of every sort pass in the same read.
-//   k_sort_pass  one stable LSD radix pass (ParallelSort of Algorithm 1):
-//                single-pass "onesweep" ranking with wave ballots, LDS-staged
-//                scatter and decoupled look-back across tiles.
+//   k_sort_pass  one stable LSD radix pass (ParallelSort of Algorithm 1) on
+//                8- or 9-bit digits: single-pass "onesweep" ranking with wave
+//                ballots, LDS-staged scatter and decoupled look-back across
+//                tiles; the first pass may drop events that join no cluster.
 //   k_scan       Distribute / ProcessBuffer of Algorithm 1 as a flat scan:
-//                composes nibble-packed transition maps (a segment head is
-//                the constant map to delta(q0, c)), so each instance's final
+//                composes byte-packed transition maps (a segment head is the
+//                constant map to delta(q0, c)), so each instance's final
 //                state lambda(delta(q0, u^D)) (Def. 6) is found without one
 //                thread per monitor; also the compaction (ParallelCompact)
 //                into instance and node numbering.
-//   k_count      ApplyQuantifiers of Algorithm 1 for one level: the 6-bin
+//   k_count_leaves, k_count
+//                ApplyQuantifiers of Algorithm 1 for one level: the 6-bin
 //                count vector v of every quantifier submonitor (Def. 8) from
-//                its children's verdicts.
-//   k_finalize   Def. 7 at the root.
+//                its children's verdicts (Def. 7 at every child node); at the
+//                root the last block also runs Def. 7 at the root.
+//   k_finalize   Def. 7 at the root of a one-level tree.
 #include "internal.h"
 
 namespace ltl4c {
