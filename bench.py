@@ -82,6 +82,7 @@ def serving_bench(n_chunks=3000, pool_events=1_000_000, n_streams=64, plain_chun
     in flight).  Plain: one synchronous push per chunk, in arrival order.
     Latency = verdict visible (push completed) - chunk arrival."""
     import collections
+    import gc
     import numpy as np
     import torch
     from paper_1411_2239_amd import lib, workloads
@@ -160,14 +161,26 @@ def serving_bench(n_chunks=3000, pool_events=1_000_000, n_streams=64, plain_chun
     log("[bench] serving: warmup")
     run_batched(grp, min(200, n_chunks))
     grp.close()
-    grp = lib.StreamGroup(ctx, [pid], n_streams, 100_000, max_batch)
-    log(f"[bench] serving: batched, {n_chunks} chunks")
-    lat, ev, el = run_batched(grp, n_chunks)
-    v, c, b = grp.read()
-    batched = {"events_per_s": ev / el, "chunks": n_chunks, "events": ev, "seconds": el,
-               "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-               "live_bindings": int(b.sum()), "pushes": pushes[0]}
-    grp.close()
+    # three runs of the schedule, each on a fresh group, with Python's garbage
+    # collector paused; the run with the median p99 is reported (a host-side
+    # stall of the open-loop driver shows up as latency of every chunk that
+    # arrives meanwhile)
+    runs = []
+    for rep in range(3):
+        grp = lib.StreamGroup(ctx, [pid], n_streams, 100_000, max_batch)
+        log(f"[bench] serving: batched, {n_chunks} chunks, run {rep + 1}/3")
+        gc.disable()
+        try:
+            lat, ev, el = run_batched(grp, n_chunks)
+        finally:
+            gc.enable()
+        v, c, b = grp.read()
+        runs.append({"events_per_s": ev / el, "chunks": n_chunks, "events": ev, "seconds": el,
+                     "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                     "live_bindings": int(b.sum()), "pushes": pushes[0]})
+        grp.close()
+    batched = sorted(runs, key=lambda r: r["p99_ms"])[1]
+    batched["p99_ms_of_runs"] = [r["p99_ms"] for r in runs]
     # per-kernel time of the same batched schedule, in a separate profiled run
     grp = lib.StreamGroup(ctx, [pid], n_streams, 100_000, max_batch)
     ctx.profile(True)
@@ -178,12 +191,21 @@ def serving_bench(n_chunks=3000, pool_events=1_000_000, n_streams=64, plain_chun
     batched["kernel_ms"] = {k: round(x[0], 3) for k, x in prof.items()}
     batched["profiled_pushes"] = pushes[0]
     grp.close()
-    # capacity: every chunk available at once (closed loop), same pushes
-    grp = lib.StreamGroup(ctx, [pid], n_streams, 100_000, max_batch)
-    _, ev_c, el_c = run_batched(grp, n_chunks, np.zeros(n_chunks))
-    batched["capacity_events_per_s"] = ev_c / el_c
+    # capacity: every chunk available at once (closed loop), same pushes;
+    # median of three runs
+    caps = []
+    for rep in range(3):
+        grp = lib.StreamGroup(ctx, [pid], n_streams, 100_000, max_batch)
+        gc.disable()
+        try:
+            _, ev_c, el_c = run_batched(grp, n_chunks, np.zeros(n_chunks))
+        finally:
+            gc.enable()
+        caps.append(ev_c / el_c)
+        grp.close()
+    batched["capacity_events_per_s"] = sorted(caps)[1]
+    batched["capacity_events_per_s_of_runs"] = caps
     batched["capacity_pushes"] = pushes[0]
-    grp.close()
     grp = lib.StreamGroup(ctx, [pid], n_streams, 100_000, max_batch)
     log(f"[bench] serving: plain, {plain_chunks} chunks")
     lat_p, ev_p, el_p = run_plain(grp, plain_chunks)

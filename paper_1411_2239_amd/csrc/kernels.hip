@@ -194,7 +194,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     // Records of one grid-stride step are loaded before any is processed, so
     // that each thread keeps U loads in flight.
-    constexpr int U = (RDW > 0 && !GROUP) ? 4 : 1;
+    constexpr int U = RDW > 0 ? 4 : 1;
     constexpr int NDW = RDW > 0 ? RDW : 1;
     auto process = [&](uint64_t i, uint32_t t, const uint32_t* f, uint32_t chunk) {
         bool ok = !(a.check_type_range && t > 255u);
