@@ -318,6 +318,35 @@ def large_bench(n_events=500_000_000, reps=3, log=print):
     return out
 
 
+def predicates_bench(n_events=10_000_000, reps=10, log=print):
+    """Data predicates as class bits: the cloud-storage fairness shape (every
+    event carries the user's average chunk size, compared on the device with
+    a maximum and with zero), 10,000 users, three properties in one pass."""
+    import torch
+    from paper_1411_2239_amd import lib, workloads
+
+    log("[bench] data predicates: generating the chunk-upload trace")
+    wl = workloads.gen_chunk_uploads(n_events, n_preds=2)
+    ctx, ids, rec = lib.open_workload(wl)
+    ws = ctx.workspace(n_events, ids)
+    res = ctx.alloc_result(len(ids))
+    ctx.eval_into(rec, n_events, ids, res, ws)
+    ctx.wait()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.eval_into(rec, n_events, ids, res, ws)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    ctx.wait()
+    out = {"workload": f"{n_events} events, 10,000 users, 2 data predicates (avg chunk < 4 MiB, != 0), "
+                       f"3 properties",
+           "events": n_events, "events_per_s": n_events / el, "ms": el * 1e3,
+           "root_verdict": [lib.VERDICT_NAMES[v] for v in res.root_verdict.cpu().numpy().tolist()]}
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -331,6 +360,7 @@ def main():
     ap.add_argument("--no-batching", action="store_true", help="skip the batched-traces section")
     ap.add_argument("--batch-traces", type=int, default=4096)
     ap.add_argument("--no-large", action="store_true", help="skip the 500M-event single-trace section")
+    ap.add_argument("--no-predicates", action="store_true", help="skip the data-predicate section")
     ap.add_argument("--large-events", type=int, default=500_000_000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")
@@ -413,6 +443,9 @@ def main():
     large = None
     if not args.no_large:
         large = large_bench(args.large_events, log=log)
+    predicates = None
+    if not args.no_predicates:
+        predicates = predicates_bench(log=log)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -439,6 +472,7 @@ def main():
         "serving": serving,
         "batching": batching,
         "large_trace": large,
+        "data_predicates": predicates,
         "batched_vs_plain_speedup": batching["batched_vs_plain"] if batching else None,
         "p99_chunk_latency_ms": serving["batched"]["p99_ms"] if serving else None,
         "cpu_baseline": cpu,

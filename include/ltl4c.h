@@ -80,7 +80,27 @@ typedef struct ltl4c_ctx ltl4c_ctx;
  * below 2^key_bits[m].  The composite binding key (key 0 in the most
  * significant bits) plus the class bits must fit in 63 bits.  A wider value
  * is detected on the device and reported as LTL4C_ERANGE by ltl4c_wait().
+ *
+ * Data predicates (propositions computed from a record's data, such as the
+ * comparison of a session's average chunk size with a maximum in the paper's
+ * cloud-storage case study, Section 5): predicate i holds for an event when
+ * its field (an unsigned little-endian integer of pred[i].bytes = 1, 2 or 4
+ * bytes at pred[i].offset, naturally aligned) compared by pred[i].op with
+ * pred[i].value is true.  The event's class is then
+ *   class_of_type[type] + (sum over holding predicates i of 2^i) << pred_shift,
+ * which must stay below n_classes for every type and predicate outcome
+ * (checked by ltl4c_set_layout).  n_preds = 0 leaves the class as
+ * class_of_type[type].
  */
+enum { LTL4C_CMP_LT = 0, LTL4C_CMP_LE = 1, LTL4C_CMP_GT = 2, LTL4C_CMP_GE = 3, LTL4C_CMP_EQ = 4, LTL4C_CMP_NE = 5 };
+
+typedef struct {
+    uint32_t offset;
+    uint32_t bytes;                  /* 1, 2 or 4 */
+    uint32_t op;                     /* LTL4C_CMP_* */
+    uint32_t value;
+} ltl4c_pred;
+
 typedef struct {
     uint32_t record_bytes;
     uint32_t type_offset;
@@ -92,6 +112,9 @@ typedef struct {
     uint32_t n_classes;              /* 1..16 */
     uint8_t  class_of_type[256];
     uint8_t  key_present[256];
+    uint32_t n_preds;                /* data predicates, 0..3 */
+    uint32_t pred_shift;             /* class bit of predicate 0 */
+    ltl4c_pred pred[3];
 } ltl4c_layout;
 
 /*

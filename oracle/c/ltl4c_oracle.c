@@ -37,7 +37,24 @@ typedef struct {
     uint32_t key_offset[4], key_bytes[4];
     const uint8_t *class_of_type;     /* [256] */
     const uint8_t *key_present;       /* [256]: bit m set = the type carries key m */
+    /* data predicates (propositions read off a record's data, as in the
+     * cloud-storage case study of Section 5): predicate i holds when the
+     * unsigned field at pred_offset[i] compares true with pred_value[i];
+     * the letter of the event is then its type's letter plus
+     * 2^(pred_shift + i) for every holding predicate i */
+    uint32_t n_preds, pred_shift;
+    uint32_t pred_offset[3], pred_bytes[3], pred_op[3], pred_value[3];
 } ora_layout;
+
+/* comparison codes of a data predicate: < <= > >= == != */
+static int pred_true(uint32_t op, uint32_t x, uint32_t v) {
+    if (op == 0) return x < v;
+    if (op == 1) return x <= v;
+    if (op == 2) return x > v;
+    if (op == 3) return x >= v;
+    if (op == 4) return x == v;
+    return x != v;
+}
 
 typedef struct {
     uint32_t n_states, n_classes, q0, pad;
@@ -189,6 +206,9 @@ ora_result *ora_eval(const uint8_t *records, uint64_t n, const ora_layout *L,
         for (int m = 0; m < nk; ++m) e.key[m] = read_field(rec, L->key_offset[m], L->key_bytes[m]);
         e.pos = i;
         e.cls = L->class_of_type[type];
+        for (uint32_t q = 0; q < L->n_preds && q < 3; ++q)
+            if (pred_true(L->pred_op[q], read_field(rec, L->pred_offset[q], L->pred_bytes[q]), L->pred_value[q]))
+                e.cls += 1u << (L->pred_shift + q);
         ev[ne++] = e;
     }
     g_nk = nk;

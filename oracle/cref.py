@@ -37,7 +37,10 @@ def build(verbose=False):
 class _Layout(C.Structure):
     _fields_ = [("record_bytes", C.c_uint32), ("type_offset", C.c_uint32), ("type_bytes", C.c_uint32),
                 ("n_keys", C.c_uint32), ("key_offset", C.c_uint32 * 4), ("key_bytes", C.c_uint32 * 4),
-                ("class_of_type", C.POINTER(C.c_uint8)), ("key_present", C.POINTER(C.c_uint8))]
+                ("class_of_type", C.POINTER(C.c_uint8)), ("key_present", C.POINTER(C.c_uint8)),
+                ("n_preds", C.c_uint32), ("pred_shift", C.c_uint32),
+                ("pred_offset", C.c_uint32 * 3), ("pred_bytes", C.c_uint32 * 3),
+                ("pred_op", C.c_uint32 * 3), ("pred_value", C.c_uint32 * 3)]
 
 
 class _Prop(C.Structure):
@@ -111,8 +114,9 @@ class OracleResult:
 
 
 def evaluate_records(records, record_bytes, type_offset, type_bytes, key_offsets, key_bytes,
-                     class_of_type, key_present, props):
-    """Run the C oracle.  `records` is a uint8 buffer of n * record_bytes bytes."""
+                     class_of_type, key_present, props, preds=(), pred_shift=0):
+    """Run the C oracle.  `records` is a uint8 buffer of n * record_bytes bytes.
+    preds: data predicates (offset, bytes, op, value), op 0..5 = < <= > >= == !=."""
     lib = _load()
     buf = np.ascontiguousarray(records).view(np.uint8).reshape(-1)
     n = buf.size // record_bytes
@@ -124,6 +128,12 @@ def evaluate_records(records, record_bytes, type_offset, type_bytes, key_offsets
                   (C.c_uint32 * 4)(*list(key_offsets) + [0] * (4 - nk)),
                   (C.c_uint32 * 4)(*list(key_bytes) + [0] * (4 - nk)),
                   cot.ctypes.data_as(C.POINTER(C.c_uint8)), kp.ctypes.data_as(C.POINTER(C.c_uint8)))
+    if len(preds) > 3:
+        raise ValueError("at most 3 data predicates")
+    lay.n_preds = len(preds)
+    lay.pred_shift = pred_shift
+    for q, (off, nb, op, val) in enumerate(preds):
+        lay.pred_offset[q], lay.pred_bytes[q], lay.pred_op[q], lay.pred_value[q] = off, nb, op, val
     keep = []
     arr = (_Prop * len(props))()
     for i, p in enumerate(props):

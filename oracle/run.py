@@ -44,4 +44,5 @@ def evaluate_workload(wl, specs=None, records=None):
     recs = wl.raw() if records is None else np.ascontiguousarray(records).view(np.uint8).reshape(-1)
     return cref.evaluate_records(recs, lay.record_bytes, lay.type_offset, lay.type_bytes,
                                  lay.key_offsets, lay.key_bytes, lay.class_of_type, lay.key_present,
-                                 [oracle_property(s, lay) for s in specs])
+                                 [oracle_property(s, lay) for s in specs],
+                                 preds=lay.preds, pred_shift=lay.pred_shift)

@@ -56,6 +56,9 @@ struct ClassifyArgs {
     uint32_t n_keys;
     uint32_t key_dw[kMaxLevels], key_shift[kMaxLevels], key_mask[kMaxLevels], key_bits[kMaxLevels];
     uint32_t need_mask;              // key_present bits every event must carry
+    uint32_t n_preds;                // data predicates: class += (holding predicates' bits) << pred_class_shift
+    uint32_t pred_class_shift;
+    uint32_t pred_dw[3], pred_shift[3], pred_mask[3], pred_op[3], pred_val[3];
     uint32_t check_type_range;       // the type field can exceed 255
     uint32_t cbits;
     uint32_t excl_shift;             // bit set in the word of an excluded event

@@ -170,6 +170,18 @@ __device__ __forceinline__ void load_record(const uint8_t* rec, uint32_t* dw) {
     }
 }
 
+// A data predicate: an unsigned comparison of a record field with a constant.
+__device__ __forceinline__ bool pred_holds(uint32_t op, uint32_t x, uint32_t v) {
+    switch (op) {
+        case 0: return x < v;
+        case 1: return x <= v;
+        case 2: return x > v;
+        case 3: return x >= v;
+        case 4: return x == v;
+        default: return x != v;
+    }
+}
+
 template <int RDW, bool GROUP>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_classify(ClassifyArgs a) {
     __shared__ uint8_t s_cls[256];
@@ -196,7 +208,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     // that each thread keeps U loads in flight.
     constexpr int U = RDW > 0 ? 4 : 1;
     constexpr int NDW = RDW > 0 ? RDW : 1;
-    auto process = [&](uint64_t i, uint32_t t, const uint32_t* f, uint32_t chunk) {
+    auto process = [&](uint64_t i, uint32_t t, const uint32_t* f, uint32_t pm, uint32_t chunk) {
         bool ok = !(a.check_type_range && t > 255u);
         const uint32_t t8 = t & 255u;
         ok = ok && ((s_kp[t8] & a.need_mask) == a.need_mask);
@@ -212,7 +224,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         }
         if (ok && over) err |= kErrRange;
         if constexpr (GROUP) key |= (uint64_t)s_cstream[chunk] << a.stream_shift;
-        const uint64_t word = ok ? ((key << a.cbits) | s_cls[t8]) : (1ull << a.excl_shift);
+        const uint64_t word = ok ? ((key << a.cbits) | (s_cls[t8] + (pm << a.pred_class_shift))) : (1ull << a.excl_shift);
         a.words[i] = word;
         // with n_valid set the first radix pass drops excluded events, so
         // they enter no histogram
@@ -249,20 +261,34 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         for (int u = 0; u < U; ++u) {
             const uint64_t i = i0 + u * stride;
             if (i >= a.n) continue;
-            uint32_t t, f[kMaxLevels];
+            uint32_t t, f[kMaxLevels], pm = 0;
             if constexpr (RDW > 0) {
                 t = (dw[u][a.type_dw] >> a.type_shift) & a.type_mask;
 #pragma unroll
                 for (int m = 0; m < kMaxLevels; ++m)
                     f[m] = m < (int)a.n_keys ? (dw[u][a.key_dw[m]] >> a.key_shift[m]) & a.key_mask[m] : 0u;
+                if (a.n_preds) {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q)
+                        if (q < (int)a.n_preds)
+                            pm |= (uint32_t)pred_holds(a.pred_op[q], (dw[u][a.pred_dw[q]] >> a.pred_shift[q]) & a.pred_mask[q],
+                                                       a.pred_val[q]) << q;
+                }
             } else {
                 const uint32_t* rec = reinterpret_cast<const uint32_t*>(rec_ptr[u]);
                 t = (rec[a.type_dw] >> a.type_shift) & a.type_mask;
 #pragma unroll
                 for (int m = 0; m < kMaxLevels; ++m)
                     f[m] = m < (int)a.n_keys ? (rec[a.key_dw[m]] >> a.key_shift[m]) & a.key_mask[m] : 0u;
+                if (a.n_preds) {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q)
+                        if (q < (int)a.n_preds)
+                            pm |= (uint32_t)pred_holds(a.pred_op[q], (rec[a.pred_dw[q]] >> a.pred_shift[q]) & a.pred_mask[q],
+                                                       a.pred_val[q]) << q;
+                }
             }
-            process(i, t, f, chunk[u]);
+            process(i, t, f, pm, chunk[u]);
         }
     }
     if (err) atomicOr(a.err, err);

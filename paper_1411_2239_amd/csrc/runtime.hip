@@ -242,8 +242,17 @@ int32_t check_layout(const ltl4c_layout* L) {
     }
     if (L->n_classes < 1 || L->n_classes > LTL4C_MAX_CLASSES)
         return fail(LTL4C_EUNSUPPORTED, "n_classes must be 1..16");
+    if (L->n_preds > 3) return fail(LTL4C_EUNSUPPORTED, "n_preds must be 0..3");
+    for (uint32_t i = 0; i < L->n_preds; ++i) {
+        if (!field_ok(L->pred[i].offset, L->pred[i].bytes)) return fail(LTL4C_EINVAL, "bad predicate field");
+        if (L->pred[i].op > LTL4C_CMP_NE) return fail(LTL4C_EINVAL, "unknown predicate comparison");
+    }
+    if (L->n_preds > 0 && L->pred_shift > 3) return fail(LTL4C_EINVAL, "pred_shift must be 0..3");
+    // the largest class any event can take: type class plus every predicate bit
+    const uint32_t pred_top = L->n_preds ? ((1u << L->n_preds) - 1u) << L->pred_shift : 0u;
     for (int t = 0; t < 256; ++t)
-        if (L->class_of_type[t] >= L->n_classes) return fail(LTL4C_EINVAL, "class_of_type entry >= n_classes");
+        if ((uint32_t)L->class_of_type[t] + pred_top >= L->n_classes)
+            return fail(LTL4C_EINVAL, "class_of_type entry (plus predicate bits) >= n_classes");
     Geometry g = geometry(*L);
     if (g.cbits + g.key_bits_total + (g.excl ? 1 : 0) > 63)
         return fail(LTL4C_EUNSUPPORTED, "packed binding key plus class bits exceed 63 bits");
@@ -403,6 +412,15 @@ int32_t enqueue_front(ltl4c_ctx* ctx, const ltl4c_layout& L, const Geometry& g, 
         ca.key_bits[m] = L.key_bits[m];
     }
     ca.need_mask = (1u << NL) - 1u;
+    ca.n_preds = L.n_preds;
+    ca.pred_class_shift = L.pred_shift;
+    for (uint32_t q = 0; q < L.n_preds && q < 3; ++q) {
+        ca.pred_dw[q] = L.pred[q].offset / 4;
+        ca.pred_shift[q] = (L.pred[q].offset % 4) * 8;
+        ca.pred_mask[q] = L.pred[q].bytes == 4 ? 0xFFFFFFFFu : ((1u << (8 * L.pred[q].bytes)) - 1u);
+        ca.pred_op[q] = L.pred[q].op;
+        ca.pred_val[q] = L.pred[q].value;
+    }
     ca.check_type_range = L.type_bytes > 1;
     ca.cbits = g.cbits;
     ca.excl_shift = g.cbits + g.key_bits_total;

@@ -38,7 +38,8 @@ class Layout(C.Structure):
     _fields_ = [("record_bytes", C.c_uint32), ("type_offset", C.c_uint32), ("type_bytes", C.c_uint32),
                 ("n_keys", C.c_uint32), ("key_offset", C.c_uint32 * 4), ("key_bytes", C.c_uint32 * 4),
                 ("key_bits", C.c_uint32 * 4), ("n_classes", C.c_uint32),
-                ("class_of_type", C.c_uint8 * 256), ("key_present", C.c_uint8 * 256)]
+                ("class_of_type", C.c_uint8 * 256), ("key_present", C.c_uint8 * 256),
+                ("n_preds", C.c_uint32), ("pred_shift", C.c_uint32), ("pred", C.c_uint32 * 12)]
 
 
 class MonitorDesc(C.Structure):
@@ -155,6 +156,11 @@ def layout_desc(layout):
     d.n_classes = layout.n_classes
     C.memmove(d.class_of_type, np.ascontiguousarray(layout.class_of_type, dtype=np.uint8).ctypes.data, 256)
     C.memmove(d.key_present, np.ascontiguousarray(layout.key_present, dtype=np.uint8).ctypes.data, 256)
+    preds = getattr(layout, "preds", [])
+    d.n_preds = len(preds)
+    d.pred_shift = getattr(layout, "pred_shift", 0)
+    for q, (off, nb, op, val) in enumerate(preds[:3]):
+        d.pred[4 * q:4 * q + 4] = [off, nb, op, val]
     return d
 
 

@@ -33,6 +33,10 @@ class Layout:
     key_present: np.ndarray         # [256] uint8, bit m = the type carries key m
     class_props: list               # class -> set of propositions that hold
     type_names: dict = field(default_factory=dict)
+    # data predicates (offset, bytes, op, value), op 0..5 = < <= > >= == !=;
+    # an event's class is class_of_type[type] + (holding predicates' bits) << pred_shift
+    preds: list = field(default_factory=list)
+    pred_shift: int = 0
 
     @property
     def n_keys(self):
@@ -174,6 +178,67 @@ def gen_user_requests(n_events=10_000_000, n_users=10_000, zipf_s=1.2, p_done=0.
     rec["k1"] = req_ids[ev_req[order]]
     lay = user_request_layout(max(1, int(n_users - 1).bit_length()), max(1, int(n_req - 1).bit_length()))
     return Workload("users", rec, lay, user_request_properties())
+
+
+CHUNK_MAX = 4 << 20          # largest upload chunk, bytes
+
+
+def chunk_upload_layout(n_preds=1, user_bits=14):
+    """Records {ts, type, user, avg_chunk}: type 0 = upload, 1 = other; the
+    propositions 'small' (avg_chunk < CHUNK_MAX) and, with n_preds = 2,
+    'active' (avg_chunk != 0) are data predicates on the record, class bits
+    1 and 2 above the type's letter."""
+    cot = np.zeros(256, dtype=np.uint8)
+    cot[1] = 1
+    kp = np.zeros(256, dtype=np.uint8)
+    kp[0] = kp[1] = 1
+    preds = [(12, 4, 0, CHUNK_MAX)]                  # avg_chunk < CHUNK_MAX
+    names = ["small"]
+    if n_preds >= 2:
+        preds.append((12, 4, 5, 0))                  # avg_chunk != 0
+        names.append("active")
+    props = []
+    for c in range(2 << len(preds)):
+        ps = {"upload"} if (c & 1) == 0 else set()
+        ps |= {names[q] for q in range(len(preds)) if (c >> (1 + q)) & 1}
+        props.append(ps)
+    return Layout(16, 4, 4, [8], [4], [user_bits], cot, kp, props, {0: "upload", 1: "other"},
+                  preds=preds, pred_shift=1)
+
+
+def chunk_upload_properties(n_preds=1):
+    out = [PropertySpec("F small", [("A", "=", 1)], "users-A=1-F-small"),
+           PropertySpec("G(upload -> F small)", [("A", ">=", "19/20")], "users-A>=0.95-G(upload->F small)")]
+    if n_preds >= 2:
+        out.append(PropertySpec("G(active -> small) | F(upload & small)", [("E", ">=", 10)], "users-E>=10-active"))
+    return out
+
+
+def gen_chunk_uploads(n_events=10_000_000, n_users=10_000, zipf_s=1.1, p_heavy=0.02, n_preds=1,
+                      seed=0x14112239 + 6):
+    """Cloud-storage fairness shape (Section 5, second case study): every
+    event carries the user's current average chunk size.  Users act with
+    Zipf(zipf_s) frequencies; a fraction p_heavy of them only ever uploads
+    maximum-size chunks (average at CHUNK_MAX), the others report averages
+    below it, sometimes exactly at it, sometimes 0 (no upload yet)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ranks = zipf_ranks(rng, n_events, n_users, zipf_s)
+    user_of_rank = rng.permutation(n_users).astype(np.uint32)
+    user = user_of_rank[ranks]
+    heavy = rng.random(n_users) < p_heavy
+    typ = (rng.random(n_events) < 0.4).astype(np.uint32)          # 0 = upload (60 %)
+    avg = rng.integers(1, CHUNK_MAX, size=n_events, dtype=np.int64)
+    u = rng.random(n_events)
+    avg[u < 0.05] = CHUNK_MAX
+    avg[(u >= 0.05) & (u < 0.08)] = 0
+    avg[heavy[user]] = CHUNK_MAX
+    rec = np.zeros(n_events, dtype=REC16)
+    rec["ts"] = np.arange(n_events, dtype=np.uint32)
+    rec["type"] = typ
+    rec["k0"] = user
+    rec["k1"] = avg.astype(np.uint32)
+    lay = chunk_upload_layout(n_preds, max(1, int(n_users - 1).bit_length()))
+    return Workload("chunks", rec, lay, chunk_upload_properties(n_preds))
 
 
 def prop_layout(n_props=3, n_levels=1, key_bits=None):

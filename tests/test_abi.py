@@ -53,9 +53,24 @@ def test_create_without_gpu_fails_cleanly():
     assert so.ltl4c_last_error()
 
 
-def test_struct_sizes_match_header_layout():
+def test_struct_sizes_match_header_layout(tmp_path):
     from paper_1411_2239_amd import lib
-    # 8 u32 + 3*4 u32 + 2*256 bytes
-    assert ctypes.sizeof(lib.Layout) == 4 * (4 + 4 * 3 + 1) + 512
+    # 8 u32 + 3*4 u32 + 2*256 bytes + 2 u32 + 3 predicates of 4 u32
+    assert ctypes.sizeof(lib.Layout) == 4 * (4 + 4 * 3 + 1) + 512 + 4 * (2 + 3 * 4)
+    # and the header as a C compiler lays it out
+    import os
+    import subprocess
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    src = tmp_path / "sizes.c"
+    src.write_text('#include "ltl4c.h"\n#include <stdio.h>\n#include <stddef.h>\n'
+                   'int main(void) { printf("%zu %zu %zu %zu", sizeof(ltl4c_layout), '
+                   'offsetof(ltl4c_layout, n_preds), sizeof(ltl4c_quant), sizeof(ltl4c_property)); return 0; }\n')
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-I", inc, str(src), "-o", str(exe)], check=True)
+    sz, off_preds, qsz, psz = map(int, subprocess.run([str(exe)], check=True, capture_output=True,
+                                                      text=True).stdout.split())
+    assert sz == ctypes.sizeof(lib.Layout)
+    assert off_preds == lib.Layout.n_preds.offset
+    assert qsz == ctypes.sizeof(lib.Quant) and psz == ctypes.sizeof(lib.PropertyDesc)
     assert ctypes.sizeof(lib.Quant) == 16
     assert ctypes.sizeof(lib.PropertyDesc) == 8 + 4 * 16
