@@ -170,8 +170,20 @@ typedef struct {
  *   node_keys[m] [capacity]                 packed prefix (keys 0..m-1) of node j
  *   node_counts[m] [n_props * capacity * 6] 6-bin counts v of node j (Def. 8)
  *   node_verdict[m] [n_props * capacity]    verdict of node j
+ *   inst_conclusive [n_props * capacity]    verdict timeline of instance i:
+ *                                           the number of its events (in
+ *                                           trace order) after which its
+ *                                           verdict is first conclusive (T or
+ *                                           F, final by Def. 5); 0 when the
+ *                                           empty prefix already is;
+ *                                           LTL4C_NEVER when no prefix is.
+ *                                           Needs inst_verdict, and monitors
+ *                                           whose T and F states only lead to
+ *                                           states of the same label
+ *                                           (LTL4C_EINVAL otherwise).
  * (node_* index m runs over 1..n_levels-1; index 0 is unused.)
  */
+#define LTL4C_NEVER 0xFFFFFFFFu
 /* (inst_keys and inst_verdict are given together or not at all; so are the
  * three node_* arrays of a level.) */
 typedef struct {
@@ -184,6 +196,7 @@ typedef struct {
     uint64_t *node_keys[4];
     uint32_t *node_counts[4];
     uint8_t  *node_verdict[4];
+    uint32_t *inst_conclusive;
 } ltl4c_result;
 
 /* ---- context ----------------------------------------------------------- */

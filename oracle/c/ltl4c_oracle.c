@@ -27,6 +27,7 @@
 #include <string.h>
 
 enum { V_BOT = 0, V_BOT_C = 1, V_BOT_P = 2, V_TOP_P = 3, V_TOP_C = 4, V_TOP = 5 };
+#define ORA_NEVER 0xFFFFFFFFu
 enum { Q_PERCENT = 0, Q_COUNT = 1 };
 enum { OP_LT = 0, OP_LE = 1, OP_GT = 2, OP_GE = 3, OP_EQ = 4 };
 
@@ -69,6 +70,8 @@ typedef struct {
     uint64_t n_inst;
     uint32_t *inst_keys;              /* [n_inst * n_levels] */
     uint8_t *inst_verdict;            /* [n_props * n_inst] */
+    uint32_t *inst_conc;              /* [n_props * n_inst]: events of the instance read when its
+                                         verdict was first T or F (0: before any), or ORA_NEVER */
     uint64_t level_nodes[4];          /* nodes at level m (prefix length m) */
     uint32_t *level_keys[4];          /* [nodes * m] */
     uint64_t *level_counts[4];        /* [n_props * nodes * 6] */
@@ -180,6 +183,7 @@ void ora_free(ora_result *r) {
     if (!r) return;
     free(r->inst_keys);
     free(r->inst_verdict);
+    free(r->inst_conc);
     for (int m = 0; m < 4; ++m) {
         free(r->level_keys[m]);
         free(r->level_counts[m]);
@@ -223,16 +227,27 @@ ora_result *ora_eval(const uint8_t *records, uint64_t n, const ora_layout *L,
     r->n_inst = ni;
     r->inst_keys = (uint32_t *)malloc(sizeof(uint32_t) * nk * (ni ? ni : 1));
     r->inst_verdict = (uint8_t *)malloc((size_t)n_props * (ni ? ni : 1));
+    r->inst_conc = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n_props * (ni ? ni : 1));
 
     /* leaves: step every property's table over each cluster (Def. 6) */
     uint32_t *state = (uint32_t *)malloc(sizeof(uint32_t) * n_props);
     uint64_t inst = 0;
     for (uint64_t i = 0; i < ne;) {
         uint64_t j = i;
-        for (int p = 0; p < n_props; ++p) state[p] = P[p].q0;
+        for (int p = 0; p < n_props; ++p) {
+            state[p] = P[p].q0;
+            /* the prefix verdict timeline: the first prefix (by its length)
+               whose verdict is T or F */
+            const uint8_t l0 = P[p].label[state[p]];
+            r->inst_conc[(uint64_t)p * ni + inst] = (l0 == V_TOP || l0 == V_BOT) ? 0u : ORA_NEVER;
+        }
         while (j < ne && same_prefix(ev[j].key, ev[i].key, nk)) {
-            for (int p = 0; p < n_props; ++p)
+            for (int p = 0; p < n_props; ++p) {
                 state[p] = P[p].delta[(uint64_t)state[p] * P[p].n_classes + ev[j].cls];
+                const uint8_t l = P[p].label[state[p]];
+                uint32_t *c = &r->inst_conc[(uint64_t)p * ni + inst];
+                if (*c == ORA_NEVER && (l == V_TOP || l == V_BOT)) *c = (uint32_t)(j - i + 1);
+            }
             ++j;
         }
         memcpy(r->inst_keys + inst * nk, ev[i].key, sizeof(uint32_t) * nk);
@@ -282,6 +297,7 @@ uint64_t ora_n_inst(const ora_result *r) { return r->n_inst; }
 uint64_t ora_level_nodes(const ora_result *r, int m) { return r->level_nodes[m]; }
 const uint32_t *ora_inst_keys(const ora_result *r) { return r->inst_keys; }
 const uint8_t *ora_inst_verdict(const ora_result *r) { return r->inst_verdict; }
+const uint32_t *ora_inst_conc(const ora_result *r) { return r->inst_conc; }
 const uint32_t *ora_level_keys(const ora_result *r, int m) { return r->level_keys[m]; }
 const uint64_t *ora_level_counts(const ora_result *r, int m) { return r->level_counts[m]; }
 const uint8_t *ora_level_verdict(const ora_result *r, int m) { return r->level_verdict[m]; }

@@ -23,6 +23,7 @@ SRC = os.path.join(HERE, "c", "ltl4c_oracle.c")
 LIB = os.path.join(HERE, "c", "libltl4c_oracle.so")
 
 KIND = {"A": 0, "E": 1}
+NEVER = 0xFFFFFFFF   # inst_conc: no prefix of the instance has a T or F verdict
 OPCODE = {"<": 0, "<=": 1, ">": 2, ">=": 3, "=": 4}
 
 
@@ -66,7 +67,7 @@ def _load():
         lib.ora_n_inst.argtypes = [C.c_void_p]
         lib.ora_level_nodes.restype = C.c_uint64
         lib.ora_level_nodes.argtypes = [C.c_void_p, C.c_int]
-        for name, ty in (("ora_inst_keys", C.c_uint32), ("ora_inst_verdict", C.c_uint8)):
+        for name, ty in (("ora_inst_keys", C.c_uint32), ("ora_inst_verdict", C.c_uint8), ("ora_inst_conc", C.c_uint32)):
             getattr(lib, name).restype = C.POINTER(ty)
             getattr(lib, name).argtypes = [C.c_void_p]
         for name, ty in (("ora_level_keys", C.c_uint32), ("ora_level_counts", C.c_uint64),
@@ -103,6 +104,7 @@ class OracleResult:
     level_keys: list             # level m: [nodes, m] uint32
     level_counts: list           # level m: [n_props, nodes, 6] uint64
     level_verdict: list          # level m: [n_props, nodes] uint8
+    inst_conc: np.ndarray = None # [n_props, n_inst] uint32: prefix length at the first T/F verdict, or NEVER
 
     @property
     def root_verdict(self):
@@ -158,6 +160,7 @@ def evaluate_records(records, record_bytes, type_offset, type_bytes, key_offsets
         P = len(props)
         ik = np.ctypeslib.as_array(lib.ora_inst_keys(res), shape=(max(ni, 1) * nk,))[:ni * nk].reshape(ni, nk).copy()
         iv = np.ctypeslib.as_array(lib.ora_inst_verdict(res), shape=(max(P * ni, 1),))[:P * ni].reshape(P, ni).copy()
+        ic = np.ctypeslib.as_array(lib.ora_inst_conc(res), shape=(max(P * ni, 1),))[:P * ni].reshape(P, ni).copy()
         lk, lc, lv = [], [], []
         for m in range(nk):
             nodes = lib.ora_level_nodes(res, m)
@@ -167,6 +170,6 @@ def evaluate_records(records, record_bytes, type_offset, type_bytes, key_offsets
             lc.append(cnt.reshape(P, nodes, 6).copy())
             ver = np.ctypeslib.as_array(lib.ora_level_verdict(res, m), shape=(P * nodes,))
             lv.append(ver.reshape(P, nodes).copy())
-        return OracleResult(ik, iv, lk, lc, lv)
+        return OracleResult(ik, iv, lk, lc, lv, ic)
     finally:
         lib.ora_free(res)

@@ -116,6 +116,8 @@ struct ScanArgs {
     uint32_t* node_counts[kMaxLevels];   // level m: [p][node_stride][6], zeroed when node j is created
     uint64_t node_stride[kMaxLevels];
     uint32_t* inst_parent;               // optional [inst_limit]: level n_levels-1 node of each instance
+    uint32_t* inst_conc;                 // optional [n_props_all][inst_stride]: first conclusive position (timeline)
+    uint32_t* inst_start;                // with inst_conc: sorted position of every instance's first word
     uint64_t* node_keys[kMaxLevels];     // optional
     uint64_t node_limit[kMaxLevels];     // nodes with an id below this are written
     uint32_t* status;                    // look-back rows [2 * kScanRows][tiles], zeroed before the launch
@@ -125,6 +127,16 @@ struct ScanArgs {
     uint64_t* sizes;                     // [1 + n_levels] written by the last tile
     uint32_t* sizes32;                   // same, 32-bit, for the counting kernels
     uint32_t* err;
+};
+
+constexpr uint32_t kNever = 0xFFFFFFFFu;     // timeline: the instance never became conclusive
+
+struct InstConclusiveArgs {
+    uint32_t* inst_conc;                 // [n_props][inst_stride], positions in, word counts out
+    const uint32_t* inst_start;          // [inst_limit]
+    const uint32_t* n_inst;              // device count of instances
+    uint64_t inst_limit, inst_stride;
+    uint32_t n_props;
 };
 
 struct FinalizeArgs {
@@ -241,6 +253,7 @@ uint32_t scan_tile(int variant);      // words per scan tile of a scan variant
 constexpr int kScanVariants = 4;
 hipError_t launch_count(const CountArgs& a, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
+hipError_t launch_inst_conclusive(const InstConclusiveArgs& a, hipStream_t s);
 hipError_t launch_group_update(const GroupUpdateArgs& a, uint64_t max_seg, hipStream_t s);
 hipError_t launch_group_level(const GroupState& g, uint32_t level, hipStream_t s);
 hipError_t launch_group_roots(const GroupState& g, bool all, hipStream_t s);

@@ -932,6 +932,45 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(4))) vo
             }
         }
     }
+    // On request, the verdict timeline of every instance: the first prefix
+    // whose verdict is conclusive (T or F).  Those verdicts are final (Def. 5),
+    // so the monitor enters a conclusive state at most once per instance: the
+    // word where it does writes its 1-based sorted position (or the head's
+    // position, when q0 itself is conclusive), the word ending an instance
+    // that never got there writes kNever.  Positions become counts of the
+    // instance's words in k_inst_conclusive.
+    if (a.inst_conc) {
+        uint32_t st[PMAX];
+#pragma unroll
+        for (int p = 0; p < PMAX; ++p)
+            st[p] = p < (int)P ? bm_at<MW>(bm_compose<MW>(excl[p], bm_load<MW>(s_tprefix[p])), 0) : 0u;
+        auto conclusive = [&](int p, uint32_t q) {
+            const uint32_t v = (s_lab[p][q >> 3] >> (4 * (q & 7u))) & 15u;
+            return v == 0u || v == 5u;
+        };
+#pragma unroll 1
+        for (int j = 0; j < kScanItems; ++j) {
+            if (!((m_valid >> j) & 1u)) break;
+            const uint32_t c = (uint32_t)(cls >> (4 * j)) & 15u;
+            const bool hd = (m_head >> j) & 1u, end = (m_end >> j) & 1u;
+            const uint64_t id = (uint64_t)id_base + cexcl[0] + __popc(m_head & ((2u << j) - 1u)) - 1u;
+            const uint32_t pos = (uint32_t)(base + (uint64_t)tid * kScanItems + j);
+            if (id >= a.inst_limit) continue;
+            if (hd && structure) a.inst_start[id] = pos;
+#pragma unroll
+            for (int p = 0; p < PMAX; ++p) {
+                if (p >= (int)P) continue;
+                const uint32_t pre = hd ? s_q0[p] : st[p];
+                const uint32_t post = bm_at<MW>(bm_load<MW>(s_cm[p][c]), pre);
+                st[p] = post;
+                uint32_t* out = a.inst_conc + a.prop_idx[p] * a.inst_stride + id;
+                const bool cpre = conclusive(p, pre), cpost = conclusive(p, post);
+                if (hd && cpre) *out = pos;
+                else if (cpost && !cpre) *out = pos + 1u;
+                if (end && !cpost) *out = kNever;
+            }
+        }
+    }
     // nodes of levels 1.. open at their first word; every such word is a
     // level-(L-1) head, and a level-m head is also a level-(m+1) head
     if (structure && L >= 2) {
@@ -992,6 +1031,22 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(4))) vo
             const uint32_t tot = s_tcnt[m] + cexcl[m] + cnt[m];
             a.sizes[m] = tot;
             a.sizes32[m] = tot;
+        }
+    }
+}
+
+// Verdict timeline, second step: a sorted position p of the first conclusive
+// word becomes p - start, the number of the instance's words consumed (0 when
+// its empty prefix is already conclusive); kNever stays.
+__global__ __launch_bounds__(256) void k_inst_conclusive(InstConclusiveArgs a) {
+    const uint64_t n = min<uint64_t>(*a.n_inst, a.inst_limit);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t start = a.inst_start[i];
+        for (uint32_t p = 0; p < a.n_props; ++p) {
+            uint32_t* o = a.inst_conc + p * a.inst_stride + i;
+            const uint32_t v = *o;
+            if (v != kNever) *o = v - start;
         }
     }
 }
@@ -1638,6 +1693,13 @@ hipError_t launch_count(const CountArgs& a, hipStream_t s) {
         hipLaunchKernelGGL(k_count_leaves, dim3(blocks), dim3(kCountThreads), 0, s, a);
     else
         hipLaunchKernelGGL(k_count<2>, dim3(blocks), dim3(kCountThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_inst_conclusive(const InstConclusiveArgs& a, hipStream_t s) {
+    const uint64_t want = (a.inst_limit + 255) / 256;
+    const uint32_t blocks = (uint32_t)(want < 2048 ? (want ? want : 1) : 2048);
+    hipLaunchKernelGGL(k_inst_conclusive, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

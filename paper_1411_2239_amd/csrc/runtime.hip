@@ -128,7 +128,7 @@ struct WsLayout {
     uint64_t zero_off, zero_words;
     uint64_t hist_off, n_valid_off, sort_ticket_off, scan_ticket_off, root_counts_off, sizes32_off, sizes64_off;
     uint64_t sort_status_off, scan_status_off;
-    uint64_t words_a_off, words_b_off, inst_verdict_off, inst_parent_off;
+    uint64_t words_a_off, words_b_off, inst_verdict_off, inst_parent_off, inst_start_off;
     uint64_t node_start_off[kMaxLevels], counts_off[kMaxLevels];
     uint64_t cap_node[kMaxLevels];
     uint32_t tiles_sort, tiles_scan;
@@ -214,6 +214,7 @@ WsLayout plan_workspace(const ltl4c_layout& L, const Geometry& g, uint64_t n, ui
         w.inst_parent_off = off;
         off = align256(off + 4 * n);
     }
+    w.inst_start_off = off; off = align256(off + 4 * n);   // verdict timeline, when asked for
     (void)L;
     for (uint32_t m = 1; m < g.n_levels; ++m) {
         uint64_t cap = n;
@@ -835,6 +836,11 @@ static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, v
         }
         uint32_t* inst_parent = NL >= 2 ? reinterpret_cast<uint32_t*>(ws + w.inst_parent_off) : nullptr;
         sa.inst_parent = inst_parent;
+        uint32_t* inst_start = reinterpret_cast<uint32_t*>(ws + w.inst_start_off);
+        if (out->inst_conclusive) {
+            sa.inst_conc = out->inst_conclusive;
+            sa.inst_start = inst_start;
+        }
         sa.sizes = sizes64;
         sa.sizes32 = sizes32;
         sa.err = ctx->err_dev;
@@ -851,6 +857,17 @@ static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, v
             if (s) return s;
         }
 
+        if (out->inst_conclusive) {
+            InstConclusiveArgs ia{};
+            ia.inst_conc = out->inst_conclusive;
+            ia.inst_start = inst_start;
+            ia.n_inst = sizes32 + 0;
+            ia.inst_limit = inst_stride;
+            ia.inst_stride = inst_stride;
+            ia.n_props = P;
+            s = launch(ctx, "timeline", [&] { return launch_inst_conclusive(ia, st); });
+            if (s) return s;
+        }
         fused_finalize = NL >= 2;                             // the node-level root count ends with Def. 7
         for (int m = (int)NL - 1; m >= 0; --m) {
             CountArgs c{};
@@ -917,6 +934,20 @@ int32_t ltl4c_eval(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int3
     if (ws_bytes < w.total) return fail(LTL4C_ENOMEM, "workspace smaller than ltl4c_workspace_bytes()");
     if ((out->inst_keys != nullptr) != (out->inst_verdict != nullptr))
         return fail(LTL4C_EINVAL, "inst_keys and inst_verdict are given together or not at all");
+    if (out->inst_conclusive) {
+        if (!out->inst_verdict) return fail(LTL4C_EINVAL, "inst_conclusive needs inst_verdict");
+        // T and F must be final: a conclusive state only leads to states of its label
+        for (int32_t i = 0; i < n_props; ++i) {
+            const MonitorHost& M = ctx->monitors[ctx->props[props[i]].monitor];
+            for (uint32_t q = 0; q < M.n_states; ++q) {
+                const uint8_t l = M.label[q];
+                if (l != LTL4C_BOT && l != LTL4C_TOP) continue;
+                for (uint32_t c = 0; c < M.n_classes; ++c)
+                    if (M.label[M.delta[q * M.n_classes + c]] != l)
+                        return fail(LTL4C_EINVAL, "inst_conclusive needs monitors whose T and F states are final");
+            }
+        }
+    }
     bool any_optional = out->inst_verdict != nullptr;
     for (uint32_t m = 1; m < L.n_keys; ++m) {
         const bool k = out->node_keys[m] != nullptr, c = out->node_counts[m] != nullptr,

@@ -24,6 +24,7 @@ BOT, BOT_C, BOT_P, TOP_P, TOP_C, TOP = range(6)
 OPT_SORT_TILE = 0
 OPT_SCAN_TILE = 1
 VERDICT_NAMES = ["F", "Fc", "Fp", "Tp", "Tc", "T"]
+NEVER = 0xFFFFFFFF   # timeline: the instance never became conclusive
 KIND = {"A": 0, "E": 1}
 OP = {"<": 0, "<=": 1, ">": 2, ">=": 3, "=": 4}
 
@@ -58,7 +59,8 @@ class PropertyDesc(C.Structure):
 class Result(C.Structure):
     _fields_ = [("root_verdict", C.c_void_p), ("root_counts", C.c_void_p), ("sizes", C.c_void_p),
                 ("capacity", C.c_uint64), ("inst_keys", C.c_void_p), ("inst_verdict", C.c_void_p),
-                ("node_keys", C.c_void_p * 4), ("node_counts", C.c_void_p * 4), ("node_verdict", C.c_void_p * 4)]
+                ("node_keys", C.c_void_p * 4), ("node_counts", C.c_void_p * 4), ("node_verdict", C.c_void_p * 4),
+                ("inst_conclusive", C.c_void_p)]
 
 
 _lib = None
@@ -175,6 +177,7 @@ class EvalResult:
     node_keys: list = None
     node_counts: list = None
     node_verdict: list = None
+    inst_conclusive: object = None   # [n_props * capacity] int32 (NEVER = -1): verdict timeline
 
 
 class Context:
@@ -253,7 +256,7 @@ class Context:
             self._workspace = ws
         return ws
 
-    def alloc_result(self, n_props, capacity=0, instances=False, nodes=False):
+    def alloc_result(self, n_props, capacity=0, instances=False, nodes=False, timeline=False):
         t, dev = self.torch, f"cuda:{self.device}"
         L = self.n_levels
         r = EvalResult(t.empty(n_props, dtype=t.uint8, device=dev),
@@ -262,6 +265,8 @@ class Context:
         if instances:
             r.inst_keys = t.empty(capacity, dtype=t.int64, device=dev)
             r.inst_verdict = t.empty(n_props * capacity, dtype=t.uint8, device=dev)
+        if timeline:
+            r.inst_conclusive = t.empty(n_props * capacity, dtype=t.int32, device=dev)
         if nodes:
             r.node_keys = [None] + [t.empty(capacity, dtype=t.int64, device=dev) for _ in range(1, L)]
             r.node_counts = [None] + [t.empty(n_props * capacity * 6, dtype=t.int32, device=dev)
@@ -282,6 +287,8 @@ class Context:
         if result.inst_verdict is not None:
             res.inst_keys = result.inst_keys.data_ptr()
             res.inst_verdict = result.inst_verdict.data_ptr()
+        if getattr(result, "inst_conclusive", None) is not None:
+            res.inst_conclusive = result.inst_conclusive.data_ptr()
         if result.node_counts is not None:
             for m in range(1, self.n_levels):
                 res.node_keys[m] = result.node_keys[m].data_ptr()
@@ -292,12 +299,12 @@ class Context:
                                    len(props), C.c_void_p(workspace.data_ptr()), workspace.numel(),
                                    C.byref(res)), "ltl4c_eval")
 
-    def eval(self, records, props, instances=False, nodes=False, capacity=None):
+    def eval(self, records, props, instances=False, nodes=False, capacity=None, timeline=False):
         """Evaluate and wait; returns an EvalResult of device tensors."""
         n = records.numel() // self.record_bytes
         if capacity is None:
             capacity = max(n, 1)
-        r = self.alloc_result(len(props), capacity, instances, nodes)
+        r = self.alloc_result(len(props), capacity, instances, nodes, timeline)
         self.eval_into(records, n, props, r, self.workspace(n, props))
         self.wait()
         return r

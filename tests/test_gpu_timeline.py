@@ -1,0 +1,52 @@
+"""Verdict timeline of every instance (the length of its first prefix with a
+T or F verdict) through the C ABI, element by element against the oracle."""
+import numpy as np
+import pytest
+
+from oracle.run import evaluate_workload
+from paper_1411_2239_amd import workloads as W
+
+from _util import compare_full, prop_workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(wl, **kw):
+    import torch
+    from paper_1411_2239_amd import lib
+    print(f"[case] timeline {wl.name} n={wl.n_events} props={len(wl.props)} levels={wl.layout.n_keys}", flush=True)
+    ctx, ids, rec = lib.open_workload(wl)
+    for k, v in kw.items():
+        ctx.set_option(getattr(lib, k), v)
+    r = ctx.eval(rec, ids, instances=True, timeline=True)
+    torch.cuda.synchronize()
+    ctx.close()
+    o = evaluate_workload(wl)
+    compare_full(r, o, len(ids), wl.layout.n_keys)
+    n_inst = int(r.sizes[0].item())
+    got = r.inst_conclusive.cpu().numpy().view(np.uint32).reshape(len(ids), -1)[:, :n_inst]
+    assert np.array_equal(got, o.inst_conc)
+    return got
+
+
+@pytest.mark.parametrize("n,levels,keys", [(200_000, 1, [300]), (200_000, 2, [40, 50]), (4097, 3, [3, 4, 5]),
+                                           (100_000, 1, [1])])
+def test_timeline_parity(n, levels, keys):
+    got = _run(prop_workload(n, levels, keys, seed=90 + levels, n_props=8))
+    assert (got != 0xFFFFFFFF).any()
+
+
+def test_timeline_many_property_groups():
+    # 16 properties: several scan launches write their own rows
+    _run(prop_workload(60_000, 1, [500], seed=93, n_props=16))
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_timeline_scan_tiles(variant):
+    _run(prop_workload(150_000, 2, [20, 30], seed=94, n_props=4), OPT_SCAN_TILE=variant)
+
+
+def test_timeline_never_conclusive():
+    # G(issue -> F done) has no conclusive finite prefix
+    got = _run(W.gen_user_requests(n_events=200_000, n_users=400, seed=95))
+    assert (got == 0xFFFFFFFF).all()
