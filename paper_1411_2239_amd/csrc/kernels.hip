@@ -182,7 +182,7 @@ __device__ __forceinline__ bool pred_holds(uint32_t op, uint32_t x, uint32_t v) 
     }
 }
 
-template <int RDW, bool GROUP>
+template <int RDW, bool GROUP, bool PRED>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_classify(ClassifyArgs a) {
     __shared__ uint8_t s_cls[256];
     __shared__ uint8_t s_kp[256];
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
 #pragma unroll
                 for (int m = 0; m < kMaxLevels; ++m)
                     f[m] = m < (int)a.n_keys ? (dw[u][a.key_dw[m]] >> a.key_shift[m]) & a.key_mask[m] : 0u;
-                if (a.n_preds) {
+                if (PRED) {
 #pragma unroll
                     for (int q = 0; q < 3; ++q)
                         if (q < (int)a.n_preds)
@@ -280,7 +280,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
 #pragma unroll
                 for (int m = 0; m < kMaxLevels; ++m)
                     f[m] = m < (int)a.n_keys ? (rec[a.key_dw[m]] >> a.key_shift[m]) & a.key_mask[m] : 0u;
-                if (a.n_preds) {
+                if (PRED) {
 #pragma unroll
                     for (int q = 0; q < 3; ++q)
                         if (q < (int)a.n_preds)
@@ -1587,19 +1587,25 @@ hipError_t launch_zero(const ZeroArgs& a, uint32_t blocks, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int RDW, bool GROUP>
+static void launch_classify_t(const ClassifyArgs& a, uint32_t blocks, hipStream_t s) {
+    if (a.n_preds > 0) hipLaunchKernelGGL((k_classify<RDW, GROUP, true>), dim3(blocks), dim3(1024), 0, s, a);
+    else hipLaunchKernelGGL((k_classify<RDW, GROUP, false>), dim3(blocks), dim3(1024), 0, s, a);
+}
+
 hipError_t launch_classify(const ClassifyArgs& a, hipStream_t s) {
     const uint64_t want = (a.n + 1023) / 1024;
     const uint32_t blocks = (uint32_t)(want < 512 ? (want ? want : 1) : 512);
     const bool group = a.chunk_off != nullptr;
     if (a.record_bytes == 16 && (reinterpret_cast<uintptr_t>(a.records) & 15) == 0 && a.vec_ok) {
-        if (group) hipLaunchKernelGGL((k_classify<4, true>), dim3(blocks), dim3(1024), 0, s, a);
-        else hipLaunchKernelGGL((k_classify<4, false>), dim3(blocks), dim3(1024), 0, s, a);
+        if (group) launch_classify_t<4, true>(a, blocks, s);
+        else launch_classify_t<4, false>(a, blocks, s);
     } else if (a.record_bytes == 12) {
-        if (group) hipLaunchKernelGGL((k_classify<3, true>), dim3(blocks), dim3(1024), 0, s, a);
-        else hipLaunchKernelGGL((k_classify<3, false>), dim3(blocks), dim3(1024), 0, s, a);
+        if (group) launch_classify_t<3, true>(a, blocks, s);
+        else launch_classify_t<3, false>(a, blocks, s);
     } else {
-        if (group) hipLaunchKernelGGL((k_classify<0, true>), dim3(blocks), dim3(1024), 0, s, a);
-        else hipLaunchKernelGGL((k_classify<0, false>), dim3(blocks), dim3(1024), 0, s, a);
+        if (group) launch_classify_t<0, true>(a, blocks, s);
+        else launch_classify_t<0, false>(a, blocks, s);
     }
     return hipGetLastError();
 }
