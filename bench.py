@@ -347,6 +347,39 @@ def predicates_bench(n_events=10_000_000, reps=10, log=print):
     return out
 
 
+def timeline_bench(n_events=10_000_000, reps=10, log=print):
+    """The verdict timeline on a one-level trace whose properties do become
+    conclusive: evaluations with and without the per-instance first
+    conclusive prefix length."""
+    import torch
+    from paper_1411_2239_amd import lib, workloads
+
+    log("[bench] timeline: generating the trace")
+    wl = workloads.gen_prop_trace(n_events, 100_000, 1.1, seed=7, props=workloads.timeline_properties())
+    ctx, ids, rec = lib.open_workload(wl)
+    ws = ctx.workspace(n_events, ids)
+    out = {"workload": f"{n_events} events, 100,000 keys Zipf(1.1), {len(ids)} properties that become conclusive"}
+    for label, timeline in (("plain", False), ("timeline", True)):
+        res = ctx.alloc_result(len(ids), n_events, instances=True, timeline=timeline)
+        ctx.eval_into(rec, n_events, ids, res, ws)
+        ctx.wait()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.eval_into(rec, n_events, ids, res, ws)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        ctx.wait()
+        out[label] = {"events_per_s": n_events / el, "ms": el * 1e3}
+        if timeline:
+            n_inst = int(res.sizes[0].item())
+            conc = res.inst_conclusive.view(len(ids), -1)[:, :n_inst]
+            out["conclusive_fraction"] = [round(float((conc[p] != -1).float().mean().item()), 4)
+                                          for p in range(len(ids))]
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -361,6 +394,7 @@ def main():
     ap.add_argument("--batch-traces", type=int, default=4096)
     ap.add_argument("--no-large", action="store_true", help="skip the 500M-event single-trace section")
     ap.add_argument("--no-predicates", action="store_true", help="skip the data-predicate section")
+    ap.add_argument("--no-timeline", action="store_true", help="skip the verdict-timeline section")
     ap.add_argument("--large-events", type=int, default=500_000_000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")
@@ -446,6 +480,9 @@ def main():
     predicates = None
     if not args.no_predicates:
         predicates = predicates_bench(log=log)
+    timeline = None
+    if not args.no_timeline:
+        timeline = timeline_bench(log=log)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -473,6 +510,7 @@ def main():
         "batching": batching,
         "large_trace": large,
         "data_predicates": predicates,
+        "verdict_timeline": timeline,
         "batched_vs_plain_speedup": batching["batched_vs_plain"] if batching else None,
         "p99_chunk_latency_ms": serving["batched"]["p99_ms"] if serving else None,
         "cpu_baseline": cpu,

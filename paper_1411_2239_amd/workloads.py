@@ -263,6 +263,14 @@ def zipf_ranks(rng, n, n_ranks, s, dtype=np.float64):
     return np.minimum(np.searchsorted(cdf.astype(dtype), rng.random(n, dtype=dtype), side="right"), n_ranks - 1)
 
 
+def timeline_properties():
+    """Properties over the propositions a, b, c of gen_prop_trace whose
+    instances do reach a conclusive verdict on finite prefixes."""
+    return [PropertySpec("F(a & X b)", [("A", ">=", "1/2")], "A>=1/2 F(a & X b)"),
+            PropertySpec("G(b | c)", [("E", ">=", 100)], "E>=100 G(b | c)"),
+            PropertySpec("!c U a", [("A", ">", "1/4")], "A>1/4 (!c U a)")]
+
+
 def gen_prop_trace(n_events, n_keys, zipf_s, p_props=(0.02, 0.9, 0.5), seed=0, key_space_bits=32,
                    props=None, name="proptrace"):
     """One long trace: proposition bits drawn independently, keys Zipf-skewed
