@@ -22,6 +22,8 @@ def _stream_traces(kind, n_streams, n_events, seed):
             out.append(W.gen_user_requests(n_events=n_events, n_users=40, seed=seed + s))
         elif kind == "sockets":
             out.append(W.gen_sockets(n_events=n_events, n_sockets=30, seed=seed + s))
+        elif kind == "chunks":
+            out.append(W.gen_chunk_uploads(n_events, 50, n_preds=2, seed=seed + s))
         else:
             out.append(prop_workload(n_events, 3, [3, 4, 5], seed=seed + s, n_props=2,
                                      formulas=["G(a -> F b)", "a U (b U c)"],
@@ -80,6 +82,11 @@ def test_serving_users_two_levels():
 
 def test_serving_sockets_one_level():
     _check_group("sockets", n_streams=4, n_events=4000)
+
+
+def test_serving_data_predicates():
+    # letters that depend on record data (two predicates) in the online mode
+    _check_group("chunks", n_streams=4, n_events=3000)
 
 
 def test_serving_three_levels_two_properties():
