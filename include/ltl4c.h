@@ -181,9 +181,20 @@ typedef struct {
  *                                           whose T and F states only lead to
  *                                           states of the same label
  *                                           (LTL4C_EINVAL otherwise).
+ *   event_verdict [n_props * n_events]     per event, in trace order: the
+ *                                           verdict of the event's instance
+ *                                           on its prefix up to and with the
+ *                                           event; LTL4C_NO_INSTANCE for an
+ *                                           event that joins no cluster.
+ *                                           Needs the trace index beside the
+ *                                           key in the sort word: binding key
+ *                                           + class bits + ceil(log2 n_events)
+ *                                           must fit 63 bits (else
+ *                                           LTL4C_EUNSUPPORTED).
  * (node_* index m runs over 1..n_levels-1; index 0 is unused.)
  */
 #define LTL4C_NEVER 0xFFFFFFFFu
+#define LTL4C_NO_INSTANCE 0xFFu
 /* (inst_keys and inst_verdict are given together or not at all; so are the
  * three node_* arrays of a level.) */
 typedef struct {
@@ -197,6 +208,7 @@ typedef struct {
     uint32_t *node_counts[4];
     uint8_t  *node_verdict[4];
     uint32_t *inst_conclusive;
+    uint8_t  *event_verdict;
 } ltl4c_result;
 
 /* ---- context ----------------------------------------------------------- */

@@ -72,6 +72,10 @@ typedef struct {
     uint8_t *inst_verdict;            /* [n_props * n_inst] */
     uint32_t *inst_conc;              /* [n_props * n_inst]: events of the instance read when its
                                          verdict was first T or F (0: before any), or ORA_NEVER */
+    uint64_t n_events;
+    uint8_t *event_verdict;           /* [n_props * n_events], trace order: the verdict of the
+                                         event's instance on its prefix ending at the event;
+                                         0xFF for an event of no cluster */
     uint64_t level_nodes[4];          /* nodes at level m (prefix length m) */
     uint32_t *level_keys[4];          /* [nodes * m] */
     uint64_t *level_counts[4];        /* [n_props * nodes * 6] */
@@ -184,6 +188,7 @@ void ora_free(ora_result *r) {
     free(r->inst_keys);
     free(r->inst_verdict);
     free(r->inst_conc);
+    free(r->event_verdict);
     for (int m = 0; m < 4; ++m) {
         free(r->level_keys[m]);
         free(r->level_counts[m]);
@@ -228,6 +233,9 @@ ora_result *ora_eval(const uint8_t *records, uint64_t n, const ora_layout *L,
     r->inst_keys = (uint32_t *)malloc(sizeof(uint32_t) * nk * (ni ? ni : 1));
     r->inst_verdict = (uint8_t *)malloc((size_t)n_props * (ni ? ni : 1));
     r->inst_conc = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n_props * (ni ? ni : 1));
+    r->n_events = n;
+    r->event_verdict = (uint8_t *)malloc((size_t)n_props * (n ? n : 1));
+    memset(r->event_verdict, 0xFF, (size_t)n_props * (n ? n : 1));
 
     /* leaves: step every property's table over each cluster (Def. 6) */
     uint32_t *state = (uint32_t *)malloc(sizeof(uint32_t) * n_props);
@@ -245,6 +253,7 @@ ora_result *ora_eval(const uint8_t *records, uint64_t n, const ora_layout *L,
             for (int p = 0; p < n_props; ++p) {
                 state[p] = P[p].delta[(uint64_t)state[p] * P[p].n_classes + ev[j].cls];
                 const uint8_t l = P[p].label[state[p]];
+                r->event_verdict[(uint64_t)p * n + ev[j].pos] = l;
                 uint32_t *c = &r->inst_conc[(uint64_t)p * ni + inst];
                 if (*c == ORA_NEVER && (l == V_TOP || l == V_BOT)) *c = (uint32_t)(j - i + 1);
             }
@@ -298,6 +307,7 @@ uint64_t ora_level_nodes(const ora_result *r, int m) { return r->level_nodes[m];
 const uint32_t *ora_inst_keys(const ora_result *r) { return r->inst_keys; }
 const uint8_t *ora_inst_verdict(const ora_result *r) { return r->inst_verdict; }
 const uint32_t *ora_inst_conc(const ora_result *r) { return r->inst_conc; }
+const uint8_t *ora_event_verdict(const ora_result *r) { return r->event_verdict; }
 const uint32_t *ora_level_keys(const ora_result *r, int m) { return r->level_keys[m]; }
 const uint64_t *ora_level_counts(const ora_result *r, int m) { return r->level_counts[m]; }
 const uint8_t *ora_level_verdict(const ora_result *r, int m) { return r->level_verdict[m]; }

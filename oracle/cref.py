@@ -67,7 +67,8 @@ def _load():
         lib.ora_n_inst.argtypes = [C.c_void_p]
         lib.ora_level_nodes.restype = C.c_uint64
         lib.ora_level_nodes.argtypes = [C.c_void_p, C.c_int]
-        for name, ty in (("ora_inst_keys", C.c_uint32), ("ora_inst_verdict", C.c_uint8), ("ora_inst_conc", C.c_uint32)):
+        for name, ty in (("ora_inst_keys", C.c_uint32), ("ora_inst_verdict", C.c_uint8), ("ora_inst_conc", C.c_uint32),
+                         ("ora_event_verdict", C.c_uint8)):
             getattr(lib, name).restype = C.POINTER(ty)
             getattr(lib, name).argtypes = [C.c_void_p]
         for name, ty in (("ora_level_keys", C.c_uint32), ("ora_level_counts", C.c_uint64),
@@ -105,6 +106,7 @@ class OracleResult:
     level_counts: list           # level m: [n_props, nodes, 6] uint64
     level_verdict: list          # level m: [n_props, nodes] uint8
     inst_conc: np.ndarray = None # [n_props, n_inst] uint32: prefix length at the first T/F verdict, or NEVER
+    event_verdict: np.ndarray = None  # [n_props, n_events] uint8, trace order; 0xFF: the event joins no cluster
 
     @property
     def root_verdict(self):
@@ -161,6 +163,7 @@ def evaluate_records(records, record_bytes, type_offset, type_bytes, key_offsets
         ik = np.ctypeslib.as_array(lib.ora_inst_keys(res), shape=(max(ni, 1) * nk,))[:ni * nk].reshape(ni, nk).copy()
         iv = np.ctypeslib.as_array(lib.ora_inst_verdict(res), shape=(max(P * ni, 1),))[:P * ni].reshape(P, ni).copy()
         ic = np.ctypeslib.as_array(lib.ora_inst_conc(res), shape=(max(P * ni, 1),))[:P * ni].reshape(P, ni).copy()
+        evv = np.ctypeslib.as_array(lib.ora_event_verdict(res), shape=(max(P * n, 1),))[:P * n].reshape(P, n).copy()
         lk, lc, lv = [], [], []
         for m in range(nk):
             nodes = lib.ora_level_nodes(res, m)
@@ -170,6 +173,6 @@ def evaluate_records(records, record_bytes, type_offset, type_bytes, key_offsets
             lc.append(cnt.reshape(P, nodes, 6).copy())
             ver = np.ctypeslib.as_array(lib.ora_level_verdict(res, m), shape=(P * nodes,))
             lv.append(ver.reshape(P, nodes).copy())
-        return OracleResult(ik, iv, lk, lc, lv, ic)
+        return OracleResult(ik, iv, lk, lc, lv, ic, evv)
     finally:
         lib.ora_free(res)

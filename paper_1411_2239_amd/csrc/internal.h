@@ -61,6 +61,7 @@ struct ClassifyArgs {
     uint32_t pred_dw[3], pred_shift[3], pred_mask[3], pred_op[3], pred_val[3];
     uint32_t check_type_range;       // the type field can exceed 255
     uint32_t cbits;
+    uint32_t ibits;                  // trace index bits between the class and the key (0: none)
     uint32_t excl_shift;             // bit set in the word of an excluded event
     uint32_t n_pass;                 // radix passes whose histograms are built here
     uint32_t digit_bits;             // radix digit width (8 or 9)
@@ -118,6 +119,10 @@ struct ScanArgs {
     uint32_t* inst_parent;               // optional [inst_limit]: level n_levels-1 node of each instance
     uint32_t* inst_conc;                 // optional [n_props_all][inst_stride]: first conclusive position (timeline)
     uint32_t* inst_start;                // with inst_conc: sorted position of every instance's first word
+    uint8_t* event_verdict;              // optional [n_props_all][n_events]: verdict after every event, trace order
+    uint64_t n_events;                   // row stride of event_verdict
+    uint32_t class_mask;                 // class bits of a word (below the trace index, if any)
+    uint32_t index_shift, index_mask;    // trace index of a word: (word >> index_shift) & index_mask
     uint64_t* node_keys[kMaxLevels];     // optional
     uint64_t node_limit[kMaxLevels];     // nodes with an id below this are written
     uint32_t* status;                    // look-back rows [2 * kScanRows][tiles], zeroed before the launch
@@ -254,6 +259,7 @@ constexpr int kScanVariants = 4;
 hipError_t launch_count(const CountArgs& a, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
 hipError_t launch_inst_conclusive(const InstConclusiveArgs& a, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* p, uint8_t v, uint64_t n, hipStream_t s);
 hipError_t launch_group_update(const GroupUpdateArgs& a, uint64_t max_seg, hipStream_t s);
 hipError_t launch_group_level(const GroupState& g, uint32_t level, hipStream_t s);
 hipError_t launch_group_roots(const GroupState& g, bool all, hipStream_t s);

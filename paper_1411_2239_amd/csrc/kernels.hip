@@ -224,7 +224,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         }
         if (ok && over) err |= kErrRange;
         if constexpr (GROUP) key |= (uint64_t)s_cstream[chunk] << a.stream_shift;
-        const uint64_t word = ok ? ((key << a.cbits) | (s_cls[t8] + (pm << a.pred_class_shift))) : (1ull << a.excl_shift);
+        // [key][trace index, when asked for][class]
+        const uint64_t word = ok ? ((key << (a.cbits + a.ibits)) | (a.ibits ? i << a.cbits : 0ull) |
+                                    (s_cls[t8] + (pm << a.pred_class_shift)))
+                                 : (1ull << a.excl_shift);
         a.words[i] = word;
         // with n_valid set the first radix pass drops excluded events, so
         // they enter no histogram
@@ -667,7 +670,7 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(4))) vo
     const uint64_t wn = tid == THREADS - 1 ? s_next : s_w[pad_idx(tid * kScanItems + kScanItems)];
     const bool has_prev = base + (uint64_t)tid * kScanItems > 0;
     const uint32_t cb = a.cbits, vs = a.valid_shift, L = a.n_levels;
-    const uint32_t cmask = (1u << cb) - 1u;
+    const uint32_t cmask = a.class_mask;    // the class; cb is where the key starts
 
     // per-event flags as bit masks (excluded events sort last, so the valid
     // events of a thread are a prefix of its run).  Branch-free: with d the
@@ -938,16 +941,14 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(4))) vo
     // word where it does writes its 1-based sorted position (or the head's
     // position, when q0 itself is conclusive), the word ending an instance
     // that never got there writes kNever.  Positions become counts of the
-    // instance's words in k_inst_conclusive.
-    if (a.inst_conc) {
+    // instance's words in k_inst_conclusive.  Also on request, the verdict
+    // after every event, stored at the event's trace index.
+    if (a.inst_conc || a.event_verdict) {
         uint32_t st[PMAX];
 #pragma unroll
         for (int p = 0; p < PMAX; ++p)
             st[p] = p < (int)P ? bm_at<MW>(bm_compose<MW>(excl[p], bm_load<MW>(s_tprefix[p])), 0) : 0u;
-        auto conclusive = [&](int p, uint32_t q) {
-            const uint32_t v = (s_lab[p][q >> 3] >> (4 * (q & 7u))) & 15u;
-            return v == 0u || v == 5u;
-        };
+        auto label = [&](int p, uint32_t q) { return (s_lab[p][q >> 3] >> (4 * (q & 7u))) & 15u; };
 #pragma unroll 1
         for (int j = 0; j < kScanItems; ++j) {
             if (!((m_valid >> j) & 1u)) break;
@@ -955,16 +956,22 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(4))) vo
             const bool hd = (m_head >> j) & 1u, end = (m_end >> j) & 1u;
             const uint64_t id = (uint64_t)id_base + cexcl[0] + __popc(m_head & ((2u << j) - 1u)) - 1u;
             const uint32_t pos = (uint32_t)(base + (uint64_t)tid * kScanItems + j);
-            if (id >= a.inst_limit) continue;
-            if (hd && structure) a.inst_start[id] = pos;
+            const bool conc_out = a.inst_conc && id < a.inst_limit;
+            if (conc_out && hd && structure) a.inst_start[id] = pos;
+            // the event's trace index rides in the word between class and key
+            const uint64_t ev = a.event_verdict ? (a.words[pos] >> a.index_shift) & a.index_mask : 0ull;
 #pragma unroll
             for (int p = 0; p < PMAX; ++p) {
                 if (p >= (int)P) continue;
                 const uint32_t pre = hd ? s_q0[p] : st[p];
                 const uint32_t post = bm_at<MW>(bm_load<MW>(s_cm[p][c]), pre);
                 st[p] = post;
+                const uint32_t lpost = label(p, post);
+                if (a.event_verdict) a.event_verdict[a.prop_idx[p] * a.n_events + ev] = (uint8_t)lpost;
+                if (!conc_out) continue;
                 uint32_t* out = a.inst_conc + a.prop_idx[p] * a.inst_stride + id;
-                const bool cpre = conclusive(p, pre), cpost = conclusive(p, post);
+                const uint32_t lpre = label(p, pre);
+                const bool cpre = lpre == 0u || lpre == 5u, cpost = lpost == 0u || lpost == 5u;
                 if (hd && cpre) *out = pos;
                 else if (cpost && !cpre) *out = pos + 1u;
                 if (end && !cpost) *out = kNever;
@@ -1033,6 +1040,18 @@ __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(4))) vo
             a.sizes32[m] = tot;
         }
     }
+}
+
+// Byte fill: the per-event verdicts start as "no instance" (events that join
+// no cluster are never visited by the scan).
+__global__ __launch_bounds__(256) void k_fill_u8(uint8_t* p, uint8_t v, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t n16 = (reinterpret_cast<uintptr_t>(p) & 15) == 0 ? n / 16 : 0;
+    const uint32_t v4 = 0x01010101u * v;
+    uint4* p16 = reinterpret_cast<uint4*>(p);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+        p16[i] = make_uint4(v4, v4, v4, v4);
+    for (uint64_t i = n16 * 16 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
 // Verdict timeline, second step: a sorted position p of the first conclusive
@@ -1699,6 +1718,13 @@ hipError_t launch_count(const CountArgs& a, hipStream_t s) {
         hipLaunchKernelGGL(k_count_leaves, dim3(blocks), dim3(kCountThreads), 0, s, a);
     else
         hipLaunchKernelGGL(k_count<2>, dim3(blocks), dim3(kCountThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t* p, uint8_t v, uint64_t n, hipStream_t s) {
+    const uint64_t want = (n / 16 + 255) / 256;
+    const uint32_t blocks = (uint32_t)(want < 2048 ? (want ? want : 1) : 2048);
+    hipLaunchKernelGGL(k_fill_u8, dim3(blocks), dim3(256), 0, s, p, v, n);
     return hipGetLastError();
 }
 

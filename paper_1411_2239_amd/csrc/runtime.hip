@@ -82,6 +82,7 @@ namespace {
 // Derived quantities of a layout shared by the workspace query and eval.
 struct Geometry {
     uint32_t cbits, key_bits_total, sort_bits, n_pass;
+    uint32_t ibits;                         // trace index bits between class and key (per-event verdicts)
     uint32_t digit_bits;                    // radix digit width: 8, or 9 when that saves a pass
     bool compact;                           // the first radix pass drops excluded events
     uint32_t stream_bits;                   // stream / trace id above the keys
@@ -424,11 +425,12 @@ int32_t enqueue_front(ltl4c_ctx* ctx, const ltl4c_layout& L, const Geometry& g, 
     }
     ca.check_type_range = L.type_bytes > 1;
     ca.cbits = g.cbits;
-    ca.excl_shift = g.cbits + g.key_bits_total;
+    ca.ibits = g.ibits;
+    ca.excl_shift = g.cbits + g.ibits + g.key_bits_total;
     ca.n_pass = g.n_pass;
     ca.digit_bits = g.digit_bits;
     ca.n_valid = g.compact ? z + w.n_valid_off : nullptr;
-    ca.sort_shift = g.cbits;
+    ca.sort_shift = g.cbits + g.ibits;
     ca.plan = plan;
     ca.words = words_a;
     ca.hist = hist;
@@ -448,7 +450,7 @@ int32_t enqueue_front(ltl4c_ctx* ctx, const ltl4c_layout& L, const Geometry& g, 
         sa.in = in;
         sa.out = outw;
         sa.n = (uint32_t)n;
-        sa.shift = g.cbits + g.digit_bits * p;
+        sa.shift = g.cbits + g.ibits + g.digit_bits * p;
         sa.nbits = std::min<uint32_t>(g.digit_bits, g.sort_bits - g.digit_bits * p);
         sa.hist = hist + ((uint64_t)p << g.digit_bits);
         sa.status = sort_status + (((uint64_t)p * w.tiles_sort) << g.digit_bits);
@@ -817,10 +819,13 @@ static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, v
         sa.words = sorted;
         sa.n = (uint32_t)n;
         sa.n_dev = g.compact ? z + w.n_valid_off : nullptr;   // the first radix pass dropped excluded events
-        sa.cbits = g.cbits;
+        sa.cbits = g.cbits + g.ibits;                        // where the key starts
+        sa.class_mask = (1u << g.cbits) - 1u;
+        sa.index_shift = g.cbits;
+        sa.index_mask = g.ibits ? (uint32_t)((1ull << g.ibits) - 1u) : 0u;
         sa.n_levels = NL;
-        for (uint32_t m = 1; m < NL; ++m) sa.prefix_shift[m] = g.cbits + (g.key_bits_total - g.prefix_bits[m]);
-        sa.valid_shift = g.cbits + g.key_bits_total;
+        for (uint32_t m = 1; m < NL; ++m) sa.prefix_shift[m] = sa.cbits + (g.key_bits_total - g.prefix_bits[m]);
+        sa.valid_shift = sa.cbits + g.key_bits_total;
         sa.n_props_all = P;
         sa.plan = plan;
         sa.inst_verdict = inst_verdict;
@@ -840,6 +845,13 @@ static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, v
         if (out->inst_conclusive) {
             sa.inst_conc = out->inst_conclusive;
             sa.inst_start = inst_start;
+        }
+        if (out->event_verdict) {
+            // events that join no cluster keep "no instance"
+            s = launch(ctx, "fill", [&] { return launch_fill_u8(out->event_verdict, LTL4C_NO_INSTANCE, (uint64_t)P * n, st); });
+            if (s) return s;
+            sa.event_verdict = out->event_verdict;
+            sa.n_events = n;
         }
         sa.sizes = sizes64;
         sa.sizes32 = sizes32;
@@ -934,6 +946,12 @@ int32_t ltl4c_eval(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int3
     if (ws_bytes < w.total) return fail(LTL4C_ENOMEM, "workspace smaller than ltl4c_workspace_bytes()");
     if ((out->inst_keys != nullptr) != (out->inst_verdict != nullptr))
         return fail(LTL4C_EINVAL, "inst_keys and inst_verdict are given together or not at all");
+    if (out->event_verdict) {
+        // the trace index rides in the sort word between the class and the key
+        g.ibits = std::max<uint32_t>(1, bits_for((uint32_t)std::max<uint64_t>(n, 1)));
+        if (g.cbits + g.ibits + g.key_bits_total + (g.excl ? 1 : 0) > 63)
+            return fail(LTL4C_EUNSUPPORTED, "event_verdict: binding key, class and trace index exceed 63 bits");
+    }
     if (out->inst_conclusive) {
         if (!out->inst_verdict) return fail(LTL4C_EINVAL, "inst_conclusive needs inst_verdict");
         // T and F must be final: a conclusive state only leads to states of its label
@@ -1287,6 +1305,7 @@ static int32_t group_push_impl(ltl4c_ctx* ctx, int32_t group, const void* d_reco
         sa.words = sorted;
         sa.n = (uint32_t)n;
         sa.cbits = G->g.cbits;
+        sa.class_mask = (1u << G->g.cbits) - 1u;
         sa.n_levels = 1;
         sa.valid_shift = G->g.cbits + G->g.key_bits_total;
         sa.n_props_all = G->V;

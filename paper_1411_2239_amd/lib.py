@@ -25,6 +25,7 @@ OPT_SORT_TILE = 0
 OPT_SCAN_TILE = 1
 VERDICT_NAMES = ["F", "Fc", "Fp", "Tp", "Tc", "T"]
 NEVER = 0xFFFFFFFF   # timeline: the instance never became conclusive
+NO_INSTANCE = 0xFF   # event verdicts: the event joins no cluster
 KIND = {"A": 0, "E": 1}
 OP = {"<": 0, "<=": 1, ">": 2, ">=": 3, "=": 4}
 
@@ -60,7 +61,7 @@ class Result(C.Structure):
     _fields_ = [("root_verdict", C.c_void_p), ("root_counts", C.c_void_p), ("sizes", C.c_void_p),
                 ("capacity", C.c_uint64), ("inst_keys", C.c_void_p), ("inst_verdict", C.c_void_p),
                 ("node_keys", C.c_void_p * 4), ("node_counts", C.c_void_p * 4), ("node_verdict", C.c_void_p * 4),
-                ("inst_conclusive", C.c_void_p)]
+                ("inst_conclusive", C.c_void_p), ("event_verdict", C.c_void_p)]
 
 
 _lib = None
@@ -178,6 +179,7 @@ class EvalResult:
     node_counts: list = None
     node_verdict: list = None
     inst_conclusive: object = None   # [n_props * capacity] int32 (NEVER = -1): verdict timeline
+    event_verdict: object = None     # [n_props * n_events] uint8, trace order (NO_INSTANCE = 255)
 
 
 class Context:
@@ -256,7 +258,9 @@ class Context:
             self._workspace = ws
         return ws
 
-    def alloc_result(self, n_props, capacity=0, instances=False, nodes=False, timeline=False):
+    def alloc_result(self, n_props, capacity=0, instances=False, nodes=False, timeline=False, n_events=0):
+        """timeline: per-instance first conclusive prefix; n_events > 0: the
+        verdict after every event (in trace order) for that many events."""
         t, dev = self.torch, f"cuda:{self.device}"
         L = self.n_levels
         r = EvalResult(t.empty(n_props, dtype=t.uint8, device=dev),
@@ -267,6 +271,8 @@ class Context:
             r.inst_verdict = t.empty(n_props * capacity, dtype=t.uint8, device=dev)
         if timeline:
             r.inst_conclusive = t.empty(n_props * capacity, dtype=t.int32, device=dev)
+        if n_events:
+            r.event_verdict = t.empty(n_props * n_events, dtype=t.uint8, device=dev)
         if nodes:
             r.node_keys = [None] + [t.empty(capacity, dtype=t.int64, device=dev) for _ in range(1, L)]
             r.node_counts = [None] + [t.empty(n_props * capacity * 6, dtype=t.int32, device=dev)
@@ -289,6 +295,8 @@ class Context:
             res.inst_verdict = result.inst_verdict.data_ptr()
         if getattr(result, "inst_conclusive", None) is not None:
             res.inst_conclusive = result.inst_conclusive.data_ptr()
+        if getattr(result, "event_verdict", None) is not None:
+            res.event_verdict = result.event_verdict.data_ptr()
         if result.node_counts is not None:
             for m in range(1, self.n_levels):
                 res.node_keys[m] = result.node_keys[m].data_ptr()
@@ -299,12 +307,12 @@ class Context:
                                    len(props), C.c_void_p(workspace.data_ptr()), workspace.numel(),
                                    C.byref(res)), "ltl4c_eval")
 
-    def eval(self, records, props, instances=False, nodes=False, capacity=None, timeline=False):
+    def eval(self, records, props, instances=False, nodes=False, capacity=None, timeline=False, events=False):
         """Evaluate and wait; returns an EvalResult of device tensors."""
         n = records.numel() // self.record_bytes
         if capacity is None:
             capacity = max(n, 1)
-        r = self.alloc_result(len(props), capacity, instances, nodes, timeline)
+        r = self.alloc_result(len(props), capacity, instances, nodes, timeline, n if events else 0)
         self.eval_into(records, n, props, r, self.workspace(n, props))
         self.wait()
         return r

@@ -54,3 +54,41 @@ def test_timeline_agrees_with_final_verdicts():
         assert np.array_equal(conclusive_end, o.inst_conc[p] != NEVER)
         fin = o.inst_conc[p][o.inst_conc[p] != NEVER]
         assert (fin <= lengths[o.inst_conc[p] != NEVER]).all()
+
+
+@pytest.mark.parametrize("formula,want", [
+    ("F a", lambda a_so_far, not_a_so_far: np.where(a_so_far, 5, 2)),
+    ("G a", lambda a_so_far, not_a_so_far: np.where(not_a_so_far, 0, 3)),
+])
+def test_event_verdicts_closed_forms(formula, want):
+    # after each event: F a is T once an a was seen in the instance, else Fp;
+    # G a is F once an event without a was seen, else Tp
+    wl = prop_workload(3_000, 1, [40], seed=17, n_props=1, formulas=[formula], quants=[[("E", ">=", 1)]])
+    o = evaluate_workload(wl)
+    has_a = (wl.records["type"] & 1).astype(bool)
+    exp = np.zeros(wl.n_events, dtype=np.uint8)
+    for c in _clusters(wl):
+        exp[c] = want(np.cumsum(has_a[c]) > 0, np.cumsum(~has_a[c]) > 0)
+    assert np.array_equal(o.event_verdict[0], exp)
+
+
+def test_event_verdicts_mark_excluded_events_and_end_in_the_instance_verdict():
+    wl = prop_workload(5_000, 2, [10, 20], seed=18, n_props=3)
+    rng = np.random.default_rng(18)
+    t = wl.records["type"].copy()
+    out = rng.random(wl.n_events) < 0.2
+    t[out] = 300
+    wl.records["type"] = t
+    wl.layout.type_bytes = 2
+    o = evaluate_workload(wl)
+    assert (o.event_verdict[:, out] == 0xFF).all() and (o.event_verdict[:, ~out] <= 5).all()
+    # the last event of every instance carries the instance's verdict
+    keys = np.stack([wl.records["k0"], wl.records["k1"]], axis=1).astype(np.int64)
+    keys[out] = -1
+    inst = {tuple(k): i for i, k in enumerate(o.inst_keys.astype(np.int64))}
+    last = {}
+    for pos in range(wl.n_events):
+        if not out[pos]:
+            last[tuple(keys[pos])] = pos
+    for k, pos in last.items():
+        assert np.array_equal(o.event_verdict[:, pos], o.inst_verdict[:, inst[k]])
