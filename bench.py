@@ -349,8 +349,9 @@ def predicates_bench(n_events=10_000_000, reps=10, log=print):
 
 def timeline_bench(n_events=10_000_000, reps=10, log=print):
     """The verdict timeline on a one-level trace whose properties do become
-    conclusive: evaluations with and without the per-instance first
-    conclusive prefix length."""
+    conclusive: evaluations without it, with the per-instance first
+    conclusive prefix length, and with that plus the verdict after every
+    event in trace order."""
     import torch
     from paper_1411_2239_amd import lib, workloads
 
@@ -359,8 +360,10 @@ def timeline_bench(n_events=10_000_000, reps=10, log=print):
     ctx, ids, rec = lib.open_workload(wl)
     ws = ctx.workspace(n_events, ids)
     out = {"workload": f"{n_events} events, 100,000 keys Zipf(1.1), {len(ids)} properties that become conclusive"}
-    for label, timeline in (("plain", False), ("timeline", True)):
-        res = ctx.alloc_result(len(ids), n_events, instances=True, timeline=timeline)
+    for label, timeline, events in (("plain", False, False), ("timeline", True, False),
+                                    ("timeline_and_event_verdicts", True, True)):
+        res = ctx.alloc_result(len(ids), n_events, instances=True, timeline=timeline,
+                               n_events=n_events if events else 0)
         ctx.eval_into(rec, n_events, ids, res, ws)
         ctx.wait()
         torch.cuda.synchronize()
@@ -371,7 +374,7 @@ def timeline_bench(n_events=10_000_000, reps=10, log=print):
         el = (time.perf_counter() - t0) / reps
         ctx.wait()
         out[label] = {"events_per_s": n_events / el, "ms": el * 1e3}
-        if timeline:
+        if timeline and not events:
             n_inst = int(res.sizes[0].item())
             conc = res.inst_conclusive.view(len(ids), -1)[:, :n_inst]
             out["conclusive_fraction"] = [round(float((conc[p] != -1).float().mean().item()), 4)
