@@ -8,7 +8,7 @@ namespace ltl4c {
 
 constexpr int kMaxProps = 16;
 constexpr int kMaxLevels = 4;
-constexpr int kStates = 16;          // nibble-packed maps always carry 16 lanes
+constexpr int kStates = 16;          // monitor states, at most (a map holds one byte per state)
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
 constexpr int kRadixBitsWide = 9;        // digit of the passes of 512-thread tiles, when it saves a pass
