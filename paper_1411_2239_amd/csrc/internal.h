@@ -10,7 +10,6 @@ constexpr int kMaxProps = 16;
 constexpr int kMaxLevels = 4;
 constexpr int kStates = 16;          // monitor states, at most (a map holds one byte per state)
 constexpr int kRadixBits = 8;
-constexpr int kRadix = 1 << kRadixBits;
 constexpr int kRadixBitsWide = 9;        // digit of the passes of 512-thread tiles, when it saves a pass
 constexpr int kHistWords = 4096;         // classify's histograms: n_pass << digit bits, at most
 constexpr int kSortThreads = 256;

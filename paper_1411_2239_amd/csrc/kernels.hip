@@ -314,7 +314,6 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
 constexpr uint32_t kFlagAgg = 1u << 30, kFlagInc = 2u << 30, kValMask = (1u << 30) - 1;
 constexpr int kSortLookWindow = 4;
 constexpr bool kSortSpinSleep = true;    // back off while a predecessor has not published
-constexpr int kScanLookWindow = 4;
 
 // 16-item tiles are held to 128 VGPRs (two 512-thread blocks per CU), 8-item
 // tiles to 80 (three).  Tiles above 8192 words are written out in PHASES
@@ -612,8 +611,9 @@ __device__ __forceinline__ BMap<MW> bm_load(const uint32_t* p) {
 // carries its own validity bit 31 (counts stay below 2^30 and map bytes below
 // 16): readers need no fence.
 //
-// Every instance is held to 128 VGPRs so that two 512-thread blocks share a
-// CU; the 4 x 16-state instance spills a few words, and still runs faster so.
+// Every instance is held to 128 VGPRs so that 16 waves share a CU (two
+// 512-thread blocks, or one 1024-thread block); the 4 x 16-state instance
+// spills a few words, and still runs faster so.
 template <int PMAX, int MW, int THREADS>
 __global__ __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_scan(ScanArgs a) {
     static_assert(PMAX * MW <= 16 && 4 + PMAX * MW <= kScanRows, "look-back record of at most 20 words");
