@@ -7,11 +7,16 @@
  *
  * What it computes (paper sections in brackets):
  *   1. the value vector of every event from its key fields (Eq. 5,
- *      Section 4.1); an event that lacks a key joins no cluster;
+ *      Section 4.1); an event that lacks a key joins no cluster; its letter
+ *      from its type and, when declared, from comparisons of record fields
+ *      with constants (the data predicates of Section 5's cloud-storage
+ *      case study);
  *   2. the clusters u^D: events grouped by vector, trace order kept inside a
  *      group (Section 2.4.3) -- a plain qsort on (vector, position);
  *   3. the leaf verdict lambda(delta(q0, u^D)) of every instance (Def. 6),
- *      stepping the monitor table one event at a time;
+ *      stepping the monitor table one event at a time; on the way, the
+ *      verdict after every event (stored at the event's trace position) and
+ *      the length of each instance's first prefix with a T or F verdict;
  *   4. for every quantifier level from the innermost out, the 6-bin count of
  *      child verdicts of each node (Def. 8) and its verdict by Def. 7 with the
  *      numerical constraint of Eq. 6 and the permanence rules (Table 1 and
