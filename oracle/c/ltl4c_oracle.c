@@ -172,7 +172,9 @@ typedef struct {
     uint8_t cls;
 } ev_t;
 
-static int g_nk;
+/* key count for the comparator; one per thread, so that evaluations of
+   disjoint partitions may run concurrently */
+static _Thread_local int g_nk;
 
 static int ev_cmp(const void *a, const void *b) {
     const ev_t *x = (const ev_t *)a, *y = (const ev_t *)b;

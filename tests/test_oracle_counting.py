@@ -11,7 +11,7 @@ import pytest
 
 from oracle import cref
 from oracle.counting import evaluate, perm_sat, perm_viol, valuate, constraint
-from oracle.ltl import BOT, BOT_C, BOT_P, TOP, TOP_C, TOP_P, ltl4, parse
+from oracle.ltl import BOT, BOT_C, BOT_P, TOP, TOP_C, TOP_P, ltl4, parse, props
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 OPS = ["<", "<=", ">", ">=", "="]
@@ -207,3 +207,91 @@ def test_c_pipeline_matches_python():
                     assert tuple(res.level_keys[m][j]) == pre
                     assert list(res.level_counts[m][p, j]) == nodes[pre][0]
                     assert res.level_verdict[m][p, j] == nodes[pre][1]
+
+
+def _pred_true(op, x, v):
+    return [x < v, x <= v, x > v, x >= v, x == v, x != v][op]
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_c_pipeline_matches_python_levels_exclusions_predicates(seed):
+    """The C restatement against the Python oracle with 1-4 quantifier levels,
+    events that join no cluster (a type >= 256, or a type that lacks some
+    level's key), and 0-2 data predicates that add letter bits.  The Python
+    side takes each event's letter and key vector directly from the record
+    fields, with the exclusion rule and the comparisons written out here."""
+    from oracle.run import oracle_monitor
+    rng = np.random.default_rng(0xC0DE + seed)
+    n_levels = 1 + seed % 4
+    n = int(rng.integers(1, 90))
+    n_preds = int(rng.integers(0, 3))
+    # record: ts, type, data, k0..k{n-1}
+    rec = np.zeros((n, 3 + n_levels), dtype=np.uint32)
+    typ = rng.integers(0, 6, size=n).astype(np.uint32)
+    big = rng.random(n) < 0.1
+    typ[big] = rng.choice([256, 300, 1 << 20, 0xFFFFFFFF], size=int(big.sum()))
+    rec[:, 1] = typ
+    rec[:, 2] = rng.integers(0, 10, size=n)
+    rec[:, 3:] = rng.integers(0, 3, size=(n, n_levels))
+    # types 0..3 carry propositions a, b by their bits; types 4, 5 reuse letters
+    cot = np.zeros(256, dtype=np.uint8)
+    cot[:6] = [0, 1, 2, 3, 1, 0]
+    full = (1 << n_levels) - 1
+    kp = np.zeros(256, dtype=np.uint8)
+    kp[:6] = full
+    kp[4] = full & ~(1 << int(rng.integers(0, n_levels)))   # type 4 lacks one level's key
+    kp[5] = int(rng.integers(0, full + 1))                     # type 5: a random key set
+    pred_shift = 2
+    preds = [(8, 4, int(rng.integers(0, 6)), int(rng.integers(0, 10))) for _ in range(n_preds)]
+    names = ["a", "b", "c", "d"]
+    n_cls = 1 << (2 + n_preds)
+    class_props = [frozenset(names[i] for i in range(4) if (c >> i) & 1) for c in range(n_cls)]
+    pool = ["G(a -> F b)", "a U b", "G(a -> X b)", "F(a & X F a)", "!X a", "G a | (b U c)", "F c & G(b -> F a)",
+            "G(c -> X d)", "(a U c) | G d"]
+    allowed = set(names[:2 + n_preds])
+    pool = [f for f in pool if set(props(parse(f))) <= allowed]
+    specs = []
+    for p in range(3):
+        f = pool[int(rng.integers(0, len(pool)))]
+        q = []
+        for _ in range(n_levels):
+            kind = "A" if rng.random() < 0.5 else "E"
+            op = OPS[int(rng.integers(0, 5))]
+            const = Fraction(int(rng.integers(0, 4)), 3) if kind == "A" else int(rng.integers(0, 3))
+            q.append((kind, op, const))
+        specs.append((f, q))
+    oprops = []
+    for f, q in specs:
+        m = oracle_monitor(f)
+        oprops.append(cref.OracleProperty(np.array(m.class_table(class_props), dtype=np.uint32),
+                                          np.array(m.label, dtype=np.uint8), m.q0, q))
+    res = cref.evaluate_records(rec.view(np.uint8).reshape(-1), 4 * (3 + n_levels), 4, 4,
+                                [12 + 4 * m for m in range(n_levels)], [4] * n_levels, cot, kp, oprops,
+                                preds=preds, pred_shift=pred_shift)
+    events = []
+    for i in range(n):
+        t = int(typ[i])
+        key = None
+        if t < 256 and all((int(kp[t]) >> m) & 1 for m in range(n_levels)):
+            key = tuple(int(x) for x in rec[i, 3:])
+        cls = int(cot[t]) if t < 256 else 0
+        for qi, (_, _, op, v) in enumerate(preds):
+            if _pred_true(op, int(rec[i, 2]), v):
+                cls += 1 << (pred_shift + qi)
+        events.append((class_props[cls], key))
+    for p, (f, q) in enumerate(specs):
+        ff = parse(f)
+        root, nodes, leaves = evaluate(events, q, lambda w: ltl4(ff, w))
+        assert res.root_verdict[p] == root
+        assert list(res.root_counts[p]) == nodes[()][0]
+        assert res.inst_keys.shape[0] == len(leaves)
+        for i, d in enumerate(sorted(leaves)):
+            assert tuple(res.inst_keys[i]) == d
+            assert res.inst_verdict[p, i] == leaves[d]
+        for m in range(1, n_levels):
+            pres = sorted(k for k in nodes if len(k) == m)
+            assert res.level_keys[m].shape[0] == len(pres)
+            for j, pre in enumerate(pres):
+                assert tuple(res.level_keys[m][j]) == pre
+                assert list(res.level_counts[m][p, j]) == nodes[pre][0]
+                assert res.level_verdict[m][p, j] == nodes[pre][1]
