@@ -23,8 +23,14 @@ constexpr int kCountWindow = 64;     // nodes kept in LDS per counting tile
 constexpr uint32_t kSpinLimit = 1u << 22;   // bounded waits in decoupled look-back
 constexpr uint32_t kMaxChunks = 4096;        // chunks in one stream-group push
 
-// Error bits raised on the device and reported by ltl4c_wait().
-enum : uint32_t { kErrRange = 1u, kErrCapacity = 2u, kErrSpin = 4u };
+// Error bits raised on the device and reported by ltl4c_wait():
+//   kErrRange     an event key wider than its declared key_bits
+//   kErrCapacity  more instances, nodes or bindings than the capacity
+//   kErrSpin      a bounded look-back wait expired
+//   kErrData      an internal consistency check failed (a verdict byte
+//                 outside 0..5, a radix scatter destination past the kept
+//                 events); such values are dropped, never written
+enum : uint32_t { kErrRange = 1u, kErrCapacity = 2u, kErrSpin = 4u, kErrData = 8u };
 
 // One property as the kernels see it (lives in device memory).
 struct PropDev {

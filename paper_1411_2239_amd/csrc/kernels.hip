@@ -495,7 +495,7 @@ void k_sort_pass(SortPassArgs a) {
             const uint32_t d = (uint32_t)(k >> a.shift) & dmask;
             const uint64_t dst = (uint64_t)(uint32_t)(s_gbase[d] + i);
             if (dst < n_out) a.out[dst] = k;
-            else atomicOr(a.err, kErrSpin);
+            else atomicOr(a.err, kErrData);
         }
     }
 }
@@ -1191,7 +1191,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count(CountArgs a) {
                 const uint32_t c = c0 + k * kCountThreads + tid;
                 const bool valid = c < nch;
                 if (valid && b[k] > 5u) {
-                    atomicOr(a.err, kErrSpin);
+                    atomicOr(a.err, kErrData);
                     b[k] = 6u;
                 }
                 count_child(a, s_cnt, p, lo, nn, valid, node[k], b[k]);
@@ -1303,7 +1303,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count_leaves(CountArgs a) {
                     acc = 0;
                 }
                 const uint32_t b = (vw[k >> 2] >> (8 * (k & 3))) & 0xFFu;
-                if (b > 5u) err |= kErrSpin;
+                if (b > 5u) err |= kErrData;
                 else acc += 1u << (5 * b);
             }
             leaf_flush(a, s_cnt, p, lo, nn, cur, acc);

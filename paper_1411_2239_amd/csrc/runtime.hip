@@ -1105,6 +1105,9 @@ int32_t ltl4c_wait(ltl4c_ctx* ctx) {
     if (err) {
         HIP_TRY(hipMemset(ctx->err_dev, 0, 4));
         if (err & kErrSpin) return fail(LTL4C_EDEVICE, "a look-back wait exceeded its bound");
+        if (err & kErrData)
+            return fail(LTL4C_EDEVICE, "an internal consistency check failed on the device "
+                                       "(a verdict outside 0..5 or a sort destination past the kept events)");
         if (err & kErrRange) return fail(LTL4C_ERANGE, "an event key exceeds its declared key_bits");
         if (err & kErrCapacity) return fail(LTL4C_ECAPACITY, "more instances or nodes than the capacity");
     }

@@ -141,8 +141,16 @@ def quant_desc(kind, op, const):
         fr = Fraction(str(const))
         if not (0 <= fr <= 1):
             raise ValueError("percentage constant must be in [0, 1]")
+        if fr.denominator >= 1 << 32:
+            # the ABI holds num/den in 32-bit fields; the exact constant must fit
+            raise ValueError(f"percentage constant {const!r} needs a denominator below 2^32")
         return Quant(KIND[kind], OP[op], fr.numerator, fr.denominator)
-    return Quant(KIND[kind], OP[op], int(const), 1)
+    if kind != "E":
+        raise ValueError(f"unknown quantifier kind {kind!r}")
+    fr = Fraction(str(const))
+    if fr.denominator != 1 or not (0 <= fr < 1 << 32):
+        raise ValueError(f"instance-count constant {const!r} must be an integer in [0, 2^32)")
+    return Quant(KIND[kind], OP[op], int(fr), 1)
 
 
 def layout_desc(layout):
@@ -213,6 +221,7 @@ class Context:
 
     def set_layout(self, layout):
         self.n_levels = layout.n_keys
+        self.key_bits = list(layout.key_bits)
         self.record_bytes = layout.record_bytes
         self.n_classes = layout.n_classes
         self.class_props = layout.class_props
@@ -280,6 +289,7 @@ class Context:
             r.node_verdict = [None] + [t.empty(n_props * capacity, dtype=t.uint8, device=dev)
                                        for _ in range(1, L)]
         r.capacity = capacity
+        r.key_bits = list(self.key_bits)
         return r
 
     def eval_into(self, records, n_events, props, result, workspace):

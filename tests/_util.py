@@ -64,7 +64,7 @@ def prop_workload(n_events, n_levels, keys_per_level, seed, n_props=3, formulas=
     return W.Workload(f"props-{seed}", rec, lay, specs)
 
 
-def compare_full(r, o, n_props, n_levels, check_instances=True, check_nodes=True):
+def compare_full(r, o, n_props, n_levels, check_instances=True, check_nodes=True, key_bits=None):
     """Element-by-element equality of a GPU EvalResult and an oracle result."""
     rv = r.root_verdict.cpu().numpy()
     assert np.array_equal(rv, o.root_verdict), (rv, o.root_verdict)
@@ -75,12 +75,20 @@ def compare_full(r, o, n_props, n_levels, check_instances=True, check_nodes=True
     assert n_inst == o.inst_keys.shape[0], (n_inst, o.inst_keys.shape)
     for m in range(1, n_levels):
         assert int(sizes[m]) == o.level_keys[m].shape[0], (m, sizes, o.level_keys[m].shape)
+    if key_bits is None:
+        key_bits = getattr(r, "key_bits", None)
     if check_instances and r.inst_verdict is not None:
         iv = r.inst_verdict.cpu().numpy().reshape(n_props, -1)[:, :n_inst]
         assert np.array_equal(iv, o.inst_verdict)
+        if key_bits is not None:
+            ik = r.inst_keys.cpu().numpy().view(np.uint64)[:n_inst]
+            assert np.array_equal(ik, pack_keys(o.inst_keys, key_bits[:n_levels]))
     if check_nodes and r.node_counts is not None:
         for m in range(1, n_levels):
             nm = int(sizes[m])
+            if key_bits is not None and r.node_keys is not None and r.node_keys[m] is not None:
+                nk = r.node_keys[m].cpu().numpy().view(np.uint64)[:nm]
+                assert np.array_equal(nk, pack_keys(o.level_keys[m], key_bits[:m])), m
             nc = r.node_counts[m].cpu().numpy().reshape(n_props, -1, 6)[:, :nm]
             assert np.array_equal(nc.astype(np.int64), o.level_counts[m].astype(np.int64)), m
             nv = r.node_verdict[m].cpu().numpy().reshape(n_props, -1)[:, :nm]
