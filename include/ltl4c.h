@@ -247,6 +247,26 @@ int32_t ltl4c_eval(ltl4c_ctx *ctx, const void *d_records, uint64_t n_events,
                    void *d_workspace, uint64_t workspace_bytes,
                    const ltl4c_result *out);
 
+/* ---- evaluation without allocation ----------------------------------------
+ *
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * evaluation as ltl4c_eval (same outputs, same errors), with the workspace and
+ * the property table in a fixed scratch array that the library holds on every
+ * device it runs on, from load to process end (LTL4C_NOALLOC_SCRATCH_BYTES per
+ * device).  The call allocates nothing (no device or pinned memory, no
+ * events; the property table travels to the device inside kernel launches)
+ * and enqueues kernels only.  A trace whose ltl4c_workspace_bytes() exceeds
+ * the scratch (minus the 6 KiB property table) is refused with LTL4C_ENOMEM;
+ * one 16-byte-record trace of the two-level user/request shape fits up to
+ * about 2.8 million events.  All calls on one device share that device's
+ * scratch: calls that overlap in time on one device (two streams, two host
+ * threads) race and give wrong results; serialise them.  Profiling
+ * (ltl4c_profile_enable) does not time these calls. */
+#define LTL4C_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int32_t ltl4c_eval_noalloc(ltl4c_ctx *ctx, const void *d_records, uint64_t n_events,
+                           const int32_t *props, int32_t n_props, const ltl4c_result *out);
+
 /* ---- batches: many independent traces in one pass -------------------------
  *
  * Evaluate the properties on n_traces (1..4096) independent traces at once:
@@ -285,7 +305,8 @@ int32_t ltl4c_wait(ltl4c_ctx *ctx);
  * group's device memory itself, within the context's memory budget. */
 
 /* Cap on the device memory the context's stream groups may hold (default:
- * unlimited).  A group that would exceed it is refused with LTL4C_EADMIT. */
+ * unlimited).  A group (or its host-ingestion staging) that would exceed it
+ * is refused with LTL4C_EADMIT. */
 int32_t ltl4c_set_memory_budget(ltl4c_ctx *ctx, uint64_t bytes);
 
 /* Device bytes a group with these limits would take. */
@@ -318,9 +339,70 @@ int32_t ltl4c_group_push_chunks(ltl4c_ctx *ctx, int32_t group, const void *const
 int32_t ltl4c_group_read(ltl4c_ctx *ctx, int32_t group, uint8_t *d_root_verdict, uint64_t *d_root_counts,
                          uint64_t *d_bindings);
 
+/* The quantifier nodes of level `level` (1..n_levels-1) of every stream, in
+ * no particular order (device outputs, room for `capacity` nodes):
+ * keys[j] = the node's packed prefix with the stream id above key 0 (the
+ * stream id takes ceil(log2 max_streams) bits, or 1, and each key m its
+ * key_bits[m]); counts[(p * capacity + j) * 6 + b] its 6-bin count vector
+ * (Def. 8) and verdict[p * capacity + j] its verdict for property p; *d_n
+ * (a device uint64) the number of nodes.  More nodes than capacity report
+ * LTL4C_ECAPACITY from ltl4c_wait(). */
+int32_t ltl4c_group_read_nodes(ltl4c_ctx *ctx, int32_t group, uint32_t level, uint64_t *d_keys, uint32_t *d_counts,
+                               uint8_t *d_verdict, uint64_t capacity, uint64_t *d_n);
+
+/* ---- streams of a group: admission, sequence numbers, host ingestion ----
+ *
+ * A group opened by ltl4c_group_open admits all its max_streams streams at
+ * once, each with room for max_bindings bindings.  A group opened by
+ * ltl4c_group_open_pool is a pool of pool_bindings binding slots (its hash
+ * tables and node tables are sized for them, and charged to the memory
+ * budget when it opens) with no stream admitted: ltl4c_stream_open admits one
+ * stream with its own binding limit when the pool still has room for it
+ * (LTL4C_EADMIT otherwise), and ltl4c_stream_close frees its slots and its
+ * reservation.  Pushes to a stream that is not open fail with LTL4C_ESEQ.
+ *
+ * Every stream counts its chunks: ltl4c_group_push_seq takes each chunk's
+ * sequence number and refuses the whole push (LTL4C_ESEQ, nothing enqueued)
+ * unless every chunk carries its stream's next number, so a repeated chunk
+ * or a lost one is caught before it reaches the monitor tree.  The other
+ * push calls number their chunks implicitly.  ltl4c_stream_poll reports,
+ * without blocking, the next number the stream expects and the number of
+ * chunks whose verdict updates have completed on the device. */
+int32_t ltl4c_group_open_pool(ltl4c_ctx *ctx, const int32_t *props, int32_t n_props, uint32_t max_streams,
+                              uint64_t pool_bindings, uint64_t max_batch, int32_t *group);
+/* Admit stream `stream` (< max_streams) with at most max_bindings bindings;
+ * its first chunk will carry sequence number first_seq.  LTL4C_ESEQ if the
+ * stream is already open.  Enqueued on the context's stream. */
+int32_t ltl4c_stream_open(ltl4c_ctx *ctx, int32_t group, uint32_t stream, uint32_t max_bindings, uint64_t first_seq);
+/* Close the stream: its bindings, nodes, counts and root are cleared (the
+ * slots are reused by later inserts) and its reservation returns to the
+ * pool.  Enqueued on the context's stream, after the pushes before it. */
+int32_t ltl4c_stream_close(ltl4c_ctx *ctx, int32_t group, uint32_t stream);
+/* *next_seq: the sequence number the stream's next chunk must carry;
+ * *done_seq: every chunk numbered below it has been applied on the device
+ * (its verdicts are visible to ltl4c_group_read).  Either may be NULL. */
+int32_t ltl4c_stream_poll(ltl4c_ctx *ctx, int32_t group, uint32_t stream, uint64_t *next_seq, uint64_t *done_seq);
+/* Open streams without a push for at least idle_ns nanoseconds (host steady
+ * clock): up to `capacity` ids into streams[], their number in *n_stalled. */
+int32_t ltl4c_group_stalled(ltl4c_ctx *ctx, int32_t group, uint64_t idle_ns, uint32_t *streams, uint32_t capacity,
+                            uint32_t *n_stalled);
+/* Push n_chunks chunks with sequence numbers: chunk i is sizes[i] records at
+ * chunks[i], continuing stream streams[i] with number seqs[i] (host arrays).
+ * is_device = 1: chunks[i] are device pointers (they must stay valid until
+ * the push has run).  is_device = 0: chunks[i] are pinned host memory
+ * (hipHostMalloc; pageable memory gives LTL4C_EINVAL); the library copies
+ * them with the copy engine into one of two device staging buffers of
+ * max_batch records (allocated at the first such push, within the memory
+ * budget) on a copy stream of its own, so the copy of one push overlaps the
+ * kernels of the previous one; the host memory must stay valid until
+ * ltl4c_stream_poll reports the chunks done. */
+int32_t ltl4c_group_push_seq(ltl4c_ctx *ctx, int32_t group, const void *const *chunks, const uint64_t *sizes,
+                             const uint32_t *streams, const uint64_t *seqs, int32_t n_chunks, int32_t is_device);
+
 /* Checkpoint / resume: copy the group's resident state to host memory
  * (*bytes is its size; host == NULL only queries it) and back.  Both
- * synchronise the context's stream. */
+ * synchronise the context's stream.  The streams' admission and sequence
+ * numbers are host state of the open group and are not part of it. */
 int32_t ltl4c_group_snapshot(ltl4c_ctx *ctx, int32_t group, void *host, uint64_t *bytes);
 int32_t ltl4c_group_restore(ltl4c_ctx *ctx, int32_t group, const void *host, uint64_t bytes);
 

@@ -46,6 +46,8 @@ def cpu_model():
 
 
 def _field(rec2d, off, nbytes):
+    if nbytes == 4 and off % 4 == 0 and rec2d.shape[1] % 4 == 0:
+        return rec2d.view(np.uint32)[:, off // 4].astype(np.uint64)
     v = np.zeros(rec2d.shape[0], dtype=np.uint64)
     for b in range(nbytes):
         v |= rec2d[:, off + b].astype(np.uint64) << np.uint64(8 * b)
@@ -58,7 +60,7 @@ def partition_ids(records_u8, layout, n_parts):
     rec2d = records_u8.reshape(-1, rb)
     k0 = _field(rec2d, layout.key_offsets[0], layout.key_bytes[0])
     h = (k0 * np.uint64(0x9E3779B97F4A7C15)) >> np.uint64(40)
-    return (h % np.uint64(n_parts)).astype(np.int64)
+    return (h % np.uint64(n_parts)).astype(np.uint8 if n_parts <= 256 else np.int64)
 
 
 def _merge_levels(parts, n_props, n_levels):
@@ -95,7 +97,7 @@ def evaluate_partitioned(records_u8, layout, props, n_parts=None, threads=None, 
     pid = partition_ids(recs, layout, n_parts) if parts_idx is None else parts_idx
     # a stable grouping keeps trace order inside every partition
     order = np.argsort(pid, kind="stable")
-    bounds = np.searchsorted(pid[order], np.arange(n_parts + 1))
+    bounds = np.concatenate([[0], np.cumsum(np.bincount(pid, minlength=n_parts))])
 
     def run(p):
         rows = order[bounds[p]:bounds[p + 1]]

@@ -198,6 +198,9 @@ struct ZeroArgs {
 // Bindings and quantifier nodes live in open-addressing hash tables keyed by
 // the packed (stream, key...) prefix; a node's id is its slot.
 constexpr uint64_t kEmptyKey = ~0ull;
+// A slot of a closed stream: skipped by lookups, reusable by inserts.  Real
+// keys stay below 2^63, so neither marker is ever a key.
+constexpr uint64_t kDeadKey = ~0ull - 1ull;
 constexpr uint8_t kNoVerdict = 0xFF;     // node not yet counted in its parent
 
 struct GroupState {
@@ -206,7 +209,8 @@ struct GroupState {
     const Plan* plan;                    // real properties (labels, q0, quantifiers)
     uint32_t level_shift[kMaxLevels];    // key >> level_shift[m] = (stream, keys 0..m-1), m >= 1
     uint32_t stream_shift;               // key >> stream_shift = stream
-    uint32_t max_streams, max_bindings;
+    uint32_t max_streams;
+    uint32_t* stream_max;                // [max_streams]: bindings a stream may hold
     // bindings
     uint64_t* bslot;                     // [bcap][2]: key, then parent | states of properties 0..3 << 32
     uint64_t bmask;
@@ -268,6 +272,18 @@ hipError_t launch_fill_u8(uint8_t* p, uint8_t v, uint64_t n, hipStream_t s);
 hipError_t launch_group_update(const GroupUpdateArgs& a, uint64_t max_seg, hipStream_t s);
 hipError_t launch_group_level(const GroupState& g, uint32_t level, hipStream_t s);
 hipError_t launch_group_roots(const GroupState& g, bool all, hipStream_t s);
+hipError_t launch_group_purge(const GroupState& g, uint32_t stream, hipStream_t s);
+hipError_t launch_group_nodes(const GroupState& g, uint32_t level, uint64_t* keys, uint32_t* counts, uint8_t* verdict,
+                              uint64_t capacity, uint64_t* n_out, hipStream_t s);
+hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s);
+// Up to kPutWords 32-bit words carried by value in the launch itself: a
+// device write of host data with no host buffer, copy or allocation.
+constexpr uint32_t kPutWords = 448;
+struct PutWords {
+    uint32_t n;
+    uint32_t w[kPutWords];
+};
+hipError_t launch_put_words(uint32_t* dst, const PutWords& a, hipStream_t s);
 hipError_t launch_group_read(const GroupState& g, uint8_t* verdict, uint64_t* counts, uint64_t* bindings,
                              hipStream_t s);
 hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);

@@ -1337,31 +1337,47 @@ __device__ __forceinline__ uint64_t mix64(uint64_t x) {
 }
 
 // Insert-or-find `key` in an open-addressing table; returns its slot and
-// whether this call inserted it, or ~0 when the table is full.  A slot only
-// ever changes from empty to a key, so probes read through the caches: a
-// stale copy can only show "empty", and the compare-and-swap that follows
-// returns the slot's real content.
+// whether this call inserted it, or ~0 when the table is full.  Within one
+// kernel a slot only changes from empty (or dead: a slot of a closed stream)
+// to a key, so probes read through the caches: a stale copy can only show a
+// free slot, and the compare-and-swap that claims it returns the slot's real
+// content.  A key may sit past a dead slot (it was inserted before that slot
+// died), so a free slot is only claimed once the walk has reached an empty
+// one: the key is then absent, and it is put into the first free slot of its
+// probe sequence.  Slots before that one never become free during a kernel,
+// so concurrent inserts of one key race for the same slot and the loser sees
+// the winner's key.  A lost race with another key restarts the walk.
 // Keys sit `stride` words apart (a slot may carry data after its key).
 __device__ uint64_t table_slot(uint64_t* keys, uint32_t stride, uint64_t mask, uint64_t key, bool* fresh) {
-    uint64_t h = mix64(key) & mask;
-    for (uint64_t probe = 0; probe <= mask; ++probe) {
-        const uint64_t k = __hip_atomic_load(keys + h * stride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (k == key) {
-            *fresh = false;
-            return h;
-        }
-        if (k == kEmptyKey) {
-            const uint64_t prev = atomicCAS(reinterpret_cast<unsigned long long*>(keys + h * stride), kEmptyKey, key);
-            if (prev == kEmptyKey) {
-                *fresh = true;
-                return h;
-            }
-            if (prev == key) {
+    const uint64_t h0 = mix64(key) & mask;
+    for (uint32_t attempt = 0; attempt < 64; ++attempt) {
+        uint64_t h = h0, dead = ~0ull, probe = 0;
+        for (; probe <= mask; ++probe) {
+            const uint64_t k = __hip_atomic_load(keys + h * stride, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (k == key) {
                 *fresh = false;
                 return h;
             }
+            if (k == kDeadKey) {
+                if (dead == ~0ull) dead = h;
+            } else if (k == kEmptyKey) {
+                break;
+            }
+            h = (h + 1) & mask;
         }
-        h = (h + 1) & mask;
+        const bool use_dead = dead != ~0ull;
+        if (!use_dead && probe > mask) break;             // full: no empty and no dead slot
+        const uint64_t at = use_dead ? dead : h;
+        const uint64_t expect = use_dead ? kDeadKey : kEmptyKey;
+        const uint64_t prev = atomicCAS(reinterpret_cast<unsigned long long*>(keys + at * stride), expect, key);
+        if (prev == expect) {
+            *fresh = true;
+            return at;
+        }
+        if (prev == key) {
+            *fresh = false;
+            return at;
+        }
     }
     *fresh = false;
     return ~0ull;
@@ -1463,7 +1479,8 @@ __global__ __launch_bounds__(256) void k_group_update(GroupUpdateArgs a) {
                 const int end = later ? __ffsll((unsigned long long)later) - 1 : 64;
                 const uint64_t srun = (end == 64 ? ~0ull : ((1ull << end) - 1ull)) & ~((1ull << lane) - 1ull);
                 const uint32_t nf = (uint32_t)__popcll(freshm & srun);
-                if (nf && atomicAdd(g.stream_bindings + stream, nf) + nf > g.max_bindings) atomicOr(g.err, kErrCapacity);
+                if (nf && atomicAdd(g.stream_bindings + stream, nf) + nf > g.stream_max[stream])
+                    atomicOr(g.err, kErrCapacity);
             }
         }
         // runs of lanes with one parent (all lanes take part in the ballots)
@@ -1566,6 +1583,81 @@ __global__ __launch_bounds__(256) void k_group_read(GroupState g, uint8_t* verdi
         for (int b = 0; b < 6; ++b) counts[(uint64_t)i * 6 + b] = g.rcounts[(uint64_t)i * 6 + b];
         if (bindings && i % g.n_props == 0) bindings[i / g.n_props] = g.stream_bindings[i / g.n_props];
     }
+}
+
+// Close stream `stream`: its bindings and quantifier nodes become dead slots
+// (free for later inserts, with cleared data), its root counts and binding
+// count return to zero and its root is valued on the empty tree again.
+__global__ __launch_bounds__(256) void k_group_purge(GroupState g, uint32_t stream) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t t0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint64_t b = t0; b <= g.bmask; b += stride) {
+        const uint64_t k = g.bslot[2 * b];
+        if (k >= kDeadKey || (uint32_t)(k >> g.stream_shift) != stream) continue;
+        g.bslot[2 * b] = kDeadKey;
+        g.bslot[2 * b + 1] = 0;
+        for (uint32_t p = 4; p < g.n_props; ++p) g.bstate[(uint64_t)(p - 4) * (g.bmask + 1) + b] = 0;
+    }
+    for (uint32_t m = 1; m < g.n_levels; ++m) {
+        const uint32_t sh = g.stream_shift - g.level_shift[m];
+        for (uint64_t j = t0; j <= g.nmask; j += stride) {
+            const uint64_t k = g.nkeys[m][j];
+            if (k >= kDeadKey || (uint32_t)(k >> sh) != stream) continue;
+            g.nkeys[m][j] = kDeadKey;
+            for (uint32_t p = 0; p < g.n_props; ++p) {
+                uint32_t* c = counts_of(g, m, (uint32_t)j, p);
+                for (int q = 0; q < 6; ++q) c[q] = 0u;
+                g.nverdict[m][(uint64_t)p * (g.nmask + 1) + j] = kNoVerdict;
+            }
+            g.nparent[m][j] = 0u;
+            g.ndirty[m][j] = 0u;
+        }
+    }
+    if (t0 == 0) {
+        g.stream_bindings[stream] = 0u;
+        g.rdirty[stream] = 0u;
+        for (uint32_t p = 0; p < g.n_props; ++p) {
+            uint32_t* c = counts_of(g, 0, stream, p);
+            for (int q = 0; q < 6; ++q) c[q] = 0u;
+            g.rverdict[(uint64_t)stream * g.n_props + p] = (uint8_t)valuate(g.plan->prop[p], 0, c);
+        }
+    }
+}
+
+// The live quantifier nodes of one level (>= 1), in table order: key (the
+// packed stream id and key prefix), 6-bin counts and verdict per property.
+__global__ __launch_bounds__(256) void k_group_nodes(GroupState g, uint32_t level, uint64_t* keys, uint32_t* counts,
+                                                     uint8_t* verdict, uint64_t capacity, uint64_t* n_out) {
+    const int lane = threadIdx.x & 63;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base <= g.nmask; base += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t j = base + threadIdx.x;
+        const uint64_t k = j <= g.nmask ? g.nkeys[level][j] : kEmptyKey;
+        const bool live = k < kDeadKey && g.nverdict[level][j] != kNoVerdict;
+        const uint64_t m = __ballot(live);
+        if (m == 0) continue;
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        unsigned long long at = 0;
+        if (lane == leader) at = atomicAdd(reinterpret_cast<unsigned long long*>(n_out), (unsigned long long)__popcll(m));
+        at = __shfl(at, leader, 64);
+        if (!live) continue;
+        const uint64_t o = at + (uint64_t)__popcll(m & ((1ull << lane) - 1ull));
+        if (o >= capacity) {
+            atomicOr(g.err, kErrCapacity);
+            continue;
+        }
+        keys[o] = k;
+        for (uint32_t p = 0; p < g.n_props; ++p) {
+            const uint32_t* c = counts_of(g, level, (uint32_t)j, p);
+            for (int q = 0; q < 6; ++q) counts[((uint64_t)p * capacity + o) * 6 + q] = c[q];
+            verdict[(uint64_t)p * capacity + o] = g.nverdict[level][(uint64_t)p * (g.nmask + 1) + j];
+        }
+    }
+}
+
+__global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
+
+__global__ __launch_bounds__(64) void k_put_words(uint32_t* dst, PutWords a) {
+    for (uint32_t i = threadIdx.x; i < a.n; i += blockDim.x) dst[i] = a.w[i];
 }
 
 // One thread per trace of a batch.
@@ -1764,6 +1856,27 @@ hipError_t launch_group_roots(const GroupState& g, bool all, hipStream_t s) {
 hipError_t launch_group_read(const GroupState& g, uint8_t* verdict, uint64_t* counts, uint64_t* bindings,
                              hipStream_t s) {
     hipLaunchKernelGGL(k_group_read, dim3(64), dim3(256), 0, s, g, verdict, counts, bindings);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_purge(const GroupState& g, uint32_t stream, hipStream_t s) {
+    hipLaunchKernelGGL(k_group_purge, dim3(512), dim3(256), 0, s, g, stream);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_nodes(const GroupState& g, uint32_t level, uint64_t* keys, uint32_t* counts, uint8_t* verdict,
+                              uint64_t capacity, uint64_t* n_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_group_nodes, dim3(512), dim3(256), 0, s, g, level, keys, counts, verdict, capacity, n_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_put_words(uint32_t* dst, const PutWords& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_put_words, dim3(1), dim3(64), 0, s, dst, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_u32(uint32_t* p, uint32_t v, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, p, v);
     return hipGetLastError();
 }
 

@@ -8,9 +8,12 @@
 // which is Algorithm 1 (SortTrace, SpawnMonitors/Distribute as one flat scan,
 // ApplyQuantifiers level by level) without host round trips.
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -55,8 +58,39 @@ uint32_t bits_for(uint32_t n_values) {  // bits to hold values 0..n_values-1
 
 }  // namespace
 
+// Scratch memory of the no-allocation entry point (ltl4c_eval_noalloc): a
+// file-scope device array, so that a call needs no allocation at all.  Each
+// device holds its own copy from the time the library is loaded until the
+// process ends.  Host code never passes `scratch` itself to a kernel (in host
+// code the name is only a stand-in): it uses the address hipGetSymbolAddress
+// returns for the current device, kept per device in g_scratch_ptr.
+constexpr uint64_t kNoAllocScratchBytes = LTL4C_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be the current device.
+hipError_t scratch_address(int device, uint8_t** out) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = static_cast<uint8_t*>(p);
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+}  // namespace
+
 struct ltl4c_ctx {
     int device = 0;
+    uint8_t* scratch = nullptr;        // this device's copy of `scratch`
+    bool no_timing = false;            // launches without profiling events (no-allocation calls)
     hipStream_t stream = nullptr;
     bool has_layout = false;
     ltl4c_layout layout{};
@@ -347,13 +381,14 @@ hipEvent_t take_event(ltl4c_ctx* ctx) {
 template <typename F>
 int32_t launch(ltl4c_ctx* ctx, const char* name, F&& f) {
     hipEvent_t a = nullptr, b = nullptr;
-    if (ctx->prof) {
+    const bool timed = ctx->prof && !ctx->no_timing;
+    if (timed) {
         a = take_event(ctx);
         b = take_event(ctx);
         if (a) (void)hipEventRecord(a, ctx->stream);
     }
     hipError_t e = f();
-    if (ctx->prof && a && b) {
+    if (timed && a && b) {
         (void)hipEventRecord(b, ctx->stream);
         ctx->timed.push_back({name, a, b});
     }
@@ -476,7 +511,26 @@ struct GroupHost {
     std::vector<ScanGroup> sgroups;    // scan launches over the virtual properties
     int sort_variant = 0, scan_variant = 0;   // schedules fixed when the group opens
     uint32_t P = 0, V = 0, S = 0, max_bindings = 0;
+    uint64_t table_bindings = 0;       // bindings the hash table is sized for (load factor <= 1/2)
+    uint64_t admitted = 0;             // bindings reserved by the open streams
     uint64_t max_batch = 0;
+    // per stream (host side): admission, sequence numbers, last push
+    std::vector<uint8_t> open;
+    std::vector<uint32_t> smax;
+    std::vector<uint64_t> next_seq, done_seq;
+    std::vector<std::chrono::steady_clock::time_point> last_push;
+    struct Pending {
+        hipEvent_t ev;
+        std::vector<std::pair<uint32_t, uint64_t>> seq_after;   // (stream, next sequence number)
+    };
+    std::deque<Pending> pending;       // pushes whose completion poll has not seen yet
+    std::vector<hipEvent_t> spare_events;
+    // pushes from host memory: double-buffered device staging filled on a copy stream
+    hipStream_t copy_stream = nullptr;
+    uint8_t* stage[2] = {nullptr, nullptr};
+    hipEvent_t stage_free[2] = {nullptr, nullptr}, stage_ready[2] = {nullptr, nullptr};
+    int stage_i = 0;
+    uint64_t stage_bytes = 0;
     Geometry g{};
     ltl4c_layout lay_ws{};             // layout copy with one level for workspace sizing
     Plan* vplan = nullptr;             // one virtual property per (property, start state)
@@ -508,7 +562,7 @@ uint64_t pow2_at_least(uint64_t x) {
 
 // Offsets of the resident state of a group; fills gs pointers when base != nullptr.
 uint64_t group_state_layout(const GroupHost& G, uint32_t L, uint8_t* base, GroupState* gs) {
-    const uint64_t bcap = pow2_at_least(2ull * G.S * G.max_bindings);
+    const uint64_t bcap = pow2_at_least(2ull * G.table_bindings);
     const uint64_t ncap = bcap;
     uint64_t off = 0;
     auto take = [&](uint64_t bytes) {
@@ -519,6 +573,7 @@ uint64_t group_state_layout(const GroupHost& G, uint32_t L, uint8_t* base, Group
     uint8_t* bslot = take(16 * bcap);
     uint8_t* bstate = take((uint64_t)(G.P > 4 ? G.P - 4 : 0) * bcap);
     uint8_t* sb = take(4ull * G.S);
+    uint8_t* smx = take(4ull * G.S);
     uint8_t* nk[kMaxLevels] = {}, *nc[kMaxLevels] = {}, *nv[kMaxLevels] = {}, *np[kMaxLevels] = {},
              *nd[kMaxLevels] = {}, *nl[kMaxLevels] = {};
     for (uint32_t m = 1; m < L; ++m) {
@@ -539,6 +594,7 @@ uint64_t group_state_layout(const GroupHost& G, uint32_t L, uint8_t* base, Group
         gs->bmask = bcap - 1;
         gs->bstate = bstate;
         gs->stream_bindings = reinterpret_cast<uint32_t*>(sb);
+        gs->stream_max = reinterpret_cast<uint32_t*>(smx);
         gs->nmask = ncap - 1;
         for (uint32_t m = 1; m < L; ++m) {
             gs->nkeys[m] = reinterpret_cast<uint64_t*>(nk[m]);
@@ -557,19 +613,21 @@ uint64_t group_state_layout(const GroupHost& G, uint32_t L, uint8_t* base, Group
     return off;
 }
 
+// table_bindings: bindings of all streams together the group's tables hold.
 int32_t group_configure(ltl4c_ctx* ctx, GroupHost& G, const int32_t* props, int32_t n_props, uint32_t max_streams,
-                        uint32_t max_bindings, uint64_t max_batch) {
+                        uint32_t max_bindings, uint64_t table_bindings, uint64_t max_batch) {
     int32_t s = check_props(ctx, props, n_props);
     if (s) return s;
-    if (max_streams < 1 || max_bindings < 1) return fail(LTL4C_EINVAL, "max_streams and max_bindings must be >= 1");
+    if (max_streams < 1 || max_bindings < 1 || table_bindings < 1)
+        return fail(LTL4C_EINVAL, "max_streams and the binding limits must be >= 1");
     if (max_batch < 1 || max_batch > LTL4C_MAX_EVENTS) return fail(LTL4C_EUNSUPPORTED, "max_batch out of range");
-    if ((uint64_t)max_streams * max_bindings > (1ull << 31))
-        return fail(LTL4C_EUNSUPPORTED, "max_streams * max_bindings exceeds 2^31");
+    if (table_bindings > (1ull << 31)) return fail(LTL4C_EUNSUPPORTED, "the group's bindings exceed 2^31");
     const ltl4c_layout& L = ctx->layout;
     G.props.assign(props, props + n_props);
     G.P = (uint32_t)n_props;
     G.S = max_streams;
     G.max_bindings = max_bindings;
+    G.table_bindings = table_bindings;
     G.max_batch = max_batch;
     G.V = 0;
     for (int32_t i = 0; i < n_props; ++i) G.V += ctx->monitors[ctx->props[props[i]].monitor].n_states;
@@ -601,6 +659,15 @@ int32_t group_configure(ltl4c_ctx* ctx, GroupHost& G, const int32_t* props, int3
 
 void group_free(GroupHost* G) {
     if (!G) return;
+    if (G->copy_stream) (void)hipStreamSynchronize(G->copy_stream);
+    for (int i = 0; i < 2; ++i) {
+        (void)hipFree(G->stage[i]);
+        if (G->stage_free[i]) (void)hipEventDestroy(G->stage_free[i]);
+        if (G->stage_ready[i]) (void)hipEventDestroy(G->stage_ready[i]);
+    }
+    if (G->copy_stream) (void)hipStreamDestroy(G->copy_stream);
+    for (auto& p : G->pending) (void)hipEventDestroy(p.ev);
+    for (auto e : G->spare_events) (void)hipEventDestroy(e);
     (void)hipFree(G->state);
     (void)hipFree(G->ws);
     (void)hipFree(G->chunk_dev);
@@ -650,6 +717,7 @@ int32_t ltl4c_create(ltl4c_ctx** out, int32_t device) {
     ctx->device = device;
     hipError_t e = hipMalloc(&ctx->err_dev, 256);
     if (e == hipSuccess) e = hipMemset(ctx->err_dev, 0, 256);
+    if (e == hipSuccess) e = scratch_address(device, &ctx->scratch);
     if (e != hipSuccess) {
         delete ctx;
         return fail(LTL4C_EDEVICE, std::string("context allocation: ") + hipGetErrorString(e));
@@ -927,8 +995,39 @@ static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, v
     return s;
 }
 
+// The property table of one evaluation, as the kernels read it.
+static Plan host_plan(ltl4c_ctx* ctx, const int32_t* props, int32_t n_props) {
+    Plan host;
+    std::memset(&host, 0, sizeof host);
+    for (int32_t i = 0; i < n_props; ++i) {
+        const ltl4c_property& p = ctx->props[props[i]];
+        host.prop[i] = make_prop(ctx->monitors[p.monitor], p);
+    }
+    std::memcpy(host.class_of_type, ctx->layout.class_of_type, 256);
+    std::memcpy(host.key_present, ctx->layout.key_present, 256);
+    return host;
+}
+
+static int32_t eval_impl(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int32_t* props, int32_t n_props,
+                         void* d_ws, uint64_t ws_bytes, const ltl4c_result* out, bool noalloc);
+
 int32_t ltl4c_eval(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int32_t* props, int32_t n_props,
                    void* d_ws, uint64_t ws_bytes, const ltl4c_result* out) {
+    return eval_impl(ctx, d_records, n, props, n_props, d_ws, ws_bytes, out, false);
+}
+
+int32_t ltl4c_eval_noalloc(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int32_t* props, int32_t n_props,
+                           const ltl4c_result* out) {
+    if (!ctx) return fail(LTL4C_EINVAL, "ctx is NULL");
+    if (!ctx->scratch) return fail(LTL4C_EDEVICE, "the library's scratch memory has no address on this device");
+    // the plan sits at the start of the scratch, the workspace after it
+    const uint64_t plan_bytes = align256(sizeof(Plan));
+    return eval_impl(ctx, d_records, n, props, n_props, ctx->scratch + plan_bytes, kNoAllocScratchBytes - plan_bytes,
+                     out, true);
+}
+
+static int32_t eval_impl(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int32_t* props, int32_t n_props,
+                         void* d_ws, uint64_t ws_bytes, const ltl4c_result* out, bool noalloc) {
     int32_t s = check_props(ctx, props, n_props);
     if (s) return s;
     if (n > LTL4C_MAX_EVENTS) return fail(LTL4C_EUNSUPPORTED, "too many events for one call");
@@ -943,7 +1042,15 @@ int32_t ltl4c_eval(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int3
     Geometry g = geometry(L, 0, false, true, sort_threads(ctx->sort_variant) >= 512);
     const std::vector<ScanGroup> groups = scan_groups(monitor_states(ctx, props, n_props));
     WsLayout w = plan_workspace(L, g, n, P, (uint32_t)groups.size(), ctx->sort_variant, ctx->scan_variant);
-    if (ws_bytes < w.total) return fail(LTL4C_ENOMEM, "workspace smaller than ltl4c_workspace_bytes()");
+    if (ws_bytes < w.total) {
+        if (!noalloc) return fail(LTL4C_ENOMEM, "workspace smaller than ltl4c_workspace_bytes()");
+        char buf[200];
+        std::snprintf(buf, sizeof buf,
+                      "ltl4c_eval_noalloc: %llu events need %llu bytes of scratch; the library's scratch holds %llu "
+                      "(use ltl4c_eval with a workspace)",
+                      (unsigned long long)n, (unsigned long long)w.total, (unsigned long long)ws_bytes);
+        return fail(LTL4C_ENOMEM, buf);
+    }
     if ((out->inst_keys != nullptr) != (out->inst_verdict != nullptr))
         return fail(LTL4C_EINVAL, "inst_keys and inst_verdict are given together or not at all");
     if (out->event_verdict) {
@@ -977,11 +1084,32 @@ int32_t ltl4c_eval(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int3
     if (any_optional && out->capacity == 0)
         return fail(LTL4C_EINVAL, "capacity must be > 0 when optional outputs are given");
     Plan* plan = nullptr;
-    s = get_plan(ctx, props, n_props, &plan);
-    if (s) return s;
+    if (!noalloc) {
+        s = get_plan(ctx, props, n_props, &plan);
+        if (s) return s;
+        HIP_TRY(hipSetDevice(ctx->device));
+        return eval_core(ctx, g, w, d_ws, d_records, n, plan, P, groups, nullptr, nullptr, 0, out);
+    }
+    // no allocation: the plan travels inside kernel launches into the
+    // scratch, and no profiling events are taken
     HIP_TRY(hipSetDevice(ctx->device));
-
-    return eval_core(ctx, g, w, d_ws, d_records, n, plan, P, groups, nullptr, nullptr, 0, out);
+    const Plan hp = host_plan(ctx, props, n_props);
+    plan = reinterpret_cast<Plan*>(ctx->scratch);
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(&hp);
+    static_assert(sizeof(Plan) % 4 == 0, "the plan is copied in 32-bit words");
+    const uint32_t words = (uint32_t)(sizeof(Plan) / 4);
+    ctx->no_timing = true;
+    for (uint32_t at = 0; at < words && s == LTL4C_OK; at += kPutWords) {
+        PutWords pw;
+        pw.n = std::min<uint32_t>(kPutWords, words - at);
+        std::memcpy(pw.w, src + at, 4ull * pw.n);
+        s = launch(ctx, "put_words", [&] {
+            return launch_put_words(reinterpret_cast<uint32_t*>(ctx->scratch) + at, pw, ctx->stream);
+        });
+    }
+    if (s == LTL4C_OK) s = eval_core(ctx, g, w, d_ws, d_records, n, plan, P, groups, nullptr, nullptr, 0, out);
+    ctx->no_timing = false;
+    return s;
 }
 
 
@@ -1125,17 +1253,19 @@ int32_t ltl4c_group_bytes(ltl4c_ctx* ctx, const int32_t* props, int32_t n_props,
                           uint32_t max_bindings, uint64_t max_batch, uint64_t* bytes) {
     if (!bytes) return fail(LTL4C_EINVAL, "bytes is NULL");
     GroupHost G;
-    int32_t s = group_configure(ctx, G, props, n_props, max_streams, max_bindings, max_batch);
+    int32_t s = group_configure(ctx, G, props, n_props, max_streams, max_bindings,
+                                (uint64_t)max_streams * max_bindings, max_batch);
     if (s) return s;
     *bytes = G.total_bytes;
     return LTL4C_OK;
 }
 
-int32_t ltl4c_group_open(ltl4c_ctx* ctx, const int32_t* props, int32_t n_props, uint32_t max_streams,
-                         uint32_t max_bindings, uint64_t max_batch, int32_t* group) {
+static int32_t group_open_impl(ltl4c_ctx* ctx, const int32_t* props, int32_t n_props, uint32_t max_streams,
+                               uint32_t max_bindings, uint64_t table_bindings, uint64_t max_batch, bool admit_all,
+                               int32_t* group) {
     if (!group) return fail(LTL4C_EINVAL, "group is NULL");
     GroupHost* G = new GroupHost();
-    int32_t s = group_configure(ctx, *G, props, n_props, max_streams, max_bindings, max_batch);
+    int32_t s = group_configure(ctx, *G, props, n_props, max_streams, max_bindings, table_bindings, max_batch);
     if (s) {
         delete G;
         return s;
@@ -1190,11 +1320,11 @@ int32_t ltl4c_group_open(ltl4c_ctx* ctx, const int32_t* props, int32_t n_props, 
     for (uint32_t m = 1; m < L; ++m) gs.level_shift[m] = G->g.key_bits_total - G->g.prefix_bits[m];
     gs.stream_shift = G->g.key_bits_total - G->g.stream_bits;
     gs.max_streams = G->S;
-    gs.max_bindings = G->max_bindings;
     gs.err = ctx->err_dev;
     // empty tree: no keys, no verdicts yet, zero counts; then value every root
     const hipStream_t st = ctx->stream;
     e = hipMemsetAsync(G->state, 0, G->state_bytes, st);
+    if (e == hipSuccess && admit_all) e = hipMemsetD32Async(gs.stream_max, (int)max_bindings, G->S, st);
     if (e == hipSuccess) e = launch_fill_u64(gs.bslot, 2 * (gs.bmask + 1), kEmptyKey, st);
     for (uint32_t m = 1; m < L && e == hipSuccess; ++m) {
         e = launch_fill_u64(gs.nkeys[m], gs.nmask + 1, kEmptyKey, st);
@@ -1218,8 +1348,128 @@ int32_t ltl4c_group_open(ltl4c_ctx* ctx, const int32_t* props, int32_t n_props, 
         ctx->groups.push_back(nullptr);
     }
     ctx->groups[id] = G;
+    G->open.assign(G->S, admit_all ? 1 : 0);
+    G->smax.assign(G->S, admit_all ? max_bindings : 0u);
+    G->admitted = admit_all ? (uint64_t)G->S * max_bindings : 0;
+    G->next_seq.assign(G->S, 0);
+    G->done_seq.assign(G->S, 0);
+    G->last_push.assign(G->S, std::chrono::steady_clock::now());
     *group = id;
     return LTL4C_OK;
+}
+
+int32_t ltl4c_group_open(ltl4c_ctx* ctx, const int32_t* props, int32_t n_props, uint32_t max_streams,
+                         uint32_t max_bindings, uint64_t max_batch, int32_t* group) {
+    return group_open_impl(ctx, props, n_props, max_streams, max_bindings, (uint64_t)max_streams * max_bindings,
+                           max_batch, true, group);
+}
+
+int32_t ltl4c_group_open_pool(ltl4c_ctx* ctx, const int32_t* props, int32_t n_props, uint32_t max_streams,
+                              uint64_t pool_bindings, uint64_t max_batch, int32_t* group) {
+    if (pool_bindings < 1 || pool_bindings > (1ull << 31))
+        return fail(LTL4C_EUNSUPPORTED, "pool_bindings must be in 1..2^31");
+    return group_open_impl(ctx, props, n_props, max_streams, (uint32_t)std::min<uint64_t>(pool_bindings, 0xFFFFFFFFu),
+                           pool_bindings, max_batch, false, group);
+}
+
+int32_t ltl4c_stream_open(ltl4c_ctx* ctx, int32_t group, uint32_t stream, uint32_t max_bindings, uint64_t first_seq) {
+    GroupHost* G = nullptr;
+    int32_t s = get_group(ctx, group, &G);
+    if (s) return s;
+    if (stream >= G->S) return fail(LTL4C_EINVAL, "stream id >= max_streams");
+    if (max_bindings < 1) return fail(LTL4C_EINVAL, "max_bindings must be >= 1");
+    if (G->open[stream]) return fail(LTL4C_ESEQ, "the stream is already open");
+    if (G->admitted + max_bindings > G->table_bindings)
+        return fail(LTL4C_EADMIT, "the group's binding pool cannot hold this stream's max_bindings");
+    HIP_TRY(hipSetDevice(ctx->device));
+    s = launch(ctx, "set_u32", [&] { return launch_set_u32(G->gs.stream_max + stream, max_bindings, ctx->stream); });
+    if (s) return s;
+    G->open[stream] = 1;
+    G->smax[stream] = max_bindings;
+    G->admitted += max_bindings;
+    G->next_seq[stream] = G->done_seq[stream] = first_seq;
+    G->last_push[stream] = std::chrono::steady_clock::now();
+    return LTL4C_OK;
+}
+
+int32_t ltl4c_stream_close(ltl4c_ctx* ctx, int32_t group, uint32_t stream) {
+    GroupHost* G = nullptr;
+    int32_t s = get_group(ctx, group, &G);
+    if (s) return s;
+    if (stream >= G->S) return fail(LTL4C_EINVAL, "stream id >= max_streams");
+    if (!G->open[stream]) return fail(LTL4C_ESEQ, "the stream is not open");
+    HIP_TRY(hipSetDevice(ctx->device));
+    s = launch(ctx, "group_purge", [&] { return launch_group_purge(G->gs, stream, ctx->stream); });
+    if (s) return s;
+    s = launch(ctx, "set_u32", [&] { return launch_set_u32(G->gs.stream_max + stream, 0u, ctx->stream); });
+    if (s) return s;
+    G->open[stream] = 0;
+    G->admitted -= G->smax[stream];
+    G->smax[stream] = 0;
+    return LTL4C_OK;
+}
+
+// Completed pushes, oldest first, update the per-stream completed sequence numbers.
+static int32_t drain_pending(GroupHost* G) {
+    while (!G->pending.empty()) {
+        hipError_t q = hipEventQuery(G->pending.front().ev);
+        if (q == hipErrorNotReady) break;
+        if (q != hipSuccess) return fail(LTL4C_EDEVICE, std::string("push completion: ") + hipGetErrorString(q));
+        for (auto& sa : G->pending.front().seq_after) G->done_seq[sa.first] = std::max(G->done_seq[sa.first], sa.second);
+        G->spare_events.push_back(G->pending.front().ev);
+        G->pending.pop_front();
+    }
+    return LTL4C_OK;
+}
+
+int32_t ltl4c_stream_poll(ltl4c_ctx* ctx, int32_t group, uint32_t stream, uint64_t* next_seq, uint64_t* done_seq) {
+    GroupHost* G = nullptr;
+    int32_t s = get_group(ctx, group, &G);
+    if (s) return s;
+    if (stream >= G->S) return fail(LTL4C_EINVAL, "stream id >= max_streams");
+    HIP_TRY(hipSetDevice(ctx->device));
+    s = drain_pending(G);
+    if (s) return s;
+    if (next_seq) *next_seq = G->next_seq[stream];
+    if (done_seq) *done_seq = G->done_seq[stream];
+    return LTL4C_OK;
+}
+
+int32_t ltl4c_group_stalled(ltl4c_ctx* ctx, int32_t group, uint64_t idle_ns, uint32_t* streams, uint32_t capacity,
+                            uint32_t* n_stalled) {
+    GroupHost* G = nullptr;
+    int32_t s = get_group(ctx, group, &G);
+    if (s) return s;
+    if (!n_stalled || (capacity && !streams)) return fail(LTL4C_EINVAL, "outputs are NULL");
+    const auto now = std::chrono::steady_clock::now();
+    uint32_t n = 0;
+    for (uint32_t i = 0; i < G->S; ++i) {
+        if (!G->open[i]) continue;
+        const uint64_t idle = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(now - G->last_push[i]).count();
+        if (idle >= idle_ns) {
+            if (n < capacity) streams[n] = i;
+            ++n;
+        }
+    }
+    *n_stalled = n;
+    return LTL4C_OK;
+}
+
+int32_t ltl4c_group_read_nodes(ltl4c_ctx* ctx, int32_t group, uint32_t level, uint64_t* d_keys, uint32_t* d_counts,
+                               uint8_t* d_verdict, uint64_t capacity, uint64_t* d_n) {
+    GroupHost* G = nullptr;
+    int32_t s = get_group(ctx, group, &G);
+    if (s) return s;
+    if (level < 1 || level >= G->gs.n_levels) return fail(LTL4C_EINVAL, "level must be 1..n_levels-1");
+    if (!d_keys || !d_counts || !d_verdict || !d_n) return fail(LTL4C_EINVAL, "outputs are NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    s = launch(ctx, "zero", [&] { return launch_set_u32(reinterpret_cast<uint32_t*>(d_n), 0u, ctx->stream); });
+    if (s) return s;
+    s = launch(ctx, "zero", [&] { return launch_set_u32(reinterpret_cast<uint32_t*>(d_n) + 1, 0u, ctx->stream); });
+    if (s) return s;
+    return launch(ctx, "group_nodes", [&] {
+        return launch_group_nodes(G->gs, level, d_keys, d_counts, d_verdict, capacity, d_n, ctx->stream);
+    });
 }
 
 int32_t ltl4c_group_close(ltl4c_ctx* ctx, int32_t group) {
@@ -1234,10 +1484,53 @@ int32_t ltl4c_group_close(ltl4c_ctx* ctx, int32_t group) {
     return LTL4C_OK;
 }
 
-// Shared by both push entry points: chunk i holds sizes[i] records at
-// chunk_ptr[i] (or at d_records + offset when chunk_ptr is NULL).
+// Host memory of a push must be pinned (page-locked, allocated by HIP), so
+// that the copy engine can read it while the host goes on.
+static bool pinned_host(const void* p) {
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeHost;
+}
+
+// Host-side bookkeeping once a push is enqueued: sequence numbers, the
+// completion event poll reads, the time of the stream's last push.
+static int32_t note_push(ltl4c_ctx* ctx, GroupHost* G, const uint32_t* streams, int32_t n_chunks) {
+    GroupHost::Pending pd;
+    const auto now = std::chrono::steady_clock::now();
+    for (int32_t i = 0; i < n_chunks; ++i) {
+        const uint32_t st = streams[i];
+        ++G->next_seq[st];
+        G->last_push[st] = now;
+    }
+    for (int32_t i = 0; i < n_chunks; ++i) {
+        const uint32_t st = streams[i];
+        bool seen = false;
+        for (auto& sa : pd.seq_after)
+            if (sa.first == st) seen = true;
+        if (!seen) pd.seq_after.emplace_back(st, G->next_seq[st]);
+    }
+    if (G->spare_events.empty()) {
+        hipEvent_t e = nullptr;
+        HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        G->spare_events.push_back(e);
+    }
+    pd.ev = G->spare_events.back();
+    G->spare_events.pop_back();
+    HIP_TRY(hipEventRecord(pd.ev, ctx->stream));
+    G->pending.push_back(std::move(pd));
+    return drain_pending(G);
+}
+
+// Shared by the push entry points: chunk i holds sizes[i] records at
+// chunk_ptr[i] (or at d_records + offset when chunk_ptr is NULL).  seqs, when
+// given, are the chunks' sequence numbers (checked against each stream's
+// next one).  from_host: chunk_ptr points to pinned host memory.
 static int32_t group_push_impl(ltl4c_ctx* ctx, int32_t group, const void* d_records, const void* const* chunk_ptr,
-                               const uint64_t* sizes, const uint32_t* streams, int32_t n_chunks) {
+                               const uint64_t* sizes, const uint32_t* streams, int32_t n_chunks,
+                               const uint64_t* seqs = nullptr, bool from_host = false) {
     GroupHost* G = nullptr;
     int32_t s = get_group(ctx, group, &G);
     if (s) return s;
@@ -1247,19 +1540,86 @@ static int32_t group_push_impl(ltl4c_ctx* ctx, int32_t group, const void* d_reco
     bool vec_ok = ctx->layout.record_bytes == 16;
     for (int32_t i = 0; i < n_chunks; ++i) {
         if (streams[i] >= G->S) return fail(LTL4C_EINVAL, "stream id >= max_streams");
+        if (!G->open[streams[i]]) return fail(LTL4C_ESEQ, "push to a stream that is not open");
         if (chunk_ptr && sizes[i] > 0) {
             const uintptr_t a = reinterpret_cast<uintptr_t>(chunk_ptr[i]);
             if (!a || (a & 3)) return fail(LTL4C_EINVAL, "chunk records must be non-NULL and 4-byte aligned");
             if (a & 15) vec_ok = false;
+            if (from_host && !pinned_host(chunk_ptr[i]))
+                return fail(LTL4C_EINVAL, "host chunks must be in pinned memory (hipHostMalloc)");
         }
         n += sizes[i];
+    }
+    if (seqs) {
+        // every chunk must carry its stream's next sequence number: a smaller
+        // one repeats a chunk, a larger one leaves a gap
+        std::vector<std::pair<uint32_t, uint64_t>> expect;
+        for (int32_t i = 0; i < n_chunks; ++i) {
+            uint64_t* e = nullptr;
+            for (auto& x : expect)
+                if (x.first == streams[i]) e = &x.second;
+            if (!e) {
+                expect.emplace_back(streams[i], G->next_seq[streams[i]]);
+                e = &expect.back().second;
+            }
+            if (seqs[i] != *e) {
+                char buf[160];
+                std::snprintf(buf, sizeof buf, "stream %u: chunk sequence number %llu, expected %llu (%s)", streams[i],
+                              (unsigned long long)seqs[i], (unsigned long long)*e,
+                              seqs[i] < *e ? "duplicate" : "gap");
+                return fail(LTL4C_ESEQ, buf);
+            }
+            ++*e;
+        }
     }
     if (n > G->max_batch) return fail(LTL4C_ECAPACITY, "batch larger than the group's max_batch");
     if (!chunk_ptr && n > 0 && (!d_records || (reinterpret_cast<uintptr_t>(d_records) & 3)))
         return fail(LTL4C_EINVAL, "records must be non-NULL and 4-byte aligned");
-    if (n == 0) return LTL4C_OK;
     HIP_TRY(hipSetDevice(ctx->device));
+    if (n == 0) return note_push(ctx, G, streams, n_chunks);
     const hipStream_t st = ctx->stream;
+    if (from_host) {
+        // copy the chunks into one of two device staging buffers on the copy
+        // stream (the buffer's previous push must have consumed it), then run
+        // the push from there: the copy of one push overlaps the kernels of
+        // the one before
+        const uint64_t rb = ctx->layout.record_bytes;
+        if (!G->copy_stream) {
+            const uint64_t bytes = align256(G->max_batch * rb);
+            if (ctx->used + 2 * bytes > ctx->budget)
+                return fail(LTL4C_EADMIT, "host-memory staging does not fit the memory budget");
+            hipError_t e = hipStreamCreateWithFlags(&G->copy_stream, hipStreamNonBlocking);
+            for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+                e = hipMalloc(&G->stage[i], bytes);
+                if (e == hipSuccess) e = hipEventCreateWithFlags(&G->stage_free[i], hipEventDisableTiming);
+                if (e == hipSuccess) e = hipEventCreateWithFlags(&G->stage_ready[i], hipEventDisableTiming);
+            }
+            if (e != hipSuccess) return fail(LTL4C_ENOMEM, std::string("host-memory staging: ") + hipGetErrorString(e));
+            G->stage_bytes = 2 * bytes;
+            G->total_bytes += 2 * bytes;
+            ctx->used += 2 * bytes;
+        }
+        const int b = G->stage_i;
+        uint8_t* dst = G->stage[b];
+        HIP_TRY(hipStreamWaitEvent(G->copy_stream, G->stage_free[b], 0));
+        uint64_t off = 0;
+        for (int32_t i = 0; i < n_chunks;) {
+            // adjacent chunks in host memory go in one copy
+            const uint8_t* src = static_cast<const uint8_t*>(chunk_ptr[i]);
+            uint64_t len = sizes[i] * rb;
+            int32_t j = i + 1;
+            while (j < n_chunks && static_cast<const uint8_t*>(chunk_ptr[j]) == src + len) len += sizes[j++] * rb;
+            if (len) HIP_TRY(hipMemcpyAsync(dst + off, src, len, hipMemcpyHostToDevice, G->copy_stream));
+            off += len;
+            i = j;
+        }
+        HIP_TRY(hipEventRecord(G->stage_ready[b], G->copy_stream));
+        HIP_TRY(hipStreamWaitEvent(st, G->stage_ready[b], 0));
+        d_records = dst;
+        chunk_ptr = nullptr;
+        vec_ok = true;
+        G->stage_i ^= 1;
+    }
     // packed chunk table [offsets n+1][streams n][pad][pointers n] through a
     // pinned ring slot, reused only after its copy has run
     uint32_t* slot = G->chunk_host + (uint64_t)G->ring_i * kChunkTableWords;
@@ -1345,7 +1705,10 @@ static int32_t group_push_impl(ltl4c_ctx* ctx, int32_t group, const void* d_reco
         s = launch(ctx, "group_level", [&] { return launch_group_level(G->gs, (uint32_t)m, st); });
         if (s) return s;
     }
-    return launch(ctx, "group_roots", [&] { return launch_group_roots(G->gs, false, st); });
+    s = launch(ctx, "group_roots", [&] { return launch_group_roots(G->gs, false, st); });
+    if (s) return s;
+    if (from_host) HIP_TRY(hipEventRecord(G->stage_free[G->stage_i ^ 1], st));
+    return note_push(ctx, G, streams, n_chunks);
 }
 
 int32_t ltl4c_group_push(ltl4c_ctx* ctx, int32_t group, const void* d_records, const uint64_t* offsets,
@@ -1365,6 +1728,13 @@ int32_t ltl4c_group_push_chunks(ltl4c_ctx* ctx, int32_t group, const void* const
                                 const uint32_t* streams, int32_t n_chunks) {
     if (!d_chunks) return fail(LTL4C_EINVAL, "chunk pointers are NULL");
     return group_push_impl(ctx, group, nullptr, d_chunks, sizes, streams, n_chunks);
+}
+
+int32_t ltl4c_group_push_seq(ltl4c_ctx* ctx, int32_t group, const void* const* chunks, const uint64_t* sizes,
+                             const uint32_t* streams, const uint64_t* seqs, int32_t n_chunks, int32_t is_device) {
+    if (!chunks) return fail(LTL4C_EINVAL, "chunk pointers are NULL");
+    if (!seqs) return fail(LTL4C_EINVAL, "sequence numbers are NULL");
+    return group_push_impl(ctx, group, nullptr, chunks, sizes, streams, n_chunks, seqs, is_device == 0);
 }
 
 int32_t ltl4c_group_read(ltl4c_ctx* ctx, int32_t group, uint8_t* d_root_verdict, uint64_t* d_root_counts,

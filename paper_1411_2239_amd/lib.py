@@ -81,6 +81,8 @@ SIGNATURES = [
     ("ltl4c_eval", C.c_int32,
      [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(C.c_int32), C.c_int32, C.c_void_p, C.c_uint64,
       C.POINTER(Result)]),
+    ("ltl4c_eval_noalloc", C.c_int32,
+     [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(C.c_int32), C.c_int32, C.POINTER(Result)]),
     ("ltl4c_batch_workspace_bytes", C.c_int32, [C.c_void_p, C.c_uint64, C.c_int32, C.POINTER(C.c_int32), C.c_int32,
                                                 C.POINTER(C.c_uint64)]),
     ("ltl4c_eval_batch", C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_uint64), C.c_int32,
@@ -98,6 +100,18 @@ SIGNATURES = [
     ("ltl4c_group_push_chunks", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_uint64),
                                             C.POINTER(C.c_uint32), C.c_int32]),
     ("ltl4c_group_read", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("ltl4c_group_read_nodes", C.c_int32, [C.c_void_p, C.c_int32, C.c_uint32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.c_uint64, C.c_void_p]),
+    ("ltl4c_group_open_pool", C.c_int32, [C.c_void_p, C.POINTER(C.c_int32), C.c_int32, C.c_uint32, C.c_uint64,
+                                          C.c_uint64, C.POINTER(C.c_int32)]),
+    ("ltl4c_stream_open", C.c_int32, [C.c_void_p, C.c_int32, C.c_uint32, C.c_uint32, C.c_uint64]),
+    ("ltl4c_stream_close", C.c_int32, [C.c_void_p, C.c_int32, C.c_uint32]),
+    ("ltl4c_stream_poll", C.c_int32, [C.c_void_p, C.c_int32, C.c_uint32, C.POINTER(C.c_uint64),
+                                      C.POINTER(C.c_uint64)]),
+    ("ltl4c_group_stalled", C.c_int32, [C.c_void_p, C.c_int32, C.c_uint64, C.POINTER(C.c_uint32), C.c_uint32,
+                                        C.POINTER(C.c_uint32)]),
+    ("ltl4c_group_push_seq", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_uint64),
+                                         C.POINTER(C.c_uint32), C.POINTER(C.c_uint64), C.c_int32, C.c_int32]),
     ("ltl4c_group_snapshot", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_uint64)]),
     ("ltl4c_group_restore", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_uint64]),
     ("ltl4c_set_option", C.c_int32, [C.c_void_p, C.c_int32, C.c_int64]),
@@ -295,6 +309,13 @@ class Context:
     def eval_into(self, records, n_events, props, result, workspace):
         """Enqueue one evaluation; `records` is a device tensor of n_events records."""
         self._bind_stream()
+        res = self._result_desc(result)
+        arr = (C.c_int32 * len(props))(*props)
+        _check(self.lib.ltl4c_eval(self.h, C.c_void_p(records.data_ptr() if n_events else 0), n_events, arr,
+                                   len(props), C.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                   C.byref(res)), "ltl4c_eval")
+
+    def _result_desc(self, result):
         res = Result()
         res.root_verdict = result.root_verdict.data_ptr()
         res.root_counts = result.root_counts.data_ptr()
@@ -312,10 +333,16 @@ class Context:
                 res.node_keys[m] = result.node_keys[m].data_ptr()
                 res.node_counts[m] = result.node_counts[m].data_ptr()
                 res.node_verdict[m] = result.node_verdict[m].data_ptr()
+        return res
+
+    def eval_noalloc_into(self, records, n_events, props, result):
+        """Enqueue one evaluation in the library's own scratch memory (no
+        workspace, no allocation by the library)."""
+        self._bind_stream()
+        res = self._result_desc(result)
         arr = (C.c_int32 * len(props))(*props)
-        _check(self.lib.ltl4c_eval(self.h, C.c_void_p(records.data_ptr() if n_events else 0), n_events, arr,
-                                   len(props), C.c_void_p(workspace.data_ptr()), workspace.numel(),
-                                   C.byref(res)), "ltl4c_eval")
+        _check(self.lib.ltl4c_eval_noalloc(self.h, C.c_void_p(records.data_ptr() if n_events else 0), n_events, arr,
+                                           len(props), C.byref(res)), "ltl4c_eval_noalloc")
 
     def eval(self, records, props, instances=False, nodes=False, capacity=None, timeline=False, events=False):
         """Evaluate and wait; returns an EvalResult of device tensors."""
@@ -398,15 +425,23 @@ class Context:
 
 
 class StreamGroup:
-    """Online monitoring of many streams with device-resident state."""
+    """Online monitoring of many streams with device-resident state.
 
-    def __init__(self, ctx, props, max_streams, max_bindings, max_batch):
+    pool_bindings=None: every stream is admitted at once with max_bindings
+    (ltl4c_group_open).  Otherwise the group is a pool of that many binding
+    slots and streams are admitted one by one with open_stream()."""
+
+    def __init__(self, ctx, props, max_streams, max_bindings, max_batch, pool_bindings=None):
         self.ctx, self.lib, self.props = ctx, ctx.lib, list(props)
         self.max_streams = max_streams
         arr = (C.c_int32 * len(props))(*props)
         g = C.c_int32()
-        _check(self.lib.ltl4c_group_open(ctx.h, arr, len(props), max_streams, max_bindings, max_batch,
-                                         C.byref(g)), "ltl4c_group_open")
+        if pool_bindings is None:
+            _check(self.lib.ltl4c_group_open(ctx.h, arr, len(props), max_streams, max_bindings, max_batch,
+                                             C.byref(g)), "ltl4c_group_open")
+        else:
+            _check(self.lib.ltl4c_group_open_pool(ctx.h, arr, len(props), max_streams, pool_bindings, max_batch,
+                                                  C.byref(g)), "ltl4c_group_open_pool")
         self.id = g.value
         t, dev = ctx.torch, f"cuda:{ctx.device}"
         self.verdict = t.empty(max_streams * len(props), dtype=t.uint8, device=dev)
@@ -431,6 +466,59 @@ class StreamGroup:
         sz = (C.c_uint64 * n)(*[int(x) for x in sizes])
         st = (C.c_uint32 * n)(*[int(x) for x in streams])
         _check(self.lib.ltl4c_group_push_chunks(self.ctx.h, self.id, p, sz, st, n), "ltl4c_group_push_chunks")
+
+    def push_seq(self, ptrs, sizes, streams, seqs, on_device=True):
+        """Enqueue chunks with sequence numbers; ptrs are device addresses, or
+        pinned host addresses when on_device is False."""
+        self.ctx._bind_stream()
+        n = len(streams)
+        p = (C.c_void_p * n)(*[int(x) for x in ptrs])
+        sz = (C.c_uint64 * n)(*[int(x) for x in sizes])
+        st = (C.c_uint32 * n)(*[int(x) for x in streams])
+        sq = (C.c_uint64 * n)(*[int(x) for x in seqs])
+        _check(self.lib.ltl4c_group_push_seq(self.ctx.h, self.id, p, sz, st, sq, n, 1 if on_device else 0),
+               "ltl4c_group_push_seq")
+
+    def open_stream(self, stream, max_bindings, first_seq=0):
+        self.ctx._bind_stream()
+        _check(self.lib.ltl4c_stream_open(self.ctx.h, self.id, stream, max_bindings, first_seq), "ltl4c_stream_open")
+
+    def close_stream(self, stream):
+        self.ctx._bind_stream()
+        _check(self.lib.ltl4c_stream_close(self.ctx.h, self.id, stream), "ltl4c_stream_close")
+
+    def poll(self, stream):
+        """(next sequence number expected, chunks applied on the device)."""
+        a, b = C.c_uint64(), C.c_uint64()
+        _check(self.lib.ltl4c_stream_poll(self.ctx.h, self.id, stream, C.byref(a), C.byref(b)), "ltl4c_stream_poll")
+        return a.value, b.value
+
+    def stalled(self, idle_s):
+        out = (C.c_uint32 * self.max_streams)()
+        n = C.c_uint32()
+        _check(self.lib.ltl4c_group_stalled(self.ctx.h, self.id, int(idle_s * 1e9), out, self.max_streams,
+                                            C.byref(n)), "ltl4c_group_stalled")
+        return list(out[:n.value])
+
+    def read_nodes(self, level, capacity):
+        """(keys [n], counts [P, n, 6], verdict [P, n]) of the level's nodes, sorted by key."""
+        t, dev = self.ctx.torch, f"cuda:{self.ctx.device}"
+        P = len(self.props)
+        keys = t.empty(capacity, dtype=t.int64, device=dev)
+        counts = t.empty(P * capacity * 6, dtype=t.int32, device=dev)
+        verdict = t.empty(P * capacity, dtype=t.uint8, device=dev)
+        n = t.zeros(1, dtype=t.int64, device=dev)
+        self.ctx._bind_stream()
+        _check(self.lib.ltl4c_group_read_nodes(self.ctx.h, self.id, level, C.c_void_p(keys.data_ptr()),
+                                               C.c_void_p(counts.data_ptr()), C.c_void_p(verdict.data_ptr()),
+                                               capacity, C.c_void_p(n.data_ptr())), "ltl4c_group_read_nodes")
+        self.ctx.wait()
+        k = int(n.item())
+        kk = keys[:k].cpu().numpy().view(np.uint64)
+        o = np.argsort(kk, kind="stable")
+        c = counts.view(P, capacity, 6)[:, :k].cpu().numpy()[:, o]
+        v = verdict.view(P, capacity)[:, :k].cpu().numpy()[:, o]
+        return kk[o], c, v
 
     def read(self):
         """(verdict [S, P], counts [S, P, 6], bindings [S]) as numpy, after a wait."""

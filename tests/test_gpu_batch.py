@@ -63,3 +63,35 @@ def test_batch_equals_per_trace_eval():
 
 def test_batch_4096_traces_sampled():
     _check_batch(4096, 100, 20000, 16, seed=4, sample=24)
+
+
+def test_batch_4096_traces_full_size_every_trace():
+    """The benchmark's batch: 4096 traces of 1k-1M events (log-uniform),
+    16 properties; every trace's 16 root verdicts and count vectors against
+    the C oracle on that trace alone (traces spread over the host's cores)."""
+    import torch
+    from oracle import cref, parallel
+    from oracle.run import oracle_property
+    wl, offsets = W.gen_batch(4096)
+    print(f"[case] batch full size: 4096 traces, {wl.n_events} events, 16 properties", flush=True)
+    ctx, ids, rec = lib.open_workload(wl)
+    v, c = ctx.eval_batch(rec, offsets, ids)
+    del rec
+    ctx.close()
+    torch.cuda.empty_cache()
+    lay = wl.layout
+    props = [oracle_property(s, lay) for s in wl.props]
+    raw = wl.raw()
+    rb = lay.record_bytes
+
+    def job(t):
+        a, b = int(offsets[t]), int(offsets[t + 1])
+        return lambda: cref.evaluate_records(raw[a * rb:b * rb], rb, lay.type_offset, lay.type_bytes,
+                                             lay.key_offsets, lay.key_bytes, lay.class_of_type, lay.key_present,
+                                             props)
+    # longest traces first keeps the pool busy to the end
+    order = np.argsort(-np.diff(offsets))
+    res = parallel.evaluate_many([job(int(t)) for t in order])
+    for t, o in zip(order, res):
+        assert np.array_equal(v[t], o.root_verdict), (t, v[t], o.root_verdict)
+        assert np.array_equal(c[t], o.root_counts.astype(np.int64)), t

@@ -24,30 +24,27 @@ def test_large_trace_scaled_down_full_parity():
     ctx.close()
 
 
-def test_large_trace_full_size_sampled():
+def test_large_trace_full_size_every_instance():
+    """500M events, 1M Zipf keys, three properties (3/8/16-state monitors):
+    the root verdicts and counts and every instance's key and verdict against
+    the C oracle run over key-0 partitions on the host's cores (the root
+    counts of disjoint partitions add up)."""
     import torch
+    from oracle import parallel
+    from oracle.run import oracle_property
     print("[case] large full size 500M events", flush=True)
     wl, rec = W.gen_large_trace_device()
-    n = rec.numel() // 16
     ctx = lib.Context(0)
     ctx.set_layout(wl.layout)
     ids = [ctx.add_spec(p) for p in wl.props]
-    r = ctx.eval(rec, ids, instances=True)
+    r = ctx.eval(rec, ids, instances=True, capacity=1 << 21)
     n_inst = int(r.sizes[0].item())
-    keys = r.inst_keys[:n_inst].cpu().numpy().astype(np.uint64)
-    iv = r.inst_verdict.view(len(ids), -1)[:, :n_inst].cpu().numpy()
-    # properties that hold at any size
-    rc = r.root_counts.cpu().numpy().reshape(len(ids), 6)
-    assert (rc.sum(axis=1) == n_inst).all()
-    for p in range(len(ids)):
-        assert np.array_equal(np.bincount(iv[p], minlength=6), rc[p])
-    assert np.all(np.diff(keys.astype(np.int64)) > 0)
-    # a key partition, evaluated by the oracle on exactly its events
-    rv = rec.view(torch.int32).view(-1, 4)
-    sel = (rv[:, 2].to(torch.int64) & 0xFFFFFFFF) % 128 == 0
-    part = rv[sel].cpu().numpy().view(np.uint8).reshape(-1)
-    o = evaluate_workload(wl, records=part)
-    mine = (keys % 128) == 0
-    assert np.array_equal(keys[mine], o.inst_keys[:, 0].astype(np.uint64))
-    assert np.array_equal(iv[:, mine], o.inst_verdict)
+    print(f"[case] large: {n_inst} instances on the device; copying the trace to the host", flush=True)
+    host = rec.cpu().numpy()
+    del rec
+    torch.cuda.empty_cache()
+    props = [oracle_property(s, wl.layout) for s in wl.props]
+    o = parallel.evaluate_partitioned(host, wl.layout, props, n_parts=64)
+    print(f"[case] large: oracle done ({o.inst_keys.shape[0]} instances)", flush=True)
+    compare_full(r, o, len(ids), 1)
     ctx.close()
