@@ -53,34 +53,117 @@ def measured_traffic(kernel, launches_per_step):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def cpu_baseline(wl, min_seconds=10.0):
-    """The plain C oracle on the full trace, repeated until ~min_seconds."""
-    from oracle import cref
+def ci95(xs):
+    """Median, mean and the 95% confidence interval of the mean (Student t),
+    the statistics the paper reports over its 20 replicates (Section 5)."""
+    import numpy as np
+    from scipy import stats
+    a = np.asarray(xs, dtype=np.float64)
+    n = a.size
+    mean = float(a.mean())
+    half = float(stats.t.ppf(0.975, n - 1) * a.std(ddof=1) / np.sqrt(n)) if n > 1 else float("nan")
+    return {"n": int(n), "median": float(np.median(a)), "mean": mean, "ci95": [mean - half, mean + half],
+            "min": float(a.min()), "max": float(a.max())}
+
+
+def cpu_baseline(wl, min_seconds=8.0):
+    """The plain C oracle on the full trace: once on one thread (the paper's
+    single-core variant), once over key-0 partitions on every host thread this
+    process may use (the paper's parallel variant; the partitions are
+    independent subtrees of the quantifier tree).  Each is repeated until
+    ~min_seconds; the all-thread rate is the reported value."""
+    from oracle import cref, parallel
     from oracle.run import oracle_property
     lay = wl.layout
     props = [oracle_property(s, lay) for s in wl.props]
     raw = wl.raw()
     cref.evaluate_records(raw[: lay.record_bytes * 1000], lay.record_bytes, lay.type_offset, lay.type_bytes,
                           lay.key_offsets, lay.key_bytes, lay.class_of_type, lay.key_present, props)
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        cref.evaluate_records(raw, lay.record_bytes, lay.type_offset, lay.type_bytes, lay.key_offsets,
-                              lay.key_bytes, lay.class_of_type, lay.key_present, props)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= min_seconds:
-            break
-    return {"value": reps * wl.n_events / el, "unit": "events/s", "cores": 1, "kind": "oracle",
-            "sample": f"the full {wl.n_events}-event trace, {reps} run(s), single thread, input in host RAM"}
+
+    def timed(fn):
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            fn()
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= min_seconds:
+                return reps, el
+
+    r1, e1 = timed(lambda: cref.evaluate_records(raw, lay.record_bytes, lay.type_offset, lay.type_bytes,
+                                                  lay.key_offsets, lay.key_bytes, lay.class_of_type,
+                                                  lay.key_present, props))
+    threads = parallel.host_threads()
+    rn, en = timed(lambda: parallel.evaluate_partitioned(raw, lay, props, n_parts=4 * threads, threads=threads))
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    return {"value": rn * wl.n_events / en, "unit": "events/s", "cores": threads, "kind": "oracle",
+            "sample": f"the full {wl.n_events}-event trace, input in host RAM: {rn} run(s) over "
+                      f"{4 * threads} key-0 partitions on {threads} threads; single thread {r1} run(s)",
+            "single_thread_events_per_s": r1 * wl.n_events / e1, "threads": threads,
+            "host_cpus_available": nproc, "cpu_model": parallel.cpu_model()}
 
 
-def serving_bench(n_chunks=3000, pool_events=1_000_000, n_streams=64, plain_chunks=300, log=print):
+def config1_bench(reps=30, log=print):
+    """The socket trace (one quantifier, 12-byte records, 1,000 sockets):
+    end-to-end latency of one synchronous call at 100k events, and the
+    paper's trace-size sweep from 16,384 to 8,388,608 events (Section 5),
+    each point the median and 95% CI over `reps` replicates."""
+    import numpy as np
+    import torch
+    from paper_1411_2239_amd import lib, workloads
+
+    log("[bench] config 1: socket trace latency and size sweep")
+    out = {"workload": "A>=0.95 s: socket(s) => G(receive -> F respond), and the literal (G receive) -> "
+                       "(F respond), 1,000 sockets, 12-byte records"}
+    sizes = [100_000] + [1 << k for k in range(14, 24)]
+    sweep = []
+    for n in sizes:
+        wl = workloads.gen_sockets(n_events=n)
+        ctx, ids, rec = lib.open_workload(wl)
+        ws = ctx.workspace(n, ids)
+        res = ctx.alloc_result(len(ids))
+        for _ in range(3):
+            ctx.eval_into(rec, n, ids, res, ws)
+        ctx.wait()
+        torch.cuda.synchronize()
+        wall, dev = [], []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            a.record()
+            ctx.eval_into(rec, n, ids, res, ws)
+            b.record()
+            b.synchronize()
+            wall.append((time.perf_counter() - t0) * 1e6)
+            dev.append(a.elapsed_time(b) * 1e3)
+        ctx.wait()
+        pt = {"events": n, "end_to_end_us": ci95(wall), "device_us": ci95(dev),
+              "events_per_s_median": n / (float(np.median(wall)) * 1e-6)}
+        if n == 100_000:
+            out["latency_100k"] = pt
+        else:
+            sweep.append({"events": n, "end_to_end_us_median": pt["end_to_end_us"]["median"],
+                          "end_to_end_us_ci95": pt["end_to_end_us"]["ci95"],
+                          "device_us_median": pt["device_us"]["median"],
+                          "events_per_s_median": pt["events_per_s_median"]})
+        ctx.close()
+    out["sweep"] = sweep
+    return out
+
+
+def serving_bench(n_chunks=100_000, pool_events=1_000_000, n_streams=64, plain_chunks=300, log=print):
     """Online monitoring under open-loop Poisson arrivals (2e9 events/s offered,
     64 streams, chunks of 4k-256k events, 100k bindings per stream).
 
     Batched: every push takes all chunks that have arrived (at most two pushes
-    in flight).  Plain: one synchronous push per chunk, in arrival order.
-    Latency = verdict visible (push completed) - chunk arrival."""
+    in flight), with per-stream sequence numbers.  Two ingestion paths: chunks
+    already in device memory, and chunks in pinned host memory that the
+    library copies to the device on its own copy stream (the realistic path:
+    a log shipper hands over host buffers).  Plain: one synchronous push per
+    chunk, in arrival order.  Latency = verdict visible (push completed) -
+    chunk arrival."""
     import collections
     import gc
     import numpy as np
@@ -90,8 +173,10 @@ def serving_bench(n_chunks=3000, pool_events=1_000_000, n_streams=64, plain_chun
     log("[bench] serving: generating stream pools")
     lay = workloads.serving_layout(n_streams)
     spec = workloads.user_request_properties()[0]
-    pools = [torch.from_numpy(workloads.gen_serving_pool(s, pool_events).view(np.uint8)).to("cuda:0")
-             for s in range(n_streams)]
+    host_pools = [workloads.gen_serving_pool(s, pool_events).view(np.uint8) for s in range(n_streams)]
+    pools = {"device": [torch.from_numpy(p).to("cuda:0") for p in host_pools],
+             "pinned_host": [torch.from_numpy(p).pin_memory() for p in host_pools]}
+    del host_pools
     arr, streams, sizes = workloads.serving_schedule(n_chunks, n_streams)
     ctx = lib.Context(0)
     ctx.set_layout(lay)
@@ -99,23 +184,26 @@ def serving_bench(n_chunks=3000, pool_events=1_000_000, n_streams=64, plain_chun
     rb = lay.record_bytes
     max_batch = 1 << 24
 
-    def chunk_ptrs():
+    def chunk_ptrs(mode):
         pos = [0] * n_streams
         out = []
         for st, sz in zip(streams, sizes):
             if pos[st] + sz > pool_events:
                 pos[st] = 0
-            out.append(pools[st].data_ptr() + pos[st] * rb)
+            out.append(pools[mode][st].data_ptr() + pos[st] * rb)
             pos[st] += sz
         return out
 
-    ptrs = chunk_ptrs()
+    ptrs = {m: chunk_ptrs(m) for m in pools}
     torch.cuda.synchronize()
 
     pushes = [0]
 
-    def run_batched(grp, count, arrivals=None):
+    def run_batched(grp, count, mode, arrivals=None):
         arr_ = arr if arrivals is None else arrivals
+        p_ = ptrs[mode]
+        on_dev = mode == "device"
+        seq = [0] * n_streams
         lat = np.zeros(count)
         inflight = collections.deque()
         i, done_events = 0, 0
@@ -134,7 +222,12 @@ def serving_bench(n_chunks=3000, pool_events=1_000_000, n_streams=64, plain_chun
                 while j < count and arr_[j] <= now and j - i < 4096 and tot + sizes[j] <= max_batch:
                     tot += int(sizes[j])
                     j += 1
-                grp.push_chunks(ptrs[i:j], sizes[i:j], streams[i:j])
+                sq = []
+                for k in range(i, j):
+                    st = int(streams[k])
+                    sq.append(seq[st])
+                    seq[st] += 1
+                grp.push_seq(p_[i:j], sizes[i:j], streams[i:j], sq, on_device=on_dev)
                 pushes[0] += 1
                 ev = torch.cuda.Event()
                 ev.record()
@@ -151,74 +244,85 @@ def serving_bench(n_chunks=3000, pool_events=1_000_000, n_streams=64, plain_chun
         for i in range(count):
             while time.perf_counter() - t0 < arr[i]:
                 pass
-            grp.push_chunks(ptrs[i:i + 1], sizes[i:i + 1], streams[i:i + 1])
+            grp.push_chunks(ptrs["device"][i:i + 1], sizes[i:i + 1], streams[i:i + 1])
             torch.cuda.synchronize()
             lat[i] = time.perf_counter() - t0 - arr[i]
             total += int(sizes[i])
         return lat, total, time.perf_counter() - t0
 
-    grp = lib.StreamGroup(ctx, [pid], n_streams, 100_000, max_batch)
-    log("[bench] serving: warmup")
-    run_batched(grp, min(200, n_chunks))
-    grp.close()
-    # three runs of the schedule, each on a fresh group, with Python's garbage
-    # collector paused; the run with the median p99 is reported (a host-side
-    # stall of the open-loop driver shows up as latency of every chunk that
-    # arrives meanwhile)
-    runs = []
-    for rep in range(3):
-        grp = lib.StreamGroup(ctx, [pid], n_streams, 100_000, max_batch)
-        log(f"[bench] serving: batched, {n_chunks} chunks, run {rep + 1}/3")
-        gc.disable()
-        try:
-            lat, ev, el = run_batched(grp, n_chunks)
-        finally:
-            gc.enable()
-        v, c, b = grp.read()
-        runs.append({"events_per_s": ev / el, "chunks": n_chunks, "events": ev, "seconds": el,
-                     "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                     "live_bindings": int(b.sum()), "pushes": pushes[0]})
+    def group():
+        return lib.StreamGroup(ctx, [pid], n_streams, 100_000, max_batch)
+
+    out = {"workload": f"{n_streams} streams, 100k bindings each, chunks 4k-256k log-uniform, Poisson arrivals",
+           "offered_events_per_s": float(sizes[:n_chunks].sum() / arr[n_chunks - 1])}
+    for mode in ("device", "pinned_host"):
+        grp = group()
+        log(f"[bench] serving ({mode}): warmup")
+        run_batched(grp, min(2000, n_chunks), mode)
         grp.close()
-    batched = sorted(runs, key=lambda r: r["p99_ms"])[1]
-    batched["p99_ms_of_runs"] = [r["p99_ms"] for r in runs]
-    # per-kernel time of the same batched schedule, in a separate profiled run
-    grp = lib.StreamGroup(ctx, [pid], n_streams, 100_000, max_batch)
-    ctx.profile(True)
-    ctx.profile_reset()
-    run_batched(grp, n_chunks)
-    prof = ctx.profile_read()
-    ctx.profile(False)
-    batched["kernel_ms"] = {k: round(x[0], 3) for k, x in prof.items()}
-    batched["profiled_pushes"] = pushes[0]
-    grp.close()
-    # capacity: every chunk available at once (closed loop), same pushes;
-    # median of three runs
-    caps = []
-    for rep in range(3):
-        grp = lib.StreamGroup(ctx, [pid], n_streams, 100_000, max_batch)
-        gc.disable()
-        try:
-            _, ev_c, el_c = run_batched(grp, n_chunks, np.zeros(n_chunks))
-        finally:
-            gc.enable()
-        caps.append(ev_c / el_c)
-        grp.close()
-    batched["capacity_events_per_s"] = sorted(caps)[1]
-    batched["capacity_events_per_s_of_runs"] = caps
-    batched["capacity_pushes"] = pushes[0]
-    grp = lib.StreamGroup(ctx, [pid], n_streams, 100_000, max_batch)
+        # three runs of the schedule, each on a fresh group, with Python's
+        # garbage collector paused; the run with the median p99 is reported (a
+        # host-side stall of the open-loop driver shows up as latency of every
+        # chunk that arrives meanwhile)
+        runs = []
+        for rep in range(3):
+            grp = group()
+            log(f"[bench] serving ({mode}): batched, {n_chunks} chunks, run {rep + 1}/3")
+            gc.disable()
+            try:
+                lat, ev, el = run_batched(grp, n_chunks, mode)
+            finally:
+                gc.enable()
+            v, c, b = grp.read()
+            runs.append({"events_per_s": ev / el, "chunks": n_chunks, "events": ev, "seconds": el,
+                         "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                         "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                         "live_bindings": int(b.sum()), "pushes": pushes[0]})
+            grp.close()
+        res = sorted(runs, key=lambda r: r["p99_ms"])[1]
+        res["p99_ms_of_runs"] = [r["p99_ms"] for r in runs]
+        res["p50_ms_of_runs"] = [r["p50_ms"] for r in runs]
+        if mode == "device":
+            # per-kernel time of the same schedule, in a separate profiled run
+            grp = group()
+            ctx.profile(True)
+            ctx.profile_reset()
+            run_batched(grp, n_chunks, mode)
+            prof = ctx.profile_read()
+            ctx.profile(False)
+            res["kernel_ms"] = {k: round(x[0], 3) for k, x in prof.items()}
+            res["profiled_pushes"] = pushes[0]
+            grp.close()
+        # capacity: every chunk available at once (closed loop); median of three
+        caps = []
+        for rep in range(3):
+            grp = group()
+            gc.disable()
+            try:
+                _, ev_c, el_c = run_batched(grp, n_chunks, mode, np.zeros(n_chunks))
+            finally:
+                gc.enable()
+            caps.append(ev_c / el_c)
+            grp.close()
+        res["capacity_events_per_s"] = sorted(caps)[1]
+        res["capacity_events_per_s_of_runs"] = caps
+        res["capacity_pushes"] = pushes[0]
+        out["batched_" + mode] = res
+    grp = group()
     log(f"[bench] serving: plain, {plain_chunks} chunks")
     lat_p, ev_p, el_p = run_plain(grp, plain_chunks)
     plain = {"events_per_s": ev_p / el_p, "chunks": plain_chunks, "events": ev_p, "seconds": el_p,
-             "p50_ms": float(np.percentile(lat_p, 50) * 1e3), "p99_ms": float(np.percentile(lat_p, 99) * 1e3)}
+             "p50_ms": float(np.percentile(lat_p, 50) * 1e3), "p99_ms": float(np.percentile(lat_p, 99) * 1e3),
+             "ingestion": "device"}
     grp.close()
     ctx.close()
-    offered = float(sizes[:n_chunks].sum() / arr[n_chunks - 1])
-    return {"workload": f"{n_streams} streams, 100k bindings each, chunks 4k-256k log-uniform, Poisson arrivals, "
-                        f"device-resident chunk pools",
-            "offered_events_per_s": offered, "batched": batched, "plain_per_chunk": plain,
-            "batched_vs_plain_throughput": batched["events_per_s"] / plain["events_per_s"],
-            "capacity_vs_plain_throughput": batched["capacity_events_per_s"] / plain["events_per_s"]}
+    out["plain_per_chunk"] = plain
+    out["batched"] = out["batched_device"]
+    for mode in ("device", "pinned_host"):
+        r = out["batched_" + mode]
+        out[f"{mode}_sustained_vs_plain_throughput"] = r["events_per_s"] / plain["events_per_s"]
+        out[f"{mode}_capacity_vs_plain_throughput"] = r["capacity_events_per_s"] / plain["events_per_s"]
+    return out
 
 
 def batching_bench(n_traces=4096, reps=3, log=print):
@@ -398,6 +502,8 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 500M-event single-trace section")
     ap.add_argument("--no-predicates", action="store_true", help="skip the data-predicate section")
     ap.add_argument("--no-timeline", action="store_true", help="skip the verdict-timeline section")
+    ap.add_argument("--no-config1", action="store_true", help="skip the socket-trace latency and size sweep")
+    ap.add_argument("--serving-chunks", type=int, default=100_000)
     ap.add_argument("--large-events", type=int, default=500_000_000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")
@@ -441,6 +547,24 @@ def main():
     ms_step = el / args.steps * 1e3
     value = n * args.steps / el
 
+    # replicates for the statistics (Section 5 reports 20 replicates with 95%
+    # confidence intervals): every step bracketed by HIP events on the stream
+    # the library launches on
+    n_rep = max(20, min(args.steps, 100))
+    log(f"[bench] {n_rep} replicate steps for median and 95% CI")
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_rep)]
+    torch.cuda.synchronize()
+    for i in range(n_rep):
+        evs[i][0].record()
+        ctx.eval_into(copies[i % 4], n, ids, res, ws)
+        evs[i][1].record()
+    torch.cuda.synchronize()
+    ctx.wait()
+    step_ms = [a.elapsed_time(b) for a, b in evs]
+    step_stats = ci95(step_ms)
+    step_stats["unit"] = "ms per step"
+    step_stats["events_per_s_median"] = n / (step_stats["median"] * 1e-3)
+
     # per-kernel durations from HIP events recorded on the library's stream
     log("[bench] per-kernel timing pass")
     ctx.profile(True)
@@ -470,9 +594,12 @@ def main():
     root = res.root_verdict.cpu().numpy().tolist()
     counts = res.root_counts.cpu().numpy().reshape(len(ids), 6).tolist()
 
+    config1 = None
+    if not args.no_config1:
+        config1 = config1_bench(log=log)
     serving = None
     if not args.no_serving:
-        serving = serving_bench(log=log)
+        serving = serving_bench(n_chunks=args.serving_chunks, log=log)
     batching = None
     if not args.no_batching:
         batching = batching_bench(args.batch_traces, log=log)
@@ -507,8 +634,10 @@ def main():
                      "traffic": measured_traffic(dom, prof[dom][1] / args.steps)},
         "scan_reduce_path": {"kernels": ["scan", "count"], "ms_per_step": scan_path_s * 1e3,
                              "frac_of_hbm_peak": scan_frac},
+        "step_stats": step_stats,
         "per_kernel": per_kernel,
         "root_verdict": [lib.VERDICT_NAMES[v] for v in root], "root_counts": counts,
+        "config1_sockets": config1,
         "serving": serving,
         "batching": batching,
         "large_trace": large,
@@ -516,6 +645,7 @@ def main():
         "verdict_timeline": timeline,
         "batched_vs_plain_speedup": batching["batched_vs_plain"] if batching else None,
         "p99_chunk_latency_ms": serving["batched"]["p99_ms"] if serving else None,
+        "p99_chunk_latency_ms_pinned_host": serving["batched_pinned_host"]["p99_ms"] if serving else None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

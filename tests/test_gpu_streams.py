@@ -58,7 +58,7 @@ def test_sequence_numbers_reject_gaps_and_duplicates():
     seq = [1, 12, 20]
     _check(grp, traces, [traces[s].records[:pos[s]] for s in range(3)])
     # a duplicate (stream 1 repeats 11) and a gap (stream 2 skips 20) are refused whole
-    for bad in ([[0, 1], [1, 12]], [[2, 21]], [[0, 1], [2, 20], [2, 22]]):
+    for bad in ([[0, 1], [1, 11]], [[2, 21]], [[0, 1], [2, 20], [2, 22]]):
         ptrs = [dev[s].data_ptr() + pos[s] * rb for s, _ in bad]
         with pytest.raises(lib.LTL4CError) as e:
             grp.push_seq(ptrs, [100] * len(bad), [s for s, _ in bad], [q for _, q in bad])
