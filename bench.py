@@ -325,6 +325,116 @@ def serving_bench(n_chunks=100_000, pool_events=1_000_000, n_streams=64, plain_c
     return out
 
 
+def pin_default_schedule(ctx, on):
+    """Pin the default tiles (on) or return to the tuned table (off)."""
+    from paper_1411_2239_amd import lib
+    ctx.set_option(lib.OPT_SORT_TILE, 1 if on else -1)
+    ctx.set_option(lib.OPT_SCAN_TILE, 3 if on else -1)
+
+
+def tune_all(out_path, log=print):
+    """Tune the kernel schedules on the benchmark's workloads (10M-event
+    user/request trace, the 100k-event socket trace and its size sweep, the
+    500M-event trace, the 4096-trace batch) and save the table to out_path."""
+    import numpy as np
+    import torch
+    from paper_1411_2239_amd import lib, workloads
+
+    ctx = lib.Context(0, use_tuned=False)
+    found = []
+
+    def tune(wl, rec, reps, offsets=None, label=""):
+        ctx.set_layout(wl.layout)
+        ids = [ctx.add_spec(p) for p in wl.props]
+        t = ctx.tune(rec, ids, n_events=wl.n_events if offsets is None else None, offsets=offsets, reps=reps)
+        t["workload"] = label
+        found.append(t)
+        log(f"[bench] tune {label}: {t}")
+
+    for k in range(14, 24):
+        wl = workloads.gen_sockets(n_events=1 << k)
+        tune(wl, torch.from_numpy(np.ascontiguousarray(wl.raw())).to("cuda:0"), 15, label=f"sockets {1 << k}")
+    wl = workloads.gen_sockets(n_events=100_000)
+    tune(wl, torch.from_numpy(np.ascontiguousarray(wl.raw())).to("cuda:0"), 15, label="sockets 100000")
+    wl = workloads.gen_user_requests()
+    tune(wl, torch.from_numpy(np.ascontiguousarray(wl.raw())).to("cuda:0"), 9, label="user/request 10M")
+    wl = workloads.gen_chunk_uploads(10_000_000, n_preds=2)
+    tune(wl, torch.from_numpy(np.ascontiguousarray(wl.raw())).to("cuda:0"), 9, label="chunk uploads 10M")
+    wl = workloads.gen_prop_trace(10_000_000, 100_000, 1.1, seed=7, props=workloads.timeline_properties())
+    tune(wl, torch.from_numpy(np.ascontiguousarray(wl.raw())).to("cuda:0"), 9, label="timeline trace 10M")
+    torch.cuda.empty_cache()
+    wl, rec = workloads.gen_large_trace_device()
+    tune(wl, rec, 3, label="large trace 500M")
+    del rec
+    torch.cuda.empty_cache()
+    wl, offsets = workloads.gen_batch(4096)
+    tune(wl, torch.from_numpy(np.ascontiguousarray(wl.raw())).to("cuda:0"), 2, offsets=offsets,
+         label="batch 4096 traces")
+    torch.cuda.empty_cache()
+    ctx.save_schedules(out_path)
+    ctx.close()
+    return found
+
+
+def graphs_bench(reps=30, log=print):
+    """One captured kernel sequence (hipGraph) per call against the same
+    calls enqueued launch by launch: the socket trace (100k events, latency
+    bound), and a fixed-shape push of 64 device chunks of 16,384 events to a
+    64-stream group.  Every call is synchronised; medians of `reps`."""
+    import numpy as np
+    import torch
+    from paper_1411_2239_amd import lib, workloads
+
+    log("[bench] graphs: captured vs enqueued calls")
+    out = {}
+    wl = workloads.gen_sockets(n_events=100_000)
+    ctx, ids, rec = lib.open_workload(wl)
+    n = wl.n_events
+    ws = ctx.workspace(n, ids)
+    res = ctx.alloc_result(len(ids))
+    g = ctx.graph_eval(rec, n, ids, res, ws)
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            t.append((time.perf_counter() - t0) * 1e6)
+        return ci95(t)
+
+    eager = timed(lambda: ctx.eval_into(rec, n, ids, res, ws))
+    graph = timed(lambda: ctx.graph_launch(g))
+    ctx.wait()
+    out["sockets_100k"] = {"enqueued_us": eager, "graph_us": graph,
+                           "graph_speedup_median": eager["median"] / graph["median"]}
+    ctx.graph_destroy(g)
+    ctx.close()
+
+    lay = workloads.serving_layout(64)
+    ctx = lib.Context(0)
+    ctx.set_layout(lay)
+    pid = ctx.add_spec(workloads.user_request_properties()[0])
+    chunk = 16_384
+    pools = [torch.from_numpy(workloads.gen_serving_pool(s, chunk).view(np.uint8)).to("cuda:0") for s in range(64)]
+    ptrs = [p.data_ptr() for p in pools]
+    grp = lib.StreamGroup(ctx, [pid], 64, 100_000, 64 * chunk)
+    gp = grp.capture_push(ptrs, [chunk] * 64, list(range(64)))
+    eager = timed(lambda: grp.push_chunks(ptrs, [chunk] * 64, list(range(64))))
+    graph = timed(lambda: ctx.graph_launch(gp))
+    ctx.wait()
+    out["push_64x16k"] = {"enqueued_us": eager, "graph_us": graph,
+                          "graph_speedup_median": eager["median"] / graph["median"],
+                          "events_per_push": 64 * chunk}
+    ctx.graph_destroy(gp)
+    grp.close()
+    ctx.close()
+    return out
+
+
 def batching_bench(n_traces=4096, reps=3, log=print):
     """Many traces x 16 properties in one ltl4c_eval_batch call against the
     plain path (one ltl4c_eval per trace, synchronised each time)."""
@@ -350,6 +460,29 @@ def batching_bench(n_traces=4096, reps=3, log=print):
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / reps
     ctx.wait()
+    # the same pass under the default tiles, and captured as one graph
+    pin_default_schedule(ctx, True)
+    ws_d = ctx.batch_workspace(n, n_traces, ids)
+    ctx.eval_batch_into(rec, offsets, ids, v, c, ws_d)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.eval_batch_into(rec, offsets, ids, v, c, ws_d)
+    torch.cuda.synchronize()
+    el_default = (time.perf_counter() - t0) / reps
+    ctx.wait()
+    pin_default_schedule(ctx, False)
+    ws = ctx.batch_workspace(n, n_traces, ids)
+    g = ctx.graph_eval_batch(rec, offsets, ids, v, c, ws)
+    ctx.graph_launch(g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.graph_launch(g)
+    torch.cuda.synchronize()
+    el_graph = (time.perf_counter() - t0) / reps
+    ctx.wait()
+    ctx.graph_destroy(g)
     ctx.profile(True)
     ctx.profile_reset()
     ctx.eval_batch_into(rec, offsets, ids, v, c, ws)
@@ -377,6 +510,8 @@ def batching_bench(n_traces=4096, reps=3, log=print):
     return {"workload": f"{n_traces} traces, lengths log-uniform 1k-1M, 16 properties with 3-16-state monitors",
             "events": n, "traces": n_traces, "properties": len(ids),
             "batched_events_per_s": n / el, "batched_ms": el * 1e3,
+            "schedules_loaded": ctx.schedules_loaded if hasattr(ctx, "schedules_loaded") else 0,
+            "batched_ms_default_schedule": el_default * 1e3, "batched_ms_graph": el_graph * 1e3,
             "plain_events_per_s": n / el_plain, "plain_ms": el_plain * 1e3,
             "batched_vs_plain": el_plain / el, "last_trace_plain_equals_batched": same,
             "batched_kernel_ms": {k: round(x[0], 3) for k, x in prof.items()}}
@@ -504,6 +639,9 @@ def main():
     ap.add_argument("--no-timeline", action="store_true", help="skip the verdict-timeline section")
     ap.add_argument("--no-config1", action="store_true", help="skip the socket-trace latency and size sweep")
     ap.add_argument("--serving-chunks", type=int, default=100_000)
+    ap.add_argument("--no-graphs", action="store_true", help="skip the captured-graph section")
+    ap.add_argument("--tune", metavar="PATH", default=None,
+                    help="tune the kernel schedules on the benchmark workloads, save the table to PATH and exit")
     ap.add_argument("--large-events", type=int, default=500_000_000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")
@@ -518,6 +656,10 @@ def main():
     from paper_1411_2239_amd import lib, workloads
 
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    if args.tune:
+        found = tune_all(args.tune, log=log)
+        print(json.dumps({"tuned": found, "saved": args.tune}))
+        return
     log("[bench] generating the user/request trace")
     wl = workloads.gen_user_requests(n_events=args.events)
     ctx, ids, rec0 = lib.open_workload(wl)
@@ -564,6 +706,24 @@ def main():
     step_stats = ci95(step_ms)
     step_stats["unit"] = "ms per step"
     step_stats["events_per_s_median"] = n / (step_stats["median"] * 1e-3)
+    # the same steps under the default tiles (the table is tuned per shape)
+    pin_default_schedule(ctx, True)
+    ws_d = ctx.workspace(n, ids)
+    for i in range(3):
+        ctx.eval_into(copies[i % 4], n, ids, res, ws_d)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ctx.eval_into(copies[i % 4], n, ids, res, ws_d)
+    torch.cuda.synchronize()
+    ms_default = (time.perf_counter() - t0) / args.steps * 1e3
+    ctx.wait()
+    pin_default_schedule(ctx, False)
+    if args.sort_tile is not None:
+        ctx.set_option(lib.OPT_SORT_TILE, args.sort_tile)
+    if args.scan_tile is not None:
+        ctx.set_option(lib.OPT_SCAN_TILE, args.scan_tile)
+    ws = ctx.workspace(n, ids)
 
     # per-kernel durations from HIP events recorded on the library's stream
     log("[bench] per-kernel timing pass")
@@ -594,6 +754,9 @@ def main():
     root = res.root_verdict.cpu().numpy().tolist()
     counts = res.root_counts.cpu().numpy().reshape(len(ids), 6).tolist()
 
+    graphs = None
+    if not args.no_graphs:
+        graphs = graphs_bench(log=log)
     config1 = None
     if not args.no_config1:
         config1 = config1_bench(log=log)
@@ -635,6 +798,9 @@ def main():
         "scan_reduce_path": {"kernels": ["scan", "count"], "ms_per_step": scan_path_s * 1e3,
                              "frac_of_hbm_peak": scan_frac},
         "step_stats": step_stats,
+        "schedules_loaded": ctx.schedules_loaded,
+        "ms_per_step_default_schedule": ms_default,
+        "graphs": graphs,
         "per_kernel": per_kernel,
         "root_verdict": [lib.VERDICT_NAMES[v] for v in root], "root_counts": counts,
         "config1_sockets": config1,

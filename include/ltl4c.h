@@ -418,8 +418,78 @@ enum { LTL4C_OPT_SORT_TILE = 0, LTL4C_OPT_SCAN_TILE = 1 };
 /* LTL4C_OPT_SCAN_TILE: map-scan tile of 0 = 256 threads x 16 words,
  * 1 = 512 x 16, 2 = 1024 x 16, or 3 = per launch (default): 1024 x 16 when a
  * launch's maps take at most 4 dwords per event (one or two properties of at
- * most 8 states, or one of at most 16), else 512 x 16. */
+ * most 8 states, or one of at most 16), else 512 x 16.
+ * A value pins that tile: tuned schedules (below) no longer override it;
+ * -1 returns the option to its default and unpins it. */
 int32_t ltl4c_set_option(ltl4c_ctx *ctx, int32_t option, int64_t value);
+
+/* ---- autotuned schedules ------------------------------------------------
+ *
+ * A schedule is the pair (radix-pass tile, map-scan tile) of the options
+ * above.  The context keeps a table of tuned schedules keyed by a shape
+ * class: single trace or batch of traces, packed key bits (with a batch's
+ * trace id; they fix the radix passes), number of properties, whether some
+ * monitor has more than 8 states, tree levels, and floor(log2(events)).
+ * ltl4c_eval, ltl4c_eval_batch and the graph captures below run the tuned
+ * schedule of their class (the entry of the nearest size within a factor of
+ * 4) unless a tile is pinned; the workspace queries cover both the context's
+ * own schedule and the tuned one, and a workspace too small for the tuned
+ * one runs the context's own.  Results are identical under every schedule. */
+typedef struct {
+    int32_t sort_tile, scan_tile;     /* the chosen schedule */
+    double tuned_us, default_us;      /* median time of one call under it and under the default */
+    int32_t candidates;               /* schedules timed (those whose workspace fit) */
+} ltl4c_tuned;
+
+/* Workspace that every schedule of this call fits (the one to pass to
+ * ltl4c_tune).  offsets == NULL: one trace of n_events; else a batch of
+ * n_traces traces given by host offsets as in ltl4c_eval_batch. */
+int32_t ltl4c_tune_workspace_bytes(ltl4c_ctx *ctx, uint64_t n_events, const uint64_t *offsets, int32_t n_traces,
+                                   const int32_t *props, int32_t n_props, uint64_t *bytes);
+/* Time the schedules on the caller's own data (device records, as for
+ * ltl4c_eval / ltl4c_eval_batch) and record the fastest for its shape class,
+ * replacing an entry of the same class and size.  Each candidate runs once to
+ * warm up, then `reps` (1..1000) times; the median counts.  Coordinate
+ * descent: every radix tile under the default scan tile, then every scan tile
+ * under the best radix tile; a candidate must beat the best so far by 1 %.
+ * Candidates whose workspace exceeds ws_bytes are skipped.  Synchronous:
+ * returns when the timing is done; result may be NULL. */
+int32_t ltl4c_tune(ltl4c_ctx *ctx, const void *d_records, uint64_t n_events, const uint64_t *offsets,
+                   int32_t n_traces, const int32_t *props, int32_t n_props, void *d_workspace,
+                   uint64_t workspace_bytes, int32_t reps, ltl4c_tuned *result);
+/* Write the table as JSON, keyed by the device's architecture name (e.g.
+ * "gfx950"); load such a file, ignoring it when it was tuned on another
+ * architecture (*n_loaded = 0), replacing entries of the same class and
+ * size; clear the table. */
+int32_t ltl4c_schedule_save(ltl4c_ctx *ctx, const char *path);
+int32_t ltl4c_schedule_load(ltl4c_ctx *ctx, const char *path, int32_t *n_loaded);
+int32_t ltl4c_schedule_clear(ltl4c_ctx *ctx);
+
+/* ---- graphs: captured kernel sequences -----------------------------------
+ *
+ * The same work as ltl4c_eval, ltl4c_eval_batch or ltl4c_group_push_chunks,
+ * captured once into a HIP graph instead of run; ltl4c_graph_launch replays
+ * it on the context's stream, one launch for the whole kernel sequence.
+ * Arguments are validated as by the plain call, and the plan and the trace /
+ * chunk table are copied to the device at capture (the graph owns its own
+ * table), so a replay reads only device memory: the same record addresses,
+ * outputs and workspace as at capture, whose contents may change between
+ * replays (new records in the same buffers).  A group-push graph takes device
+ * chunks only; every replay counts as one push of its chunks (sequence
+ * numbers advance, ltl4c_stream_poll sees it) and needs its streams open.
+ * Replays are ordered on the context's stream like any other call; a replay
+ * and a plain call using one workspace must not overlap. */
+int32_t ltl4c_graph_eval(ltl4c_ctx *ctx, const void *d_records, uint64_t n_events, const int32_t *props,
+                         int32_t n_props, void *d_workspace, uint64_t workspace_bytes, const ltl4c_result *out,
+                         int32_t *graph);
+int32_t ltl4c_graph_eval_batch(ltl4c_ctx *ctx, const void *d_records, const uint64_t *offsets, int32_t n_traces,
+                               const int32_t *props, int32_t n_props, void *d_workspace, uint64_t workspace_bytes,
+                               uint8_t *d_root_verdicts, uint64_t *d_root_counts, int32_t *graph);
+int32_t ltl4c_graph_group_push(ltl4c_ctx *ctx, int32_t group, const void *const *d_chunks, const uint64_t *sizes,
+                               const uint32_t *streams, int32_t n_chunks, int32_t *graph);
+int32_t ltl4c_graph_launch(ltl4c_ctx *ctx, int32_t graph);
+/* Synchronises the context's stream, then frees the graph. */
+int32_t ltl4c_graph_destroy(ltl4c_ctx *ctx, int32_t graph);
 
 /* ---- profiling: per-kernel time of the enqueued work ------------------- */
 

@@ -262,9 +262,11 @@ hipError_t launch_sort_pass(const SortPassArgs& a, int variant, uint32_t digit_b
 uint32_t sort_threads(int variant);   // threads per block of a sort variant
 uint32_t sort_tile(int variant);      // words per radix tile of a sort variant
 constexpr int kSortVariants = 7;
+constexpr int kDefaultSortVariant = 1;     // 512 threads x 16 words
 hipError_t launch_scan(const ScanArgs& a, int variant, hipStream_t s);
 uint32_t scan_tile(int variant);      // words per scan tile of a scan variant
 constexpr int kScanVariants = 4;
+constexpr int kDefaultScanVariant = 3;     // tile chosen per launch
 hipError_t launch_count(const CountArgs& a, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
 hipError_t launch_inst_conclusive(const InstConclusiveArgs& a, hipStream_t s);

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -87,8 +88,33 @@ hipError_t scratch_address(int device, uint8_t** out) {
 }
 }  // namespace
 
+// One tuned kernel schedule (radix-pass tile, map-scan tile) of a shape class.
+struct SchedEntry {
+    int kind = 0;                      // 0: one trace (ltl4c_eval), 1: a batch of traces (ltl4c_eval_batch)
+    uint32_t key_bits = 0;             // packed key bits (with the trace id of a batch)
+    uint32_t n_props = 0;
+    uint32_t big = 0;                  // 1 when some monitor has more than 8 states
+    uint32_t levels = 0;               // quantifier levels (plus the trace level of a batch)
+    uint32_t log2n = 0;                // floor(log2(events))
+    int sort = 1, scan = 3;
+    double us = 0.0, default_us = 0.0; // measured median of the chosen and of the default schedule
+};
+
+// A captured kernel sequence (hipGraph) and what its replay must also do on the host.
+struct GraphHost {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void* table_dev = nullptr;         // the graph's own chunk / trace table
+    int32_t group = -1;                // a group push: the group and its chunks' streams
+    std::vector<uint32_t> streams;
+};
+
 struct ltl4c_ctx {
     int device = 0;
+    std::vector<SchedEntry> sched;     // tuned schedules (ltl4c_tune, ltl4c_schedule_load)
+    bool pin_sort = false, pin_scan = false;   // set by ltl4c_set_option: tuned schedules do not override
+    hipStream_t cap_stream = nullptr;  // private stream for graph capture
+    std::vector<GraphHost*> graphs;
     uint8_t* scratch = nullptr;        // this device's copy of `scratch`
     bool no_timing = false;            // launches without profiling events (no-allocation calls)
     hipStream_t stream = nullptr;
@@ -98,8 +124,8 @@ struct ltl4c_ctx {
     std::vector<ltl4c_property> props;
     std::map<std::vector<int32_t>, Plan*> plans;
     uint32_t* err_dev = nullptr;
-    int sort_variant = 1;
-    int scan_variant = 3;
+    int sort_variant = kDefaultSortVariant;
+    int scan_variant = kDefaultScanVariant;
     uint64_t budget = ~0ull, used = 0;
     uint32_t* batch_chunk_dev = nullptr;      // trace table of ltl4c_eval_batch
     uint32_t* batch_chunk_host = nullptr;     // pinned staging for it
@@ -741,6 +767,14 @@ int32_t ltl4c_destroy(ltl4c_ctx* ctx) {
         (void)hipEventDestroy(t.stop);
     }
     for (auto e : ctx->free_events) (void)hipEventDestroy(e);
+    for (auto* gh : ctx->graphs) {
+        if (!gh) continue;
+        if (gh->exec) (void)hipGraphExecDestroy(gh->exec);
+        if (gh->graph) (void)hipGraphDestroy(gh->graph);
+        (void)hipFree(gh->table_dev);
+        delete gh;
+    }
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     (void)hipFree(ctx->err_dev);
     delete ctx;
     return LTL4C_OK;
@@ -805,17 +839,97 @@ int32_t ltl4c_add_property(ltl4c_ctx* ctx, const ltl4c_property* p, int32_t* id)
     return LTL4C_OK;
 }
 
+// ---- kernel schedules ---------------------------------------------------------
+namespace {
+
+uint32_t log2_floor(uint64_t n) {
+    uint32_t b = 0;
+    while (n >>= 1) ++b;
+    return b;
+}
+
+// The shape class of a call, which tuned schedules are keyed by: the kind of
+// call, the packed key bits (which fix the radix passes), the properties, the
+// monitor size class, the tree levels and the trace size in powers of two.
+SchedEntry shape_of(const ltl4c_ctx* ctx, int kind, uint64_t n, int32_t n_traces, const int32_t* props,
+                    int32_t n_props) {
+    SchedEntry e;
+    e.kind = kind;
+    uint32_t kb = 0;
+    for (uint32_t m = 0; m < ctx->layout.n_keys; ++m) kb += ctx->layout.key_bits[m];
+    e.levels = ctx->layout.n_keys;
+    if (kind == 1) {
+        kb += std::max<uint32_t>(1, bits_for((uint32_t)n_traces));
+        e.levels += 1;
+    }
+    e.key_bits = kb;
+    e.n_props = (uint32_t)n_props;
+    for (uint32_t st : monitor_states(ctx, props, n_props))
+        if (st > 8) e.big = 1;
+    e.log2n = log2_floor(std::max<uint64_t>(n, 1));
+    return e;
+}
+
+bool same_class(const SchedEntry& a, const SchedEntry& b) {
+    return a.kind == b.kind && a.key_bits == b.key_bits && a.n_props == b.n_props && a.big == b.big &&
+           a.levels == b.levels;
+}
+
+// The tuned entry of the same class whose trace size is nearest (at most a
+// factor of 4 away), or null.
+const SchedEntry* find_sched(const ltl4c_ctx* ctx, const SchedEntry& shape) {
+    const SchedEntry* best = nullptr;
+    uint32_t bd = 3;
+    for (const auto& e : ctx->sched) {
+        if (!same_class(e, shape)) continue;
+        const uint32_t d = e.log2n > shape.log2n ? e.log2n - shape.log2n : shape.log2n - e.log2n;
+        if (d < bd) {
+            bd = d;
+            best = &e;
+        }
+    }
+    return best;
+}
+
+// For the duration of one call: the tuned schedule of its shape class, unless
+// ltl4c_set_option pinned a tile; revert() returns to the context's own.
+struct SchedScope {
+    ltl4c_ctx* ctx;
+    int sort0, scan0;
+    SchedScope(ltl4c_ctx* c, const SchedEntry* e) : ctx(c), sort0(c->sort_variant), scan0(c->scan_variant) {
+        if (e && !c->pin_sort) c->sort_variant = e->sort;
+        if (e && !c->pin_scan) c->scan_variant = e->scan;
+    }
+    bool changed() const { return ctx->sort_variant != sort0 || ctx->scan_variant != scan0; }
+    void revert() {
+        ctx->sort_variant = sort0;
+        ctx->scan_variant = scan0;
+    }
+    ~SchedScope() { revert(); }
+};
+
+uint64_t eval_ws_bytes(ltl4c_ctx* ctx, uint64_t n, const int32_t* props, int32_t n_props) {
+    Geometry g = geometry(ctx->layout, 0, false, true, sort_threads(ctx->sort_variant) >= 512);
+    return plan_workspace(ctx->layout, g, n, (uint32_t)n_props,
+                          (uint32_t)scan_groups(monitor_states(ctx, props, n_props)).size(), ctx->sort_variant,
+                          ctx->scan_variant)
+        .total;
+}
+
+}  // namespace
+
+// Enough for the context's schedule and for the tuned one of this shape, so
+// that a workspace sized before or after tuning fits whichever runs.
 int32_t ltl4c_workspace_bytes(ltl4c_ctx* ctx, uint64_t n_events, const int32_t* props, int32_t n_props,
                               uint64_t* bytes) {
     int32_t s = check_props(ctx, props, n_props);
     if (s) return s;
     if (!bytes) return fail(LTL4C_EINVAL, "bytes is NULL");
     if (n_events > LTL4C_MAX_EVENTS) return fail(LTL4C_EUNSUPPORTED, "too many events for one call");
-    Geometry g = geometry(ctx->layout, 0, false, true, sort_threads(ctx->sort_variant) >= 512);
-    *bytes = plan_workspace(ctx->layout, g, n_events, (uint32_t)n_props,
-                            (uint32_t)scan_groups(monitor_states(ctx, props, n_props)).size(), ctx->sort_variant,
-                            ctx->scan_variant)
-                 .total;
+    uint64_t b = eval_ws_bytes(ctx, n_events, props, n_props);
+    SchedScope sc(ctx, find_sched(ctx, shape_of(ctx, 0, n_events, 0, props, n_props)));
+    if (sc.changed()) b = std::max(b, eval_ws_bytes(ctx, n_events, props, n_props));
+    *bytes = b;
     return LTL4C_OK;
 }
 
@@ -1009,7 +1123,8 @@ static Plan host_plan(ltl4c_ctx* ctx, const int32_t* props, int32_t n_props) {
 }
 
 static int32_t eval_impl(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int32_t* props, int32_t n_props,
-                         void* d_ws, uint64_t ws_bytes, const ltl4c_result* out, bool noalloc);
+                         void* d_ws, uint64_t ws_bytes, const ltl4c_result* out, bool noalloc,
+                         GraphHost* cap = nullptr);
 
 int32_t ltl4c_eval(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int32_t* props, int32_t n_props,
                    void* d_ws, uint64_t ws_bytes, const ltl4c_result* out) {
@@ -1026,8 +1141,11 @@ int32_t ltl4c_eval_noalloc(ltl4c_ctx* ctx, const void* d_records, uint64_t n, co
                      out, true);
 }
 
+static int32_t capture_graph(ltl4c_ctx* ctx, GraphHost* gh, const std::function<int32_t()>& enqueue);
+
+// cap: capture the kernel sequence into a graph instead of running it.
 static int32_t eval_impl(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int32_t* props, int32_t n_props,
-                         void* d_ws, uint64_t ws_bytes, const ltl4c_result* out, bool noalloc) {
+                         void* d_ws, uint64_t ws_bytes, const ltl4c_result* out, bool noalloc, GraphHost* cap) {
     int32_t s = check_props(ctx, props, n_props);
     if (s) return s;
     if (n > LTL4C_MAX_EVENTS) return fail(LTL4C_EUNSUPPORTED, "too many events for one call");
@@ -1039,9 +1157,16 @@ static int32_t eval_impl(ltl4c_ctx* ctx, const void* d_records, uint64_t n, cons
     const uint32_t P = (uint32_t)n_props;
     if (n > 0 && (reinterpret_cast<uintptr_t>(d_records) & 3))
         return fail(LTL4C_EINVAL, "records must be 4-byte aligned");
+    SchedScope sc(ctx, find_sched(ctx, shape_of(ctx, 0, n, 0, props, n_props)));
     Geometry g = geometry(L, 0, false, true, sort_threads(ctx->sort_variant) >= 512);
     const std::vector<ScanGroup> groups = scan_groups(monitor_states(ctx, props, n_props));
     WsLayout w = plan_workspace(L, g, n, P, (uint32_t)groups.size(), ctx->sort_variant, ctx->scan_variant);
+    if (ws_bytes < w.total && sc.changed()) {
+        // a workspace sized for the context's own schedule: run that one
+        sc.revert();
+        g = geometry(L, 0, false, true, sort_threads(ctx->sort_variant) >= 512);
+        w = plan_workspace(L, g, n, P, (uint32_t)groups.size(), ctx->sort_variant, ctx->scan_variant);
+    }
     if (ws_bytes < w.total) {
         if (!noalloc) return fail(LTL4C_ENOMEM, "workspace smaller than ltl4c_workspace_bytes()");
         char buf[200];
@@ -1088,7 +1213,8 @@ static int32_t eval_impl(ltl4c_ctx* ctx, const void* d_records, uint64_t n, cons
         s = get_plan(ctx, props, n_props, &plan);
         if (s) return s;
         HIP_TRY(hipSetDevice(ctx->device));
-        return eval_core(ctx, g, w, d_ws, d_records, n, plan, P, groups, nullptr, nullptr, 0, out);
+        auto enqueue = [&]() { return eval_core(ctx, g, w, d_ws, d_records, n, plan, P, groups, nullptr, nullptr, 0, out); };
+        return cap ? capture_graph(ctx, cap, enqueue) : enqueue();
     }
     // no allocation: the plan travels inside kernel launches into the
     // scratch, and no profiling events are taken
@@ -1151,17 +1277,24 @@ int32_t ltl4c_batch_workspace_bytes(ltl4c_ctx* ctx, uint64_t n_events, int32_t n
     int32_t s = check_props(ctx, props, n_props);
     if (s) return s;
     if (!bytes) return fail(LTL4C_EINVAL, "bytes is NULL");
+    const uint32_t n_groups = (uint32_t)scan_groups(monitor_states(ctx, props, n_props)).size();
     BatchLayout b;
-    s = batch_layout(ctx, n_events, n_traces, (uint32_t)n_props,
-                     (uint32_t)scan_groups(monitor_states(ctx, props, n_props)).size(), &b);
+    s = batch_layout(ctx, n_events, n_traces, (uint32_t)n_props, n_groups, &b);
     if (s) return s;
-    *bytes = b.total;
+    uint64_t total = b.total;
+    SchedScope sc(ctx, find_sched(ctx, shape_of(ctx, 1, n_events, n_traces, props, n_props)));
+    if (sc.changed() && batch_layout(ctx, n_events, n_traces, (uint32_t)n_props, n_groups, &b) == LTL4C_OK)
+        total = std::max(total, b.total);
+    *bytes = total;
     return LTL4C_OK;
 }
 
-int32_t ltl4c_eval_batch(ltl4c_ctx* ctx, const void* d_records, const uint64_t* offsets, int32_t n_traces,
-                         const int32_t* props, int32_t n_props, void* d_ws, uint64_t ws_bytes,
-                         uint8_t* d_root_verdict, uint64_t* d_root_counts) {
+
+// cap: capture the kernel sequence into a graph instead of running it; the
+// trace table then lives in the graph's own device buffer.
+static int32_t batch_impl(ltl4c_ctx* ctx, const void* d_records, const uint64_t* offsets, int32_t n_traces,
+                          const int32_t* props, int32_t n_props, void* d_ws, uint64_t ws_bytes,
+                          uint8_t* d_root_verdict, uint64_t* d_root_counts, GraphHost* cap) {
     int32_t s = check_props(ctx, props, n_props);
     if (s) return s;
     if (!offsets || !d_root_verdict || !d_root_counts) return fail(LTL4C_EINVAL, "NULL argument");
@@ -1172,9 +1305,15 @@ int32_t ltl4c_eval_batch(ltl4c_ctx* ctx, const void* d_records, const uint64_t* 
     const uint64_t n = offsets[n_traces];
     const uint32_t P = (uint32_t)n_props;
     const std::vector<ScanGroup> groups = scan_groups(monitor_states(ctx, props, n_props));
+    SchedScope sc(ctx, find_sched(ctx, shape_of(ctx, 1, n, n_traces, props, n_props)));
     BatchLayout b;
     s = batch_layout(ctx, n, n_traces, P, (uint32_t)groups.size(), &b);
     if (s) return s;
+    if (ws_bytes < b.total && sc.changed()) {
+        sc.revert();
+        s = batch_layout(ctx, n, n_traces, P, (uint32_t)groups.size(), &b);
+        if (s) return s;
+    }
     if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) & 255)) return fail(LTL4C_EINVAL, "workspace must be 256-byte aligned");
     if (ws_bytes < b.total) return fail(LTL4C_ENOMEM, "workspace smaller than ltl4c_batch_workspace_bytes()");
     if (n > 0 && (!d_records || (reinterpret_cast<uintptr_t>(d_records) & 3)))
@@ -1188,14 +1327,24 @@ int32_t ltl4c_eval_batch(ltl4c_ctx* ctx, const void* d_records, const uint64_t* 
         HIP_TRY(hipHostMalloc(&ctx->batch_chunk_host, 4 * (2 * kMaxChunks + 2), hipHostMallocDefault));
         HIP_TRY(hipEventCreateWithFlags(&ctx->batch_ev, hipEventDisableTiming));
     }
-    const hipStream_t st = ctx->stream;
     // trace table: chunk t is trace t
-    HIP_TRY(hipEventSynchronize(ctx->batch_ev));
-    uint32_t* h = ctx->batch_chunk_host;
-    for (int32_t t = 0; t <= n_traces; ++t) h[t] = (uint32_t)offsets[t];
-    for (int32_t t = 0; t < n_traces; ++t) h[n_traces + 1 + t] = (uint32_t)t;
-    HIP_TRY(hipMemcpyAsync(ctx->batch_chunk_dev, h, 4ull * (2 * n_traces + 1), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipEventRecord(ctx->batch_ev, st));
+    const uint64_t table_bytes = 4ull * (2 * n_traces + 1);
+    uint32_t* table = ctx->batch_chunk_dev;
+    if (cap) {
+        std::vector<uint32_t> h(2 * n_traces + 1);
+        for (int32_t t = 0; t <= n_traces; ++t) h[t] = (uint32_t)offsets[t];
+        for (int32_t t = 0; t < n_traces; ++t) h[n_traces + 1 + t] = (uint32_t)t;
+        HIP_TRY(hipMalloc(&cap->table_dev, table_bytes));
+        HIP_TRY(hipMemcpy(cap->table_dev, h.data(), table_bytes, hipMemcpyHostToDevice));
+        table = static_cast<uint32_t*>(cap->table_dev);
+    } else {
+        HIP_TRY(hipEventSynchronize(ctx->batch_ev));
+        uint32_t* h = ctx->batch_chunk_host;
+        for (int32_t t = 0; t <= n_traces; ++t) h[t] = (uint32_t)offsets[t];
+        for (int32_t t = 0; t < n_traces; ++t) h[n_traces + 1 + t] = (uint32_t)t;
+        HIP_TRY(hipMemcpyAsync(ctx->batch_chunk_dev, h, table_bytes, hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(hipEventRecord(ctx->batch_ev, ctx->stream));
+    }
 
     uint8_t* ws = static_cast<uint8_t*>(d_ws);
     ltl4c_result r{};
@@ -1206,9 +1355,6 @@ int32_t ltl4c_eval_batch(ltl4c_ctx* ctx, const void* d_records, const uint64_t* 
     r.node_keys[1] = reinterpret_cast<uint64_t*>(ws + b.keys_off);
     r.node_counts[1] = reinterpret_cast<uint32_t*>(ws + b.counts_off);
     r.node_verdict[1] = ws + b.verdict_off;
-    s = eval_core(ctx, b.g, b.w, d_ws, d_records, n, plan, P, groups, ctx->batch_chunk_dev,
-                  ctx->batch_chunk_dev + n_traces + 1, (uint32_t)n_traces, &r);
-    if (s) return s;
     BatchOutArgs o{};
     o.n_props = P;
     o.n_traces = (uint32_t)n_traces;
@@ -1220,8 +1366,20 @@ int32_t ltl4c_eval_batch(ltl4c_ctx* ctx, const void* d_records, const uint64_t* 
     o.stride = b.cap1;
     o.verdict = d_root_verdict;
     o.counts = d_root_counts;
-    s = launch(ctx, "batch_out", [&] { return launch_batch_out(o, st); });
-    return s;
+    auto enqueue = [&]() -> int32_t {
+        int32_t e = eval_core(ctx, b.g, b.w, d_ws, d_records, n, plan, P, groups, table, table + n_traces + 1,
+                              (uint32_t)n_traces, &r);
+        if (e) return e;
+        return launch(ctx, "batch_out", [&] { return launch_batch_out(o, ctx->stream); });
+    };
+    return cap ? capture_graph(ctx, cap, enqueue) : enqueue();
+}
+
+int32_t ltl4c_eval_batch(ltl4c_ctx* ctx, const void* d_records, const uint64_t* offsets, int32_t n_traces,
+                         const int32_t* props, int32_t n_props, void* d_ws, uint64_t ws_bytes,
+                         uint8_t* d_root_verdict, uint64_t* d_root_counts) {
+    return batch_impl(ctx, d_records, offsets, n_traces, props, n_props, d_ws, ws_bytes, d_root_verdict,
+                      d_root_counts, nullptr);
 }
 
 int32_t ltl4c_wait(ltl4c_ctx* ctx) {
@@ -1528,12 +1686,18 @@ static int32_t note_push(ltl4c_ctx* ctx, GroupHost* G, const uint32_t* streams, 
 // chunk_ptr[i] (or at d_records + offset when chunk_ptr is NULL).  seqs, when
 // given, are the chunks' sequence numbers (checked against each stream's
 // next one).  from_host: chunk_ptr points to pinned host memory.
+static int32_t capture_graph(ltl4c_ctx* ctx, GraphHost* gh, const std::function<int32_t()>& enqueue);
+
+// cap: capture the push's kernel sequence into a graph (device chunks only)
+// instead of running it; the chunk table then lives in the graph's own
+// device buffer, and each replay counts as a push of the same chunks.
 static int32_t group_push_impl(ltl4c_ctx* ctx, int32_t group, const void* d_records, const void* const* chunk_ptr,
                                const uint64_t* sizes, const uint32_t* streams, int32_t n_chunks,
-                               const uint64_t* seqs = nullptr, bool from_host = false) {
+                               const uint64_t* seqs = nullptr, bool from_host = false, GraphHost* cap = nullptr) {
     GroupHost* G = nullptr;
     int32_t s = get_group(ctx, group, &G);
     if (s) return s;
+    if (cap && from_host) return fail(LTL4C_EINVAL, "a captured push takes device chunks only");
     if (n_chunks < 1 || n_chunks > (int32_t)kMaxChunks) return fail(LTL4C_EINVAL, "n_chunks must be 1..4096");
     if (!sizes || !streams) return fail(LTL4C_EINVAL, "chunk sizes / streams are NULL");
     uint64_t n = 0;
@@ -1576,7 +1740,10 @@ static int32_t group_push_impl(ltl4c_ctx* ctx, int32_t group, const void* d_reco
     if (!chunk_ptr && n > 0 && (!d_records || (reinterpret_cast<uintptr_t>(d_records) & 3)))
         return fail(LTL4C_EINVAL, "records must be non-NULL and 4-byte aligned");
     HIP_TRY(hipSetDevice(ctx->device));
-    if (n == 0) return note_push(ctx, G, streams, n_chunks);
+    if (n == 0) {
+        if (cap) return fail(LTL4C_EINVAL, "a captured push needs events");
+        return note_push(ctx, G, streams, n_chunks);
+    }
     const hipStream_t st = ctx->stream;
     if (from_host) {
         // copy the chunks into one of two device staging buffers on the copy
@@ -1621,9 +1788,16 @@ static int32_t group_push_impl(ltl4c_ctx* ctx, int32_t group, const void* d_reco
         G->stage_i ^= 1;
     }
     // packed chunk table [offsets n+1][streams n][pad][pointers n] through a
-    // pinned ring slot, reused only after its copy has run
+    // pinned ring slot, reused only after its copy has run (a captured push:
+    // through the graph's own buffer)
+    std::vector<uint32_t> cap_table;
     uint32_t* slot = G->chunk_host + (uint64_t)G->ring_i * kChunkTableWords;
-    HIP_TRY(hipEventSynchronize(G->ring_ev[G->ring_i]));
+    if (cap) {
+        cap_table.assign(kChunkTableWords, 0u);
+        slot = cap_table.data();
+    } else {
+        HIP_TRY(hipEventSynchronize(G->ring_ev[G->ring_i]));
+    }
     uint64_t acc = 0;
     for (int32_t i = 0; i < n_chunks; ++i) {
         slot[i] = (uint32_t)acc;
@@ -1638,74 +1812,94 @@ static int32_t group_push_impl(ltl4c_ctx* ctx, int32_t group, const void* d_reco
         for (int32_t i = 0; i < n_chunks; ++i) pp[i] = reinterpret_cast<uint64_t>(chunk_ptr[i]);
         words = po + 2ull * n_chunks;
     }
-    HIP_TRY(hipMemcpyAsync(G->chunk_dev, slot, 4 * words, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipEventRecord(G->ring_ev[G->ring_i], st));
-    G->ring_i = (G->ring_i + 1) % kChunkRing;
-
-    const ltl4c_layout& L = ctx->layout;
-    const WsLayout& w = G->w;
-    uint8_t* ws = G->ws;
-    uint32_t* z = reinterpret_cast<uint32_t*>(ws);
-    {
-        ZeroArgs za{z, nullptr, 0, w.zero_words, 0};
-        uint32_t blocks = (uint32_t)std::min<uint64_t>(1024, (w.zero_words + 255) / 256);
-        s = launch(ctx, "zero", [&] { return launch_zero(za, blocks ? blocks : 1, st); });
-        if (s) return s;
-        ZeroArgs zl{G->gs.list_cnt, nullptr, 0, kMaxLevels, 0};
-        s = launch(ctx, "zero", [&] { return launch_zero(zl, 1, st); });
-        if (s) return s;
+    uint32_t* table = G->chunk_dev;
+    if (cap) {
+        HIP_TRY(hipMalloc(&cap->table_dev, 4 * words));
+        HIP_TRY(hipMemcpy(cap->table_dev, slot, 4 * words, hipMemcpyHostToDevice));
+        table = static_cast<uint32_t*>(cap->table_dev);
+    } else {
+        HIP_TRY(hipMemcpyAsync(G->chunk_dev, slot, 4 * words, hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(hipEventRecord(G->ring_ev[G->ring_i], ctx->stream));
+        G->ring_i = (G->ring_i + 1) % kChunkRing;
     }
-    uint64_t* sorted = nullptr;
-    s = enqueue_front(ctx, L, G->g, w, ws, d_records, n, G->vplan, G->chunk_dev, G->chunk_dev + so,
-                      chunk_ptr ? reinterpret_cast<const uint64_t*>(G->chunk_dev + po) : nullptr,
-                      (uint32_t)n_chunks, chunk_ptr ? vec_ok : true, &sorted, G->sort_variant);
-    if (s) return s;
-    uint64_t* seg_keys = reinterpret_cast<uint64_t*>(ws + G->seg_keys_off);
-    uint8_t* seg_state = ws + w.inst_verdict_off;
-    uint32_t* sizes32 = z + w.sizes32_off;
-    {
-        ScanArgs sa{};
-        sa.words = sorted;
-        sa.n = (uint32_t)n;
-        sa.cbits = G->g.cbits;
-        sa.class_mask = (1u << G->g.cbits) - 1u;
-        sa.n_levels = 1;
-        sa.valid_shift = G->g.cbits + G->g.key_bits_total;
-        sa.n_props_all = G->V;
-        sa.plan = G->vplan;
-        sa.inst_verdict = seg_state;
-        sa.inst_stride = G->max_batch;
-        sa.inst_limit = G->max_batch;
-        sa.inst_keys = seg_keys;
-        sa.sizes = reinterpret_cast<uint64_t*>(z + w.sizes64_off);
-        sa.sizes32 = sizes32;
-        sa.err = ctx->err_dev;
-        sa.emit_state = 1;
-        uint32_t* scan_status = z + w.scan_status_off;
-        for (size_t gi = 0; gi < G->sgroups.size(); ++gi) {
-            sa.n_props = G->sgroups[gi].cnt;
-            std::memcpy(sa.prop_idx, G->sgroups[gi].idx, sizeof sa.prop_idx);
-            sa.max_states = G->sgroups[gi].states;
-            sa.structure = G->sgroups[gi].structure ? 1u : 0u;
-            sa.status = scan_status + gi * 2ull * kScanRows * w.tiles_scan;
-            sa.ticket = z + w.scan_ticket_off + gi;
-            s = launch(ctx, "scan", [&] { return launch_scan(sa, G->scan_variant, st); });
+
+    auto enqueue = [&]() -> int32_t {
+        const hipStream_t st = ctx->stream;
+        const ltl4c_layout& L = ctx->layout;
+        const WsLayout& w = G->w;
+        uint8_t* ws = G->ws;
+        uint32_t* z = reinterpret_cast<uint32_t*>(ws);
+        {
+            ZeroArgs za{z, nullptr, 0, w.zero_words, 0};
+            uint32_t blocks = (uint32_t)std::min<uint64_t>(1024, (w.zero_words + 255) / 256);
+            s = launch(ctx, "zero", [&] { return launch_zero(za, blocks ? blocks : 1, st); });
+            if (s) return s;
+            ZeroArgs zl{G->gs.list_cnt, nullptr, 0, kMaxLevels, 0};
+            s = launch(ctx, "zero", [&] { return launch_zero(zl, 1, st); });
             if (s) return s;
         }
-    }
-    GroupUpdateArgs ua{};
-    ua.g = G->gs;
-    ua.n_seg = sizes32;
-    ua.seg_key = seg_keys;
-    ua.seg_state = seg_state;
-    ua.seg_stride = G->max_batch;
-    s = launch(ctx, "group_update", [&] { return launch_group_update(ua, n, st); });
-    if (s) return s;
-    for (int m = (int)L.n_keys - 1; m >= 1; --m) {
-        s = launch(ctx, "group_level", [&] { return launch_group_level(G->gs, (uint32_t)m, st); });
+        uint64_t* sorted = nullptr;
+        s = enqueue_front(ctx, L, G->g, w, ws, d_records, n, G->vplan, table, table + so,
+                          chunk_ptr ? reinterpret_cast<const uint64_t*>(table + po) : nullptr,
+                          (uint32_t)n_chunks, chunk_ptr ? vec_ok : true, &sorted, G->sort_variant);
         if (s) return s;
+        uint64_t* seg_keys = reinterpret_cast<uint64_t*>(ws + G->seg_keys_off);
+        uint8_t* seg_state = ws + w.inst_verdict_off;
+        uint32_t* sizes32 = z + w.sizes32_off;
+        {
+            ScanArgs sa{};
+            sa.words = sorted;
+            sa.n = (uint32_t)n;
+            sa.cbits = G->g.cbits;
+            sa.class_mask = (1u << G->g.cbits) - 1u;
+            sa.n_levels = 1;
+            sa.valid_shift = G->g.cbits + G->g.key_bits_total;
+            sa.n_props_all = G->V;
+            sa.plan = G->vplan;
+            sa.inst_verdict = seg_state;
+            sa.inst_stride = G->max_batch;
+            sa.inst_limit = G->max_batch;
+            sa.inst_keys = seg_keys;
+            sa.sizes = reinterpret_cast<uint64_t*>(z + w.sizes64_off);
+            sa.sizes32 = sizes32;
+            sa.err = ctx->err_dev;
+            sa.emit_state = 1;
+            uint32_t* scan_status = z + w.scan_status_off;
+            for (size_t gi = 0; gi < G->sgroups.size(); ++gi) {
+                sa.n_props = G->sgroups[gi].cnt;
+                std::memcpy(sa.prop_idx, G->sgroups[gi].idx, sizeof sa.prop_idx);
+                sa.max_states = G->sgroups[gi].states;
+                sa.structure = G->sgroups[gi].structure ? 1u : 0u;
+                sa.status = scan_status + gi * 2ull * kScanRows * w.tiles_scan;
+                sa.ticket = z + w.scan_ticket_off + gi;
+                s = launch(ctx, "scan", [&] { return launch_scan(sa, G->scan_variant, st); });
+                if (s) return s;
+            }
+        }
+        GroupUpdateArgs ua{};
+        ua.g = G->gs;
+        ua.n_seg = sizes32;
+        ua.seg_key = seg_keys;
+        ua.seg_state = seg_state;
+        ua.seg_stride = G->max_batch;
+        s = launch(ctx, "group_update", [&] { return launch_group_update(ua, n, st); });
+        if (s) return s;
+        for (int m = (int)L.n_keys - 1; m >= 1; --m) {
+            s = launch(ctx, "group_level", [&] { return launch_group_level(G->gs, (uint32_t)m, st); });
+            if (s) return s;
+        }
+        s = launch(ctx, "group_roots", [&] { return launch_group_roots(G->gs, false, st); });
+        if (s) return s;
+        return LTL4C_OK;
+    };
+    if (cap) {
+        s = capture_graph(ctx, cap, enqueue);
+        if (s) return s;
+        cap->group = group;
+        cap->streams.assign(streams, streams + n_chunks);
+        return LTL4C_OK;
     }
-    s = launch(ctx, "group_roots", [&] { return launch_group_roots(G->gs, false, st); });
+    s = enqueue();
     if (s) return s;
     if (from_host) HIP_TRY(hipEventRecord(G->stage_free[G->stage_i ^ 1], st));
     return note_push(ctx, G, streams, n_chunks);
@@ -1780,12 +1974,14 @@ int32_t ltl4c_set_option(ltl4c_ctx* ctx, int32_t option, int64_t value) {
     if (!ctx) return fail(LTL4C_EINVAL, "ctx is NULL");
     switch (option) {
         case LTL4C_OPT_SORT_TILE:
-            if (value < 0 || value >= kSortVariants) return fail(LTL4C_EINVAL, "sort tile variant out of range");
-            ctx->sort_variant = (int)value;
+            if (value < -1 || value >= kSortVariants) return fail(LTL4C_EINVAL, "sort tile variant out of range");
+            ctx->pin_sort = value >= 0;
+            ctx->sort_variant = value >= 0 ? (int)value : kDefaultSortVariant;
             return LTL4C_OK;
         case LTL4C_OPT_SCAN_TILE:
-            if (value < 0 || value >= kScanVariants) return fail(LTL4C_EINVAL, "scan tile variant out of range");
-            ctx->scan_variant = (int)value;
+            if (value < -1 || value >= kScanVariants) return fail(LTL4C_EINVAL, "scan tile variant out of range");
+            ctx->pin_scan = value >= 0;
+            ctx->scan_variant = value >= 0 ? (int)value : kDefaultScanVariant;
             return LTL4C_OK;
         default:
             return fail(LTL4C_EINVAL, "unknown option");
@@ -1819,6 +2015,373 @@ int32_t ltl4c_profile_reset(ltl4c_ctx* ctx) {
     int32_t s = drain_profile(ctx);
     ctx->prof_acc.clear();
     return s;
+}
+
+// ---- graphs: captured kernel sequences ----------------------------------------
+
+// Runs `enqueue` with the context's launches redirected to a private stream
+// in capture mode, and instantiates what it recorded.  Nothing runs; no
+// profiling events are recorded into the graph.
+static int32_t capture_graph(ltl4c_ctx* ctx, GraphHost* gh, const std::function<int32_t()>& enqueue) {
+    if (!ctx->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    // work the caller enqueued before must not be reordered with the graph's
+    // later replays: the capture only records, so no ordering is needed here
+    const hipStream_t saved = ctx->stream;
+    const bool saved_nt = ctx->no_timing;
+    HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    ctx->stream = ctx->cap_stream;
+    ctx->no_timing = true;
+    const int32_t s = enqueue();
+    ctx->stream = saved;
+    ctx->no_timing = saved_nt;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &g);
+    if (s) {
+        if (g) (void)hipGraphDestroy(g);
+        return s;
+    }
+    if (e != hipSuccess || !g) return fail(LTL4C_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    gh->graph = g;
+    HIP_TRY(hipGraphInstantiate(&gh->exec, g, nullptr, nullptr, 0));
+    return LTL4C_OK;
+}
+
+static int32_t keep_graph(ltl4c_ctx* ctx, GraphHost* gh, int32_t s, int32_t* graph) {
+    if (s) {
+        if (gh->exec) (void)hipGraphExecDestroy(gh->exec);
+        if (gh->graph) (void)hipGraphDestroy(gh->graph);
+        (void)hipFree(gh->table_dev);
+        delete gh;
+        return s;
+    }
+    int32_t id = -1;
+    for (size_t i = 0; i < ctx->graphs.size(); ++i)
+        if (!ctx->graphs[i]) id = (int32_t)i;
+    if (id < 0) {
+        id = (int32_t)ctx->graphs.size();
+        ctx->graphs.push_back(nullptr);
+    }
+    ctx->graphs[id] = gh;
+    *graph = id;
+    return LTL4C_OK;
+}
+
+int32_t ltl4c_graph_eval(ltl4c_ctx* ctx, const void* d_records, uint64_t n_events, const int32_t* props,
+                         int32_t n_props, void* d_ws, uint64_t ws_bytes, const ltl4c_result* out, int32_t* graph) {
+    if (!ctx || !graph) return fail(LTL4C_EINVAL, "ctx or graph is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    GraphHost* gh = new GraphHost();
+    const int32_t s = eval_impl(ctx, d_records, n_events, props, n_props, d_ws, ws_bytes, out, false, gh);
+    return keep_graph(ctx, gh, s, graph);
+}
+
+int32_t ltl4c_graph_eval_batch(ltl4c_ctx* ctx, const void* d_records, const uint64_t* offsets, int32_t n_traces,
+                               const int32_t* props, int32_t n_props, void* d_ws, uint64_t ws_bytes,
+                               uint8_t* d_root_verdict, uint64_t* d_root_counts, int32_t* graph) {
+    if (!ctx || !graph) return fail(LTL4C_EINVAL, "ctx or graph is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    GraphHost* gh = new GraphHost();
+    const int32_t s = batch_impl(ctx, d_records, offsets, n_traces, props, n_props, d_ws, ws_bytes, d_root_verdict,
+                                 d_root_counts, gh);
+    return keep_graph(ctx, gh, s, graph);
+}
+
+int32_t ltl4c_graph_group_push(ltl4c_ctx* ctx, int32_t group, const void* const* d_chunks, const uint64_t* sizes,
+                               const uint32_t* streams, int32_t n_chunks, int32_t* graph) {
+    if (!ctx || !graph) return fail(LTL4C_EINVAL, "ctx or graph is NULL");
+    if (!d_chunks) return fail(LTL4C_EINVAL, "chunk pointers are NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    GraphHost* gh = new GraphHost();
+    const int32_t s = group_push_impl(ctx, group, nullptr, d_chunks, sizes, streams, n_chunks, nullptr, false, gh);
+    return keep_graph(ctx, gh, s, graph);
+}
+
+int32_t ltl4c_graph_launch(ltl4c_ctx* ctx, int32_t graph) {
+    if (!ctx) return fail(LTL4C_EINVAL, "ctx is NULL");
+    if (graph < 0 || graph >= (int32_t)ctx->graphs.size() || !ctx->graphs[graph])
+        return fail(LTL4C_EINVAL, "unknown graph id");
+    GraphHost* gh = ctx->graphs[graph];
+    GroupHost* G = nullptr;
+    if (gh->group >= 0) {
+        int32_t s = get_group(ctx, gh->group, &G);
+        if (s) return fail(LTL4C_EINVAL, "the graph's stream group was closed");
+        for (uint32_t st : gh->streams)
+            if (!G->open[st]) return fail(LTL4C_ESEQ, "the graph pushes to a stream that is not open");
+    }
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipGraphLaunch(gh->exec, ctx->stream));
+    if (G) return note_push(ctx, G, gh->streams.data(), (int32_t)gh->streams.size());
+    return LTL4C_OK;
+}
+
+int32_t ltl4c_graph_destroy(ltl4c_ctx* ctx, int32_t graph) {
+    if (!ctx) return fail(LTL4C_EINVAL, "ctx is NULL");
+    if (graph < 0 || graph >= (int32_t)ctx->graphs.size() || !ctx->graphs[graph])
+        return fail(LTL4C_EINVAL, "unknown graph id");
+    GraphHost* gh = ctx->graphs[graph];
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (gh->exec) (void)hipGraphExecDestroy(gh->exec);
+    if (gh->graph) (void)hipGraphDestroy(gh->graph);
+    (void)hipFree(gh->table_dev);
+    delete gh;
+    ctx->graphs[graph] = nullptr;
+    return LTL4C_OK;
+}
+
+// ---- autotuning -------------------------------------------------------------
+
+int32_t ltl4c_tune_workspace_bytes(ltl4c_ctx* ctx, uint64_t n_events, const uint64_t* offsets, int32_t n_traces,
+                                   const int32_t* props, int32_t n_props, uint64_t* bytes) {
+    int32_t s = check_props(ctx, props, n_props);
+    if (s) return s;
+    if (!bytes) return fail(LTL4C_EINVAL, "bytes is NULL");
+    if (offsets && (n_traces < 1 || n_traces > (int32_t)kMaxChunks))
+        return fail(LTL4C_EUNSUPPORTED, "n_traces must be 1..4096");
+    const uint64_t n = offsets ? offsets[n_traces] : n_events;
+    const int sv0 = ctx->sort_variant, cv0 = ctx->scan_variant;
+    const bool ps0 = ctx->pin_sort, pc0 = ctx->pin_scan;
+    ctx->pin_sort = ctx->pin_scan = true;
+    uint64_t most = 0;
+    for (int sv = 0; sv < kSortVariants && s == LTL4C_OK; ++sv)
+        for (int cv = 0; cv < kScanVariants && s == LTL4C_OK; ++cv) {
+            ctx->sort_variant = sv;
+            ctx->scan_variant = cv;
+            uint64_t b = 0;
+            s = offsets ? ltl4c_batch_workspace_bytes(ctx, n, n_traces, props, n_props, &b)
+                        : ltl4c_workspace_bytes(ctx, n, props, n_props, &b);
+            most = std::max(most, b);
+        }
+    ctx->sort_variant = sv0;
+    ctx->scan_variant = cv0;
+    ctx->pin_sort = ps0;
+    ctx->pin_scan = pc0;
+    if (s) return s;
+    *bytes = most;
+    return LTL4C_OK;
+}
+
+int32_t ltl4c_tune(ltl4c_ctx* ctx, const void* d_records, uint64_t n_events, const uint64_t* offsets, int32_t n_traces,
+                   const int32_t* props, int32_t n_props, void* d_ws, uint64_t ws_bytes, int32_t reps,
+                   ltl4c_tuned* result) {
+    int32_t s = check_props(ctx, props, n_props);
+    if (s) return s;
+    if (reps < 1 || reps > 1000) return fail(LTL4C_EINVAL, "reps must be 1..1000");
+    if (offsets && (n_traces < 1 || n_traces > (int32_t)kMaxChunks))
+        return fail(LTL4C_EUNSUPPORTED, "n_traces must be 1..4096");
+    const bool batch = offsets != nullptr;
+    const uint64_t n = batch ? offsets[n_traces] : n_events;
+    HIP_TRY(hipSetDevice(ctx->device));
+    // outputs of the timed calls
+    const uint64_t cells = batch ? (uint64_t)n_traces * n_props : (uint64_t)n_props;
+    uint8_t* outs = nullptr;
+    HIP_TRY(hipMalloc(&outs, align256(cells) + 48 * cells + 1024));
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    struct Restore {
+        ltl4c_ctx* c;
+        int sv, cv;
+        bool ps, pc, prof;
+        uint8_t* outs;
+        hipEvent_t* ev;
+        ~Restore() {
+            c->sort_variant = sv;
+            c->scan_variant = cv;
+            c->pin_sort = ps;
+            c->pin_scan = pc;
+            c->prof = prof;
+            (void)hipStreamSynchronize(c->stream);
+            (void)hipFree(outs);
+            for (int i = 0; i < 2; ++i)
+                if (ev[i]) (void)hipEventDestroy(ev[i]);
+        }
+    } restore{ctx, ctx->sort_variant, ctx->scan_variant, ctx->pin_sort, ctx->pin_scan, ctx->prof, outs, ev};
+    HIP_TRY(hipEventCreate(&ev[0]));
+    HIP_TRY(hipEventCreate(&ev[1]));
+    ctx->prof = false;
+    ctx->pin_sort = ctx->pin_scan = true;      // the candidate is the schedule
+    ltl4c_result r{};
+    r.root_verdict = outs;
+    r.root_counts = reinterpret_cast<uint64_t*>(outs + align256(cells));
+    r.sizes = reinterpret_cast<uint64_t*>(outs + align256(cells) + 48 * cells);
+    int32_t tried = 0;
+    // median time of `reps` runs after one warm-up; +inf when the candidate's
+    // workspace exceeds ws_bytes
+    auto run = [&](int sv, int cv, double* med) -> int32_t {
+        ctx->sort_variant = sv;
+        ctx->scan_variant = cv;
+        uint64_t need = 0;
+        int32_t e = batch ? ltl4c_batch_workspace_bytes(ctx, n, n_traces, props, n_props, &need)
+                          : ltl4c_workspace_bytes(ctx, n, props, n_props, &need);
+        if (e) return e;
+        if (need > ws_bytes) {
+            *med = 1e300;
+            return LTL4C_OK;
+        }
+        ++tried;
+        std::vector<float> t;
+        for (int i = 0; i <= reps; ++i) {
+            HIP_TRY(hipEventRecord(ev[0], ctx->stream));
+            e = batch ? ltl4c_eval_batch(ctx, d_records, offsets, n_traces, props, n_props, d_ws, ws_bytes,
+                                         r.root_verdict, r.root_counts)
+                      : ltl4c_eval(ctx, d_records, n, props, n_props, d_ws, ws_bytes, &r);
+            if (e) return e;
+            HIP_TRY(hipEventRecord(ev[1], ctx->stream));
+            HIP_TRY(hipEventSynchronize(ev[1]));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ev[0], ev[1]));
+            if (i > 0) t.push_back(ms);
+        }
+        std::sort(t.begin(), t.end());
+        *med = 1e3 * t[t.size() / 2];
+        return LTL4C_OK;
+    };
+    double def_us = 0.0;
+    s = run(kDefaultSortVariant, kDefaultScanVariant, &def_us);
+    if (s) return s;
+    int bs = kDefaultSortVariant, bc = kDefaultScanVariant;
+    double best = def_us;
+    // coordinate descent: the radix tile with the default scan, then the
+    // scan tile with that radix tile; a candidate must win by 1 %
+    for (int sv = 0; sv < kSortVariants; ++sv) {
+        if (sv == bs) continue;
+        double u = 0.0;
+        s = run(sv, bc, &u);
+        if (s) return s;
+        if (u < 0.99 * best) {
+            best = u;
+            bs = sv;
+        }
+    }
+    for (int cv = 0; cv < kScanVariants; ++cv) {
+        if (cv == bc) continue;
+        double u = 0.0;
+        s = run(bs, cv, &u);
+        if (s) return s;
+        if (u < 0.99 * best) {
+            best = u;
+            bc = cv;
+        }
+    }
+    s = ltl4c_wait(ctx);
+    if (s) return s;
+    SchedEntry e = shape_of(ctx, batch ? 1 : 0, n, n_traces, props, n_props);
+    e.sort = bs;
+    e.scan = bc;
+    e.us = best;
+    e.default_us = def_us;
+    bool replaced = false;
+    for (auto& x : ctx->sched)
+        if (same_class(x, e) && x.log2n == e.log2n) {
+            x = e;
+            replaced = true;
+        }
+    if (!replaced) ctx->sched.push_back(e);
+    if (result) {
+        result->sort_tile = bs;
+        result->scan_tile = bc;
+        result->tuned_us = best;
+        result->default_us = def_us;
+        result->candidates = tried;
+    }
+    return LTL4C_OK;
+}
+
+namespace {
+std::string arch_of(int device) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, device) != hipSuccess) return "unknown";
+    std::string a = p.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+// The number after "\"key\":" inside [b, e), or false.
+bool json_num(const std::string& t, size_t b, size_t e, const char* key, double* out) {
+    const std::string k = std::string("\"") + key + "\":";
+    const size_t at = t.find(k, b);
+    if (at == std::string::npos || at >= e) return false;
+    char* end = nullptr;
+    const double v = std::strtod(t.c_str() + at + k.size(), &end);
+    if (end == t.c_str() + at + k.size()) return false;
+    *out = v;
+    return true;
+}
+}  // namespace
+
+int32_t ltl4c_schedule_save(ltl4c_ctx* ctx, const char* path) {
+    if (!ctx || !path) return fail(LTL4C_EINVAL, "ctx or path is NULL");
+    FILE* f = std::fopen(path, "w");
+    if (!f) return fail(LTL4C_EINVAL, std::string("cannot write ") + path);
+    std::fprintf(f, "{\"arch\": \"%s\", \"schedules\": [\n", arch_of(ctx->device).c_str());
+    for (size_t i = 0; i < ctx->sched.size(); ++i) {
+        const SchedEntry& e = ctx->sched[i];
+        std::fprintf(f,
+                     "  {\"batch\": %d, \"key_bits\": %u, \"props\": %u, \"big_monitors\": %u, \"levels\": %u, "
+                     "\"log2_events\": %u, \"sort_tile\": %d, \"scan_tile\": %d, \"us\": %.2f, \"default_us\": %.2f}%s\n",
+                     e.kind, e.key_bits, e.n_props, e.big, e.levels, e.log2n, e.sort, e.scan, e.us, e.default_us,
+                     i + 1 < ctx->sched.size() ? "," : "");
+    }
+    std::fprintf(f, "]}\n");
+    const bool ok = std::fclose(f) == 0;
+    return ok ? LTL4C_OK : fail(LTL4C_EINVAL, std::string("cannot write ") + path);
+}
+
+int32_t ltl4c_schedule_load(ltl4c_ctx* ctx, const char* path, int32_t* n_loaded) {
+    if (!ctx || !path) return fail(LTL4C_EINVAL, "ctx or path is NULL");
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(LTL4C_EINVAL, std::string("cannot read ") + path);
+    std::string t;
+    char buf[4096];
+    size_t k;
+    while ((k = std::fread(buf, 1, sizeof buf, f)) > 0) t.append(buf, k);
+    std::fclose(f);
+    int32_t loaded = 0;
+    const size_t a = t.find("\"arch\":");
+    const size_t q0 = a == std::string::npos ? a : t.find('"', a + 7);
+    const size_t q1 = q0 == std::string::npos ? q0 : t.find('"', q0 + 1);
+    if (q1 == std::string::npos) return fail(LTL4C_EINVAL, "schedule file without an arch");
+    if (t.substr(q0 + 1, q1 - q0 - 1) == arch_of(ctx->device)) {
+        size_t at = t.find('{', q1);
+        while (at != std::string::npos) {
+            const size_t end = t.find('}', at);
+            if (end == std::string::npos) break;
+            double v[8];
+            const char* keys[8] = {"batch", "key_bits", "props", "big_monitors", "levels", "log2_events", "sort_tile",
+                                   "scan_tile"};
+            bool ok = true;
+            for (int i = 0; i < 8 && ok; ++i) ok = json_num(t, at, end, keys[i], &v[i]);
+            if (!ok || v[6] < 0 || v[6] >= kSortVariants || v[7] < 0 || v[7] >= kScanVariants || v[0] < 0 || v[0] > 1)
+                return fail(LTL4C_EINVAL, "malformed schedule entry");
+            SchedEntry e;
+            e.kind = (int)v[0];
+            e.key_bits = (uint32_t)v[1];
+            e.n_props = (uint32_t)v[2];
+            e.big = (uint32_t)v[3];
+            e.levels = (uint32_t)v[4];
+            e.log2n = (uint32_t)v[5];
+            e.sort = (int)v[6];
+            e.scan = (int)v[7];
+            (void)json_num(t, at, end, "us", &e.us);
+            (void)json_num(t, at, end, "default_us", &e.default_us);
+            bool replaced = false;
+            for (auto& x : ctx->sched)
+                if (same_class(x, e) && x.log2n == e.log2n) {
+                    x = e;
+                    replaced = true;
+                }
+            if (!replaced) ctx->sched.push_back(e);
+            ++loaded;
+            at = t.find('{', end);
+        }
+    }
+    if (n_loaded) *n_loaded = loaded;
+    return LTL4C_OK;
+}
+
+int32_t ltl4c_schedule_clear(ltl4c_ctx* ctx) {
+    if (!ctx) return fail(LTL4C_EINVAL, "ctx is NULL");
+    ctx->sched.clear();
+    return LTL4C_OK;
 }
 
 }  // extern "C"

@@ -18,6 +18,10 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libltl4c.so")
+# kernel schedules tuned on the GPU by bench.py --tune (ltl4c_schedule_save); a
+# context loads them unless use_tuned=False, and they apply only on the
+# architecture they were tuned on
+SCHEDULES_PATH = os.path.join(HERE, "schedules.json")
 
 OK, EINVAL, ENOMEM, ECAPACITY, EDEVICE, EADMIT, ESEQ, EUNSUPPORTED, ERANGE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 BOT, BOT_C, BOT_P, TOP_P, TOP_C, TOP = range(6)
@@ -55,6 +59,11 @@ class Quant(C.Structure):
 
 class PropertyDesc(C.Structure):
     _fields_ = [("monitor", C.c_int32), ("n_levels", C.c_uint32), ("q", Quant * 4)]
+
+
+class Tuned(C.Structure):
+    _fields_ = [("sort_tile", C.c_int32), ("scan_tile", C.c_int32), ("tuned_us", C.c_double),
+                ("default_us", C.c_double), ("candidates", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -115,6 +124,22 @@ SIGNATURES = [
     ("ltl4c_group_snapshot", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_uint64)]),
     ("ltl4c_group_restore", C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_uint64]),
     ("ltl4c_set_option", C.c_int32, [C.c_void_p, C.c_int32, C.c_int64]),
+    ("ltl4c_tune_workspace_bytes", C.c_int32, [C.c_void_p, C.c_uint64, C.POINTER(C.c_uint64), C.c_int32,
+                                               C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_uint64)]),
+    ("ltl4c_tune", C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(C.c_uint64), C.c_int32,
+                               C.POINTER(C.c_int32), C.c_int32, C.c_void_p, C.c_uint64, C.c_int32, C.c_void_p]),
+    ("ltl4c_schedule_save", C.c_int32, [C.c_void_p, C.c_char_p]),
+    ("ltl4c_schedule_load", C.c_int32, [C.c_void_p, C.c_char_p, C.POINTER(C.c_int32)]),
+    ("ltl4c_schedule_clear", C.c_int32, [C.c_void_p]),
+    ("ltl4c_graph_eval", C.c_int32, [C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(C.c_int32), C.c_int32,
+                                     C.c_void_p, C.c_uint64, C.POINTER(Result), C.POINTER(C.c_int32)]),
+    ("ltl4c_graph_eval_batch", C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_uint64), C.c_int32,
+                                           C.POINTER(C.c_int32), C.c_int32, C.c_void_p, C.c_uint64, C.c_void_p,
+                                           C.c_void_p, C.POINTER(C.c_int32)]),
+    ("ltl4c_graph_group_push", C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_uint64),
+                                           C.POINTER(C.c_uint32), C.c_int32, C.POINTER(C.c_int32)]),
+    ("ltl4c_graph_launch", C.c_int32, [C.c_void_p, C.c_int32]),
+    ("ltl4c_graph_destroy", C.c_int32, [C.c_void_p, C.c_int32]),
     ("ltl4c_profile_enable", C.c_int32, [C.c_void_p, C.c_int32]),
     ("ltl4c_profile_get", C.c_int32,
      [C.c_void_p, C.c_int32, C.c_char_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
@@ -207,7 +232,9 @@ class EvalResult:
 class Context:
     """One ltl4c context on a HIP device, driven from torch tensors."""
 
-    def __init__(self, device=0):
+    def __init__(self, device=0, use_tuned=True):
+        """use_tuned: load the committed schedule table (SCHEDULES_PATH),
+        which applies only on the architecture it was tuned on."""
         import torch
         self.torch = torch
         self.lib = load()
@@ -217,6 +244,9 @@ class Context:
         self.h = h
         self.n_levels = None
         self._workspace = None
+        self.schedules_loaded = 0
+        if use_tuned and os.path.exists(SCHEDULES_PATH):
+            self.schedules_loaded = self.load_schedules(SCHEDULES_PATH)
 
     def close(self):
         if self.h:
@@ -394,6 +424,77 @@ class Context:
         self.wait()
         return v.cpu().numpy().reshape(nt, len(props)), c.cpu().numpy().reshape(nt, len(props), 6)
 
+    # ---- autotuned schedules -------------------------------------------------
+    def tune(self, records, props, n_events=None, offsets=None, reps=5):
+        """Time the kernel schedules on these records (one trace of n_events,
+        or a batch given by offsets) and keep the fastest for this shape
+        class.  Returns {sort_tile, scan_tile, tuned_us, default_us, candidates}."""
+        self._bind_stream()
+        arr = (C.c_int32 * len(props))(*props)
+        if offsets is not None:
+            nt = len(offsets) - 1
+            off = (C.c_uint64 * (nt + 1))(*[int(x) for x in offsets])
+            n = int(offsets[-1])
+        else:
+            nt, off, n = 0, None, int(n_events)
+        b = C.c_uint64()
+        _check(self.lib.ltl4c_tune_workspace_bytes(self.h, n, off, nt, arr, len(props), C.byref(b)),
+               "ltl4c_tune_workspace_bytes")
+        self._workspace = None
+        ws = self.torch.empty(max(b.value, 256), dtype=self.torch.uint8, device=f"cuda:{self.device}")
+        t = Tuned()
+        _check(self.lib.ltl4c_tune(self.h, C.c_void_p(records.data_ptr() if n else 0), n, off, nt, arr, len(props),
+                                   C.c_void_p(ws.data_ptr()), ws.numel(), reps, C.byref(t)), "ltl4c_tune")
+        del ws
+        return {"sort_tile": t.sort_tile, "scan_tile": t.scan_tile, "tuned_us": t.tuned_us,
+                "default_us": t.default_us, "candidates": t.candidates}
+
+    def save_schedules(self, path):
+        _check(self.lib.ltl4c_schedule_save(self.h, os.fsencode(path)), "ltl4c_schedule_save")
+
+    def load_schedules(self, path):
+        n = C.c_int32()
+        _check(self.lib.ltl4c_schedule_load(self.h, os.fsencode(path), C.byref(n)), "ltl4c_schedule_load")
+        self._workspace = None
+        return n.value
+
+    def clear_schedules(self):
+        _check(self.lib.ltl4c_schedule_clear(self.h), "ltl4c_schedule_clear")
+        self._workspace = None
+
+    # ---- graphs ----------------------------------------------------------------
+    def graph_eval(self, records, n_events, props, result, workspace):
+        """Capture one evaluation (same arguments as eval_into) into a graph; returns its id."""
+        self._bind_stream()
+        res = self._result_desc(result)
+        arr = (C.c_int32 * len(props))(*props)
+        g = C.c_int32()
+        _check(self.lib.ltl4c_graph_eval(self.h, C.c_void_p(records.data_ptr() if n_events else 0), n_events, arr,
+                                         len(props), C.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                         C.byref(res), C.byref(g)), "ltl4c_graph_eval")
+        return g.value
+
+    def graph_eval_batch(self, records, offsets, props, verdict, counts, workspace):
+        """Capture one batch evaluation (same arguments as eval_batch_into); returns its id."""
+        self._bind_stream()
+        nt = len(offsets) - 1
+        off = (C.c_uint64 * (nt + 1))(*[int(x) for x in offsets])
+        arr = (C.c_int32 * len(props))(*props)
+        g = C.c_int32()
+        _check(self.lib.ltl4c_graph_eval_batch(self.h, C.c_void_p(records.data_ptr() if int(offsets[-1]) else 0),
+                                               off, nt, arr, len(props), C.c_void_p(workspace.data_ptr()),
+                                               workspace.numel(), C.c_void_p(verdict.data_ptr()),
+                                               C.c_void_p(counts.data_ptr()), C.byref(g)), "ltl4c_graph_eval_batch")
+        return g.value
+
+    def graph_launch(self, graph):
+        self._bind_stream()
+        _check(self.lib.ltl4c_graph_launch(self.h, graph), "ltl4c_graph_launch")
+
+    def graph_destroy(self, graph):
+        self._bind_stream()
+        _check(self.lib.ltl4c_graph_destroy(self.h, graph), "ltl4c_graph_destroy")
+
     def set_memory_budget(self, nbytes):
         _check(self.lib.ltl4c_set_memory_budget(self.h, nbytes), "ltl4c_set_memory_budget")
 
@@ -478,6 +579,20 @@ class StreamGroup:
         sq = (C.c_uint64 * n)(*[int(x) for x in seqs])
         _check(self.lib.ltl4c_group_push_seq(self.ctx.h, self.id, p, sz, st, sq, n, 1 if on_device else 0),
                "ltl4c_group_push_seq")
+
+    def capture_push(self, ptrs, sizes, streams):
+        """Capture a push of device chunks (as push_chunks) into a graph of the
+        context; every ctx.graph_launch(id) then pushes the chunks' current
+        contents.  Returns the graph id."""
+        self.ctx._bind_stream()
+        n = len(streams)
+        p = (C.c_void_p * n)(*[int(x) for x in ptrs])
+        sz = (C.c_uint64 * n)(*[int(x) for x in sizes])
+        st = (C.c_uint32 * n)(*[int(x) for x in streams])
+        g = C.c_int32()
+        _check(self.lib.ltl4c_graph_group_push(self.ctx.h, self.id, p, sz, st, n, C.byref(g)),
+               "ltl4c_graph_group_push")
+        return g.value
 
     def open_stream(self, stream, max_bindings, first_seq=0):
         self.ctx._bind_stream()

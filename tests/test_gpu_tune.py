@@ -1,0 +1,90 @@
+"""Autotuned kernel schedules: tuning times the tile shapes on the caller's
+data and keeps the fastest per shape class; evaluations under the tuned
+schedule equal the oracle; the table round-trips through its JSON file,
+which is keyed by the device architecture; a pinned tile wins over the
+table; a workspace sized before tuning still works."""
+import json
+
+import numpy as np
+import pytest
+
+from oracle.run import evaluate_workload
+from paper_1411_2239_amd import lib
+from paper_1411_2239_amd import workloads as W
+
+from _util import compare_full
+
+pytestmark = pytest.mark.gpu
+
+
+def test_tune_eval_then_results_match_oracle(tmp_path):
+    import torch
+    wl = W.gen_user_requests(n_events=400_000, n_users=800, seed=61)
+    print(f"[case] tune eval: {wl.n_events} events", flush=True)
+    ctx = lib.Context(0, use_tuned=False)
+    ctx.set_layout(wl.layout)
+    ids = [ctx.add_spec(p) for p in wl.props]
+    rec = torch.from_numpy(np.ascontiguousarray(wl.raw())).to("cuda:0")
+    n = wl.n_events
+    ws_before = ctx.workspace(n, ids)            # sized before tuning
+    t = ctx.tune(rec, ids, n_events=n, reps=3)
+    assert 0 <= t["sort_tile"] < 7 and 0 <= t["scan_tile"] < 4
+    assert t["candidates"] >= 2 and t["tuned_us"] <= t["default_us"] * 1.0001
+    o = evaluate_workload(wl)
+    # the tuned schedule, with a workspace of the new size and with the old one
+    for ws in (ctx.workspace(n, ids), ws_before):
+        r = ctx.alloc_result(len(ids), n, instances=True, nodes=True)
+        ctx.eval_into(rec, n, ids, r, ws)
+        ctx.wait()
+        compare_full(r, o, len(ids), 2)
+    # round trip through the file
+    path = str(tmp_path / "sched.json")
+    ctx.save_schedules(path)
+    doc = json.load(open(path))
+    assert doc["arch"].startswith("gfx") and len(doc["schedules"]) == 1
+    e = doc["schedules"][0]
+    assert (e["sort_tile"], e["scan_tile"]) == (t["sort_tile"], t["scan_tile"])
+    ctx2 = lib.Context(0, use_tuned=False)
+    assert ctx2.load_schedules(path) == 1
+    # another architecture's file is ignored
+    doc["arch"] = "gfx000"
+    other = str(tmp_path / "other.json")
+    json.dump(doc, open(other, "w"))
+    assert ctx2.load_schedules(other) == 0
+    bad = str(tmp_path / "bad.json")
+    open(bad, "w").write('{"arch": "%s", "schedules": [{"batch": 0, "sort_tile": 99}]}' % doc["arch"])
+    with pytest.raises(lib.LTL4CError):
+        ctx2.load_schedules(bad)
+    ctx2.close()
+    ctx.close()
+
+
+def test_tune_batch_and_pinned_tile():
+    import torch
+    wl, offsets = W.gen_batch(64, 50, 20000, seed=62, n_props=16)
+    print(f"[case] tune batch: 64 traces, {wl.n_events} events", flush=True)
+    ctx = lib.Context(0, use_tuned=False)
+    ctx.set_layout(wl.layout)
+    ids = [ctx.add_spec(p) for p in wl.props]
+    rec = torch.from_numpy(np.ascontiguousarray(wl.raw())).to("cuda:0")
+    t = ctx.tune(rec, ids, offsets=offsets, reps=2)
+    assert t["candidates"] >= 2
+    for pin in (None, 3):
+        if pin is not None:
+            ctx.set_option(lib.OPT_SORT_TILE, pin)
+        v, c = ctx.eval_batch(rec, offsets, ids)
+        for tr in range(0, 64, 7):
+            o = evaluate_workload(wl, records=wl.records[offsets[tr]:offsets[tr + 1]])
+            assert np.array_equal(v[tr], o.root_verdict) and np.array_equal(c[tr], o.root_counts.astype(np.int64))
+    ctx.set_option(lib.OPT_SORT_TILE, -1)
+    ctx.clear_schedules()
+    ctx.close()
+
+
+def test_committed_schedules_load_on_this_device():
+    import os
+    if not os.path.exists(lib.SCHEDULES_PATH):
+        pytest.skip("no committed schedule table")
+    ctx = lib.Context(0)
+    assert ctx.schedules_loaded > 0
+    ctx.close()
