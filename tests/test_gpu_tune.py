@@ -46,13 +46,17 @@ def test_tune_eval_then_results_match_oracle(tmp_path):
     assert (e["sort_tile"], e["scan_tile"]) == (t["sort_tile"], t["scan_tile"])
     ctx2 = lib.Context(0, use_tuned=False)
     assert ctx2.load_schedules(path) == 1
+    arch = doc["arch"]
     # another architecture's file is ignored
     doc["arch"] = "gfx000"
     other = str(tmp_path / "other.json")
     json.dump(doc, open(other, "w"))
     assert ctx2.load_schedules(other) == 0
     bad = str(tmp_path / "bad.json")
-    open(bad, "w").write('{"arch": "%s", "schedules": [{"batch": 0, "sort_tile": 99}]}' % doc["arch"])
+    # an entry of this architecture with a tile out of range is an error
+    with open(bad, "w") as fh:
+        fh.write('{"arch": "%s", "schedules": [{"batch": 0, "key_bits": 36, "props": 1, "big_monitors": 0, '
+                 '"levels": 2, "log2_events": 18, "sort_tile": 99, "scan_tile": 0}]}' % arch)
     with pytest.raises(lib.LTL4CError):
         ctx2.load_schedules(bad)
     ctx2.close()
