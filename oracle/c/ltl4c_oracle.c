@@ -7,12 +7,17 @@
  *
  * What it computes (paper sections in brackets):
  *   1. the value vector of every event from its key fields (Eq. 5,
- *      Section 4.1); an event that lacks a key joins no cluster; its letter
+ *      Section 4.1); an event that lacks a key joins no cluster, except, when
+ *      the layout asks for parent events, one that carries every key but the
+ *      innermost: it joins the cluster of every instance under its parent
+ *      (reading stated below); its letter
  *      from its type and, when declared, from comparisons of record fields
  *      with constants (the data predicates of Section 5's cloud-storage
  *      case study);
  *   2. the clusters u^D: events grouped by vector, trace order kept inside a
- *      group (Section 2.4.3) -- a plain qsort on (vector, position);
+ *      group (Section 2.4.3) -- a plain qsort on (vector, position); with
+ *      parent events, u^D is the merge by trace position of D's own events
+ *      and the parent events whose keys equal the first n-1 values of D;
  *   3. the leaf verdict lambda(delta(q0, u^D)) of every instance (Def. 6),
  *      stepping the monitor table one event at a time; on the way, the
  *      verdict after every event (stored at the event's trace position) and
@@ -50,6 +55,14 @@ typedef struct {
      * 2^(pred_shift + i) for every holding predicate i */
     uint32_t n_preds, pred_shift;
     uint32_t pred_offset[3], pred_bytes[3], pred_op[3], pred_value[3];
+    /* parent events (the proxy-cache case study of Section 5: per-video
+     * events observed by every request of the video): when set, an event
+     * whose type carries keys 0..n_keys-2 and not key n_keys-1 (for one
+     * level: no key) belongs to the cluster u^D of every instance D whose
+     * first n_keys-1 values equal its own, at its trace position.  It makes
+     * no instance and no node, as the set of value vectors of Eq. 5 holds
+     * only complete vectors.  Such events report no per-event verdict. */
+    uint32_t parent_events;
 } ora_layout;
 
 /* comparison codes of a data predicate: < <= > >= == != */
@@ -80,7 +93,8 @@ typedef struct {
     uint64_t n_events;
     uint8_t *event_verdict;           /* [n_props * n_events], trace order: the verdict of the
                                          event's instance on its prefix ending at the event;
-                                         0xFF for an event of no cluster */
+                                         0xFF for an event of no cluster and for a
+                                         parent event (it is in several) */
     uint64_t level_nodes[4];          /* nodes at level m (prefix length m) */
     uint32_t *level_keys[4];          /* [nodes * m] */
     uint64_t *level_counts[4];        /* [n_props * nodes * 6] */
@@ -184,6 +198,13 @@ static int ev_cmp(const void *a, const void *b) {
     return x->pos < y->pos ? -1 : (x->pos > y->pos ? 1 : 0);
 }
 
+/* lexicographic a < b on the first m values */
+static int prefix_less(const uint32_t *a, const uint32_t *b, int m) {
+    for (int i = 0; i < m; ++i)
+        if (a[i] != b[i]) return a[i] < b[i];
+    return 0;
+}
+
 static int same_prefix(const uint32_t *a, const uint32_t *b, int m) {
     for (int i = 0; i < m; ++i)
         if (a[i] != b[i]) return 0;
@@ -210,25 +231,35 @@ ora_result *ora_eval(const uint8_t *records, uint64_t n, const ora_layout *L,
     if (nk < 1 || nk > 4 || n_props < 1) return NULL;
     uint32_t need = (1u << nk) - 1;
     ev_t *ev = (ev_t *)malloc(sizeof(ev_t) * (n ? n : 1));
-    if (!ev) return NULL;
-    uint64_t ne = 0;
+    ev_t *pev = (ev_t *)malloc(sizeof(ev_t) * (L->parent_events && n ? n : 1));
+    if (!ev || !pev) {
+        free(ev);
+        free(pev);
+        return NULL;
+    }
+    uint64_t ne = 0, npe = 0;
     for (uint64_t i = 0; i < n; ++i) {
         const uint8_t *rec = records + i * L->record_bytes;
         uint32_t type = read_field(rec, L->type_offset, L->type_bytes);
         if (type >= 256) continue;
-        if ((L->key_present[type] & need) != need) continue;
+        const uint32_t kp = L->key_present[type] & need;
+        const int parent = L->parent_events && kp == (need >> 1);
+        if (kp != need && !parent) continue;
         ev_t e;
         memset(&e, 0, sizeof e);
-        for (int m = 0; m < nk; ++m) e.key[m] = read_field(rec, L->key_offset[m], L->key_bytes[m]);
+        for (int m = 0; m < nk - parent; ++m) e.key[m] = read_field(rec, L->key_offset[m], L->key_bytes[m]);
         e.pos = i;
         e.cls = L->class_of_type[type];
         for (uint32_t q = 0; q < L->n_preds && q < 3; ++q)
             if (pred_true(L->pred_op[q], read_field(rec, L->pred_offset[q], L->pred_bytes[q]), L->pred_value[q]))
                 e.cls += 1u << (L->pred_shift + q);
-        ev[ne++] = e;
+        if (parent) pev[npe++] = e;
+        else ev[ne++] = e;
     }
     g_nk = nk;
     qsort(ev, ne, sizeof(ev_t), ev_cmp);
+    g_nk = nk - 1;   /* parent events: by (first n-1 values, position) */
+    qsort(pev, npe, sizeof(ev_t), ev_cmp);
 
     ora_result *r = (ora_result *)calloc(1, sizeof(ora_result));
     r->n_props = n_props;
@@ -256,15 +287,36 @@ ora_result *ora_eval(const uint8_t *records, uint64_t n, const ora_layout *L,
             const uint8_t l0 = P[p].label[state[p]];
             r->inst_conc[(uint64_t)p * ni + inst] = (l0 == V_TOP || l0 == V_BOT) ? 0u : ORA_NEVER;
         }
-        while (j < ne && same_prefix(ev[j].key, ev[i].key, nk)) {
-            for (int p = 0; p < n_props; ++p) {
-                state[p] = P[p].delta[(uint64_t)state[p] * P[p].n_classes + ev[j].cls];
-                const uint8_t l = P[p].label[state[p]];
-                r->event_verdict[(uint64_t)p * n + ev[j].pos] = l;
-                uint32_t *c = &r->inst_conc[(uint64_t)p * ni + inst];
-                if (*c == ORA_NEVER && (l == V_TOP || l == V_BOT)) *c = (uint32_t)(j - i + 1);
+        /* the parent events of this instance: those whose n-1 values equal
+           its first n-1 values (a contiguous run of pev, found by a plain
+           binary search for the first one not below the prefix) */
+        uint64_t pa = npe, pb = npe;
+        if (npe) {
+            uint64_t lo = 0, hi = npe;
+            while (lo < hi) {
+                const uint64_t mid = (lo + hi) / 2;
+                if (prefix_less(pev[mid].key, ev[i].key, nk - 1)) lo = mid + 1;
+                else hi = mid;
             }
-            ++j;
+            pa = pb = lo;
+            while (pb < npe && same_prefix(pev[pb].key, ev[i].key, nk - 1)) ++pb;
+        }
+        /* walk u^D: own events and parent events merged by trace position */
+        uint64_t steps = 0;
+        while ((j < ne && same_prefix(ev[j].key, ev[i].key, nk)) || pa < pb) {
+            const int own_left = j < ne && same_prefix(ev[j].key, ev[i].key, nk);
+            const int take_own = own_left && (pa >= pb || ev[j].pos < pev[pa].pos);
+            const ev_t *e = take_own ? &ev[j] : &pev[pa];
+            ++steps;
+            for (int p = 0; p < n_props; ++p) {
+                state[p] = P[p].delta[(uint64_t)state[p] * P[p].n_classes + e->cls];
+                const uint8_t l = P[p].label[state[p]];
+                if (take_own) r->event_verdict[(uint64_t)p * n + e->pos] = l;
+                uint32_t *c = &r->inst_conc[(uint64_t)p * ni + inst];
+                if (*c == ORA_NEVER && (l == V_TOP || l == V_BOT)) *c = (uint32_t)steps;
+            }
+            if (take_own) ++j;
+            else ++pa;
         }
         memcpy(r->inst_keys + inst * nk, ev[i].key, sizeof(uint32_t) * nk);
         for (int p = 0; p < n_props; ++p) r->inst_verdict[(uint64_t)p * ni + inst] = P[p].label[state[p]];
@@ -273,6 +325,7 @@ ora_result *ora_eval(const uint8_t *records, uint64_t n, const ora_layout *L,
     }
     free(state);
     free(ev);
+    free(pev);
 
     /* quantifier levels from the innermost (nk-1) out to the root (0) */
     const uint32_t *child_keys = r->inst_keys;

@@ -30,6 +30,13 @@ Readings (each one is listed in the design notes):
   counts are integers >= 0.
 * With no children (N = 0) the same rules apply with all counts zero.
 * An event that lacks the key of any quantifier joins no cluster.
+* Parent events (an option; the proxy-cache case study of Section 5 observes
+  per-video events in every request of the video): an event that carries the
+  values of x_0..x_{n-2} but none for x_{n-1} joins u^D for every D in the set
+  of value vectors (Eq. 5) whose first n-1 values are its own, at its trace
+  position.  It adds no vector to that set, so it makes no instance and no
+  node.  For a single quantifier this is an event with no key, which joins
+  every cluster.
 """
 from __future__ import annotations
 
@@ -127,12 +134,13 @@ def valuate(kind, op, const, v):
     return BOT_C
 
 
-def evaluate(events, quants, leaf):
+def evaluate(events, quants, leaf, parent_events=False):
     """Evaluate phi = Q_0 ... Q_{n-1} psi on a trace.
 
     events : sequence of (letter, key) in trace order; key is a tuple of the n
              values the event carries for x_0..x_{n-1}, or None when the event
-             lacks one of them.
+             lacks one of them.  With parent_events, a key of n-1 values marks
+             a parent event (see the module header).
     quants : [(kind, op, const)] for Q_0 .. Q_{n-1}.
     leaf   : function from a non-empty list of letters (a cluster, in trace
              order) to its LTL4 verdict.
@@ -146,9 +154,17 @@ def evaluate(events, quants, leaf):
     for letter, key in events:
         if key is None:
             continue
+        if len(key) == n - 1 and parent_events:
+            continue
         if len(key) != n:
             raise ValueError("key length must equal the number of quantifiers")
         clusters.setdefault(tuple(key), []).append(letter)
+    if parent_events:
+        # u^D written out: every event, in trace order, whose values are D's
+        # or, for a parent event, the first n-1 of D's
+        for d in clusters:
+            clusters[d] = [letter for letter, key in events
+                           if key is not None and (tuple(key) == d or (len(key) == n - 1 and tuple(key) == d[:n - 1]))]
     verdict = {d: leaf(word) for d, word in clusters.items()}
     leaves = dict(verdict)
     nodes = {}

@@ -41,7 +41,8 @@ class _Layout(C.Structure):
                 ("class_of_type", C.POINTER(C.c_uint8)), ("key_present", C.POINTER(C.c_uint8)),
                 ("n_preds", C.c_uint32), ("pred_shift", C.c_uint32),
                 ("pred_offset", C.c_uint32 * 3), ("pred_bytes", C.c_uint32 * 3),
-                ("pred_op", C.c_uint32 * 3), ("pred_value", C.c_uint32 * 3)]
+                ("pred_op", C.c_uint32 * 3), ("pred_value", C.c_uint32 * 3),
+                ("parent_events", C.c_uint32)]
 
 
 class _Prop(C.Structure):
@@ -118,9 +119,11 @@ class OracleResult:
 
 
 def evaluate_records(records, record_bytes, type_offset, type_bytes, key_offsets, key_bytes,
-                     class_of_type, key_present, props, preds=(), pred_shift=0):
+                     class_of_type, key_present, props, preds=(), pred_shift=0, parent_events=False):
     """Run the C oracle.  `records` is a uint8 buffer of n * record_bytes bytes.
-    preds: data predicates (offset, bytes, op, value), op 0..5 = < <= > >= == !=."""
+    preds: data predicates (offset, bytes, op, value), op 0..5 = < <= > >= == !=.
+    parent_events: an event whose type carries every key but the innermost
+    joins the cluster of every instance under its parent (see the C file)."""
     lib = _load()
     buf = np.ascontiguousarray(records).view(np.uint8).reshape(-1)
     n = buf.size // record_bytes
@@ -134,6 +137,7 @@ def evaluate_records(records, record_bytes, type_offset, type_bytes, key_offsets
                   cot.ctypes.data_as(C.POINTER(C.c_uint8)), kp.ctypes.data_as(C.POINTER(C.c_uint8)))
     if len(preds) > 3:
         raise ValueError("at most 3 data predicates")
+    lay.parent_events = 1 if parent_events else 0
     lay.n_preds = len(preds)
     lay.pred_shift = pred_shift
     for q, (off, nb, op, val) in enumerate(preds):

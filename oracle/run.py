@@ -45,4 +45,5 @@ def evaluate_workload(wl, specs=None, records=None):
     return cref.evaluate_records(recs, lay.record_bytes, lay.type_offset, lay.type_bytes,
                                  lay.key_offsets, lay.key_bytes, lay.class_of_type, lay.key_present,
                                  [oracle_property(s, lay) for s in specs],
-                                 preds=lay.preds, pred_shift=lay.pred_shift)
+                                 preds=lay.preds, pred_shift=lay.pred_shift,
+                                 parent_events=getattr(lay, "parent_events", False))

@@ -37,6 +37,9 @@ class Layout:
     # an event's class is class_of_type[type] + (holding predicates' bits) << pred_shift
     preds: list = field(default_factory=list)
     pred_shift: int = 0
+    # parent events: an event whose type carries every key but the innermost
+    # joins the cluster of every instance under its parent
+    parent_events: bool = False
 
     @property
     def n_keys(self):
