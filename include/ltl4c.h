@@ -91,6 +91,19 @@ typedef struct ltl4c_ctx ltl4c_ctx;
  * which must stay below n_classes for every type and predicate outcome
  * (checked by ltl4c_set_layout).  n_preds = 0 leaves the class as
  * class_of_type[type].
+ *
+ * Parent events (parent_events = 1; the proxy-cache case study of Section 5,
+ * where per-video events such as a cache insertion bear on every request of
+ * the video): an event whose type carries keys 0 .. n_keys-2 and not key
+ * n_keys-1 (for n_keys = 1: a type with no key) is a parent event.  It joins
+ * the cluster u^D of every instance D whose first n_keys-1 values equal its
+ * own, at its place in trace order; it creates no instance and no quantifier
+ * node (the value vectors of Eq. 5 are the complete ones).  Events lacking
+ * any other set of keys stay excluded.  The trace index of every event then
+ * rides in the sort word: key bits + 1 + ceil(log2 n) + class bits must not
+ * exceed 62, else ltl4c_eval reports LTL4C_EUNSUPPORTED.  Parent events are
+ * supported by ltl4c_eval (and its graph and no-allocation forms), not by
+ * batches or stream groups, and not with the verdict timeline outputs.
  */
 enum { LTL4C_CMP_LT = 0, LTL4C_CMP_LE = 1, LTL4C_CMP_GT = 2, LTL4C_CMP_GE = 3, LTL4C_CMP_EQ = 4, LTL4C_CMP_NE = 5 };
 
@@ -115,6 +128,7 @@ typedef struct {
     uint32_t n_preds;                /* data predicates, 0..3 */
     uint32_t pred_shift;             /* class bit of predicate 0 */
     ltl4c_pred pred[3];
+    uint32_t parent_events;          /* 0 or 1, see above */
 } ltl4c_layout;
 
 /*

@@ -84,6 +84,12 @@ struct ClassifyArgs {
     uint32_t n_chunks;
     uint32_t stream_shift;
     uint32_t vec_ok;                 // every record address is 16-byte aligned (16-byte records)
+    // parent events: a type whose key_present bits (within need_mask) equal
+    // parent_mask carries every key but the innermost; such an event gets
+    // the innermost key 0 and the kind bit at stream_shift, and is counted in
+    // n_par.  parent_mask > need_mask: no parent events.
+    uint32_t parent_mask;
+    uint32_t* n_par;
 };
 
 struct SortPassArgs {
@@ -255,7 +261,43 @@ struct BatchOutArgs {
     uint64_t* counts;                    // [n_traces][P][6]
 };
 
-// Launchers (defined in kernels.hip).
+// Parent events (an event with the keys of every level but the innermost
+// joins every instance under its parent): after the radix sort the own events
+// fill [0, n_own) of `words` and the parent events [n_own, n_own + n_par),
+// the latter in (prefix, trace index) order.
+constexpr int kPeThreads = 256;
+constexpr int kPeItems = 16;
+constexpr int kPeTile = kPeThreads * kPeItems;
+constexpr int kPeMaxTreeLevels = 33;
+struct ParentArgs {
+    const uint64_t* words;
+    const uint32_t* n_kept;              // events kept by classify (own + parent)
+    uint32_t* n_par;                     // parent events (classify counts them)
+    uint32_t* n_own;                     // own events (k_pe_counts)
+    uint32_t cbits;                      // class bits
+    uint32_t class_mask;
+    uint32_t ibits;                      // trace index bits above the class
+    uint64_t index_mask;
+    uint32_t key_shift;                  // word >> key_shift: the packed key (instance identity)
+    uint32_t prefix_shift;               // (word >> prefix_shift) & prefix_mask: keys 0..n-2
+    uint64_t prefix_mask;
+    uint32_t n_props;
+    const Plan* plan;
+    uint4* tree;                         // segment tree levels 1..: [level][p][tree_cnt[level]]
+    uint64_t tree_off[kPeMaxTreeLevels]; // in uint4 units
+    uint64_t tree_cnt[kPeMaxTreeLevels];
+    uint32_t* g_out;                     // reduce pass: G_i of every own event
+    const uint32_t* g_in;                // down pass: the same, read back
+    uint4* tile_agg;                     // [tiles][P]
+    uint4* tile_prefix;                  // [tiles][P]
+    uint32_t* tile_heads;                // [tiles]
+    uint32_t* tile_head_prefix;          // [tiles]
+    uint8_t* inst_verdict;               // [P][inst_stride]
+    uint64_t inst_stride, inst_limit;
+    uint32_t* err;
+};
+
+// Launchers (defined in kernels.hip and parent.hip).
 hipError_t launch_zero(const ZeroArgs& a, uint32_t blocks, hipStream_t s);
 hipError_t launch_classify(const ClassifyArgs& a, hipStream_t s);
 hipError_t launch_sort_pass(const SortPassArgs& a, int variant, uint32_t digit_bits, hipStream_t s);
@@ -291,5 +333,9 @@ hipError_t launch_group_read(const GroupState& g, uint8_t* verdict, uint64_t* co
 hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, uint64_t n, uint8_t v, hipStream_t s);
 hipError_t launch_batch_out(const BatchOutArgs& a, hipStream_t s);
+hipError_t launch_parent_counts(const ParentArgs& a, hipStream_t s);
+hipError_t launch_parent_tree(const ParentArgs& a, uint32_t level, uint64_t max_nodes, hipStream_t s);
+hipError_t launch_parent_pass(const ParentArgs& a, bool down, uint64_t max_tiles, hipStream_t s);
+hipError_t launch_parent_spine(const ParentArgs& a, hipStream_t s);
 
 }  // namespace ltl4c

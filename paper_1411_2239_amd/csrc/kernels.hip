@@ -202,7 +202,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         for (uint32_t i = threadIdx.x; i < a.n_chunks; i += blockDim.x) s_cstream[i] = a.chunk_stream[i];
     }
     __syncthreads();
-    uint32_t err = 0, kept = 0;
+    uint32_t err = 0, kept = 0, npar = 0;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     // Records of one grid-stride step are loaded before any is processed, so
     // that each thread keeps U loads in flight.
@@ -211,18 +211,26 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     auto process = [&](uint64_t i, uint32_t t, const uint32_t* f, uint32_t pm, uint32_t chunk) {
         bool ok = !(a.check_type_range && t > 255u);
         const uint32_t t8 = t & 255u;
-        ok = ok && ((s_kp[t8] & a.need_mask) == a.need_mask);
+        const uint32_t kpm = s_kp[t8] & a.need_mask;
+        // a parent event: every key but the innermost, which it takes as 0
+        const bool par = ok && kpm == a.parent_mask;
+        ok = ok && (kpm == a.need_mask || par);
         uint64_t key = 0;
         uint32_t over = 0;
 #pragma unroll
         for (int m = 0; m < kMaxLevels; ++m) {
             if (m < (int)a.n_keys) {
                 const uint32_t b = a.key_bits[m];
-                over |= b < 32 ? (f[m] >> b) : 0u;
-                key = (key << b) | f[m];
+                const uint32_t v = par && m + 1 == (int)a.n_keys ? 0u : f[m];
+                over |= b < 32 ? (v >> b) : 0u;
+                key = (key << b) | v;
             }
         }
         if (ok && over) err |= kErrRange;
+        if (par) {
+            key |= 1ull << a.stream_shift;
+            ++npar;
+        }
         if constexpr (GROUP) key |= (uint64_t)s_cstream[chunk] << a.stream_shift;
         // [key][trace index, when asked for][class]
         const uint64_t word = ok ? ((key << (a.cbits + a.ibits)) | (a.ibits ? i << a.cbits : 0ull) |
@@ -295,6 +303,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         }
     }
     if (err) atomicOr(a.err, err);
+    if (a.n_par) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) npar += __shfl_xor(npar, off, 64);
+        if ((threadIdx.x & 63) == 0 && npar) atomicAdd(a.n_par, npar);
+    }
     if (a.n_valid) {
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) kept += __shfl_xor(kept, off, 64);

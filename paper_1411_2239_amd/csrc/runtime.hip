@@ -149,6 +149,7 @@ struct Geometry {
     uint32_t n_levels;                      // levels of the monitor tree (quantifier nodes 0..n_levels-1)
     bool excl;
     uint32_t prefix_bits[kMaxLevels];       // bits of the packed prefix that identifies a level-m node
+    bool parent;                            // parent events: a kind bit above the keys (1 = parent event)
 };
 
 // stream_is_level: the id above the keys is a tree level of its own (batches
@@ -161,9 +162,12 @@ Geometry geometry(const ltl4c_layout& L, uint32_t stream_bits = 0, bool stream_i
                   bool compact = false, bool wide = false) {
     Geometry g{};
     g.cbits = bits_for(L.n_classes);
-    g.stream_bits = stream_bits;
+    // parent events sort after all own events on a kind bit above the keys,
+    // placed like a stream id that is not a tree level
+    g.parent = L.parent_events != 0;
+    g.stream_bits = stream_bits + (g.parent ? 1u : 0u);
     g.n_levels = L.n_keys + (stream_is_level ? 1u : 0u);
-    uint32_t kb = stream_bits;
+    uint32_t kb = g.stream_bits;
     const uint32_t shift = stream_is_level ? 1u : 0u;
     if (stream_is_level) g.prefix_bits[0] = 0;
     for (uint32_t m = 0; m < L.n_keys; ++m) {
@@ -172,7 +176,7 @@ Geometry geometry(const ltl4c_layout& L, uint32_t stream_bits = 0, bool stream_i
     }
     g.key_bits_total = kb;
     const uint32_t need = (1u << L.n_keys) - 1u;
-    g.excl = L.type_bytes > 1;
+    g.excl = L.type_bytes > 1 || g.parent;
     for (int t = 0; t < 256 && !g.excl; ++t)
         if ((L.key_present[t] & need) != need) g.excl = true;
     g.compact = compact && g.excl && kb > 0;
@@ -193,6 +197,10 @@ struct WsLayout {
     uint64_t node_start_off[kMaxLevels], counts_off[kMaxLevels];
     uint64_t cap_node[kMaxLevels];
     uint32_t tiles_sort, tiles_scan;
+    // parent events
+    uint64_t pe_g_off, pe_tree_off, pe_tile_agg_off, pe_tile_prefix_off, pe_tile_heads_off, pe_tile_hprefix_off;
+    uint64_t pe_tree_lvl[kPeMaxTreeLevels], pe_tree_cnt[kPeMaxTreeLevels];
+    uint32_t pe_levels, pe_tiles;
 };
 
 // Properties share scan launches by monitor size: up to 8 whose monitors have
@@ -284,6 +292,26 @@ WsLayout plan_workspace(const ltl4c_layout& L, const Geometry& g, uint64_t n, ui
         w.node_start_off[m] = off; off = align256(off + cap * 4);
         w.counts_off[m] = off;     off = align256(off + (uint64_t)P * cap * 6 * 4);
     }
+    if (g.parent) {
+        // G_i per own event, the segment tree over the parent events (levels
+        // 1 .. ceil(log2 n), per property), and the tile aggregates and prefixes
+        w.pe_g_off = off; off = align256(off + 4 * std::max<uint64_t>(n, 1));
+        w.pe_levels = 0;
+        uint64_t nodes = 0;
+        for (uint32_t lv = 1; lv < (uint32_t)kPeMaxTreeLevels && (1ull << (lv - 1)) < n; ++lv) {
+            w.pe_tree_cnt[lv] = (n + (1ull << lv) - 1) >> lv;
+            w.pe_tree_lvl[lv] = nodes;
+            nodes += (uint64_t)P * w.pe_tree_cnt[lv];
+            w.pe_levels = lv;
+        }
+        w.pe_tree_off = off; off = align256(off + 16 * std::max<uint64_t>(nodes, 1));
+        w.pe_tiles = (uint32_t)((n + kPeTile - 1) / kPeTile);
+        const uint64_t t = std::max<uint32_t>(w.pe_tiles, 1);
+        w.pe_tile_agg_off = off;     off = align256(off + 16 * t * P);
+        w.pe_tile_prefix_off = off;  off = align256(off + 16 * t * P);
+        w.pe_tile_heads_off = off;   off = align256(off + 4 * t);
+        w.pe_tile_hprefix_off = off; off = align256(off + 4 * t);
+    }
     w.total = off;
     return w;
 }
@@ -315,6 +343,7 @@ int32_t check_layout(const ltl4c_layout* L) {
     for (int t = 0; t < 256; ++t)
         if ((uint32_t)L->class_of_type[t] + pred_top >= L->n_classes)
             return fail(LTL4C_EINVAL, "class_of_type entry (plus predicate bits) >= n_classes");
+    if (L->parent_events > 1) return fail(LTL4C_EINVAL, "parent_events must be 0 or 1");
     Geometry g = geometry(*L);
     if (g.cbits + g.key_bits_total + (g.excl ? 1 : 0) > 63)
         return fail(LTL4C_EUNSUPPORTED, "packed binding key plus class bits exceed 63 bits");
@@ -502,6 +531,8 @@ int32_t enqueue_front(ltl4c_ctx* ctx, const ltl4c_layout& L, const Geometry& g, 
     ca.n_chunks = n_chunks;
     ca.vec_ok = vec_ok ? 1u : 0u;
     ca.stream_shift = g.key_bits_total - g.stream_bits;
+    ca.parent_mask = g.parent ? ca.need_mask >> 1 : 0xFFFFFFFFu;
+    ca.n_par = g.parent ? z + w.n_valid_off + 1 : nullptr;
     s = launch(ctx, "classify", [&] { return launch_classify(ca, st); });
     if (s) return s;
     uint64_t* in = words_a;
@@ -649,6 +680,7 @@ int32_t group_configure(ltl4c_ctx* ctx, GroupHost& G, const int32_t* props, int3
     if (max_batch < 1 || max_batch > LTL4C_MAX_EVENTS) return fail(LTL4C_EUNSUPPORTED, "max_batch out of range");
     if (table_bindings > (1ull << 31)) return fail(LTL4C_EUNSUPPORTED, "the group's bindings exceed 2^31");
     const ltl4c_layout& L = ctx->layout;
+    if (L.parent_events) return fail(LTL4C_EUNSUPPORTED, "stream groups do not take layouts with parent events");
     G.props.assign(props, props + n_props);
     G.P = (uint32_t)n_props;
     G.S = max_streams;
@@ -966,6 +998,18 @@ static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, v
         if (s) return s;
     }
 
+    // parent events: the own events are the first n_own sorted words
+    uint32_t* n_own = g.parent ? z + w.n_valid_off + 2 : nullptr;
+    ParentArgs pa{};
+    if (g.parent && n > 0) {
+        pa.words = sorted;
+        pa.n_kept = z + w.n_valid_off;
+        pa.n_par = z + w.n_valid_off + 1;
+        pa.n_own = n_own;
+        s = launch(ctx, "parent", [&] { return launch_parent_counts(pa, st); });
+        if (s) return s;
+    }
+
     // per-instance arrays: the verdicts always exist (caller's or workspace)
     uint8_t* inst_verdict = out->inst_verdict ? out->inst_verdict : ws + w.inst_verdict_off;
     const uint64_t inst_stride = out->inst_verdict ? out->capacity : std::max<uint64_t>(n, 1);
@@ -1000,7 +1044,7 @@ static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, v
         ScanArgs sa{};
         sa.words = sorted;
         sa.n = (uint32_t)n;
-        sa.n_dev = g.compact ? z + w.n_valid_off : nullptr;   // the first radix pass dropped excluded events
+        sa.n_dev = g.parent ? n_own : g.compact ? z + w.n_valid_off : nullptr;   // the first radix pass dropped excluded events
         sa.cbits = g.cbits + g.ibits;                        // where the key starts
         sa.class_mask = (1u << g.cbits) - 1u;
         sa.index_shift = g.cbits;
@@ -1040,7 +1084,8 @@ static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, v
         sa.err = ctx->err_dev;
         // one launch per property group, each with its own look-back rows and
         // ticket; the first one also writes the numbering
-        for (size_t gi = 0; gi < groups.size(); ++gi) {
+        // (with parent events only the numbering launch: the verdicts come after)
+        for (size_t gi = 0; gi < (g.parent ? 1 : groups.size()); ++gi) {
             sa.n_props = groups[gi].cnt;
             std::memcpy(sa.prop_idx, groups[gi].idx, sizeof sa.prop_idx);
             sa.max_states = groups[gi].states;
@@ -1051,6 +1096,46 @@ static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, v
             if (s) return s;
         }
 
+        if (g.parent) {
+            // every instance's verdict with its parent events merged in
+            pa.cbits = g.cbits;
+            pa.class_mask = (1u << g.cbits) - 1u;
+            pa.ibits = g.ibits;
+            pa.index_mask = g.ibits ? (1ull << g.ibits) - 1ull : 0ull;
+            pa.key_shift = g.cbits + g.ibits;
+            pa.prefix_shift = pa.key_shift + L.key_bits[L.n_keys - 1];
+            const uint32_t pbits = g.key_bits_total - g.stream_bits - L.key_bits[L.n_keys - 1];
+            pa.prefix_mask = pbits ? (1ull << pbits) - 1ull : 0ull;
+            pa.n_props = P;
+            pa.plan = plan;
+            pa.tree = reinterpret_cast<uint4*>(ws + w.pe_tree_off);
+            for (uint32_t lv = 1; lv <= w.pe_levels; ++lv) {
+                pa.tree_off[lv] = w.pe_tree_lvl[lv];
+                pa.tree_cnt[lv] = w.pe_tree_cnt[lv];
+            }
+            pa.tile_agg = reinterpret_cast<uint4*>(ws + w.pe_tile_agg_off);
+            pa.tile_prefix = reinterpret_cast<uint4*>(ws + w.pe_tile_prefix_off);
+            pa.tile_heads = reinterpret_cast<uint32_t*>(ws + w.pe_tile_heads_off);
+            pa.tile_head_prefix = reinterpret_cast<uint32_t*>(ws + w.pe_tile_hprefix_off);
+            pa.inst_verdict = inst_verdict;
+            pa.inst_stride = inst_stride;
+            pa.inst_limit = inst_stride;
+            pa.err = ctx->err_dev;
+            for (uint32_t lv = 1; lv <= w.pe_levels; ++lv) {
+                s = launch(ctx, "parent", [&] { return launch_parent_tree(pa, lv, w.pe_tree_cnt[lv], st); });
+                if (s) return s;
+            }
+            uint32_t* gbuf = reinterpret_cast<uint32_t*>(ws + w.pe_g_off);
+            pa.g_out = gbuf;
+            s = launch(ctx, "parent", [&] { return launch_parent_pass(pa, false, w.pe_tiles, st); });
+            if (s) return s;
+            s = launch(ctx, "parent", [&] { return launch_parent_spine(pa, st); });
+            if (s) return s;
+            pa.g_out = nullptr;
+            pa.g_in = gbuf;
+            s = launch(ctx, "parent", [&] { return launch_parent_pass(pa, true, w.pe_tiles, st); });
+            if (s) return s;
+        }
         if (out->inst_conclusive) {
             InstConclusiveArgs ia{};
             ia.inst_conc = out->inst_conclusive;
@@ -1178,6 +1263,14 @@ static int32_t eval_impl(ltl4c_ctx* ctx, const void* d_records, uint64_t n, cons
     }
     if ((out->inst_keys != nullptr) != (out->inst_verdict != nullptr))
         return fail(LTL4C_EINVAL, "inst_keys and inst_verdict are given together or not at all");
+    if (g.parent) {
+        if (out->event_verdict || out->inst_conclusive)
+            return fail(LTL4C_EUNSUPPORTED, "the verdict timeline is not available with parent events");
+        // the parent events are searched by (parent prefix, trace index)
+        g.ibits = std::max<uint32_t>(1, bits_for((uint32_t)std::max<uint64_t>(n, 1)));
+        if (g.cbits + g.ibits + g.key_bits_total + 1 > 63)
+            return fail(LTL4C_EUNSUPPORTED, "parent events: binding key, kind bit, class and trace index exceed 63 bits");
+    }
     if (out->event_verdict) {
         // the trace index rides in the sort word between the class and the key
         g.ibits = std::max<uint32_t>(1, bits_for((uint32_t)std::max<uint64_t>(n, 1)));
@@ -1254,6 +1347,7 @@ int32_t batch_layout(ltl4c_ctx* ctx, uint64_t n, int32_t n_traces, uint32_t P, u
     if (n_traces < 1 || n_traces > (int32_t)kMaxChunks) return fail(LTL4C_EUNSUPPORTED, "n_traces must be 1..4096");
     if (L.n_keys + 1 > (uint32_t)kMaxLevels)
         return fail(LTL4C_EUNSUPPORTED, "a batch takes properties with at most 3 quantifiers");
+    if (L.parent_events) return fail(LTL4C_EUNSUPPORTED, "batches do not take layouts with parent events");
     if (n > LTL4C_MAX_EVENTS) return fail(LTL4C_EUNSUPPORTED, "too many events for one call");
     b->g = geometry(L, std::max<uint32_t>(1, bits_for((uint32_t)n_traces)), true, true,
                     sort_threads(ctx->sort_variant) >= 512);

@@ -45,7 +45,8 @@ class Layout(C.Structure):
                 ("n_keys", C.c_uint32), ("key_offset", C.c_uint32 * 4), ("key_bytes", C.c_uint32 * 4),
                 ("key_bits", C.c_uint32 * 4), ("n_classes", C.c_uint32),
                 ("class_of_type", C.c_uint8 * 256), ("key_present", C.c_uint8 * 256),
-                ("n_preds", C.c_uint32), ("pred_shift", C.c_uint32), ("pred", C.c_uint32 * 12)]
+                ("n_preds", C.c_uint32), ("pred_shift", C.c_uint32), ("pred", C.c_uint32 * 12),
+                ("parent_events", C.c_uint32)]
 
 
 class MonitorDesc(C.Structure):
@@ -211,6 +212,7 @@ def layout_desc(layout):
     d.pred_shift = getattr(layout, "pred_shift", 0)
     for q, (off, nb, op, val) in enumerate(preds[:3]):
         d.pred[4 * q:4 * q + 4] = [off, nb, op, val]
+    d.parent_events = 1 if getattr(layout, "parent_events", False) else 0
     return d
 
 

@@ -298,6 +298,108 @@ def gen_prop_trace(n_events, n_keys, zipf_s, p_props=(0.02, 0.9, 0.5), seed=0, k
     return Workload(name, rec, lay, props or [])
 
 
+# --- proxy cache (Section 5, third case study) ---------------------------------
+# Event types of the proxy-cache trace.  A cache insertion or eviction names
+# only the video; a request and its progress and completion events name the
+# video and the request.  Every request event tells whether it was served from
+# the cache, fetched from outside, or fetched from outside although the video
+# was cached (the fault the case study looks for).
+PROXY_TYPES = {0: "insert", 1: "evict", 2: "request from cache", 3: "request fetched externally",
+               4: "request fetched externally while cached", 5: "progress", 6: "done"}
+
+
+def proxy_cache_layout(parent_events=True, vid_bits=12, req_bits=22):
+    """Two quantifier levels (video, request).  With parent_events the cache
+    insertions and evictions of a video join the cluster of every request of
+    the video."""
+    cot = np.zeros(256, dtype=np.uint8)
+    kp = np.zeros(256, dtype=np.uint8)
+    cot[:7] = np.arange(7)
+    kp[0:2] = 0b01
+    kp[2:7] = 0b11
+    class_props = [{"insert"}, {"evict"}, {"request", "cached"}, {"request", "external"},
+                   {"request", "external", "cached"}, {"progress"}, {"done"}]
+    return Layout(16, 4, 4, [8, 12], [4, 4], [vid_bits, req_bits], cot, kp, class_props, dict(PROXY_TYPES),
+                  parent_events=parent_events)
+
+
+def proxy_cache_properties():
+    """With parent events: at least 99% of videos have no request fetched
+    externally while the video was inserted and not yet evicted (the case
+    study's E=0 over requests, with the cache state taken from the video's
+    own events), and 95% of videos complete 90% of their requests."""
+    return [PropertySpec("F(insert & (!evict U external))", [("A", ">=", "99/100"), ("E", "=", 0)],
+                         "A>=0.99 v: E=0 r: F(insert & (!evict U external))"),
+            PropertySpec("G(request -> F done)", [("A", ">=", "19/20"), ("A", ">=", "9/10")],
+                         "A>=0.95 v: A>=0.9 r: G(request -> F done)")]
+
+
+def proxy_cache_literal_properties():
+    """The case study's formula as printed: the leaf is the proposition
+    cached & external, read at the first event of the request's cluster (its
+    request event, without parent events)."""
+    return [PropertySpec("cached & external", [("A", ">=", "99/100"), ("E", "=", 0)],
+                         "A>=0.99 v: E=0 r: cached & external")]
+
+
+def gen_proxy_cache(n_events=10_000_000, n_videos=4096, zipf_s=1.0, mean_changes=4.0, p_fault=0.002,
+                    mean_progress=1.5, p_done=0.95, seed=0x14112239 + 6, parent_events=True, literal=False):
+    """A proxy trace: requests for videos with Zipf popularity; each video's
+    cache state alternates at Poisson(mean_changes) random times (the first
+    change inserts it); a request while cached is served from the cache, but
+    with probability p_fault fetched externally; a request while not cached is
+    fetched externally.  Each request has Geometric(mean_progress) progress
+    events and, with probability p_done, a completion.  The trace is the
+    first n_events events in time order.  Keys: videos a seeded permutation of
+    0..n_videos-1, requests one of 0..R-1."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    per_req = 1.0 + mean_progress + p_done
+    n_req = int(n_events / per_req * 1.05) + 16
+    vid_rank = zipf_ranks(rng, n_req, n_videos, zipf_s)
+    t_req = rng.random(n_req)
+    # cache change points, per video in time order
+    n_chg = rng.poisson(mean_changes, size=n_videos)
+    chg_vid = np.repeat(np.arange(n_videos), n_chg)
+    chg_t = rng.random(chg_vid.size)
+    o = np.lexsort((chg_t, chg_vid))
+    chg_vid, chg_t = chg_vid[o], chg_t[o]
+    first = np.concatenate([[0], np.cumsum(n_chg)[:-1]])
+    chg_k = np.arange(chg_vid.size) - first[chg_vid]          # 0-based change index in the video
+    # the state at a request: the parity of the changes before it
+    before = np.searchsorted(chg_vid.astype(np.float64) + chg_t, vid_rank.astype(np.float64) + t_req) - first[vid_rank]
+    cached = (before & 1) == 1
+    fault = rng.random(n_req) < p_fault
+    req_type = np.where(cached, np.where(fault, 4, 2), 3).astype(np.uint32)
+    n_prog = rng.geometric(1.0 / (1.0 + mean_progress), size=n_req) - 1
+    done = rng.random(n_req) < p_done
+    gap = 1e-6
+    # events: requests, progress, completions, cache changes
+    prog_req = np.repeat(np.arange(n_req), n_prog)
+    prog_k = np.arange(prog_req.size) - np.repeat(np.cumsum(n_prog) - n_prog, n_prog)
+    t = np.concatenate([t_req, t_req[prog_req] + gap * (1 + prog_k) * rng.random(prog_req.size),
+                        t_req[done] + gap * (2 + n_prog[done]), chg_t])
+    typ = np.concatenate([req_type, np.full(prog_req.size, 5, np.uint32), np.full(int(done.sum()), 6, np.uint32),
+                          np.where(chg_k % 2 == 0, 0, 1).astype(np.uint32)])
+    vid = np.concatenate([vid_rank, vid_rank[prog_req], vid_rank[done], chg_vid])
+    req = np.concatenate([np.arange(n_req), prog_req, np.nonzero(done)[0], np.zeros(chg_vid.size, np.int64)])
+    order = np.argsort(t, kind="stable")[:n_events]
+    if order.size < n_events:
+        raise ValueError("generated too few events")
+    vid_key = rng.permutation(n_videos).astype(np.uint32)
+    req_key = rng.permutation(n_req).astype(np.uint32)
+    rec = np.zeros(n_events, dtype=REC16)
+    rec["ts"] = np.arange(n_events, dtype=np.uint32)
+    rec["type"] = typ[order]
+    rec["k0"] = vid_key[vid[order]]
+    parent = typ[order] < 2
+    rec["k1"] = np.where(parent, 0, req_key[req[order]])
+    vb = max(1, int(n_videos - 1).bit_length())
+    rb = max(1, int(n_req - 1).bit_length())
+    lay = proxy_cache_layout(parent_events and not literal, vb, rb)
+    props = proxy_cache_literal_properties() if literal else proxy_cache_properties()
+    return Workload("proxy", rec, lay, props)
+
+
 def serving_layout(n_streams=64, users=1000, bindings=100_000):
     cot, kp = _type_table(4, [0, 1, 2, 3], 0b11)
     return Layout(16, 4, 1, [8, 12], [4, 4],

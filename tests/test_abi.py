@@ -55,8 +55,8 @@ def test_create_without_gpu_fails_cleanly():
 
 def test_struct_sizes_match_header_layout(tmp_path):
     from paper_1411_2239_amd import lib
-    # 8 u32 + 3*4 u32 + 2*256 bytes + 2 u32 + 3 predicates of 4 u32
-    assert ctypes.sizeof(lib.Layout) == 4 * (4 + 4 * 3 + 1) + 512 + 4 * (2 + 3 * 4)
+    # 8 u32 + 3*4 u32 + 2*256 bytes + 2 u32 + 3 predicates of 4 u32 + parent_events
+    assert ctypes.sizeof(lib.Layout) == 4 * (4 + 4 * 3 + 1) + 512 + 4 * (2 + 3 * 4) + 4
     # and the header as a C compiler lays it out
     import os
     import subprocess
