@@ -77,9 +77,20 @@ typedef struct ltl4c_ctx ltl4c_ctx;
  * set of value vectors of Eq. 5 only contains complete vectors).
  *
  * key_bits[m] (1..32) is the declared width of key m: every key value must be
- * below 2^key_bits[m].  The composite binding key (key 0 in the most
- * significant bits) plus the class bits must fit in 63 bits.  A wider value
- * is detected on the device and reported as LTL4C_ERANGE by ltl4c_wait().
+ * below 2^key_bits[m].  A wider value is detected on the device and reported
+ * as LTL4C_ERANGE by ltl4c_wait().  The composite binding key (key 0 in the
+ * most significant bits) is packed into a 64-bit sort word with the class
+ * bits (and, when asked for, the trace index and the parent-event kind bit)
+ * and an exclusion bit.  When the declared widths do not fit 63 bits,
+ * ltl4c_eval first replaces every key value by its dense rank among the
+ * values of its level in the trace (ranks keep order and equality, so
+ * clusters, tree and output order are unchanged) and packs ranks of
+ * ceil(log2(distinct values)) bits; only if those still do not fit does it
+ * report LTL4C_EUNSUPPORTED.  Ranking ends in one synchronous read of the
+ * distinct-value counts, so graph capture and ltl4c_eval_noalloc refuse such
+ * layouts (LTL4C_EUNSUPPORTED), as do batches and stream groups.  The packed
+ * inst_keys and node_keys are then packed ranks; inst_key_values and
+ * node_key_values give the values.
  *
  * Data predicates (propositions computed from a record's data, such as the
  * comparison of a session's average chunk size with a maximum in the paper's
@@ -205,6 +216,11 @@ typedef struct {
  *                                           + class bits + ceil(log2 n_events)
  *                                           must fit 63 bits (else
  *                                           LTL4C_EUNSUPPORTED).
+ *   inst_key_values [capacity * n_keys]     the values x_0..x_{n-1} of
+ *                                           instance i (32 bits each); needs
+ *                                           inst_keys
+ *   node_key_values[m] [capacity * m]       the values x_0..x_{m-1} of node
+ *                                           j; needs node_keys[m]
  * (node_* index m runs over 1..n_levels-1; index 0 is unused.)
  */
 #define LTL4C_NEVER 0xFFFFFFFFu
@@ -223,6 +239,8 @@ typedef struct {
     uint8_t  *node_verdict[4];
     uint32_t *inst_conclusive;
     uint8_t  *event_verdict;
+    uint32_t *inst_key_values;
+    uint32_t *node_key_values[4];
 } ltl4c_result;
 
 /* ---- context ----------------------------------------------------------- */

@@ -90,6 +90,8 @@ struct ClassifyArgs {
     // n_par.  parent_mask > need_mask: no parent events.
     uint32_t parent_mask;
     uint32_t* n_par;
+    // ranked keys: key m of event i is rank[m][i] instead of its record field
+    const uint32_t* rank[kMaxLevels];
 };
 
 struct SortPassArgs {
@@ -297,7 +299,40 @@ struct ParentArgs {
     uint32_t* err;
 };
 
-// Launchers (defined in kernels.hip and parent.hip).
+// Key ranking (composite keys wider than the sort word): per level, every
+// event's value is replaced by its dense rank among the level's values.
+constexpr int kRankThreads = 256;
+constexpr int kRankItems = 16;
+constexpr int kRankTile = kRankThreads * kRankItems;
+struct RankArgs {
+    const uint8_t* records;
+    uint64_t n;
+    uint32_t record_bytes;
+    uint32_t type_dw, type_shift, type_mask;
+    uint32_t has_key[8];                 // bit t: events of type t carry this level's key
+    uint32_t level, key_dw, key_shift, key_mask;
+    uint64_t* words;                     // prep: value << 32 | event index
+    uint32_t* hist;                      // prep: [4][256] histograms of the value's bytes
+    const uint64_t* sorted;              // the words after the radix passes over the value
+    uint32_t* tile_cnt;                  // [tiles] distinct-value heads per tile
+    uint32_t* tile_off;                  // [tiles] heads before each tile
+    uint32_t* n_distinct;                // number of distinct values
+    uint32_t* rank;                      // [n] rank of every event's value
+    uint32_t* uniq;                      // [n] value of every rank
+};
+struct KeyValuesArgs {
+    const uint64_t* packed;              // packed keys (or ranks) of instances or nodes
+    const uint32_t* n_dev;               // how many (device)
+    uint64_t limit;
+    uint32_t n_fields;                   // values per key
+    uint32_t shift[kMaxLevels];
+    uint64_t mask[kMaxLevels];
+    const uint32_t* uniq[kMaxLevels];    // per field: value of every rank, or null (the field is the value)
+    uint64_t uniq_cap;                   // entries of each uniq array
+    uint32_t* out;                       // [n][n_fields]
+};
+
+// Launchers (defined in kernels.hip, parent.hip and rank.hip).
 hipError_t launch_zero(const ZeroArgs& a, uint32_t blocks, hipStream_t s);
 hipError_t launch_classify(const ClassifyArgs& a, hipStream_t s);
 hipError_t launch_sort_pass(const SortPassArgs& a, int variant, uint32_t digit_bits, hipStream_t s);
@@ -337,5 +372,8 @@ hipError_t launch_parent_counts(const ParentArgs& a, hipStream_t s);
 hipError_t launch_parent_tree(const ParentArgs& a, uint32_t level, uint64_t max_nodes, hipStream_t s);
 hipError_t launch_parent_pass(const ParentArgs& a, bool down, uint64_t max_tiles, hipStream_t s);
 hipError_t launch_parent_spine(const ParentArgs& a, hipStream_t s);
+hipError_t launch_rank_prep(const RankArgs& a, hipStream_t s);
+hipError_t launch_rank_scan(const RankArgs& a, hipStream_t s);
+hipError_t launch_key_values(const KeyValuesArgs& a, uint64_t max_n, hipStream_t s);
 
 }  // namespace ltl4c

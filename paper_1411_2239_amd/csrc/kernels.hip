@@ -221,7 +221,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         for (int m = 0; m < kMaxLevels; ++m) {
             if (m < (int)a.n_keys) {
                 const uint32_t b = a.key_bits[m];
-                const uint32_t v = par && m + 1 == (int)a.n_keys ? 0u : f[m];
+                const uint32_t v = par && m + 1 == (int)a.n_keys ? 0u : a.rank[m] ? a.rank[m][i] : f[m];
                 over |= b < 32 ? (v >> b) : 0u;
                 key = (key << b) | v;
             }

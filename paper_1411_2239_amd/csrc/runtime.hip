@@ -344,10 +344,59 @@ int32_t check_layout(const ltl4c_layout* L) {
         if ((uint32_t)L->class_of_type[t] + pred_top >= L->n_classes)
             return fail(LTL4C_EINVAL, "class_of_type entry (plus predicate bits) >= n_classes");
     if (L->parent_events > 1) return fail(LTL4C_EINVAL, "parent_events must be 0 or 1");
-    Geometry g = geometry(*L);
-    if (g.cbits + g.key_bits_total + (g.excl ? 1 : 0) > 63)
-        return fail(LTL4C_EUNSUPPORTED, "packed binding key plus class bits exceed 63 bits");
+    // keys wider than the sort word are ranked by ltl4c_eval (batches and
+    // stream groups check the width themselves)
     return LTL4C_OK;
+}
+
+// The declared widths do not fit the 64-bit sort word: ltl4c_eval ranks the
+// key values first (the trace index of parent events counts).
+bool needs_ranks(const ltl4c_layout& L, uint64_t n) {
+    const Geometry g = geometry(L);
+    const uint32_t ib = g.parent ? std::max<uint32_t>(1, bits_for((uint32_t)std::max<uint64_t>(n, 1))) : 0u;
+    return g.cbits + ib + g.key_bits_total + (g.excl ? 1 : 0) > 63;
+}
+
+// Widths of ranked keys, at most: n events have at most n distinct values.
+ltl4c_layout rank_sized(const ltl4c_layout& L, uint64_t n) {
+    ltl4c_layout r = L;
+    const uint32_t b = std::max<uint32_t>(1, bits_for((uint32_t)std::max<uint64_t>(n, 1)));
+    for (uint32_t m = 0; m < L.n_keys; ++m) r.key_bits[m] = std::min(L.key_bits[m], b);
+    return r;
+}
+
+// The ranking area at the start of the workspace (the evaluation's own
+// workspace follows it).  Offsets in bytes.
+struct RankRegion {
+    uint64_t zero_off, zero_words;        // histograms [4][256], tickets, look-back status [4][tiles][256]
+    uint64_t hist_w, ticket_w, status_w;  // word offsets inside the zero block
+    uint64_t distinct_off;                // [4] distinct values per level
+    uint64_t tile_cnt_off, tile_off_off;
+    uint64_t rank_off[kMaxLevels], uniq_off[kMaxLevels];
+    uint32_t tiles_sort;
+    uint64_t total;
+};
+
+RankRegion rank_region(const ltl4c_layout& L, uint64_t n, int sort_variant) {
+    RankRegion r{};
+    const uint64_t st = sort_tile(sort_variant);
+    r.tiles_sort = (uint32_t)((n + st - 1) / st);
+    r.hist_w = 0;
+    r.ticket_w = 4 * 256;
+    r.status_w = r.ticket_w + 64;
+    r.zero_words = r.status_w + 4ull * r.tiles_sort * 256;
+    uint64_t off = 0;
+    r.zero_off = off;       off = align256(off + 4 * r.zero_words);
+    r.distinct_off = off;   off = align256(off + 64);
+    const uint64_t tiles = std::max<uint64_t>(1, (n + kRankTile - 1) / kRankTile);
+    r.tile_cnt_off = off;   off = align256(off + 4 * tiles);
+    r.tile_off_off = off;   off = align256(off + 4 * tiles);
+    for (uint32_t m = 0; m < L.n_keys; ++m) {
+        r.rank_off[m] = off; off = align256(off + 4 * std::max<uint64_t>(n, 1));
+        r.uniq_off[m] = off; off = align256(off + 4 * std::max<uint64_t>(n, 1));
+    }
+    r.total = off;
+    return r;
 }
 
 // shift = 1 places the quantifiers one level down (level 0 gets a dummy
@@ -479,7 +528,7 @@ int32_t drain_profile(ltl4c_ctx* ctx) {
 int32_t enqueue_front(ltl4c_ctx* ctx, const ltl4c_layout& L, const Geometry& g, const WsLayout& w, uint8_t* ws,
                       const void* d_records, uint64_t n, const Plan* plan, const uint32_t* chunk_off,
                       const uint32_t* chunk_stream, const uint64_t* chunk_ptr, uint32_t n_chunks, bool vec_ok,
-                      uint64_t** sorted, int sort_variant) {
+                      uint64_t** sorted, int sort_variant, const uint32_t* const* rank = nullptr) {
     const uint32_t NL = L.n_keys;
     uint32_t* z = reinterpret_cast<uint32_t*>(ws);
     uint32_t* hist = z + w.hist_off;
@@ -531,6 +580,8 @@ int32_t enqueue_front(ltl4c_ctx* ctx, const ltl4c_layout& L, const Geometry& g, 
     ca.n_chunks = n_chunks;
     ca.vec_ok = vec_ok ? 1u : 0u;
     ca.stream_shift = g.key_bits_total - g.stream_bits;
+    if (rank)
+        for (uint32_t m = 0; m < NL; ++m) ca.rank[m] = rank[m];
     ca.parent_mask = g.parent ? ca.need_mask >> 1 : 0xFFFFFFFFu;
     ca.n_par = g.parent ? z + w.n_valid_off + 1 : nullptr;
     s = launch(ctx, "classify", [&] { return launch_classify(ca, st); });
@@ -941,11 +992,13 @@ struct SchedScope {
 };
 
 uint64_t eval_ws_bytes(ltl4c_ctx* ctx, uint64_t n, const int32_t* props, int32_t n_props) {
-    Geometry g = geometry(ctx->layout, 0, false, true, sort_threads(ctx->sort_variant) >= 512);
-    return plan_workspace(ctx->layout, g, n, (uint32_t)n_props,
-                          (uint32_t)scan_groups(monitor_states(ctx, props, n_props)).size(), ctx->sort_variant,
-                          ctx->scan_variant)
-        .total;
+    const bool ranked = needs_ranks(ctx->layout, n);
+    const ltl4c_layout L = ranked ? rank_sized(ctx->layout, n) : ctx->layout;
+    Geometry g = geometry(L, 0, false, true, sort_threads(ctx->sort_variant) >= 512);
+    return (ranked ? rank_region(L, n, ctx->sort_variant).total : 0) +
+           plan_workspace(L, g, n, (uint32_t)n_props, (uint32_t)scan_groups(monitor_states(ctx, props, n_props)).size(),
+                          ctx->sort_variant, ctx->scan_variant)
+               .total;
 }
 
 }  // namespace
@@ -968,11 +1021,11 @@ int32_t ltl4c_workspace_bytes(ltl4c_ctx* ctx, uint64_t n_events, const int32_t* 
 // The evaluation pipeline after validation: zero, classify, radix passes,
 // scan, counting per level, finalize.  g.n_levels tree levels; when a chunk
 // table is given the chunk index (a trace id) is the top key.
-static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, void* d_ws, const void* d_records,
-                         uint64_t n, const Plan* plan, uint32_t P, const std::vector<ScanGroup>& groups,
-                         const uint32_t* chunk_off,
-                         const uint32_t* chunk_stream, uint32_t n_chunks, const ltl4c_result* out) {
-    const ltl4c_layout& L = ctx->layout;
+static int32_t eval_core(ltl4c_ctx* ctx, const ltl4c_layout& L, const Geometry& g, const WsLayout& w, void* d_ws,
+                         const void* d_records, uint64_t n, const Plan* plan, uint32_t P,
+                         const std::vector<ScanGroup>& groups, const uint32_t* chunk_off,
+                         const uint32_t* chunk_stream, uint32_t n_chunks, const ltl4c_result* out,
+                         const uint32_t* const* rank = nullptr) {
     const uint32_t NL = g.n_levels;
     int32_t s = LTL4C_OK;
     uint8_t* ws = static_cast<uint8_t*>(d_ws);
@@ -994,7 +1047,7 @@ static int32_t eval_core(ltl4c_ctx* ctx, const Geometry& g, const WsLayout& w, v
     uint64_t* sorted = words_a;
     if (n > 0) {
         s = enqueue_front(ctx, L, g, w, ws, d_records, n, plan, chunk_off, chunk_stream, nullptr, n_chunks, true,
-                          &sorted, ctx->sort_variant);
+                          &sorted, ctx->sort_variant, rank);
         if (s) return s;
     }
 
@@ -1207,6 +1260,92 @@ static Plan host_plan(ltl4c_ctx* ctx, const int32_t* props, int32_t n_props) {
     return host;
 }
 
+// Dense ranks of every level's key values (see rank.hip): rank[m][i] for
+// event i, and the value of every rank; the distinct counts land in the
+// ranking area for the host to read.
+static int32_t enqueue_ranks(ltl4c_ctx* ctx, const ltl4c_layout& L, const void* d_records, uint64_t n, uint8_t* area,
+                             const RankRegion& rr, uint64_t* wa, uint64_t* wb) {
+    const hipStream_t st = ctx->stream;
+    uint32_t* z = reinterpret_cast<uint32_t*>(area + rr.zero_off);
+    int32_t s = LTL4C_OK;
+    for (uint32_t m = 0; m < L.n_keys && s == LTL4C_OK; ++m) {
+        ZeroArgs za{z, nullptr, 0, rr.zero_words, 0};
+        const uint32_t blocks = (uint32_t)std::min<uint64_t>(1024, (rr.zero_words + 255) / 256);
+        s = launch(ctx, "zero", [&] { return launch_zero(za, blocks ? blocks : 1, st); });
+        if (s) return s;
+        RankArgs ra{};
+        ra.records = static_cast<const uint8_t*>(d_records);
+        ra.n = n;
+        ra.record_bytes = L.record_bytes;
+        ra.type_dw = L.type_offset / 4;
+        ra.type_shift = (L.type_offset % 4) * 8;
+        ra.type_mask = L.type_bytes == 4 ? 0xFFFFFFFFu : ((1u << (8 * L.type_bytes)) - 1u);
+        for (uint32_t t = 0; t < 256; ++t)
+            if ((L.key_present[t] >> m) & 1u) ra.has_key[t >> 5] |= 1u << (t & 31u);
+        ra.level = m;
+        ra.key_dw = L.key_offset[m] / 4;
+        ra.key_shift = (L.key_offset[m] % 4) * 8;
+        ra.key_mask = L.key_bytes[m] == 4 ? 0xFFFFFFFFu : ((1u << (8 * L.key_bytes[m])) - 1u);
+        ra.words = wa;
+        ra.hist = z + rr.hist_w;
+        ra.sorted = wa;
+        ra.tile_cnt = reinterpret_cast<uint32_t*>(area + rr.tile_cnt_off);
+        ra.tile_off = reinterpret_cast<uint32_t*>(area + rr.tile_off_off);
+        ra.n_distinct = reinterpret_cast<uint32_t*>(area + rr.distinct_off) + m;
+        ra.rank = reinterpret_cast<uint32_t*>(area + rr.rank_off[m]);
+        ra.uniq = reinterpret_cast<uint32_t*>(area + rr.uniq_off[m]);
+        s = launch(ctx, "rank", [&] { return launch_rank_prep(ra, st); });
+        uint64_t* in = wa;
+        uint64_t* outw = wb;
+        for (uint32_t p = 0; p < 4 && s == LTL4C_OK; ++p) {
+            SortPassArgs sa{};
+            sa.in = in;
+            sa.out = outw;
+            sa.n = (uint32_t)n;
+            sa.shift = 32 + 8 * p;
+            sa.nbits = 8;
+            sa.hist = z + rr.hist_w + 256 * p;
+            sa.status = z + rr.status_w + (uint64_t)p * rr.tiles_sort * 256;
+            sa.ticket = z + rr.ticket_w + p;
+            sa.err = ctx->err_dev;
+            s = launch(ctx, "rank", [&] { return launch_sort_pass(sa, ctx->sort_variant, 8, st); });
+            std::swap(in, outw);
+        }
+        if (s == LTL4C_OK) s = launch(ctx, "rank", [&] { return launch_rank_scan(ra, st); });
+    }
+    return s;
+}
+
+// The values of the instances' and nodes' vectors, from their packed keys
+// (through the rank tables when the keys were ranked).
+static int32_t enqueue_key_values(ltl4c_ctx* ctx, const ltl4c_layout& L, const Geometry& g, const WsLayout& w,
+                                  void* d_ws, uint64_t n, const ltl4c_result* out, const uint32_t* const* value_of) {
+    const uint32_t* sizes32 = reinterpret_cast<const uint32_t*>(d_ws) + w.sizes32_off;
+    (void)g;
+    auto one = [&](const uint64_t* packed, uint32_t* dst, uint32_t level_of_count, uint32_t fields) {
+        KeyValuesArgs ka{};
+        ka.packed = packed;
+        ka.n_dev = sizes32 + level_of_count;
+        ka.limit = out->capacity;
+        ka.n_fields = fields;
+        uint32_t below = 0;
+        for (int m = (int)fields - 1; m >= 0; --m) {
+            ka.shift[m] = below;
+            ka.mask[m] = (1ull << L.key_bits[m]) - 1ull;
+            ka.uniq[m] = value_of[m];
+            below += L.key_bits[m];
+        }
+        ka.uniq_cap = std::max<uint64_t>(n, 1);
+        ka.out = dst;
+        return launch(ctx, "key_values", [&] { return launch_key_values(ka, out->capacity, ctx->stream); });
+    };
+    int32_t s = LTL4C_OK;
+    if (n > 0 && out->inst_key_values) s = one(out->inst_keys, out->inst_key_values, 0, L.n_keys);
+    for (uint32_t m = 1; m < L.n_keys && s == LTL4C_OK; ++m)
+        if (n > 0 && out->node_key_values[m]) s = one(out->node_keys[m], out->node_key_values[m], m, m);
+    return s;
+}
+
 static int32_t eval_impl(ltl4c_ctx* ctx, const void* d_records, uint64_t n, const int32_t* props, int32_t n_props,
                          void* d_ws, uint64_t ws_bytes, const ltl4c_result* out, bool noalloc,
                          GraphHost* cap = nullptr);
@@ -1238,7 +1377,10 @@ static int32_t eval_impl(ltl4c_ctx* ctx, const void* d_records, uint64_t n, cons
     if (!out || !out->root_verdict || !out->root_counts || !out->sizes)
         return fail(LTL4C_EINVAL, "root_verdict, root_counts and sizes are required");
     if (!d_ws || (reinterpret_cast<uintptr_t>(d_ws) & 255)) return fail(LTL4C_EINVAL, "workspace must be 256-byte aligned");
-    const ltl4c_layout& L = ctx->layout;
+    // keys wider than the sort word: ranked first; the workspace is sized for
+    // ranks of at most ceil(log2 n) bits and starts with the ranking area
+    const bool ranked = needs_ranks(ctx->layout, n);
+    ltl4c_layout L = ranked ? rank_sized(ctx->layout, n) : ctx->layout;
     const uint32_t P = (uint32_t)n_props;
     if (n > 0 && (reinterpret_cast<uintptr_t>(d_records) & 3))
         return fail(LTL4C_EINVAL, "records must be 4-byte aligned");
@@ -1246,13 +1388,15 @@ static int32_t eval_impl(ltl4c_ctx* ctx, const void* d_records, uint64_t n, cons
     Geometry g = geometry(L, 0, false, true, sort_threads(ctx->sort_variant) >= 512);
     const std::vector<ScanGroup> groups = scan_groups(monitor_states(ctx, props, n_props));
     WsLayout w = plan_workspace(L, g, n, P, (uint32_t)groups.size(), ctx->sort_variant, ctx->scan_variant);
-    if (ws_bytes < w.total && sc.changed()) {
+    uint64_t rbytes = ranked ? rank_region(L, n, ctx->sort_variant).total : 0;
+    if (ws_bytes < rbytes + w.total && sc.changed()) {
         // a workspace sized for the context's own schedule: run that one
         sc.revert();
         g = geometry(L, 0, false, true, sort_threads(ctx->sort_variant) >= 512);
         w = plan_workspace(L, g, n, P, (uint32_t)groups.size(), ctx->sort_variant, ctx->scan_variant);
+        rbytes = ranked ? rank_region(L, n, ctx->sort_variant).total : 0;
     }
-    if (ws_bytes < w.total) {
+    if (ws_bytes < rbytes + w.total) {
         if (!noalloc) return fail(LTL4C_ENOMEM, "workspace smaller than ltl4c_workspace_bytes()");
         char buf[200];
         std::snprintf(buf, sizeof buf,
@@ -1263,6 +1407,39 @@ static int32_t eval_impl(ltl4c_ctx* ctx, const void* d_records, uint64_t n, cons
     }
     if ((out->inst_keys != nullptr) != (out->inst_verdict != nullptr))
         return fail(LTL4C_EINVAL, "inst_keys and inst_verdict are given together or not at all");
+    if (out->inst_key_values && !out->inst_keys) return fail(LTL4C_EINVAL, "inst_key_values needs inst_keys");
+    for (uint32_t m = 1; m < L.n_keys; ++m)
+        if (out->node_key_values[m] && !out->node_keys[m])
+            return fail(LTL4C_EINVAL, "node_key_values needs the node arrays of its level");
+    const uint32_t* rank_of[kMaxLevels] = {nullptr, nullptr, nullptr, nullptr};
+    const uint32_t* value_of[kMaxLevels] = {nullptr, nullptr, nullptr, nullptr};
+    if (ranked) {
+        if (noalloc || cap)
+            return fail(LTL4C_EUNSUPPORTED, "keys wider than the sort word are ranked first, which waits for the "
+                                            "device: not under graph capture or without allocation");
+        HIP_TRY(hipSetDevice(ctx->device));
+        uint8_t* ws8 = static_cast<uint8_t*>(d_ws);
+        const RankRegion rr = rank_region(L, n, ctx->sort_variant);
+        uint64_t* wa = reinterpret_cast<uint64_t*>(ws8 + rr.total + w.words_a_off);
+        uint64_t* wb = reinterpret_cast<uint64_t*>(ws8 + rr.total + w.words_b_off);
+        s = enqueue_ranks(ctx, ctx->layout, d_records, n, ws8, rr, wa, wb);
+        if (s) return s;
+        uint32_t distinct[kMaxLevels] = {0, 0, 0, 0};
+        HIP_TRY(hipMemcpyAsync(distinct, ws8 + rr.distinct_off, sizeof distinct, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        for (uint32_t m = 0; m < L.n_keys; ++m) {
+            L.key_bits[m] = std::max<uint32_t>(1, bits_for(std::max<uint32_t>(distinct[m], 1)));
+            rank_of[m] = reinterpret_cast<const uint32_t*>(ws8 + rr.rank_off[m]);
+            value_of[m] = reinterpret_cast<const uint32_t*>(ws8 + rr.uniq_off[m]);
+        }
+        // the evaluation proper, on the ranks, in the workspace after the ranking area
+        g = geometry(L, 0, false, true, sort_threads(ctx->sort_variant) >= 512);
+        w = plan_workspace(L, g, n, P, (uint32_t)groups.size(), ctx->sort_variant, ctx->scan_variant);
+        d_ws = ws8 + rr.total;
+        ws_bytes -= rr.total;
+        if (g.cbits + g.key_bits_total + (g.excl ? 1 : 0) > 63)
+            return fail(LTL4C_EUNSUPPORTED, "even ranked, the binding key plus class bits exceed 63 bits");
+    }
     if (g.parent) {
         if (out->event_verdict || out->inst_conclusive)
             return fail(LTL4C_EUNSUPPORTED, "the verdict timeline is not available with parent events");
@@ -1306,7 +1483,12 @@ static int32_t eval_impl(ltl4c_ctx* ctx, const void* d_records, uint64_t n, cons
         s = get_plan(ctx, props, n_props, &plan);
         if (s) return s;
         HIP_TRY(hipSetDevice(ctx->device));
-        auto enqueue = [&]() { return eval_core(ctx, g, w, d_ws, d_records, n, plan, P, groups, nullptr, nullptr, 0, out); };
+        auto enqueue = [&]() {
+            int32_t e = eval_core(ctx, L, g, w, d_ws, d_records, n, plan, P, groups, nullptr, nullptr, 0, out,
+                                  ranked ? rank_of : nullptr);
+            if (e == LTL4C_OK) e = enqueue_key_values(ctx, L, g, w, d_ws, n, out, value_of);
+            return e;
+        };
         return cap ? capture_graph(ctx, cap, enqueue) : enqueue();
     }
     // no allocation: the plan travels inside kernel launches into the
@@ -1326,7 +1508,8 @@ static int32_t eval_impl(ltl4c_ctx* ctx, const void* d_records, uint64_t n, cons
             return launch_put_words(reinterpret_cast<uint32_t*>(ctx->scratch) + at, pw, ctx->stream);
         });
     }
-    if (s == LTL4C_OK) s = eval_core(ctx, g, w, d_ws, d_records, n, plan, P, groups, nullptr, nullptr, 0, out);
+    if (s == LTL4C_OK) s = eval_core(ctx, L, g, w, d_ws, d_records, n, plan, P, groups, nullptr, nullptr, 0, out);
+    if (s == LTL4C_OK) s = enqueue_key_values(ctx, L, g, w, d_ws, n, out, value_of);
     ctx->no_timing = false;
     return s;
 }
@@ -1461,7 +1644,7 @@ static int32_t batch_impl(ltl4c_ctx* ctx, const void* d_records, const uint64_t*
     o.verdict = d_root_verdict;
     o.counts = d_root_counts;
     auto enqueue = [&]() -> int32_t {
-        int32_t e = eval_core(ctx, b.g, b.w, d_ws, d_records, n, plan, P, groups, table, table + n_traces + 1,
+        int32_t e = eval_core(ctx, ctx->layout, b.g, b.w, d_ws, d_records, n, plan, P, groups, table, table + n_traces + 1,
                               (uint32_t)n_traces, &r);
         if (e) return e;
         return launch(ctx, "batch_out", [&] { return launch_batch_out(o, ctx->stream); });

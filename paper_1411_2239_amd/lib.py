@@ -71,7 +71,8 @@ class Result(C.Structure):
     _fields_ = [("root_verdict", C.c_void_p), ("root_counts", C.c_void_p), ("sizes", C.c_void_p),
                 ("capacity", C.c_uint64), ("inst_keys", C.c_void_p), ("inst_verdict", C.c_void_p),
                 ("node_keys", C.c_void_p * 4), ("node_counts", C.c_void_p * 4), ("node_verdict", C.c_void_p * 4),
-                ("inst_conclusive", C.c_void_p), ("event_verdict", C.c_void_p)]
+                ("inst_conclusive", C.c_void_p), ("event_verdict", C.c_void_p),
+                ("inst_key_values", C.c_void_p), ("node_key_values", C.c_void_p * 4)]
 
 
 _lib = None
@@ -229,6 +230,8 @@ class EvalResult:
     node_verdict: list = None
     inst_conclusive: object = None   # [n_props * capacity] int32 (NEVER = -1): verdict timeline
     event_verdict: object = None     # [n_props * n_events] uint8, trace order (NO_INSTANCE = 255)
+    inst_key_values: object = None   # [capacity * n_levels] int32: the values of each instance's vector
+    node_key_values: list = None     # level m: [capacity * m] int32
 
 
 class Context:
@@ -313,9 +316,12 @@ class Context:
             self._workspace = ws
         return ws
 
-    def alloc_result(self, n_props, capacity=0, instances=False, nodes=False, timeline=False, n_events=0):
+    def alloc_result(self, n_props, capacity=0, instances=False, nodes=False, timeline=False, n_events=0,
+                     key_values=False):
         """timeline: per-instance first conclusive prefix; n_events > 0: the
-        verdict after every event (in trace order) for that many events."""
+        verdict after every event (in trace order) for that many events;
+        key_values: the key values of every instance and node (with
+        instances / nodes)."""
         t, dev = self.torch, f"cuda:{self.device}"
         L = self.n_levels
         r = EvalResult(t.empty(n_props, dtype=t.uint8, device=dev),
@@ -334,6 +340,10 @@ class Context:
                                       for _ in range(1, L)]
             r.node_verdict = [None] + [t.empty(n_props * capacity, dtype=t.uint8, device=dev)
                                        for _ in range(1, L)]
+        if key_values and instances:
+            r.inst_key_values = t.empty(capacity * L, dtype=t.int32, device=dev)
+        if key_values and nodes:
+            r.node_key_values = [None] + [t.empty(capacity * m, dtype=t.int32, device=dev) for m in range(1, L)]
         r.capacity = capacity
         r.key_bits = list(self.key_bits)
         return r
@@ -365,6 +375,11 @@ class Context:
                 res.node_keys[m] = result.node_keys[m].data_ptr()
                 res.node_counts[m] = result.node_counts[m].data_ptr()
                 res.node_verdict[m] = result.node_verdict[m].data_ptr()
+        if getattr(result, "inst_key_values", None) is not None:
+            res.inst_key_values = result.inst_key_values.data_ptr()
+        if getattr(result, "node_key_values", None) is not None:
+            for m in range(1, self.n_levels):
+                res.node_key_values[m] = result.node_key_values[m].data_ptr()
         return res
 
     def eval_noalloc_into(self, records, n_events, props, result):
@@ -376,12 +391,13 @@ class Context:
         _check(self.lib.ltl4c_eval_noalloc(self.h, C.c_void_p(records.data_ptr() if n_events else 0), n_events, arr,
                                            len(props), C.byref(res)), "ltl4c_eval_noalloc")
 
-    def eval(self, records, props, instances=False, nodes=False, capacity=None, timeline=False, events=False):
+    def eval(self, records, props, instances=False, nodes=False, capacity=None, timeline=False, events=False,
+             key_values=False):
         """Evaluate and wait; returns an EvalResult of device tensors."""
         n = records.numel() // self.record_bytes
         if capacity is None:
             capacity = max(n, 1)
-        r = self.alloc_result(len(props), capacity, instances, nodes, timeline, n if events else 0)
+        r = self.alloc_result(len(props), capacity, instances, nodes, timeline, n if events else 0, key_values)
         self.eval_into(records, n, props, r, self.workspace(n, props))
         self.wait()
         return r

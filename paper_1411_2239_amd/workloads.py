@@ -342,8 +342,17 @@ def proxy_cache_literal_properties():
                          "A>=0.99 v: E=0 r: cached & external")]
 
 
+def distinct_u32(rng, k):
+    """k distinct random 32-bit values, in random order."""
+    vals = np.unique(rng.integers(0, 1 << 32, size=int(k * 1.1) + 16, dtype=np.uint64))
+    while vals.size < k:
+        vals = np.unique(np.concatenate([vals, rng.integers(0, 1 << 32, size=k, dtype=np.uint64)]))
+    return rng.permutation(vals)[:k].astype(np.uint32)
+
+
 def gen_proxy_cache(n_events=10_000_000, n_videos=4096, zipf_s=1.0, mean_changes=4.0, p_fault=0.002,
-                    mean_progress=1.5, p_done=0.95, seed=0x14112239 + 6, parent_events=True, literal=False):
+                    mean_progress=1.5, p_done=0.95, seed=0x14112239 + 6, parent_events=True, literal=False,
+                    wide_ids=False):
     """A proxy trace: requests for videos with Zipf popularity; each video's
     cache state alternates at Poisson(mean_changes) random times (the first
     change inserts it); a request while cached is served from the cache, but
@@ -351,7 +360,8 @@ def gen_proxy_cache(n_events=10_000_000, n_videos=4096, zipf_s=1.0, mean_changes
     fetched externally.  Each request has Geometric(mean_progress) progress
     events and, with probability p_done, a completion.  The trace is the
     first n_events events in time order.  Keys: videos a seeded permutation of
-    0..n_videos-1, requests one of 0..R-1."""
+    0..n_videos-1, requests one of 0..R-1; with wide_ids, distinct random
+    32-bit values for both (a 64-bit composite key)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     per_req = 1.0 + mean_progress + p_done
     n_req = int(n_events / per_req * 1.05) + 16
@@ -385,16 +395,20 @@ def gen_proxy_cache(n_events=10_000_000, n_videos=4096, zipf_s=1.0, mean_changes
     order = np.argsort(t, kind="stable")[:n_events]
     if order.size < n_events:
         raise ValueError("generated too few events")
-    vid_key = rng.permutation(n_videos).astype(np.uint32)
-    req_key = rng.permutation(n_req).astype(np.uint32)
+    if wide_ids:
+        vid_key = distinct_u32(rng, n_videos)
+        req_key = distinct_u32(rng, n_req)
+    else:
+        vid_key = rng.permutation(n_videos).astype(np.uint32)
+        req_key = rng.permutation(n_req).astype(np.uint32)
     rec = np.zeros(n_events, dtype=REC16)
     rec["ts"] = np.arange(n_events, dtype=np.uint32)
     rec["type"] = typ[order]
     rec["k0"] = vid_key[vid[order]]
     parent = typ[order] < 2
     rec["k1"] = np.where(parent, 0, req_key[req[order]])
-    vb = max(1, int(n_videos - 1).bit_length())
-    rb = max(1, int(n_req - 1).bit_length())
+    vb = 32 if wide_ids else max(1, int(n_videos - 1).bit_length())
+    rb = 32 if wide_ids else max(1, int(n_req - 1).bit_length())
     lay = proxy_cache_layout(parent_events and not literal, vb, rb)
     props = proxy_cache_literal_properties() if literal else proxy_cache_properties()
     return Workload("proxy", rec, lay, props)

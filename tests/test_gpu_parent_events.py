@@ -126,15 +126,23 @@ def test_calls_without_parent_events_refuse_them():
     ctx.close()
 
 
-def test_key_and_index_budget():
-    """The kind bit and the trace index ride in the sort word: keys that
-    leave no room for them are refused before anything runs."""
+def test_declared_widths_without_room_for_the_index_are_ranked():
+    """The kind bit and the trace index ride in the sort word: declared key
+    widths that leave no room for them make the library rank the keys."""
+    wl = parent_workload(30_000, 2, [5, 400], seed=81, n_props=2)
+    wl.layout.key_bits = [28, 28]
+    _check_values(wl)
+
+
+def _check_values(wl):
     import torch
     from paper_1411_2239_amd import lib
-    wl = parent_workload(1000, 2, [5, 5], seed=81, n_props=1)
-    wl.layout.key_bits = [28, 28]
     ctx, ids, rec = lib.open_workload(wl)
-    with pytest.raises(lib.LTL4CError) as e:
-        ctx.eval(rec, ids)
-    assert e.value.status == lib.EUNSUPPORTED
+    r = ctx.eval(rec, ids, instances=True, nodes=True, key_values=True)
+    torch.cuda.synchronize()
     ctx.close()
+    o = evaluate_workload(wl)
+    r.key_bits = None
+    compare_full(r, o, len(ids), 2)
+    n_inst = int(r.sizes[0].item())
+    assert np.array_equal(r.inst_key_values.cpu().numpy().view(np.uint32).reshape(-1, 2)[:n_inst], o.inst_keys)
