@@ -329,7 +329,7 @@ def pin_default_schedule(ctx, on):
     """Pin the default tiles (on) or return to the tuned table (off)."""
     from paper_1411_2239_amd import lib
     ctx.set_option(lib.OPT_SORT_TILE, 1 if on else -1)
-    ctx.set_option(lib.OPT_SCAN_TILE, 3 if on else -1)
+    ctx.set_option(lib.OPT_SCAN_TILE, 4 if on else -1)
 
 
 def tune_all(out_path, log=print):
@@ -489,6 +489,20 @@ def batching_bench(n_traces=4096, reps=3, log=print):
     prof = ctx.profile_read()
     ctx.profile(False)
     vb = v.cpu().numpy().reshape(n_traces, len(ids))
+    # ALU roofline of the map scan: per event and property one composition of
+    # n-state maps (n byte look-ups) and one state step (one look-up); the
+    # chip's byte-look-up peak is one v_perm_b32 (4 look-ups) per lane and
+    # cycle: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 4 = 157.3 T look-ups/s
+    from paper_1411_2239_amd.monitor import compile_monitor
+    states = [compile_monitor(p.formula, wl.layout.class_props).n_states for p in wl.props]
+    lookups = float(n) * sum(st + 1 for st in states)
+    scan_s = prof["scan"][0] / 1e3 if "scan" in prof else None
+    alu = None
+    if scan_s:
+        achieved = lookups / scan_s / 1e12
+        alu = {"bound": "alu", "kernel": "scan", "achieved": achieved, "peak": 157.3, "unit": "T byte look-ups/s",
+               "frac": achieved / 157.3, "monitor_states": states,
+               "note": "one n-state map composition + one state step per event and property"}
     log("[bench] batching: plain per-trace loop")
     del ws
     ctx._workspace = None
@@ -514,7 +528,8 @@ def batching_bench(n_traces=4096, reps=3, log=print):
             "batched_ms_default_schedule": el_default * 1e3, "batched_ms_graph": el_graph * 1e3,
             "plain_events_per_s": n / el_plain, "plain_ms": el_plain * 1e3,
             "batched_vs_plain": el_plain / el, "last_trace_plain_equals_batched": same,
-            "batched_kernel_ms": {k: round(x[0], 3) for k, x in prof.items()}}
+            "batched_kernel_ms": {k: round(x[0], 3) for k, x in prof.items()},
+            "scan_alu_roofline": alu}
 
 
 def large_bench(n_events=500_000_000, reps=3, log=print):
@@ -622,6 +637,47 @@ def timeline_bench(n_events=10_000_000, reps=10, log=print):
     return out
 
 
+def proxy_bench(n_events=10_000_000, reps=10, log=print):
+    """The proxy-cache case study's shape (Section 5): 10M events, 4,096 videos,
+    2.9M requests; with parent events (the videos' cache insertions and
+    evictions join every request of the video; E=0 over requests), the
+    literal propositional leaf without them, and the same trace with random
+    32-bit video and request ids (keys ranked before packing)."""
+    import torch
+    from paper_1411_2239_amd import lib, workloads
+
+    out = {"workload": f"{n_events} events, 4,096 videos, parent events (cache insert/evict), E=0 over requests"}
+    for label, kw in (("parent_events", {}), ("literal_leaf", {"literal": True}),
+                      ("parent_events_32bit_ids", {"wide_ids": True})):
+        log(f"[bench] proxy cache: {label}")
+        wl = workloads.gen_proxy_cache(n_events, **kw)
+        ctx, ids, rec = lib.open_workload(wl)
+        ws = ctx.workspace(n_events, ids)
+        res = ctx.alloc_result(len(ids))
+        ctx.eval_into(rec, n_events, ids, res, ws)
+        ctx.wait()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.eval_into(rec, n_events, ids, res, ws)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        ctx.wait()
+        ctx.profile(True)
+        ctx.profile_reset()
+        ctx.eval_into(rec, n_events, ids, res, ws)
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        ctx.wait()
+        out[label] = {"events_per_s": n_events / el, "ms": el * 1e3, "properties": len(ids),
+                      "root_verdict": [lib.VERDICT_NAMES[v] for v in res.root_verdict.cpu().numpy().tolist()],
+                      "kernel_ms": {k: round(x[0], 3) for k, x in prof.items()}}
+        ctx.close()
+        del rec, ws
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -637,6 +693,7 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 500M-event single-trace section")
     ap.add_argument("--no-predicates", action="store_true", help="skip the data-predicate section")
     ap.add_argument("--no-timeline", action="store_true", help="skip the verdict-timeline section")
+    ap.add_argument("--no-proxy", action="store_true", help="skip the proxy-cache (parent events) section")
     ap.add_argument("--no-config1", action="store_true", help="skip the socket-trace latency and size sweep")
     ap.add_argument("--serving-chunks", type=int, default=100_000)
     ap.add_argument("--no-graphs", action="store_true", help="skip the captured-graph section")
@@ -777,6 +834,10 @@ def main():
     if not args.no_timeline:
         timeline = timeline_bench(log=log)
 
+    proxy = None
+    if not args.no_proxy:
+        proxy = proxy_bench(log=log)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (C oracle)")
@@ -809,6 +870,7 @@ def main():
         "large_trace": large,
         "data_predicates": predicates,
         "verdict_timeline": timeline,
+        "proxy_cache": proxy,
         "batched_vs_plain_speedup": batching["batched_vs_plain"] if batching else None,
         "p99_chunk_latency_ms": serving["batched"]["p99_ms"] if serving else None,
         "p99_chunk_latency_ms_pinned_host": serving["batched_pinned_host"]["p99_ms"] if serving else None,

@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "parent.hip", "rank.hip", "runtime.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "mapscan.hip", "parent.hip", "rank.hip", "runtime.hip")]
 OUT = os.path.join(HERE, "libltl4c.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -145,7 +145,20 @@ struct ScanArgs {
     uint64_t* sizes;                     // [1 + n_levels] written by the last tile
     uint32_t* sizes32;                   // same, 32-bit, for the counting kernels
     uint32_t* err;
+    // the split map scan (reduce, spine, down sweep; mapscan.hip)
+    uint8_t* desc;                       // [n] per word: class | head << 4 | level-m heads << (4 + m)
+    uint32_t read_desc;                  // 1: read the descriptors instead of the words
+    uint32_t* agg;                       // [tiles][kMsRec] tile aggregates: 4 head counts, map dwords
+    uint32_t* prefix;                    // [tiles][kMsRec] exclusive prefixes of the aggregates
+    uint32_t* trec;                      // [kMsThreadRec][tiles * kMsThreads] per thread: its exclusive
+                                         // prefix within the tile (two packed head-count words, map dwords)
+    uint32_t tiles;
 };
+// the split map scan: tiles of 256 threads x 16 or 32 words, and their records
+constexpr int kMsThreads = 256;
+constexpr int kMsTileMin = kMsThreads * 16;   // workspace arrays are sized for the smaller tile
+constexpr int kMsRec = 4 + 16;
+constexpr int kMsThreadRec = 2 + 16;
 
 constexpr uint32_t kNever = 0xFFFFFFFFu;     // timeline: the instance never became conclusive
 
@@ -341,9 +354,12 @@ uint32_t sort_tile(int variant);      // words per radix tile of a sort variant
 constexpr int kSortVariants = 7;
 constexpr int kDefaultSortVariant = 1;     // 512 threads x 16 words
 hipError_t launch_scan(const ScanArgs& a, int variant, hipStream_t s);
+hipError_t launch_mapscan(const ScanArgs& a, int items, hipStream_t s);   // reduce, spine, down sweep
 uint32_t scan_tile(int variant);      // words per scan tile of a scan variant
-constexpr int kScanVariants = 4;
-constexpr int kDefaultScanVariant = 3;     // tile chosen per launch
+constexpr int kScanVariants = 6;
+constexpr int kSplitScanVariant = 4;       // reduce / spine / down sweep (mapscan.hip), 16 words a thread
+constexpr int kSplitScanVariant32 = 5;     // the same, 32 words a thread
+constexpr int kDefaultScanVariant = 4;
 hipError_t launch_count(const CountArgs& a, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
 hipError_t launch_inst_conclusive(const InstConclusiveArgs& a, hipStream_t s);

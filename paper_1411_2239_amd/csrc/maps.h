@@ -1,0 +1,90 @@
+// Transition maps of LTL4 monitors as packed bytes (see the comment below),
+// shared by the map-scan kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ltl4c {
+
+// Maps over at most 8 (MW = 2) or 16 (MW = 4) states: MW dwords whose byte q
+// holds the image of state q.  The composition g∘f (f applied first) picks,
+// for every byte of f, the byte of g it names: one byte permute per dword for
+// 8 states; for 16 states two permutes (the low and the high half of g) and a
+// per-byte select on bit 3 of the selector.  No constant-map special cases
+// are needed.
+template <int MW>
+struct BMap {
+    uint32_t d[MW];
+};
+
+template <int MW>
+__device__ __forceinline__ BMap<MW> bm_identity() {
+    BMap<MW> r;
+#pragma unroll
+    for (int i = 0; i < MW; ++i) r.d[i] = 0x03020100u + 0x04040404u * (uint32_t)i;
+    return r;
+}
+template <int MW>
+__device__ __forceinline__ BMap<MW> bm_const(uint32_t s) {
+    BMap<MW> r;
+#pragma unroll
+    for (int i = 0; i < MW; ++i) r.d[i] = s * 0x01010101u;
+    return r;
+}
+template <int MW>
+__device__ __forceinline__ BMap<MW> bm_compose(const BMap<MW>& g, const BMap<MW>& f) {
+    BMap<MW> r;
+#pragma unroll
+    for (int i = 0; i < MW; ++i) {
+        if constexpr (MW == 2) {
+            r.d[i] = __builtin_amdgcn_perm(g.d[1], g.d[0], f.d[i]);
+        } else {
+            const uint32_t sel = f.d[i], s7 = sel & 0x07070707u;
+            const uint32_t lo = __builtin_amdgcn_perm(g.d[1], g.d[0], s7);
+            const uint32_t hi = __builtin_amdgcn_perm(g.d[3], g.d[2], s7);
+            const uint32_t t = (sel >> 3) & 0x01010101u, m = (t << 8) - t;   // 0xFF where the state is >= 8
+            r.d[i] = (hi & m) | (lo & ~m);
+        }
+    }
+    return r;
+}
+template <int MW>
+__device__ __forceinline__ uint32_t bm_at(const BMap<MW>& g, uint32_t q) {
+    if constexpr (MW == 2) {
+        return __builtin_amdgcn_perm(g.d[1], g.d[0], q) & 0xFFu;
+    } else {
+        const uint32_t lo = __builtin_amdgcn_perm(g.d[1], g.d[0], q & 7u);
+        const uint32_t hi = __builtin_amdgcn_perm(g.d[3], g.d[2], q & 7u);
+        return ((q & 8u) ? hi : lo) & 0xFFu;
+    }
+}
+template <int MW>
+__device__ __forceinline__ BMap<MW> bm_shfl_up(const BMap<MW>& v, int off) {
+    BMap<MW> r;
+#pragma unroll
+    for (int i = 0; i < MW; ++i) r.d[i] = __shfl_up(v.d[i], off, 64);
+    return r;
+}
+template <int MW>
+__device__ __forceinline__ BMap<MW> bm_shfl_down(const BMap<MW>& v, int off) {
+    BMap<MW> r;
+#pragma unroll
+    for (int i = 0; i < MW; ++i) r.d[i] = __shfl_down(v.d[i], off, 64);
+    return r;
+}
+template <int MW>
+__device__ __forceinline__ BMap<MW> bm_bcast(const BMap<MW>& v, int src) {
+    BMap<MW> r;
+#pragma unroll
+    for (int i = 0; i < MW; ++i) r.d[i] = __shfl(v.d[i], src, 64);
+    return r;
+}
+template <int MW>
+__device__ __forceinline__ BMap<MW> bm_load(const uint32_t* p) {
+    BMap<MW> r;
+#pragma unroll
+    for (int i = 0; i < MW; ++i) r.d[i] = p[i];
+    return r;
+}
+
+}  // namespace ltl4c

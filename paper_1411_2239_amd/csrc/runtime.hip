@@ -197,6 +197,8 @@ struct WsLayout {
     uint64_t node_start_off[kMaxLevels], counts_off[kMaxLevels];
     uint64_t cap_node[kMaxLevels];
     uint32_t tiles_sort, tiles_scan;
+    uint64_t ms_desc_off, ms_agg_off, ms_prefix_off, ms_trec_off;   // the split map scan
+    uint32_t ms_tiles;
     // parent events
     uint64_t pe_g_off, pe_tree_off, pe_tile_agg_off, pe_tile_prefix_off, pe_tile_heads_off, pe_tile_hprefix_off;
     uint64_t pe_tree_lvl[kPeMaxTreeLevels], pe_tree_cnt[kPeMaxTreeLevels];
@@ -275,8 +277,9 @@ WsLayout plan_workspace(const ltl4c_layout& L, const Geometry& g, uint64_t n, ui
     w.zero_off = 0;
     w.zero_words = z;
     uint64_t off = align256(z * 4);
-    w.words_a_off = off;   off = align256(off + n * 8);
-    w.words_b_off = off;   off = align256(off + n * 8);
+    // (room for one map-scan run of 32 words past the end: its loads are unconditional)
+    w.words_a_off = off;   off = align256(off + n * 8 + 256);
+    w.words_b_off = off;   off = align256(off + n * 8 + 256);
     w.inst_verdict_off = off; off = align256(off + (uint64_t)P * n);
     w.inst_parent_off = 0;
     if (g.n_levels >= 2) {
@@ -284,6 +287,12 @@ WsLayout plan_workspace(const ltl4c_layout& L, const Geometry& g, uint64_t n, ui
         off = align256(off + 4 * n);
     }
     w.inst_start_off = off; off = align256(off + 4 * n);   // verdict timeline, when asked for
+    // split map scan: a descriptor byte per word, a record per tile and its prefix
+    w.ms_tiles = (uint32_t)((n + kMsTileMin - 1) / kMsTileMin);
+    w.ms_desc_off = off;   off = align256(off + n + 64);
+    w.ms_agg_off = off;    off = align256(off + 4ull * kMsRec * std::max<uint32_t>(w.ms_tiles, 1));
+    w.ms_prefix_off = off; off = align256(off + 4ull * kMsRec * std::max<uint32_t>(w.ms_tiles, 1));
+    w.ms_trec_off = off;   off = align256(off + 4ull * kMsThreadRec * kMsThreads * std::max<uint32_t>(w.ms_tiles, 1));
     (void)L;
     for (uint32_t m = 1; m < g.n_levels; ++m) {
         uint64_t cap = n;
@@ -1137,6 +1146,23 @@ static int32_t eval_core(ltl4c_ctx* ctx, const ltl4c_layout& L, const Geometry& 
         sa.err = ctx->err_dev;
         // one launch per property group, each with its own look-back rows and
         // ticket; the first one also writes the numbering
+        // The split map scan (reduce, spine, down sweep) unless the timeline or
+        // parent events need the look-back scan's per-word walk.
+        const bool split = (ctx->scan_variant == kSplitScanVariant || ctx->scan_variant == kSplitScanVariant32) &&
+                           !g.parent && !out->inst_conclusive && !out->event_verdict;
+        if (split) {
+            if (!sa.n_dev) {
+                // nothing is excluded: every word counts
+                s = launch(ctx, "scan", [&] { return launch_set_u32(z + w.n_valid_off, (uint32_t)n, st); });
+                if (s) return s;
+                sa.n_dev = z + w.n_valid_off;
+            }
+            sa.desc = ws + w.ms_desc_off;
+            sa.agg = reinterpret_cast<uint32_t*>(ws + w.ms_agg_off);
+            sa.prefix = reinterpret_cast<uint32_t*>(ws + w.ms_prefix_off);
+            sa.trec = reinterpret_cast<uint32_t*>(ws + w.ms_trec_off);
+            sa.tiles = w.ms_tiles;
+        }
         // (with parent events only the numbering launch: the verdicts come after)
         for (size_t gi = 0; gi < (g.parent ? 1 : groups.size()); ++gi) {
             sa.n_props = groups[gi].cnt;
@@ -1145,7 +1171,13 @@ static int32_t eval_core(ltl4c_ctx* ctx, const ltl4c_layout& L, const Geometry& 
             sa.structure = groups[gi].structure ? 1u : 0u;
             sa.status = scan_status + gi * 2ull * kScanRows * w.tiles_scan;
             sa.ticket = scan_ticket + gi;
-            s = launch(ctx, "scan", [&] { return launch_scan(sa, ctx->scan_variant, st); });
+            if (split) {
+                sa.read_desc = gi > 0 ? 1u : 0u;    // the first launch wrote the descriptors
+                const int items = ctx->scan_variant == kSplitScanVariant32 ? 32 : 16;
+                s = launch(ctx, "scan", [&] { return launch_mapscan(sa, items, st); });
+            } else {
+                s = launch(ctx, "scan", [&] { return launch_scan(sa, ctx->scan_variant, st); });
+            }
             if (s) return s;
         }
 

@@ -181,7 +181,7 @@ def test_sort_tile_variants(variant):
     compare_full(r, evaluate_workload(wl), len(ids), 2)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("case", ["users", "one_cluster", "wide"])
 def test_scan_tile_variants(variant, case):
     import torch

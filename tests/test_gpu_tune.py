@@ -28,7 +28,7 @@ def test_tune_eval_then_results_match_oracle(tmp_path):
     n = wl.n_events
     ws_before = ctx.workspace(n, ids)            # sized before tuning
     t = ctx.tune(rec, ids, n_events=n, reps=3)
-    assert 0 <= t["sort_tile"] < 7 and 0 <= t["scan_tile"] < 4
+    assert 0 <= t["sort_tile"] < 7 and 0 <= t["scan_tile"] < 6
     assert t["candidates"] >= 2 and t["tuned_us"] <= t["default_us"] * 1.0001
     o = evaluate_workload(wl)
     # the tuned schedule, with a workspace of the new size and with the old one
