@@ -283,6 +283,8 @@ struct BatchOutArgs {
 constexpr int kPeThreads = 256;
 constexpr int kPeItems = 16;
 constexpr int kPeTile = kPeThreads * kPeItems;
+constexpr int kPeSpineThreads = 1024;
+constexpr int kPeTreeLevelsPerLaunch = 8;
 constexpr int kPeMaxTreeLevels = 33;
 struct ParentArgs {
     const uint64_t* words;
@@ -301,10 +303,9 @@ struct ParentArgs {
     uint4* tree;                         // segment tree levels 1..: [level][p][tree_cnt[level]]
     uint64_t tree_off[kPeMaxTreeLevels]; // in uint4 units
     uint64_t tree_cnt[kPeMaxTreeLevels];
-    uint32_t* g_out;                     // reduce pass: G_i of every own event
-    const uint32_t* g_in;                // down pass: the same, read back
     uint4* tile_agg;                     // [tiles][P]
     uint4* tile_prefix;                  // [tiles][P]
+    uint4* trec;                         // [P][tiles * kPeThreads] each thread's run map
     uint32_t* tile_heads;                // [tiles]
     uint32_t* tile_head_prefix;          // [tiles]
     uint8_t* inst_verdict;               // [P][inst_stride]
@@ -317,6 +318,7 @@ struct ParentArgs {
 constexpr int kRankThreads = 256;
 constexpr int kRankItems = 16;
 constexpr int kRankTile = kRankThreads * kRankItems;
+constexpr int kRankSpineThreads = 1024;
 struct RankArgs {
     const uint8_t* records;
     uint64_t n;
@@ -385,7 +387,7 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, uint64_t n, uint8_t v, hipStream_t s);
 hipError_t launch_batch_out(const BatchOutArgs& a, hipStream_t s);
 hipError_t launch_parent_counts(const ParentArgs& a, hipStream_t s);
-hipError_t launch_parent_tree(const ParentArgs& a, uint32_t level, uint64_t max_nodes, hipStream_t s);
+hipError_t launch_parent_tree(const ParentArgs& a, uint32_t level0, uint32_t nlev, uint64_t max_nodes0, hipStream_t s);
 hipError_t launch_parent_pass(const ParentArgs& a, bool down, uint64_t max_tiles, hipStream_t s);
 hipError_t launch_parent_spine(const ParentArgs& a, hipStream_t s);
 hipError_t launch_rank_prep(const RankArgs& a, hipStream_t s);

@@ -40,23 +40,37 @@ __global__ __launch_bounds__(1024) void k_rank_prep(RankArgs a) {
     }
 }
 
-// Heads of the sorted values (a value different from the one before) in
-// thread-blocked runs of kRankItems; returns this thread's head mask.
-__device__ __forceinline__ uint32_t rank_heads(const RankArgs& a, uint64_t my0, uint32_t cnt, uint32_t* vals) {
+// This thread's kRankItems sorted words (thread-blocked, 16-byte loads
+// issued together; the word buffers are padded past the last tile), split into
+// values and event indices, and the heads among them (a value different from
+// the one before); returns the head mask.
+__device__ __forceinline__ uint32_t rank_heads(const RankArgs& a, uint64_t my0, uint32_t cnt, uint32_t* vals,
+                                               uint32_t* idx) {
+    const uint64_t ld0 = cnt ? my0 : 0;
+    const uint4* src = reinterpret_cast<const uint4*>(a.sorted + ld0);
+#pragma unroll
+    for (int q = 0; q < kRankItems / 2; ++q) {
+        const uint4 v = src[q];
+        idx[2 * q] = v.x;
+        vals[2 * q] = v.y;
+        idx[2 * q + 1] = v.z;
+        vals[2 * q + 1] = v.w;
+    }
+    const uint32_t prev = (uint32_t)(a.sorted[ld0 ? ld0 - 1 : 0] >> 32);
     uint32_t m = 0;
-    uint32_t prev = my0 > 0 ? (uint32_t)(a.sorted[my0 - 1] >> 32) : 0u;
-    for (uint32_t j = 0; j < cnt; ++j) {
-        const uint32_t v = (uint32_t)(a.sorted[my0 + j] >> 32);
-        vals[j] = v;
-        if (my0 + j == 0 || v != prev) m |= 1u << j;
-        prev = v;
+#pragma unroll
+    for (int j = 0; j < kRankItems; ++j) {
+        const uint32_t before = j ? vals[j - 1] : prev;
+        const bool head = (uint32_t)j < cnt && (my0 + j == 0 || vals[j] != before);
+        m |= (head ? 1u : 0u) << j;
     }
     return m;
 }
 
 // block-wide exclusive sum of one count per thread (thread order), and the total
+template <int THREADS>
 __device__ __forceinline__ uint32_t rank_block_excl(uint32_t c, uint32_t* total) {
-    __shared__ uint32_t s_w[kRankThreads / 64];
+    __shared__ uint32_t s_w[THREADS / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t x = c;
 #pragma unroll
@@ -67,7 +81,7 @@ __device__ __forceinline__ uint32_t rank_block_excl(uint32_t c, uint32_t* total)
     if (lane == 63) s_w[w] = x;
     __syncthreads();
     uint32_t before = 0, tot = 0;
-    for (int i = 0; i < kRankThreads / 64; ++i) {
+    for (int i = 0; i < THREADS / 64; ++i) {
         if (i < w) before += s_w[i];
         tot += s_w[i];
     }
@@ -79,39 +93,47 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tiles(RankArgs a) {
     const uint64_t base = (uint64_t)blockIdx.x * kRankTile;
     const uint64_t my0 = base + (uint64_t)threadIdx.x * kRankItems;
     const uint32_t cnt = my0 < a.n ? (uint32_t)min<uint64_t>(kRankItems, a.n - my0) : 0u;
-    uint32_t vals[kRankItems];
-    const uint32_t m = cnt ? rank_heads(a, my0, cnt, vals) : 0u;
+    uint32_t vals[kRankItems], idx[kRankItems];
+    const uint32_t m = rank_heads(a, my0, cnt, vals, idx);
     uint32_t total;
-    (void)rank_block_excl(__popc(m), &total);
+    (void)rank_block_excl<kRankThreads>(__popc(m), &total);
     if (threadIdx.x == 0) a.tile_cnt[blockIdx.x] = total;
 }
 
-__global__ void k_rank_spine(RankArgs a, uint32_t tiles) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    uint32_t s = 0;
-    for (uint32_t t = 0; t < tiles; ++t) {
+// Exclusive prefix of the tiles' head counts, and the number of distinct
+// values: each thread sums a contiguous chunk of tiles, a block scan joins
+// the chunks, and the threads walk their chunks again.
+__global__ __launch_bounds__(kRankSpineThreads) void k_rank_spine(RankArgs a, uint32_t tiles) {
+    const uint32_t chunk = (tiles + kRankSpineThreads - 1) / kRankSpineThreads;
+    const uint32_t t0 = min(tiles, threadIdx.x * chunk), t1 = min(tiles, t0 + chunk);
+    uint32_t c = 0;
+    for (uint32_t t = t0; t < t1; ++t) c += a.tile_cnt[t];
+    uint32_t total;
+    uint32_t s = rank_block_excl<kRankSpineThreads>(c, &total);
+    for (uint32_t t = t0; t < t1; ++t) {
         a.tile_off[t] = s;
         s += a.tile_cnt[t];
     }
-    *a.n_distinct = s;
+    if (threadIdx.x == 0) *a.n_distinct = total;
 }
 
 __global__ __launch_bounds__(kRankThreads) void k_rank_apply(RankArgs a) {
     const uint64_t base = (uint64_t)blockIdx.x * kRankTile;
     const uint64_t my0 = base + (uint64_t)threadIdx.x * kRankItems;
     const uint32_t cnt = my0 < a.n ? (uint32_t)min<uint64_t>(kRankItems, a.n - my0) : 0u;
-    uint32_t vals[kRankItems];
-    const uint32_t m = cnt ? rank_heads(a, my0, cnt, vals) : 0u;
+    uint32_t vals[kRankItems], idx[kRankItems];
+    const uint32_t m = rank_heads(a, my0, cnt, vals, idx);
     uint32_t total;
-    const uint32_t before = rank_block_excl(__popc(m), &total);
+    const uint32_t before = rank_block_excl<kRankThreads>(__popc(m), &total);
     uint32_t r = a.tile_off[blockIdx.x] + before;     // heads before this thread's run
-    for (uint32_t j = 0; j < cnt; ++j) {
+#pragma unroll
+    for (int j = 0; j < kRankItems; ++j) {
+        if ((uint32_t)j >= cnt) continue;
         if ((m >> j) & 1u) {
             a.uniq[r] = vals[j];
             ++r;
         }
-        const uint32_t idx = (uint32_t)a.sorted[my0 + j];
-        a.rank[idx] = r - 1u;
+        a.rank[idx[j]] = r - 1u;
     }
 }
 
@@ -139,7 +161,7 @@ hipError_t launch_rank_scan(const RankArgs& a, hipStream_t s) {
     const uint32_t tiles = (uint32_t)((a.n + kRankTile - 1) / kRankTile);
     if (tiles == 0) return hipSuccess;
     hipLaunchKernelGGL(k_rank_tiles, dim3(tiles), dim3(kRankThreads), 0, s, a);
-    hipLaunchKernelGGL(k_rank_spine, dim3(1), dim3(64), 0, s, a, tiles);
+    hipLaunchKernelGGL(k_rank_spine, dim3(1), dim3(kRankSpineThreads), 0, s, a, tiles);
     hipLaunchKernelGGL(k_rank_apply, dim3(tiles), dim3(kRankThreads), 0, s, a);
     return hipGetLastError();
 }

@@ -200,7 +200,7 @@ struct WsLayout {
     uint64_t ms_desc_off, ms_agg_off, ms_prefix_off, ms_trec_off;   // the split map scan
     uint32_t ms_tiles;
     // parent events
-    uint64_t pe_g_off, pe_tree_off, pe_tile_agg_off, pe_tile_prefix_off, pe_tile_heads_off, pe_tile_hprefix_off;
+    uint64_t pe_tree_off, pe_trec_off, pe_tile_agg_off, pe_tile_prefix_off, pe_tile_heads_off, pe_tile_hprefix_off;
     uint64_t pe_tree_lvl[kPeMaxTreeLevels], pe_tree_cnt[kPeMaxTreeLevels];
     uint32_t pe_levels, pe_tiles;
 };
@@ -302,9 +302,8 @@ WsLayout plan_workspace(const ltl4c_layout& L, const Geometry& g, uint64_t n, ui
         w.counts_off[m] = off;     off = align256(off + (uint64_t)P * cap * 6 * 4);
     }
     if (g.parent) {
-        // G_i per own event, the segment tree over the parent events (levels
-        // 1 .. ceil(log2 n), per property), and the tile aggregates and prefixes
-        w.pe_g_off = off; off = align256(off + 4 * std::max<uint64_t>(n, 1));
+        // the segment tree over the parent events (levels 1 .. ceil(log2 n),
+        // per property), and the tile aggregates and prefixes
         w.pe_levels = 0;
         uint64_t nodes = 0;
         for (uint32_t lv = 1; lv < (uint32_t)kPeMaxTreeLevels && (1ull << (lv - 1)) < n; ++lv) {
@@ -318,6 +317,7 @@ WsLayout plan_workspace(const ltl4c_layout& L, const Geometry& g, uint64_t n, ui
         const uint64_t t = std::max<uint32_t>(w.pe_tiles, 1);
         w.pe_tile_agg_off = off;     off = align256(off + 16 * t * P);
         w.pe_tile_prefix_off = off;  off = align256(off + 16 * t * P);
+        w.pe_trec_off = off;         off = align256(off + 16 * t * kPeThreads * P);
         w.pe_tile_heads_off = off;   off = align256(off + 4 * t);
         w.pe_tile_hprefix_off = off; off = align256(off + 4 * t);
     }
@@ -1200,24 +1200,23 @@ static int32_t eval_core(ltl4c_ctx* ctx, const ltl4c_layout& L, const Geometry& 
             }
             pa.tile_agg = reinterpret_cast<uint4*>(ws + w.pe_tile_agg_off);
             pa.tile_prefix = reinterpret_cast<uint4*>(ws + w.pe_tile_prefix_off);
+            pa.trec = reinterpret_cast<uint4*>(ws + w.pe_trec_off);
             pa.tile_heads = reinterpret_cast<uint32_t*>(ws + w.pe_tile_heads_off);
             pa.tile_head_prefix = reinterpret_cast<uint32_t*>(ws + w.pe_tile_hprefix_off);
             pa.inst_verdict = inst_verdict;
             pa.inst_stride = inst_stride;
             pa.inst_limit = inst_stride;
             pa.err = ctx->err_dev;
-            for (uint32_t lv = 1; lv <= w.pe_levels; ++lv) {
-                s = launch(ctx, "parent", [&] { return launch_parent_tree(pa, lv, w.pe_tree_cnt[lv], st); });
+            for (uint32_t l0 = 0; l0 < w.pe_levels; l0 += kPeTreeLevelsPerLaunch) {
+                const uint32_t nlev = std::min<uint32_t>(kPeTreeLevelsPerLaunch, w.pe_levels - l0);
+                const uint64_t nodes0 = l0 ? w.pe_tree_cnt[l0] : n;
+                s = launch(ctx, "parent", [&] { return launch_parent_tree(pa, l0, nlev, nodes0, st); });
                 if (s) return s;
             }
-            uint32_t* gbuf = reinterpret_cast<uint32_t*>(ws + w.pe_g_off);
-            pa.g_out = gbuf;
             s = launch(ctx, "parent", [&] { return launch_parent_pass(pa, false, w.pe_tiles, st); });
             if (s) return s;
             s = launch(ctx, "parent", [&] { return launch_parent_spine(pa, st); });
             if (s) return s;
-            pa.g_out = nullptr;
-            pa.g_in = gbuf;
             s = launch(ctx, "parent", [&] { return launch_parent_pass(pa, true, w.pe_tiles, st); });
             if (s) return s;
         }
