@@ -284,6 +284,10 @@ constexpr int kPeThreads = 256;
 constexpr int kPeItems = 16;
 constexpr int kPeTile = kPeThreads * kPeItems;
 constexpr int kPeSpineThreads = 1024;
+constexpr int kPeShortGap = 8;          // gaps up to this many parent entries skip the segment tree
+constexpr int kPeShortRun = 8;          // a parent's run up to this long is held in registers
+constexpr int kPeSamples = 2048;        // sample table of the parent array (fits the word rows in LDS)
+static_assert(kPeSamples <= kPeItems * kPeThreads, "samples share LDS with the staged words");
 constexpr int kPeTreeLevelsPerLaunch = 8;
 constexpr int kPeMaxTreeLevels = 33;
 struct ParentArgs {
@@ -306,6 +310,7 @@ struct ParentArgs {
     uint4* tile_agg;                     // [tiles][P]
     uint4* tile_prefix;                  // [tiles][P]
     uint4* trec;                         // [P][tiles * kPeThreads] each thread's run map
+    uint64_t* samples;                   // [kPeSamples] keys of every stride-th parent entry
     uint32_t* tile_heads;                // [tiles]
     uint32_t* tile_head_prefix;          // [tiles]
     uint8_t* inst_verdict;               // [P][inst_stride]
@@ -387,6 +392,7 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* p, uint64_t n, uint8_t v, hipStream_t s);
 hipError_t launch_batch_out(const BatchOutArgs& a, hipStream_t s);
 hipError_t launch_parent_counts(const ParentArgs& a, hipStream_t s);
+hipError_t launch_parent_samples(const ParentArgs& a, hipStream_t s);
 hipError_t launch_parent_tree(const ParentArgs& a, uint32_t level0, uint32_t nlev, uint64_t max_nodes0, hipStream_t s);
 hipError_t launch_parent_pass(const ParentArgs& a, bool down, uint64_t max_tiles, hipStream_t s);
 hipError_t launch_parent_spine(const ParentArgs& a, hipStream_t s);

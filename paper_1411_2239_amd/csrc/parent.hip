@@ -80,18 +80,6 @@ __device__ __forceinline__ Map16 m_from(const uint4& v) {
 
 __device__ __forceinline__ uint4 m_to(const Map16& m) { return make_uint4(m.d[0], m.d[1], m.d[2], m.d[3]); }
 
-__device__ __forceinline__ Map16 m_class(const PropDev& pd, uint32_t c) {
-    Map16 r;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) r.d[i] = pd.bmap[c][i];
-    return r;
-}
-
-// delta(q, c) of a class map, for one state
-__device__ __forceinline__ uint32_t class_at(const PropDev& pd, uint32_t c, uint32_t q) {
-    return (pd.bmap[c][q >> 2] >> (8 * (q & 3u))) & 0xFFu;
-}
-
 __device__ __forceinline__ Map16 m_shfl_up(const Map16& v, int off) {
     Map16 r;
 #pragma unroll
@@ -109,15 +97,28 @@ __device__ __forceinline__ uint64_t prefix_of(const ParentArgs& a, uint64_t w) {
     return (w >> a.prefix_shift) & a.prefix_mask;
 }
 
-// number of parent-array entries whose search key is below `target`
-__device__ __forceinline__ uint32_t lower_bound(const ParentArgs& a, const uint64_t* par, uint32_t k, uint64_t target) {
-    uint32_t lo = 0, hi = k;
+// number of parent-array entries whose search key is below `target`, from
+// the block's copy of the sample table (sample i is the key of entry
+// i * stride, all ones past the end): a search in LDS narrows the answer to
+// one stride, then a binary search in memory.
+__device__ __forceinline__ uint32_t lower_bound_sampled(const ParentArgs& a, const uint64_t* par, uint32_t k,
+                                                        const uint64_t* samp, uint64_t target) {
+    if (k == 0) return 0;
+    const uint32_t stride = (k + kPeSamples - 1) / kPeSamples;
+    uint32_t lo = 0, hi = kPeSamples;
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (search_key(a, par[mid]) < target) lo = mid + 1;
+        if (samp[mid] < target) lo = mid + 1;
         else hi = mid;
     }
-    return lo;
+    if (lo == 0) return 0;
+    uint32_t l = (lo - 1) * stride + 1, r = min(lo * stride, k);
+    while (l < r) {
+        const uint32_t mid = (l + r) >> 1;
+        if (search_key(a, par[mid]) < target) l = mid + 1;
+        else r = mid;
+    }
+    return l;
 }
 
 // The same, given that every entry before g is below `target`: probes at g
@@ -145,26 +146,44 @@ __device__ __forceinline__ uint32_t gallop(const ParentArgs& a, const uint64_t* 
     return (uint32_t)lo;
 }
 
-// level L node q of the segment tree of property p (level 0: a class map)
-__device__ __forceinline__ Map16 tree_node(const ParentArgs& a, const PropDev& pd, const uint64_t* par, uint32_t p,
+// search key of parent entry g, all ones past the end
+__device__ __forceinline__ uint64_t key_at(const ParentArgs& a, const uint64_t* par, uint32_t k, uint32_t g) {
+    return g < k ? search_key(a, par[g]) : ~0ull;
+}
+
+// level L node q of the segment tree of property p (level 0: the class map of
+// the entry, from the block's copy of the property's class maps)
+__device__ __forceinline__ Map16 tree_node(const ParentArgs& a, const uint4* cm, const uint64_t* par, uint32_t p,
                                            uint32_t L, uint64_t q) {
-    if (L == 0) return m_class(pd, (uint32_t)par[q] & a.class_mask);
+    if (L == 0) return m_from(cm[(uint32_t)par[q] & a.class_mask]);
     return m_from(a.tree[a.tree_off[L] + (uint64_t)p * a.tree_cnt[L] + q]);
 }
 
-// composition of the class maps of parent-array entries [l, r), in order
-__device__ __forceinline__ Map16 range_map(const ParentArgs& a, const PropDev& pd, const uint64_t* par, uint32_t p,
-                                        uint32_t l, uint32_t r) {
+// composition of the class maps of parent-array entries [l, r), in order.
+// Up to kPeShortGap entries: their words are loaded together and their maps
+// composed from LDS; longer gaps walk the segment tree.
+__device__ __forceinline__ Map16 range_map(const ParentArgs& a, const uint4* cm, const uint64_t* par, uint32_t p,
+                                           uint32_t l, uint32_t r) {
+    if (r - l <= (uint32_t)kPeShortGap) {
+        uint32_t c[kPeShortGap];
+#pragma unroll
+        for (int j = 0; j < kPeShortGap; ++j) c[j] = (uint32_t)par[min(l + (uint32_t)j, r - 1u)] & a.class_mask;
+        Map16 m = m_identity();
+#pragma unroll
+        for (int j = 0; j < kPeShortGap; ++j)
+            if (l + (uint32_t)j < r) m = m_compose(m_from(cm[c[j]]), m);
+        return m;
+    }
     Map16 left = m_identity(), right = m_identity();
     uint32_t L = 0;
     while (l < r) {
         if (l & 1u) {
-            left = m_compose(tree_node(a, pd, par, p, L, l), left);
+            left = m_compose(tree_node(a, cm, par, p, L, l), left);
             ++l;
         }
         if (r & 1u) {
             --r;
-            right = m_compose(right, tree_node(a, pd, par, p, L, r));
+            right = m_compose(right, tree_node(a, cm, par, p, L, r));
         }
         l >>= 1;
         r >>= 1;
@@ -173,76 +192,170 @@ __device__ __forceinline__ Map16 range_map(const ParentArgs& a, const PropDev& p
     return m_compose(right, left);
 }
 
-// One thread's run of own events, staged in LDS (row j + 1 of column tid is
-// its event j, row 0 the word before the run, row kPeItems + 1 the word
-// after it), with its head and end flags and the start of its gap search:
-// the parent's run start `rs` of the first event's prefix (a binary search)
-// and `g`, the bound G of the event before the run when it belongs to the
-// same instance.
+// One thread's run of own events: loaded to registers, its trace indices
+// later staged in LDS (row j of column tid holds event j's), its classes and
+// prefix ordinals (0 for the first event's prefix, one more at every change)
+// kept as nibbles, its head and end flags as bits.
 struct PeRun {
+    uint64_t my0;
     uint32_t cnt;
     uint32_t heads, ends;                // bit j
-    uint64_t pf;                         // prefix of the first event
-    uint32_t rs, g;
+    uint32_t cls[2], pord[2];            // nibble j of the pair
+    uint64_t wprev;                      // the word before the run
+    uint64_t w[kPeItems];
 };
 
-__device__ __forceinline__ void load_run(const ParentArgs& a, uint32_t n_own, uint32_t k, const uint64_t* par,
-                                         uint64_t my0, uint64_t (*s_w)[kPeThreads], PeRun& r) {
-    const int tid = threadIdx.x;
+__device__ __forceinline__ uint32_t nibble(const uint32_t* v, uint32_t j) {
+    return ((j < 8u ? v[0] : v[1]) >> (4 * (j & 7u))) & 15u;
+}
+
+__device__ __forceinline__ void load_run(const ParentArgs& a, uint32_t n_own, uint64_t my0, PeRun& r) {
+    r.my0 = my0;
     r.cnt = my0 < n_own ? (uint32_t)min<uint64_t>(kPeItems, n_own - my0) : 0u;
     // unconditional loads (the word buffers are padded past the last tile)
     const uint64_t ld0 = r.cnt ? my0 : 0;
-    uint64_t w[kPeItems];
     const uint4* src = reinterpret_cast<const uint4*>(a.words + ld0);
 #pragma unroll
     for (int q = 0; q < kPeItems / 2; ++q) {
         const uint4 v = src[q];
-        w[2 * q] = (uint64_t)v.x | ((uint64_t)v.y << 32);
-        w[2 * q + 1] = (uint64_t)v.z | ((uint64_t)v.w << 32);
+        r.w[2 * q] = (uint64_t)v.x | ((uint64_t)v.y << 32);
+        r.w[2 * q + 1] = (uint64_t)v.z | ((uint64_t)v.w << 32);
     }
-    const uint64_t wprev = a.words[ld0 ? ld0 - 1 : 0];
+    r.wprev = a.words[ld0 ? ld0 - 1 : 0];
     const uint64_t wnext = a.words[ld0 + kPeItems];
     r.heads = r.ends = 0;
+    r.cls[0] = r.cls[1] = r.pord[0] = r.pord[1] = 0;
+    uint32_t ord = 0;
 #pragma unroll
     for (int j = 0; j < kPeItems; ++j) {
-        const uint64_t key = w[j] >> a.key_shift;
-        const uint64_t kp = (j ? w[j - 1] : wprev) >> a.key_shift;
-        const uint64_t kn = (j + 1 < kPeItems ? w[j + 1] : wnext) >> a.key_shift;
+        const uint64_t key = r.w[j] >> a.key_shift;
+        const uint64_t kp = (j ? r.w[j - 1] : r.wprev) >> a.key_shift;
+        const uint64_t kn = (j + 1 < kPeItems ? r.w[j + 1] : wnext) >> a.key_shift;
         const bool valid = (uint32_t)j < r.cnt;
         const bool head = valid && (my0 + j == 0 || kp != key);
         const bool end = valid && (my0 + j + 1 == n_own || kn != key);
         r.heads |= (head ? 1u : 0u) << j;
         r.ends |= (end ? 1u : 0u) << j;
-        s_w[j + 1][tid] = w[j];
+        if (j && prefix_of(a, r.w[j]) != prefix_of(a, r.w[j - 1])) ++ord;
+        r.cls[j >> 3] |= ((uint32_t)r.w[j] & a.class_mask) << (4 * (j & 7));
+        r.pord[j >> 3] |= ord << (4 * (j & 7));
     }
-    s_w[0][tid] = wprev;
-    s_w[kPeItems + 1][tid] = wnext;
-    r.pf = prefix_of(a, w[0]);
-    r.rs = r.cnt ? lower_bound(a, par, k, r.pf << a.ibits) : 0u;
-    r.g = (r.cnt && !(r.heads & 1u)) ? gallop(a, par, k, r.rs, search_key(a, wprev)) : r.rs;
 }
 
-// The walk over a run: for each own event, its word, flags and the gap
-// [lo, g) of parent entries before it; the run starts and bounds move
-// forward by galloping.
+// The search over the parent array along a run: the parent's run [rs, re)
+// of the current prefix and the bound g of the last event.  Prefixes grow
+// along the sorted own events and the bounds grow within an instance, so
+// every search gallops forward from a known lower bound.  A short run (at
+// most kPeShortRun entries, the usual case) is read once when its prefix is
+// entered, its trace indices and classes kept in registers: bounds are then
+// counts of smaller trace indices and gap maps come from the block's class
+// maps, without memory traffic.  On a long run a bound that did not move
+// costs no load either (the key at g is kept).
 struct PeWalk {
     uint64_t pf;
-    uint32_t rs, g;
-    __device__ __forceinline__ explicit PeWalk(const PeRun& r) : pf(r.pf), rs(r.rs), g(r.g) {}
-    // returns lo; g becomes G of the event
-    __device__ __forceinline__ uint32_t step(const ParentArgs& a, const uint64_t* par, uint32_t k, uint64_t x,
-                                             bool head) {
-        if (head) {
-            const uint64_t pj = prefix_of(a, x);
-            if (pj != pf) {
-                rs = gallop(a, par, k, rs, pj << a.ibits);
-                pf = pj;
+    uint32_t ord;                        // prefix ordinal of pf within the thread's run
+    uint32_t rs, re, g;
+    uint64_t gkey;                       // long run: search key at g, all ones at re
+    uint32_t rcls;                       // short run: class of entry rs + j in bits 4j..
+    uint32_t tix[kPeShortRun];           // short run: trace index of entry rs + j
+
+    __device__ __forceinline__ bool is_short() const { return re - rs <= (uint32_t)kPeShortRun; }
+
+    // the run of prefix pj, searched from `from` (a lower bound of its start;
+    // `exact` when it is the start): the first kPeShortRun + 1 entries are
+    // read together, and only a longer run is searched further
+    __device__ __forceinline__ void enter(const ParentArgs& a, const uint64_t* par, uint32_t k, uint64_t pj,
+                                          uint32_t from, bool exact) {
+        pf = pj;
+        rs = exact ? from : gallop(a, par, k, from, pj << a.ibits);
+        uint64_t wj[kPeShortRun + 1];
+        const uint32_t last = k ? k - 1u : 0u;
+#pragma unroll
+        for (int j = 0; j <= kPeShortRun; ++j) wj[j] = k ? par[min(rs + (uint32_t)j, last)] : 0ull;
+        uint32_t n = 0;
+#pragma unroll
+        for (int j = 0; j <= kPeShortRun; ++j)
+            n += (rs + (uint32_t)j < k && prefix_of(a, wj[j]) == pj) ? 1u : 0u;
+        rcls = 0;
+        if (n <= (uint32_t)kPeShortRun) {
+            re = rs + n;
+#pragma unroll
+            for (int j = 0; j < kPeShortRun; ++j) {
+                tix[j] = (uint32_t)j < n ? (uint32_t)((wj[j] >> a.cbits) & a.index_mask) : 0xFFFFFFFFu;
+                rcls |= ((uint32_t)j < n ? ((uint32_t)wj[j] & a.class_mask) : 0u) << (4 * j);
             }
-            g = rs;
+        } else {
+            re = gallop(a, par, k, rs + kPeShortRun + 1, (pj + 1) << a.ibits);
+        }
+    }
+
+    __device__ __forceinline__ void reset_to_run_start(const ParentArgs& a, const uint64_t* par) {
+        g = rs;
+        gkey = is_short() ? ~0ull : key_at(a, par, re, rs);
+    }
+
+    // start of a run: a search in the sample table for the first prefix, then
+    // the bound of the event before the run when it belongs to the same
+    // instance
+    __device__ __forceinline__ void start(const ParentArgs& a, const uint64_t* par, uint32_t k, const PeRun& r,
+                                          const uint64_t* samp) {
+        const uint64_t pj = prefix_of(a, r.w[0]);
+        ord = 0;
+        enter(a, par, k, pj, r.cnt ? lower_bound_sampled(a, par, k, samp, pj << a.ibits) : 0u, r.cnt != 0);
+        reset_to_run_start(a, par);
+        if (r.cnt && !(r.heads & 1u)) advance(a, par, (uint32_t)((r.wprev >> a.cbits) & a.index_mask));
+    }
+
+    // g becomes the bound of an own event of the current instance with trace
+    // index t
+    __device__ __forceinline__ void advance(const ParentArgs& a, const uint64_t* par, uint32_t t) {
+        if (is_short()) {
+            uint32_t c = 0;
+#pragma unroll
+            for (int j = 0; j < kPeShortRun; ++j) c += tix[j] < t ? 1u : 0u;
+            g = rs + c;
+            return;
+        }
+        const uint64_t target = (pf << a.ibits) | t;
+        if (gkey < target) {
+            g = gallop(a, par, re, g + 1, target);
+            gkey = key_at(a, par, re, g);       // all ones at the run end
+        }
+    }
+
+    // own event j of the run, with trace index t: returns lo, the start of the
+    // gap before it; g becomes its G.  A head with a new prefix reads its word
+    // again for the prefix.
+    __device__ __forceinline__ uint32_t step(const ParentArgs& a, const uint64_t* par, uint32_t k, const PeRun& r,
+                                             uint32_t j, uint32_t t, bool head) {
+        if (head) {
+            const uint32_t oj = nibble(r.pord, j);
+            if (oj != ord) {
+                ord = oj;
+                enter(a, par, k, prefix_of(a, a.words[r.my0 + j]), re, false);
+            }
+            reset_to_run_start(a, par);
         }
         const uint32_t lo = g;
-        g = gallop(a, par, k, g, search_key(a, x));
+        advance(a, par, t);
         return lo;
+    }
+
+    // composition of the class maps of the run's entries [l, r) (l <= r)
+    __device__ __forceinline__ Map16 gap_map(const ParentArgs& a, const uint4* cm, const uint64_t* par, uint32_t p,
+                                             uint32_t l, uint32_t r) const {
+        if (!is_short()) return range_map(a, cm, par, p, l, r);
+        Map16 m = m_identity();
+        for (uint32_t e = l; e < r; ++e) m = m_compose(m_from(cm[(rcls >> (4 * (e - rs))) & 15u]), m);
+        return m;
+    }
+
+    // the same, applied to one state
+    __device__ __forceinline__ uint32_t gap_at(const ParentArgs& a, const uint4* cm, const uint64_t* par, uint32_t p,
+                                               uint32_t l, uint32_t r, uint32_t st) const {
+        if (!is_short()) return m_at(range_map(a, cm, par, p, l, r), st);
+        for (uint32_t e = l; e < r; ++e) st = m_at(m_from(cm[(rcls >> (4 * (e - rs))) & 15u]), st);
+        return st;
     }
 };
 
@@ -273,20 +386,37 @@ __global__ void k_pe_counts(ParentArgs a) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *a.n_own = *a.n_kept - *a.n_par;
 }
 
+// The sample table: entry i * stride of the parent array (stride =
+// ceil(k / kPeSamples)), all ones past the end.
+__global__ __launch_bounds__(256) void k_pe_samples(ParentArgs a) {
+    const uint32_t k = *a.n_par;
+    const uint64_t* par = a.words + *a.n_own;
+    const uint32_t stride = k ? (k + kPeSamples - 1) / kPeSamples : 1u;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < (uint32_t)kPeSamples; i += gridDim.x * blockDim.x) {
+        const uint64_t at = (uint64_t)i * stride;
+        a.samples[i] = at < k ? search_key(a, par[at]) : ~0ull;
+    }
+}
+
 // Levels L0+1 .. L0+nlev of the segment tree of property blockIdx.y, from
 // level L0: each block takes 256 level-L0 nodes and halves them in LDS.  A
 // missing right child counts as the identity.
 __global__ __launch_bounds__(256) void k_pe_tree(ParentArgs a, uint32_t L0, uint32_t nlev) {
     __shared__ uint4 s[256];
+    __shared__ uint4 s_cm[16];
     const uint32_t p = blockIdx.y;
-    const PropDev& pd = a.plan->prop[p];
+    if (threadIdx.x < 16) {
+        const uint32_t* m = a.plan->prop[p].bmap[threadIdx.x];
+        s_cm[threadIdx.x] = make_uint4(m[0], m[1], m[2], m[3]);
+    }
+    __syncthreads();
     const uint32_t k = *a.n_par;
     const uint64_t* par = a.words + *a.n_own;
     const uint64_t cnt0 = ((uint64_t)k + (1ull << L0) - 1) >> L0;
     const uint32_t t = threadIdx.x;
     for (uint64_t b = blockIdx.x; b * 256 < cnt0; b += gridDim.x) {
         const uint64_t q = b * 256 + t;
-        Map16 m = q < cnt0 ? tree_node(a, pd, par, p, L0, q) : m_identity();
+        Map16 m = q < cnt0 ? tree_node(a, s_cm, par, p, L0, q) : m_identity();
         for (uint32_t l = 1; l <= nlev; ++l) {
             if (t < (256u >> (l - 1))) s[t] = m_to(m);
             __syncthreads();
@@ -308,7 +438,10 @@ __global__ __launch_bounds__(256) void k_pe_tree(ParentArgs a, uint32_t L0, uint
 // maps; verdicts written by instance number.
 template <bool DOWN>
 __global__ __launch_bounds__(kPeThreads) void k_pe_pass(ParentArgs a) {
-    __shared__ uint64_t s_w[kPeItems + 2][kPeThreads];
+    __shared__ uint32_t s_t[kPeItems][kPeThreads];
+    __shared__ uint4 s_cm[kMaxProps][16];
+    __shared__ uint8_t s_iv[kPeTile + 4];
+    __shared__ uint32_t s_red[2][kPeThreads / 64];
     __shared__ uint4 s_map[kPeThreads / 64];
     __shared__ uint32_t s_cnt[kPeThreads / 64];
     const uint32_t n_own = *a.n_own, k = *a.n_par;
@@ -317,22 +450,49 @@ __global__ __launch_bounds__(kPeThreads) void k_pe_pass(ParentArgs a) {
     const uint64_t base = (uint64_t)tile * kPeTile;
     if (base >= n_own) return;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (uint32_t i = tid; i < a.n_props * 16u; i += kPeThreads) {
+        const uint32_t* m = a.plan->prop[i >> 4].bmap[i & 15u];
+        s_cm[i >> 4][i & 15u] = make_uint4(m[0], m[1], m[2], m[3]);
+    }
+    // the sample table of the parent array first occupies the LDS rows of the
+    // trace indices
+    static_assert(kPeSamples * 8 <= kPeItems * kPeThreads * 4, "samples share LDS with the trace indices");
+    uint64_t* s_samp = reinterpret_cast<uint64_t*>(&s_t[0][0]);
+    for (uint32_t i = tid; i < (uint32_t)kPeSamples; i += kPeThreads) s_samp[i] = a.samples[i];
     PeRun r;
-    load_run(a, n_own, k, par, base + (uint64_t)tid * kPeItems, s_w, r);
+    load_run(a, n_own, base + (uint64_t)tid * kPeItems, r);
+    __syncthreads();
+    PeWalk w0;
+    w0.start(a, par, k, r, s_samp);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kPeItems; ++j) s_t[j][tid] = (uint32_t)((r.w[j] >> a.cbits) & a.index_mask);
+    __syncthreads();
     const uint64_t row = (uint64_t)gridDim.x * kPeThreads;
     if (!DOWN) {
         for (uint32_t p = 0; p < a.n_props; ++p) {
-            const PropDev& pd = a.plan->prop[p];
+            const uint4* cm = s_cm[p];
+            const uint32_t q0 = a.plan->prop[p].q0;
             Map16 agg = m_identity();
-            PeWalk wk(r);
-            for (uint32_t j = 0; j < r.cnt; ++j) {
-                const uint64_t x = s_w[j + 1][tid];
-                const bool head = (r.heads >> j) & 1u;
-                const uint32_t lo = wk.step(a, par, k, x, head);
-                Map16 f = m_class(pd, (uint32_t)x & a.class_mask);
-                if (lo < wk.g) f = m_compose(f, range_map(a, pd, par, p, lo, wk.g));
-                if (head) f = m_const(m_at(f, pd.q0));
-                agg = m_compose(f, agg);
+            PeWalk wk = w0;
+            if (r.heads == 0) {
+                // no instance begins in the run: compose the maps of its events
+                for (uint32_t j = 0; j < r.cnt; ++j) {
+                    const uint32_t lo = wk.step(a, par, k, r, j, s_t[j][tid], false);
+                    Map16 f = m_from(cm[nibble(r.cls, j)]);
+                    if (lo < wk.g) f = m_compose(f, wk.gap_map(a, cm, par, p, lo, wk.g));
+                    agg = m_compose(f, agg);
+                }
+            } else {
+                // the last head's map is constant, so the run's map is the
+                // constant of the state reached from q0 at that head
+                uint32_t st = q0;
+                for (uint32_t j = 31u - __clz(r.heads); j < r.cnt; ++j) {
+                    const uint32_t lo = wk.step(a, par, k, r, j, s_t[j][tid], (r.heads >> j) & 1u);
+                    if (lo < wk.g) st = wk.gap_at(a, cm, par, p, lo, wk.g, st);
+                    st = m_at(m_from(cm[nibble(r.cls, j)]), st);
+                }
+                agg = m_const(st);
             }
             a.trec[(uint64_t)p * row + (uint64_t)tile * kPeThreads + tid] = m_to(agg);
             uint32_t c = __popc(r.heads);
@@ -353,6 +513,7 @@ __global__ __launch_bounds__(kPeThreads) void k_pe_pass(ParentArgs a) {
     }
     for (uint32_t p = 0; p < a.n_props; ++p) {
         const PropDev& pd = a.plan->prop[p];
+        const uint4* cm = s_cm[p];
         Map16 v = m_from(a.trec[(uint64_t)p * row + (uint64_t)tile * kPeThreads + tid]);
         uint32_t c = __popc(r.heads);
         block_scan(v, c, s_map, s_cnt);
@@ -370,28 +531,57 @@ __global__ __launch_bounds__(kPeThreads) void k_pe_pass(ParentArgs a) {
             id += exc;
         }
         __syncthreads();                 // s_map is reused by the next property
+        const uint32_t lab0 = pd.blabel[0], lab1 = pd.blabel[1];
         uint32_t st = m_at(pre, pd.q0);  // state before this thread's first event
-        PeWalk wk(r);
+        // the instances ending in the tile have consecutive numbers, from
+        // the one holding its first event (heads before the tile, minus one):
+        // their verdicts are staged in LDS and written out contiguously
+        const uint32_t inst0 = a.tile_head_prefix[tile] - 1u;
+        uint32_t my_lo = 0xFFFFFFFFu, my_hi = 0;
+        PeWalk wk = w0;
         for (uint32_t j = 0; j < r.cnt; ++j) {
-            const uint64_t x = s_w[j + 1][tid];
             const bool head = (r.heads >> j) & 1u;
-            const uint32_t lo = wk.step(a, par, k, x, head);
+            const uint32_t lo = wk.step(a, par, k, r, j, s_t[j][tid], head);
             if (head) {
                 st = pd.q0;
                 ++id;
             }
-            if (lo < wk.g) st = m_at(range_map(a, pd, par, p, lo, wk.g), st);
-            st = class_at(pd, (uint32_t)x & a.class_mask, st);
+            if (lo < wk.g) st = wk.gap_at(a, cm, par, p, lo, wk.g, st);
+            st = m_at(m_from(cm[nibble(r.cls, j)]), st);
             if ((r.ends >> j) & 1u) {
                 // the trailing gap: the parent's entries after the last own event
-                const uint32_t hi = gallop(a, par, k, wk.g, (prefix_of(a, x) + 1) << a.ibits);
                 uint32_t fin = st;
-                if (wk.g < hi) fin = m_at(range_map(a, pd, par, p, wk.g, hi), fin);
-                const uint64_t inst = (uint64_t)id - 1u;
-                if (inst < a.inst_limit) a.inst_verdict[(uint64_t)p * a.inst_stride + inst] = pd.label[fin & 15u];
-                else atomicOr(a.err, kErrCapacity);
+                if (wk.g < wk.re) fin = wk.gap_at(a, cm, par, p, wk.g, wk.re, fin);
+                const uint32_t inst = id - 1u;
+                s_iv[inst - inst0] = (uint8_t)((((fin & 8u) ? lab1 : lab0) >> (4 * (fin & 7u))) & 15u);
+                my_lo = min(my_lo, inst);
+                my_hi = max(my_hi, inst + 1u);
             }
         }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            my_lo = min(my_lo, (uint32_t)__shfl_xor(my_lo, off, 64));
+            my_hi = max(my_hi, (uint32_t)__shfl_xor(my_hi, off, 64));
+        }
+        if (lane == 0) {
+            s_red[0][w] = my_lo;
+            s_red[1][w] = my_hi;
+        }
+        __syncthreads();
+        uint32_t lo = s_red[0][0], hi = s_red[1][0];
+        for (int i = 1; i < kPeThreads / 64; ++i) {
+            lo = min(lo, s_red[0][i]);
+            hi = max(hi, s_red[1][i]);
+        }
+        if (lo < hi) {
+            if ((uint64_t)hi > a.inst_limit) {
+                if (tid == 0) atomicOr(a.err, kErrCapacity);
+                hi = (uint32_t)min<uint64_t>(hi, a.inst_limit);
+            }
+            for (uint32_t i = lo + tid; i < hi; i += kPeThreads)
+                a.inst_verdict[(uint64_t)p * a.inst_stride + i] = s_iv[i - inst0];
+        }
+        __syncthreads();                 // s_iv and s_red are reused by the next property
     }
 }
 
@@ -442,6 +632,11 @@ __global__ __launch_bounds__(kPeSpineThreads) void k_pe_spine(ParentArgs a) {
 
 hipError_t launch_parent_counts(const ParentArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_pe_counts, dim3(1), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_parent_samples(const ParentArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_pe_samples, dim3(kPeSamples / 256), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -200,7 +200,7 @@ struct WsLayout {
     uint64_t ms_desc_off, ms_agg_off, ms_prefix_off, ms_trec_off;   // the split map scan
     uint32_t ms_tiles;
     // parent events
-    uint64_t pe_tree_off, pe_trec_off, pe_tile_agg_off, pe_tile_prefix_off, pe_tile_heads_off, pe_tile_hprefix_off;
+    uint64_t pe_tree_off, pe_trec_off, pe_samples_off, pe_tile_agg_off, pe_tile_prefix_off, pe_tile_heads_off, pe_tile_hprefix_off;
     uint64_t pe_tree_lvl[kPeMaxTreeLevels], pe_tree_cnt[kPeMaxTreeLevels];
     uint32_t pe_levels, pe_tiles;
 };
@@ -318,6 +318,7 @@ WsLayout plan_workspace(const ltl4c_layout& L, const Geometry& g, uint64_t n, ui
         w.pe_tile_agg_off = off;     off = align256(off + 16 * t * P);
         w.pe_tile_prefix_off = off;  off = align256(off + 16 * t * P);
         w.pe_trec_off = off;         off = align256(off + 16 * t * kPeThreads * P);
+        w.pe_samples_off = off;      off = align256(off + 8 * kPeSamples);
         w.pe_tile_heads_off = off;   off = align256(off + 4 * t);
         w.pe_tile_hprefix_off = off; off = align256(off + 4 * t);
     }
@@ -1201,12 +1202,15 @@ static int32_t eval_core(ltl4c_ctx* ctx, const ltl4c_layout& L, const Geometry& 
             pa.tile_agg = reinterpret_cast<uint4*>(ws + w.pe_tile_agg_off);
             pa.tile_prefix = reinterpret_cast<uint4*>(ws + w.pe_tile_prefix_off);
             pa.trec = reinterpret_cast<uint4*>(ws + w.pe_trec_off);
+            pa.samples = reinterpret_cast<uint64_t*>(ws + w.pe_samples_off);
             pa.tile_heads = reinterpret_cast<uint32_t*>(ws + w.pe_tile_heads_off);
             pa.tile_head_prefix = reinterpret_cast<uint32_t*>(ws + w.pe_tile_hprefix_off);
             pa.inst_verdict = inst_verdict;
             pa.inst_stride = inst_stride;
             pa.inst_limit = inst_stride;
             pa.err = ctx->err_dev;
+            s = launch(ctx, "parent", [&] { return launch_parent_samples(pa, st); });
+            if (s) return s;
             for (uint32_t l0 = 0; l0 < w.pe_levels; l0 += kPeTreeLevelsPerLaunch) {
                 const uint32_t nlev = std::min<uint32_t>(kPeTreeLevelsPerLaunch, w.pe_levels - l0);
                 const uint64_t nodes0 = l0 ? w.pe_tree_cnt[l0] : n;
