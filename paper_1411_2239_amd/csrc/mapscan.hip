@@ -341,16 +341,19 @@ __global__ __launch_bounds__(kMsThreads) void k_ms_reduce(ScanArgs a) {
 
 // Exclusive prefixes of the tile records (maps composed in tile order, head
 // counts summed), one block.  Tiles go in passes of kSpineThreads x (up to
-// 8) tiles: each thread loads its chunk's records at once (all loads in
-// flight together), composes them, the block scans the thread totals, and the
-// running prefix carries from pass to pass.
-constexpr int kSpineThreads = 256;
+// 4) tiles, one pass up to 16M words of 4,096-word tiles: each thread loads
+// its chunk's records at once (16-byte loads, all in flight together),
+// composes them, the block scans the thread totals, and the running prefix
+// carries from pass to pass.
+constexpr int kSpineThreads = 1024;
 
 template <int PMAX, int MW, int ITEMS>
 __global__ __launch_bounds__(kSpineThreads) void k_ms_spine(ScanArgs a) {
     constexpr uint32_t TILE = kMsThreads * ITEMS;
     constexpr int NW = 4 + PMAX * MW;            // record words in use
-    constexpr int kSpineChunk = NW <= 6 ? 8 : NW <= 12 ? 4 : 2;    // records held in registers
+    constexpr int kSpineChunk = NW <= 8 ? 4 : NW <= 12 ? 2 : 1;    // records held in registers
+    constexpr int NQ = (NW + 3) / 4;             // 16-byte parts of a record (records are 80 bytes)
+    static_assert(kMsRec % 4 == 0 && NQ * 4 <= kMsRec, "records load as whole 16-byte parts");
     __shared__ uint32_t s_wm[PMAX][kSpineThreads / 64][MW];
     __shared__ uint32_t s_wc[4][kSpineThreads / 64];
     __shared__ uint32_t s_carry[NW];
@@ -363,12 +366,19 @@ __global__ __launch_bounds__(kSpineThreads) void k_ms_spine(ScanArgs a) {
         const uint32_t t0 = pass0 + threadIdx.x * kSpineChunk;
         const uint32_t cnt = t0 < tiles ? min<uint32_t>(kSpineChunk, tiles - t0) : 0u;
         // unconditional loads of clamped tiles: all of them in flight together
-        uint32_t rec[kSpineChunk][NW];
+        uint32_t rec[kSpineChunk][NQ * 4];
 #pragma unroll
         for (int i = 0; i < kSpineChunk; ++i) {
             const uint32_t t = min(t0 + (uint32_t)i, tiles - 1u);
+            const uint4* src = reinterpret_cast<const uint4*>(a.agg + (uint64_t)t * kMsRec);
 #pragma unroll
-            for (int k = 0; k < NW; ++k) rec[i][k] = a.agg[(uint64_t)t * kMsRec + k];
+            for (int q = 0; q < NQ; ++q) {
+                const uint4 v = src[q];
+                rec[i][4 * q] = v.x;
+                rec[i][4 * q + 1] = v.y;
+                rec[i][4 * q + 2] = v.z;
+                rec[i][4 * q + 3] = v.w;
+            }
         }
         BMap<MW> f[PMAX], excl[PMAX], tot[PMAX];
         uint32_t c[4] = {0, 0, 0, 0}, cexcl[4], ctot[4];
