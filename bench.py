@@ -32,7 +32,7 @@ ALG_BYTES_PER_EVENT = {"sort_pass": 16, "classify": 24, "scan": 8}
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "internal.h"):
+    for f in ("kernels.hip", "mapscan.hip", "maps.h", "internal.h"):
         with open(os.path.join(ROOT, "paper_1411_2239_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
