@@ -346,7 +346,9 @@ def tune_all(out_path, log=print):
     def tune(wl, rec, reps, offsets=None, label=""):
         ctx.set_layout(wl.layout)
         ids = [ctx.add_spec(p) for p in wl.props]
-        t = ctx.tune(rec, ids, n_events=wl.n_events if offsets is None else None, offsets=offsets, reps=reps)
+        # (the device-generated large trace has no host records: its length is the tensor's)
+        n = None if offsets is not None else wl.n_events if wl.records is not None else rec.numel() // wl.layout.record_bytes
+        t = ctx.tune(rec, ids, n_events=n, offsets=offsets, reps=reps)
         t["workload"] = label
         found.append(t)
         log(f"[bench] tune {label}: {t}")

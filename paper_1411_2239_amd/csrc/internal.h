@@ -150,12 +150,16 @@ struct ScanArgs {
     uint32_t read_desc;                  // 1: read the descriptors instead of the words
     uint32_t* agg;                       // [tiles][kMsRec] tile aggregates: 4 head counts, map dwords
     uint32_t* prefix;                    // [tiles][kMsRec] exclusive prefixes of the aggregates
+    uint32_t* chunk_agg;                 // [chunks][kMsRec] spine of many tiles: chunk compositions
+    uint32_t* chunk_pre;                 // [chunks][kMsRec] and their exclusive prefixes
+    uint32_t spine_chunk;                // tiles per spine chunk
     uint32_t* trec;                      // [kMsThreadRec][tiles * kMsThreads] per thread: its exclusive
                                          // prefix within the tile (two packed head-count words, map dwords)
     uint32_t tiles;
 };
 // the split map scan: tiles of 256 threads x 16 or 32 words, and their records
 constexpr int kMsThreads = 256;
+constexpr int kMsSpineThreads = 1024;  // the spine block; a spine chunk holds at least this many tiles
 constexpr int kMsTileMin = kMsThreads * 16;   // workspace arrays are sized for the smaller tile
 constexpr int kMsRec = 4 + 16;
 constexpr int kMsThreadRec = 2 + 16;

@@ -205,11 +205,13 @@ __device__ __forceinline__ void store_tables(const ScanArgs& a, const TableRegs&
 // thread: on return `excl` and `cexcl` hold this thread's exclusive prefix
 // within the block, `tot` / `ctot` (valid in every thread) the block's total.
 // With PACK, the counts of a tile (below 2^16) travel two to a word, and the
-// second word only when there are more than two levels.
+// second word only when there are more than two levels.  The wave totals are
+// scanned once, by wave 0 (row WAVES of s_wm / s_wc receives the block total),
+// so no thread composes more than log2(WAVES) of them.
 template <int PMAX, int MW, int THREADS, bool PACK = false>
 __device__ __forceinline__ void block_scan(uint32_t P, const BMap<MW>* f, const uint32_t* cnt, BMap<MW>* excl,
                                            uint32_t* cexcl, BMap<MW>* tot, uint32_t* ctot,
-                                           uint32_t (*s_wm)[THREADS / 64][MW], uint32_t (*s_wc)[THREADS / 64],
+                                           uint32_t (*s_wm)[THREADS / 64 + 1][MW], uint32_t (*s_wc)[THREADS / 64 + 1],
                                            uint32_t levels = 4) {
     constexpr int WAVES = THREADS / 64;
     constexpr int NC = PACK ? 2 : 4;
@@ -251,30 +253,55 @@ __device__ __forceinline__ void block_scan(uint32_t P, const BMap<MW>* f, const 
         if (lane == 63) s_wc[k][w] = x;
     }
     __syncthreads();
+    if (w == 0) {
+        // wave 0: exclusive scan of the wave totals, in place; the block total
+        // goes to row WAVES
+#pragma unroll
+        for (int p = 0; p < PMAX; ++p) {
+            if (p >= (int)P) continue;
+            BMap<MW> v = lane < WAVES ? bm_load<MW>(s_wm[p][lane]) : bm_identity<MW>();
+#pragma unroll
+            for (int off = 1; off < WAVES; off <<= 1) {
+                const BMap<MW> o = bm_shfl_up<MW>(v, off);
+                if (lane >= off) v = bm_compose<MW>(v, o);
+            }
+            const BMap<MW> e = bm_shfl_up<MW>(v, 1);
+            if (lane < WAVES) {
+                const BMap<MW> ex = lane == 0 ? bm_identity<MW>() : e;
+#pragma unroll
+                for (int k = 0; k < MW; ++k) s_wm[p][lane][k] = ex.d[k];
+            }
+            if (lane == WAVES - 1)
+#pragma unroll
+                for (int k = 0; k < MW; ++k) s_wm[p][WAVES][k] = v.d[k];
+        }
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            uint32_t x = lane < WAVES ? s_wc[k][lane] : 0u;
+#pragma unroll
+            for (int off = 1; off < WAVES; off <<= 1) {
+                const uint32_t o = __shfl_up(x, off, 64);
+                if (lane >= off) x += o;
+            }
+            const uint32_t e = __shfl_up(x, 1, 64);
+            if (lane < WAVES) s_wc[k][lane] = lane == 0 ? 0u : e;
+            if (lane == WAVES - 1) s_wc[k][WAVES] = x;
+        }
+    }
+    __syncthreads();
 #pragma unroll
     for (int p = 0; p < PMAX; ++p) {
         if (p >= (int)P) {
             tot[p] = bm_identity<MW>();
             continue;
         }
-        BMap<MW> pre = bm_identity<MW>(), all = bm_identity<MW>();
-        for (int i = 0; i < WAVES; ++i) {
-            const BMap<MW> wm = bm_load<MW>(s_wm[p][i]);
-            if (i < w) pre = bm_compose<MW>(wm, pre);
-            all = bm_compose<MW>(wm, all);
-        }
-        excl[p] = bm_compose<MW>(excl[p], pre);
-        tot[p] = all;
+        excl[p] = bm_compose<MW>(excl[p], bm_load<MW>(s_wm[p][w]));
+        tot[p] = bm_load<MW>(s_wm[p][WAVES]);
     }
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
-        uint32_t pre = 0, all = 0;
-        for (int i = 0; i < WAVES; ++i) {
-            if (i < w) pre += s_wc[k][i];
-            all += s_wc[k][i];
-        }
-        cexcl[k] += pre;
-        ctot[k] = all;
+        cexcl[k] += s_wc[k][w];
+        ctot[k] = s_wc[k][WAVES];
     }
     if (PACK) {
 #pragma unroll
@@ -294,8 +321,8 @@ __global__ __launch_bounds__(kMsThreads) void k_ms_reduce(ScanArgs a) {
     constexpr uint32_t TILE = kMsThreads * ITEMS;
     __shared__ uint32_t s_cm[PMAX][16][MW];
     __shared__ uint32_t s_q0[PMAX];
-    __shared__ uint32_t s_wm[PMAX][kMsThreads / 64][MW];
-    __shared__ uint32_t s_wc[4][kMsThreads / 64];
+    __shared__ uint32_t s_wm[PMAX][kMsThreads / 64 + 1][MW];
+    __shared__ uint32_t s_wc[4][kMsThreads / 64 + 1];
     const uint32_t n = *a.n_dev;
     const uint64_t base = (uint64_t)blockIdx.x * TILE;
     if (base >= n) return;                       // the whole block: no word of this tile
@@ -340,37 +367,60 @@ __global__ __launch_bounds__(kMsThreads) void k_ms_reduce(ScanArgs a) {
 }
 
 // Exclusive prefixes of the tile records (maps composed in tile order, head
-// counts summed), one block.  Tiles go in passes of kSpineThreads x (up to
-// 4) tiles, one pass up to 16M words of 4,096-word tiles: each thread loads
-// its chunk's records at once (16-byte loads, all in flight together),
-// composes them, the block scans the thread totals, and the running prefix
-// carries from pass to pass.
-constexpr int kSpineThreads = 1024;
+// counts summed).  Records go in passes of kSpineThreads x (up to 4) records:
+// each thread loads its chunk's records at once (16-byte loads, all in flight
+// together), composes them, the block scans the thread totals, and the running
+// prefix carries from pass to pass.  MODE 0: one block over all tiles (one
+// pass up to 16M words).  Above a few passes the work is spread: MODE 1, block
+// b composes the tiles of chunk b (a.spine_chunk tiles) into a chunk record;
+// MODE 2, one block scans the chunk records; MODE 3, block b writes the tile
+// prefixes of chunk b, starting from the chunk's prefix.
+constexpr int kSpineThreads = kMsSpineThreads;
 
-template <int PMAX, int MW, int ITEMS>
+template <int NW>
+__host__ __device__ constexpr int spine_chunk_items() { return NW <= 8 ? 4 : NW <= 12 ? 2 : 1; }
+
+template <int PMAX, int MW, int ITEMS, int MODE>
 __global__ __launch_bounds__(kSpineThreads) void k_ms_spine(ScanArgs a) {
     constexpr uint32_t TILE = kMsThreads * ITEMS;
     constexpr int NW = 4 + PMAX * MW;            // record words in use
-    constexpr int kSpineChunk = NW <= 8 ? 4 : NW <= 12 ? 2 : 1;    // records held in registers
+    constexpr int kSpineChunk = spine_chunk_items<NW>();    // records held in registers
     constexpr int NQ = (NW + 3) / 4;             // 16-byte parts of a record (records are 80 bytes)
     static_assert(kMsRec % 4 == 0 && NQ * 4 <= kMsRec, "records load as whole 16-byte parts");
-    __shared__ uint32_t s_wm[PMAX][kSpineThreads / 64][MW];
-    __shared__ uint32_t s_wc[4][kSpineThreads / 64];
+    __shared__ uint32_t s_wm[PMAX][kSpineThreads / 64 + 1][MW];
+    __shared__ uint32_t s_wc[4][kSpineThreads / 64 + 1];
     __shared__ uint32_t s_carry[NW];
     const uint32_t n = *a.n_dev;
     const uint32_t tiles = (n + TILE - 1) / TILE;
     const uint32_t P = a.n_props;
-    if (threadIdx.x < NW) s_carry[threadIdx.x] = threadIdx.x < 4 ? 0u : bm_identity<MW>().d[(threadIdx.x - 4) % MW];
+    const uint32_t nchunks = MODE == 0 ? 1u : (tiles + a.spine_chunk - 1) / a.spine_chunk;
+    uint32_t r0 = 0, r1 = tiles;                 // the records this block scans
+    const uint32_t* in = a.agg;
+    uint32_t* out = a.prefix;
+    if (MODE == 1 || MODE == 3) {
+        r0 = blockIdx.x * a.spine_chunk;
+        r1 = min(tiles, r0 + a.spine_chunk);
+        if (r0 >= r1) return;
+    } else if (MODE == 2) {
+        r1 = nchunks;
+        in = a.chunk_agg;
+        out = a.chunk_pre;
+    }
+    if (threadIdx.x < NW) {
+        uint32_t v = threadIdx.x < 4 ? 0u : bm_identity<MW>().d[(threadIdx.x - 4) % MW];
+        if (MODE == 3) v = a.chunk_pre[(uint64_t)blockIdx.x * kMsRec + threadIdx.x];
+        s_carry[threadIdx.x] = v;
+    }
     __syncthreads();
-    for (uint32_t pass0 = 0; pass0 < tiles; pass0 += kSpineThreads * kSpineChunk) {
+    for (uint32_t pass0 = r0; pass0 < r1; pass0 += kSpineThreads * kSpineChunk) {
         const uint32_t t0 = pass0 + threadIdx.x * kSpineChunk;
-        const uint32_t cnt = t0 < tiles ? min<uint32_t>(kSpineChunk, tiles - t0) : 0u;
-        // unconditional loads of clamped tiles: all of them in flight together
+        const uint32_t cnt = t0 < r1 ? min<uint32_t>(kSpineChunk, r1 - t0) : 0u;
+        // unconditional loads of clamped records: all of them in flight together
         uint32_t rec[kSpineChunk][NQ * 4];
 #pragma unroll
         for (int i = 0; i < kSpineChunk; ++i) {
-            const uint32_t t = min(t0 + (uint32_t)i, tiles - 1u);
-            const uint4* src = reinterpret_cast<const uint4*>(a.agg + (uint64_t)t * kMsRec);
+            const uint32_t t = min(t0 + (uint32_t)i, r1 - 1u);
+            const uint4* src = reinterpret_cast<const uint4*>(in + (uint64_t)t * kMsRec);
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 const uint4 v = src[q];
@@ -386,36 +436,38 @@ __global__ __launch_bounds__(kSpineThreads) void k_ms_spine(ScanArgs a) {
         for (int p = 0; p < PMAX; ++p) f[p] = bm_identity<MW>();
 #pragma unroll
         for (int i = 0; i < kSpineChunk; ++i) {
-            const bool in = (uint32_t)i < cnt;
+            const bool inr = (uint32_t)i < cnt;
 #pragma unroll
             for (int p = 0; p < PMAX; ++p)
-                if (p < (int)P && in) f[p] = bm_compose<MW>(bm_load<MW>(&rec[i][4 + MW * p]), f[p]);
+                if (p < (int)P && inr) f[p] = bm_compose<MW>(bm_load<MW>(&rec[i][4 + MW * p]), f[p]);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) c[k] += in ? rec[i][k] : 0u;
+            for (int k = 0; k < 4; ++k) c[k] += inr ? rec[i][k] : 0u;
         }
         block_scan<PMAX, MW, kSpineThreads>(P, f, c, excl, cexcl, tot, ctot, s_wm, s_wc);
-        // this thread's prefix: the carry from earlier passes, then the block's
-        BMap<MW> acc[PMAX];
-        uint32_t cc[4];
+        if (MODE != 1) {
+            // this thread's prefix: the carry from earlier passes, then the block's
+            BMap<MW> acc[PMAX];
+            uint32_t cc[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) cc[k] = s_carry[k] + cexcl[k];
+            for (int k = 0; k < 4; ++k) cc[k] = s_carry[k] + cexcl[k];
 #pragma unroll
-        for (int p = 0; p < PMAX; ++p) acc[p] = bm_compose<MW>(excl[p], bm_load<MW>(&s_carry[4 + MW * p]));
+            for (int p = 0; p < PMAX; ++p) acc[p] = bm_compose<MW>(excl[p], bm_load<MW>(&s_carry[4 + MW * p]));
 #pragma unroll
-        for (int i = 0; i < kSpineChunk; ++i) {
-            if ((uint32_t)i >= cnt) continue;
-            uint32_t* out = a.prefix + (uint64_t)(t0 + i) * kMsRec;
+            for (int i = 0; i < kSpineChunk; ++i) {
+                if ((uint32_t)i >= cnt) continue;
+                uint32_t* o = out + (uint64_t)(t0 + i) * kMsRec;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                out[k] = cc[k];
-                cc[k] += rec[i][k];
-            }
+                for (int k = 0; k < 4; ++k) {
+                    o[k] = cc[k];
+                    cc[k] += rec[i][k];
+                }
 #pragma unroll
-            for (int p = 0; p < PMAX; ++p) {
-                if (p >= (int)P) continue;
+                for (int p = 0; p < PMAX; ++p) {
+                    if (p >= (int)P) continue;
 #pragma unroll
-                for (int k = 0; k < MW; ++k) out[4 + MW * p + k] = acc[p].d[k];
-                acc[p] = bm_compose<MW>(bm_load<MW>(&rec[i][4 + MW * p]), acc[p]);
+                    for (int k = 0; k < MW; ++k) o[4 + MW * p + k] = acc[p].d[k];
+                    acc[p] = bm_compose<MW>(bm_load<MW>(&rec[i][4 + MW * p]), acc[p]);
+                }
             }
         }
         __syncthreads();                         // every thread has read the carry
@@ -431,6 +483,8 @@ __global__ __launch_bounds__(kSpineThreads) void k_ms_spine(ScanArgs a) {
         }
         __syncthreads();
     }
+    // the chunk's record: its composition (the carry started at the identity)
+    if (MODE == 1 && threadIdx.x < NW) a.chunk_agg[(uint64_t)blockIdx.x * kMsRec + threadIdx.x] = s_carry[threadIdx.x];
 }
 
 template <int PMAX, int MW, int ITEMS>
@@ -593,7 +647,18 @@ static void launch_ms_t(const ScanArgs& a, hipStream_t s) {
     ScanArgs r = a;
     r.tiles = tiles;
     hipLaunchKernelGGL((k_ms_reduce<PMAX, MW, ITEMS>), grid, dim3(kMsThreads), 0, s, r);
-    hipLaunchKernelGGL((k_ms_spine<PMAX, MW, ITEMS>), dim3(1), dim3(kSpineThreads), 0, s, r);
+    // one spine block takes kSpineThreads x chunk records per pass; beyond two
+    // passes the chunks are spread over blocks
+    constexpr uint32_t kPass = (uint32_t)kSpineThreads * spine_chunk_items<4 + PMAX * MW>();
+    if (tiles <= 2 * kPass || !a.chunk_agg || !a.chunk_pre) {
+        hipLaunchKernelGGL((k_ms_spine<PMAX, MW, ITEMS, 0>), dim3(1), dim3(kSpineThreads), 0, s, r);
+    } else {
+        r.spine_chunk = kPass;
+        const uint32_t nchunks = (tiles + kPass - 1) / kPass;
+        hipLaunchKernelGGL((k_ms_spine<PMAX, MW, ITEMS, 1>), dim3(nchunks), dim3(kSpineThreads), 0, s, r);
+        hipLaunchKernelGGL((k_ms_spine<PMAX, MW, ITEMS, 2>), dim3(1), dim3(kSpineThreads), 0, s, r);
+        hipLaunchKernelGGL((k_ms_spine<PMAX, MW, ITEMS, 3>), dim3(nchunks), dim3(kSpineThreads), 0, s, r);
+    }
     ScanArgs d = r;
     d.read_desc = 1;
     hipLaunchKernelGGL((k_ms_down<PMAX, MW, ITEMS>), grid, dim3(kMsThreads), 0, s, d);

@@ -197,7 +197,7 @@ struct WsLayout {
     uint64_t node_start_off[kMaxLevels], counts_off[kMaxLevels];
     uint64_t cap_node[kMaxLevels];
     uint32_t tiles_sort, tiles_scan;
-    uint64_t ms_desc_off, ms_agg_off, ms_prefix_off, ms_trec_off;   // the split map scan
+    uint64_t ms_desc_off, ms_agg_off, ms_prefix_off, ms_trec_off, ms_chunk_off;   // the split map scan
     uint32_t ms_tiles;
     // parent events
     uint64_t pe_tree_off, pe_trec_off, pe_samples_off, pe_tile_agg_off, pe_tile_prefix_off, pe_tile_heads_off, pe_tile_hprefix_off;
@@ -293,6 +293,8 @@ WsLayout plan_workspace(const ltl4c_layout& L, const Geometry& g, uint64_t n, ui
     w.ms_agg_off = off;    off = align256(off + 4ull * kMsRec * std::max<uint32_t>(w.ms_tiles, 1));
     w.ms_prefix_off = off; off = align256(off + 4ull * kMsRec * std::max<uint32_t>(w.ms_tiles, 1));
     w.ms_trec_off = off;   off = align256(off + 4ull * kMsThreadRec * kMsThreads * std::max<uint32_t>(w.ms_tiles, 1));
+    // spine chunks (at least kMsSpineThreads tiles each): compositions, then prefixes
+    w.ms_chunk_off = off;  off = align256(off + 2 * 4ull * kMsRec * (w.ms_tiles / kMsSpineThreads + 1));
     (void)L;
     for (uint32_t m = 1; m < g.n_levels; ++m) {
         uint64_t cap = n;
@@ -1162,6 +1164,8 @@ static int32_t eval_core(ltl4c_ctx* ctx, const ltl4c_layout& L, const Geometry& 
             sa.agg = reinterpret_cast<uint32_t*>(ws + w.ms_agg_off);
             sa.prefix = reinterpret_cast<uint32_t*>(ws + w.ms_prefix_off);
             sa.trec = reinterpret_cast<uint32_t*>(ws + w.ms_trec_off);
+            sa.chunk_agg = reinterpret_cast<uint32_t*>(ws + w.ms_chunk_off);
+            sa.chunk_pre = sa.chunk_agg + (uint64_t)kMsRec * (w.ms_tiles / kMsSpineThreads + 1);
             sa.tiles = w.ms_tiles;
         }
         // (with parent events only the numbering launch: the verdicts come after)

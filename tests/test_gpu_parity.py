@@ -223,3 +223,12 @@ def test_repeated_evaluations_share_one_workspace():
         compare_full(r, o, len(ids), a.layout.n_keys)
         assert dev.numel() == recs.shape[0] * rb
     ctx.close()
+
+
+def test_many_tiles_wide_monitors_spread_spine():
+    """Four properties of 9-10 states (maps of four dwords) over 9M events:
+    2,198 scan tiles, more than two passes of one spine block for records of
+    this width, so the spine runs spread over blocks (chunk compositions, their
+    scan, the tile prefixes)."""
+    big = [W.BATCH_FORMULAS[i] for i in (6, 8, 9, 12)]
+    _check(prop_workload(9_000_000, 2, [300, 4000], seed=91, n_props=4, formulas=big), instances=True, nodes=True)
