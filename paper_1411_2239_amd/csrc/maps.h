@@ -10,8 +10,8 @@ namespace ltl4c {
 // holds the image of state q.  The composition g∘f (f applied first) picks,
 // for every byte of f, the byte of g it names: one byte permute per dword for
 // 8 states; for 16 states two permutes (the low and the high half of g) and a
-// per-byte select on bit 3 of the selector.  No constant-map special cases
-// are needed.
+// third that picks per byte on bit 3 of the selector.  No constant-map
+// special cases are needed.
 template <int MW>
 struct BMap {
     uint32_t d[MW];
@@ -39,11 +39,16 @@ __device__ __forceinline__ BMap<MW> bm_compose(const BMap<MW>& g, const BMap<MW>
         if constexpr (MW == 2) {
             r.d[i] = __builtin_amdgcn_perm(g.d[1], g.d[0], f.d[i]);
         } else {
-            const uint32_t sel = f.d[i], s7 = sel & 0x07070707u;
-            const uint32_t lo = __builtin_amdgcn_perm(g.d[1], g.d[0], s7);
-            const uint32_t hi = __builtin_amdgcn_perm(g.d[3], g.d[2], s7);
-            const uint32_t t = (sel >> 3) & 0x01010101u, m = (t << 8) - t;   // 0xFF where the state is >= 8
-            r.d[i] = (hi & m) | (lo & ~m);
+            // lo is right in the bytes whose state is below 8, hi (selector
+            // bytes 8..15 turned into 0..7) in the others; a third permute picks
+            // byte k of lo, or byte k of hi (pair index k + 4) where bit 3 of the
+            // state is set.  All full-rate instructions (a byte mask built as
+            // t * 255 compiles to a quarter-rate multiply).
+            const uint32_t sel = f.d[i];
+            const uint32_t lo = __builtin_amdgcn_perm(g.d[1], g.d[0], sel);
+            const uint32_t hi = __builtin_amdgcn_perm(g.d[3], g.d[2], sel ^ 0x08080808u);
+            const uint32_t pick = ((sel >> 1) & 0x04040404u) | 0x03020100u;
+            r.d[i] = __builtin_amdgcn_perm(hi, lo, pick);
         }
     }
     return r;

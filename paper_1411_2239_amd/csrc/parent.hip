@@ -52,11 +52,12 @@ __device__ __forceinline__ Map16 m_compose(const Map16& g, const Map16& f) {
     Map16 r;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const uint32_t sel = f.d[i], s7 = sel & 0x07070707u;
-        const uint32_t lo = __builtin_amdgcn_perm(g.d[1], g.d[0], s7);
-        const uint32_t hi = __builtin_amdgcn_perm(g.d[3], g.d[2], s7);
-        const uint32_t t = (sel >> 3) & 0x01010101u, m = (t << 8) - t;
-        r.d[i] = (hi & m) | (lo & ~m);
+        // low half where the state is below 8, high half elsewhere; the last
+        // permute picks per byte on bit 3 of the state
+        const uint32_t sel = f.d[i];
+        const uint32_t lo = __builtin_amdgcn_perm(g.d[1], g.d[0], sel);
+        const uint32_t hi = __builtin_amdgcn_perm(g.d[3], g.d[2], sel ^ 0x08080808u);
+        r.d[i] = __builtin_amdgcn_perm(hi, lo, ((sel >> 1) & 0x04040404u) | 0x03020100u);
     }
     return r;
 }
