@@ -35,15 +35,7 @@ __device__ __forceinline__ void st_flag(uint32_t* p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        uint32_t o = __shfl_up(v, off, 64);
-        if (lane >= off) v += o;
-    }
-    return v;
-}
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) { return wave_incl_sum(v); }
 
 // Exclusive scan of one value per thread over threads 0..255 of the block
 // (every thread of the block must call it; threads >= 256 get garbage).
@@ -1260,6 +1252,9 @@ __global__ __launch_bounds__(kCountThreads) void k_count_leaves(CountArgs a) {
 // (Section 4: online mode; SpawnMonitors / AddToTree of Algorithm 1 become
 // hash-table inserts, ApplyQuantifiers a re-valuation of the touched nodes)
 // ---------------------------------------------------------------------------
+// Bit mixer of the table's hash: the 64-bit finalizer ("fmix64") of Austin
+// Appleby's public-domain MurmurHash3, with its published shift and multiplier
+// constants.
 __device__ __forceinline__ uint64_t mix64(uint64_t x) {
     x ^= x >> 33;
     x *= 0xff51afd7ed558ccdull;

@@ -63,6 +63,53 @@ __device__ __forceinline__ uint32_t bm_at(const BMap<MW>& g, uint32_t q) {
         return ((q & 8u) ? hi : lo) & 0xFFu;
     }
 }
+// Wave-wide inclusive scans with DPP row operations (GFX9 DPP controls:
+// row_shr:n = 0x110 + n within rows of 16 lanes, row_bcast:15 = 0x142 sends
+// lane 15 of a row to the next row, row_bcast:31 = 0x143 sends lane 31 to rows
+// 2 and 3, wave_shr:1 = 0x138).  A lane whose source is outside its row, or
+// whose row the row mask leaves out, keeps `old`: the operation's identity.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t old, uint32_t src) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, CTRL, ROW_MASK, 0xF, false);
+}
+
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v) {
+    v += dpp_mov<0x111, 0xF>(0u, v);
+    v += dpp_mov<0x112, 0xF>(0u, v);
+    v += dpp_mov<0x114, 0xF>(0u, v);
+    v += dpp_mov<0x118, 0xF>(0u, v);
+    v += dpp_mov<0x142, 0xA>(0u, v);
+    v += dpp_mov<0x143, 0xC>(0u, v);
+    return v;
+}
+
+template <int MW, int CTRL, int ROW_MASK>
+__device__ __forceinline__ BMap<MW> bm_dpp(const BMap<MW>& v) {
+    const BMap<MW> id = bm_identity<MW>();
+    BMap<MW> r;
+#pragma unroll
+    for (int i = 0; i < MW; ++i) r.d[i] = dpp_mov<CTRL, ROW_MASK>(id.d[i], v.d[i]);
+    return r;
+}
+
+// inclusive scan of maps in lane order (a later lane's map applies after)
+template <int MW>
+__device__ __forceinline__ BMap<MW> bm_wave_incl_scan(BMap<MW> v) {
+    v = bm_compose<MW>(v, bm_dpp<MW, 0x111, 0xF>(v));
+    v = bm_compose<MW>(v, bm_dpp<MW, 0x112, 0xF>(v));
+    v = bm_compose<MW>(v, bm_dpp<MW, 0x114, 0xF>(v));
+    v = bm_compose<MW>(v, bm_dpp<MW, 0x118, 0xF>(v));
+    v = bm_compose<MW>(v, bm_dpp<MW, 0x142, 0xA>(v));
+    v = bm_compose<MW>(v, bm_dpp<MW, 0x143, 0xC>(v));
+    return v;
+}
+
+// the previous lane's value (lane 0: the identity map)
+template <int MW>
+__device__ __forceinline__ BMap<MW> bm_wave_shr1(const BMap<MW>& v) {
+    return bm_dpp<MW, 0x138, 0xF>(v);
+}
+
 template <int MW>
 __device__ __forceinline__ BMap<MW> bm_shfl_up(const BMap<MW>& v, int off) {
     BMap<MW> r;

@@ -226,15 +226,8 @@ __device__ __forceinline__ void block_scan(uint32_t P, const BMap<MW>* f, const 
 #pragma unroll
     for (int p = 0; p < PMAX; ++p) {
         BMap<MW> v = f[p];
-        if (p < (int)P) {
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const BMap<MW> o = bm_shfl_up<MW>(v, off);
-                if (lane >= off) v = bm_compose<MW>(v, o);
-            }
-        }
-        const BMap<MW> e = bm_shfl_up<MW>(v, 1);
-        excl[p] = lane == 0 ? bm_identity<MW>() : e;
+        if (p < (int)P) v = bm_wave_incl_scan<MW>(v);
+        excl[p] = bm_wave_shr1<MW>(v);
         if (lane == 63)
 #pragma unroll
             for (int k = 0; k < MW; ++k) s_wm[p][w][k] = v.d[k];
@@ -242,13 +235,7 @@ __device__ __forceinline__ void block_scan(uint32_t P, const BMap<MW>* f, const 
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
         uint32_t x = c[k];
-        if ((uint32_t)k * (4 / NC) < levels) {    // counts of absent levels stay zero
-#pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const uint32_t o = __shfl_up(x, off, 64);
-                if (lane >= off) x += o;
-            }
-        }
+        if ((uint32_t)k * (4 / NC) < levels) x = wave_incl_sum(x);    // counts of absent levels stay zero
         cexcl[k] = x - c[k];
         if (lane == 63) s_wc[k][w] = x;
     }
@@ -260,14 +247,9 @@ __device__ __forceinline__ void block_scan(uint32_t P, const BMap<MW>* f, const 
         for (int p = 0; p < PMAX; ++p) {
             if (p >= (int)P) continue;
             BMap<MW> v = lane < WAVES ? bm_load<MW>(s_wm[p][lane]) : bm_identity<MW>();
-#pragma unroll
-            for (int off = 1; off < WAVES; off <<= 1) {
-                const BMap<MW> o = bm_shfl_up<MW>(v, off);
-                if (lane >= off) v = bm_compose<MW>(v, o);
-            }
-            const BMap<MW> e = bm_shfl_up<MW>(v, 1);
+            v = bm_wave_incl_scan<MW>(v);
+            const BMap<MW> ex = bm_wave_shr1<MW>(v);
             if (lane < WAVES) {
-                const BMap<MW> ex = lane == 0 ? bm_identity<MW>() : e;
 #pragma unroll
                 for (int k = 0; k < MW; ++k) s_wm[p][lane][k] = ex.d[k];
             }
@@ -277,14 +259,9 @@ __device__ __forceinline__ void block_scan(uint32_t P, const BMap<MW>* f, const 
         }
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
-            uint32_t x = lane < WAVES ? s_wc[k][lane] : 0u;
-#pragma unroll
-            for (int off = 1; off < WAVES; off <<= 1) {
-                const uint32_t o = __shfl_up(x, off, 64);
-                if (lane >= off) x += o;
-            }
-            const uint32_t e = __shfl_up(x, 1, 64);
-            if (lane < WAVES) s_wc[k][lane] = lane == 0 ? 0u : e;
+            const uint32_t c0 = lane < WAVES ? s_wc[k][lane] : 0u;
+            const uint32_t x = wave_incl_sum(c0);
+            if (lane < WAVES) s_wc[k][lane] = x - c0;
             if (lane == WAVES - 1) s_wc[k][WAVES] = x;
         }
     }
