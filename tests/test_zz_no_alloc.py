@@ -1,8 +1,9 @@
 """The no-allocation entry point (ltl4c_eval_noalloc) against ltl4c_eval with a
 caller workspace: the same roots, counts, instance keys and verdicts, and
 node keys, counts and verdicts, on two calls in a row (the second on a
-smaller trace, so stale scratch contents of the first would show), and the
-clear refusal of a trace too large for the scratch."""
+smaller trace, so stale scratch contents of the first would show), for plain
+and parent-event layouts, and the clear refusal of a trace too large for the
+scratch."""
 import numpy as np
 import pytest
 
@@ -34,10 +35,18 @@ def _same(a, b, n_props, n_levels):
                               b.node_verdict[m].view(n_props, -1)[:, :nm].cpu().numpy())
 
 
-@pytest.mark.parametrize("kind", ["users", "props3"])
+@pytest.mark.parametrize("kind", ["users", "props3", "parent"])
 def test_noalloc_equals_workspace_eval_twice(kind):
     import torch
-    if kind == "users":
+    if kind == "parent":
+        # parent events: the segment tree, sample table and run maps live in
+        # the scratch as well
+        from test_gpu_parent_events import parent_workload
+        big = parent_workload(200_000, 2, [40, 300], seed=25, n_props=3)
+        small = parent_workload(5_003, 2, [5, 9], seed=26, n_props=3)
+        small.layout = big.layout
+        L = 2
+    elif kind == "users":
         big = W.gen_user_requests(n_events=1_500_000, n_users=2000, seed=21)
         small = W.gen_user_requests(n_events=90_001, n_users=300, seed=22)
         L = 2
