@@ -146,3 +146,19 @@ def _check_values(wl):
     compare_full(r, o, len(ids), 2)
     n_inst = int(r.sizes[0].item())
     assert np.array_equal(r.inst_key_values.cpu().numpy().view(np.uint32).reshape(-1, 2)[:n_inst], o.inst_keys)
+
+
+@pytest.mark.parametrize("scan_tile", [0, 3, 4, 5])
+def test_parity_every_scan_tile(scan_tile):
+    """The own events are numbered by the look-back scan (tiles 0-3) or the
+    split map scan (4, 5) before the parent kernels recompute the verdicts."""
+    import torch
+    from paper_1411_2239_amd import lib
+    wl = parent_workload(70_001, 2, [30, 200], seed=101 + scan_tile, n_props=3)
+    print(f"[case] {wl.name} scan tile {scan_tile}", flush=True)
+    ctx, ids, rec = lib.open_workload(wl)
+    ctx.set_option(lib.OPT_SCAN_TILE, scan_tile)
+    r = ctx.eval(rec, ids, instances=True, nodes=True)
+    torch.cuda.synchronize()
+    ctx.close()
+    compare_full(r, evaluate_workload(wl), len(ids), 2, key_bits=wl.layout.key_bits)
