@@ -454,8 +454,7 @@ enum { LTL4C_OPT_SORT_TILE = 0, LTL4C_OPT_SCAN_TILE = 1 };
  * of 0 = 256 threads x 16 words, 1 = 512 x 16, 2 = 1024 x 16, or 3 = per
  * launch: 1024 x 16 when a launch's maps take at most 4 dwords per event (one
  * or two properties of at most 8 states, or one of at most 16), else
- * 512 x 16.  Evaluations that ask for the verdict timeline always use the
- * look-back scan (variants 4 and 5 then mean 3).
+ * 512 x 16.
  * A value pins that tile: tuned schedules (below) no longer override it;
  * -1 returns the option to its default and unpins it. */
 int32_t ltl4c_set_option(ltl4c_ctx *ctx, int32_t option, int64_t value);

@@ -513,6 +513,10 @@ __global__ __launch_bounds__(kMsThreads) void k_ms_down(ScanArgs a) {
         cur[p] = 0;
         if (p < (int)P) cur[p] = bm_at<MW>(bm_compose<MW>(tex[p], bm_load<MW>(pmap[p])), 0);
     }
+    const bool timeline = a.inst_conc || a.event_verdict;
+    uint32_t cur0[PMAX];
+#pragma unroll
+    for (int p = 0; p < PMAX; ++p) cur0[p] = cur[p];
     const uint32_t valid = valid_mask(r.cnt);
     const uint32_t m_end = r.cnt ? valid & ((r.m_head >> 1) | ((next_head ? 1u : 0u) << (r.cnt - 1u))) : 0u;
     uint8_t* s_iv = reinterpret_cast<uint8_t*>(s_stage);
@@ -544,6 +548,47 @@ __global__ __launch_bounds__(kMsThreads) void k_ms_down(ScanArgs a) {
                 if (structure && a.inst_keys) a.inst_keys[id] = a.words[my0 + j] >> a.cbits;
             } else {
                 err |= kErrCapacity;
+            }
+        }
+    }
+    // On request, the verdict timeline: a second walk from the thread's
+    // starting states.  Conclusive verdicts are final (Def. 5), so the monitor
+    // enters a conclusive state at most once per instance: the word where it
+    // does writes its 1-based sorted position (the head's position when q0
+    // itself is conclusive), the word ending an instance that never got there
+    // writes kNever; k_inst_conclusive turns positions into prefix lengths.
+    // The verdict after every event goes to the event's trace index, which
+    // rides in the word between class and key.
+    if (timeline) {
+        const uint64_t cls0 = r.cls[0], cls1 = r.cls[1];
+#pragma unroll 1
+        for (uint32_t j = 0; j < r.cnt; ++j) {
+            // both halves shifted before the choice (no indexed register array)
+            const uint32_t sh = 4 * (j & 15u);
+            const uint32_t c0 = (uint32_t)(cls0 >> sh) & 15u, c1 = (uint32_t)(cls1 >> sh) & 15u;
+            const uint32_t c = j < 16u ? c0 : c1;
+            const bool hd = (r.m_head >> j) & 1u, end = (m_end >> j) & 1u;
+            const uint32_t upto = j == 31u ? kAll : (2u << j) - 1u;
+            const uint64_t id = (uint64_t)id_base + cexcl[0] + __popc(r.m_head & upto) - 1u;
+            const uint32_t pos = (uint32_t)(my0 + j);
+            const bool conc_out = a.inst_conc && id < a.inst_limit;
+            if (conc_out && hd && structure) a.inst_start[id] = pos;
+            const uint64_t ev = a.event_verdict ? (a.words[pos] >> a.index_shift) & a.index_mask : 0ull;
+#pragma unroll
+            for (int p = 0; p < PMAX; ++p) {
+                if (p >= (int)P) continue;
+                const uint32_t pre = hd ? s_q0[p] : cur0[p];
+                const uint32_t post = bm_at<MW>(bm_load<MW>(s_cm[p][c]), pre);
+                cur0[p] = post;
+                const uint32_t lpost = (s_lab[p][post >> 3] >> (4 * (post & 7u))) & 15u;
+                if (a.event_verdict) a.event_verdict[a.prop_idx[p] * a.n_events + ev] = (uint8_t)lpost;
+                if (!conc_out) continue;
+                uint32_t* out = a.inst_conc + a.prop_idx[p] * a.inst_stride + id;
+                const uint32_t lpre = (s_lab[p][pre >> 3] >> (4 * (pre & 7u))) & 15u;
+                const bool cpre = lpre == 0u || lpre == 5u, cpost = lpost == 0u || lpost == 5u;
+                if (hd && cpre) *out = pos;
+                else if (cpost && !cpre) *out = pos + 1u;
+                if (end && !cpost) *out = kNever;
             }
         }
     }

@@ -1149,11 +1149,10 @@ static int32_t eval_core(ltl4c_ctx* ctx, const ltl4c_layout& L, const Geometry& 
         sa.err = ctx->err_dev;
         // one launch per property group, each with its own look-back rows and
         // ticket; the first one also writes the numbering
-        // The split map scan (reduce, spine, down sweep) unless the timeline
-        // needs the look-back scan's per-word walk.  With parent events it
+        // The split map scan (reduce, spine, down sweep; its down sweep also
+        // writes the verdict timeline on request).  With parent events it
         // numbers the own events (the verdicts come after).
-        const bool split = (ctx->scan_variant == kSplitScanVariant || ctx->scan_variant == kSplitScanVariant32) &&
-                           !out->inst_conclusive && !out->event_verdict;
+        const bool split = ctx->scan_variant == kSplitScanVariant || ctx->scan_variant == kSplitScanVariant32;
         if (split) {
             if (!sa.n_dev) {
                 // nothing is excluded: every word counts

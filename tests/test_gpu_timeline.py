@@ -41,9 +41,15 @@ def test_timeline_many_property_groups():
     _run(prop_workload(60_000, 1, [500], seed=93, n_props=16))
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
 def test_timeline_scan_tiles(variant):
+    # look-back scan tiles (0-3) and the split map scan's down sweep (4, 5)
     _run(prop_workload(150_000, 2, [20, 30], seed=94, n_props=4), OPT_SCAN_TILE=variant)
+
+
+@pytest.mark.parametrize("variant", [3, 4, 5])
+def test_event_verdicts_scan_tiles(variant):
+    _run_events(prop_workload(90_001, 2, [30, 40], seed=96, n_props=5), OPT_SCAN_TILE=variant)
 
 
 def test_timeline_never_conclusive():
