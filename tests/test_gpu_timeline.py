@@ -109,3 +109,10 @@ def test_event_verdicts_need_room_for_the_trace_index():
         ctx.eval(rec, ids, events=True)
     assert e.value.status == lib.EUNSUPPORTED
     ctx.close()
+
+
+def test_event_verdicts_full_size():
+    """The bench's verdict-timeline workload at full size (10M events, 100,000
+    Zipf keys, three properties that become conclusive): every event's verdict
+    and every instance's first conclusive prefix equal the oracle's."""
+    _run_events(W.gen_prop_trace(10_000_000, 100_000, 1.1, seed=7, props=W.timeline_properties()))
