@@ -464,7 +464,9 @@ __global__ __launch_bounds__(kSpineThreads) void k_ms_spine(ScanArgs a) {
     if (MODE == 1 && threadIdx.x < NW) a.chunk_agg[(uint64_t)blockIdx.x * kMsRec + threadIdx.x] = s_carry[threadIdx.x];
 }
 
-template <int PMAX, int MW, int ITEMS>
+// TL: the instantiation that also walks the verdict timeline (its registers
+// stay out of the plain sweep's occupancy)
+template <int PMAX, int MW, int ITEMS, bool TL>
 __global__ __launch_bounds__(kMsThreads) void k_ms_down(ScanArgs a) {
     constexpr uint32_t TILE = kMsThreads * ITEMS;
     constexpr bool kParents = PMAX <= 4;         // LDS room to stage parent ids
@@ -513,7 +515,7 @@ __global__ __launch_bounds__(kMsThreads) void k_ms_down(ScanArgs a) {
         cur[p] = 0;
         if (p < (int)P) cur[p] = bm_at<MW>(bm_compose<MW>(tex[p], bm_load<MW>(pmap[p])), 0);
     }
-    const bool timeline = a.inst_conc || a.event_verdict;
+    const bool timeline = TL && (a.inst_conc || a.event_verdict);
     uint32_t cur0[PMAX];
 #pragma unroll
     for (int p = 0; p < PMAX; ++p) cur0[p] = cur[p];
@@ -561,6 +563,20 @@ __global__ __launch_bounds__(kMsThreads) void k_ms_down(ScanArgs a) {
     // rides in the word between class and key.
     if (timeline) {
         const uint64_t cls0 = r.cls[0], cls1 = r.cls[1];
+        // trace indices of the thread's words: all loads in flight at once,
+        // then one taken per step and the rest moved down a register
+        uint32_t evi[ITEMS];
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) evi[k] = 0;
+        if (a.event_verdict) {
+            const uint4* wp = reinterpret_cast<const uint4*>(a.words + (r.cnt ? my0 : 0));
+#pragma unroll
+            for (int k = 0; k < ITEMS / 2; ++k) {
+                const uint4 v = wp[k];
+                evi[2 * k] = (uint32_t)((((uint64_t)v.y << 32) | v.x) >> a.index_shift) & a.index_mask;
+                evi[2 * k + 1] = (uint32_t)((((uint64_t)v.w << 32) | v.z) >> a.index_shift) & a.index_mask;
+            }
+        }
 #pragma unroll 1
         for (uint32_t j = 0; j < r.cnt; ++j) {
             // both halves shifted before the choice (no indexed register array)
@@ -573,7 +589,9 @@ __global__ __launch_bounds__(kMsThreads) void k_ms_down(ScanArgs a) {
             const uint32_t pos = (uint32_t)(my0 + j);
             const bool conc_out = a.inst_conc && id < a.inst_limit;
             if (conc_out && hd && structure) a.inst_start[id] = pos;
-            const uint64_t ev = a.event_verdict ? (a.words[pos] >> a.index_shift) & a.index_mask : 0ull;
+            const uint64_t ev = evi[0];
+#pragma unroll
+            for (int k = 0; k + 1 < ITEMS; ++k) evi[k] = evi[k + 1];
 #pragma unroll
             for (int p = 0; p < PMAX; ++p) {
                 if (p >= (int)P) continue;
@@ -683,7 +701,8 @@ static void launch_ms_t(const ScanArgs& a, hipStream_t s) {
     }
     ScanArgs d = r;
     d.read_desc = 1;
-    hipLaunchKernelGGL((k_ms_down<PMAX, MW, ITEMS>), grid, dim3(kMsThreads), 0, s, d);
+    if (a.inst_conc || a.event_verdict) hipLaunchKernelGGL((k_ms_down<PMAX, MW, ITEMS, true>), grid, dim3(kMsThreads), 0, s, d);
+    else hipLaunchKernelGGL((k_ms_down<PMAX, MW, ITEMS, false>), grid, dim3(kMsThreads), 0, s, d);
 }
 
 template <int ITEMS>
