@@ -1,21 +1,23 @@
 // The segmented transition-map scan (Def. 6: the state of every instance
 // after its cluster, composed as maps so that a cluster may spread over any
-// number of lanes and tiles), in three launches without look-back:
-//   reduce  per tile of 8,192 sorted words: every thread composes the maps of
-//           its 32 consecutive words (a head restarts from q0), the block
-//           scans the threads in order; the tile's map per property and its
-//           head counts per level go to `agg`, every thread's exclusive prefix
-//           within the tile to `trec`;
-//   spine   one block: exclusive prefixes of the tile records in tile order;
+// number of lanes and tiles), in three steps without look-back:
+//   reduce  per tile of 4,096 or 8,192 sorted words: every thread composes the
+//           maps of its 16 or 32 consecutive words (a head restarts from q0),
+//           the block scans the threads in order; the tile's map per property
+//           and its head counts per level go to `agg`, every thread's
+//           exclusive prefix within the tile to `trec`;
+//   spine   exclusive prefixes of the tile records in tile order: one block,
+//           or, for many tiles, chunk compositions, their scan and the tile
+//           prefixes of every chunk (three launches);
 //   down    per tile: every thread starts from its prefix (tile prefix, then
 //           its own), steps its states word by word and writes instance
-//           verdicts, parents, numbering and nodes.
-// Words are read as 32 consecutive 64-bit words per thread with 16-byte loads
-// (no LDS staging).  The first reduce writes one descriptor byte per word
+//           verdicts, parents, numbering and nodes (and, on request, the
+//           verdict timeline).
+// Words are read as 16 or 32 consecutive 64-bit words per thread with 16-byte
+// loads (no LDS staging).  The first reduce writes one descriptor byte per word
 // (class, head and level-head flags); the down sweep and the launches of
 // further property groups read those instead of the words.  No tile waits on
-// another, so several tiles share a CU, and a trace of 10 M words is about one
-// round of tiles.
+// another, so several tiles share a CU.
 #include "internal.h"
 #include "maps.h"
 
