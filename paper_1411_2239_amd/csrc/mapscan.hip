@@ -106,13 +106,19 @@ __device__ __forceinline__ void store_desc(const ScanArgs& a, uint64_t my0, cons
     }
 }
 
-__device__ __forceinline__ void decode(Run& r, int j, uint32_t b) {
-    const uint64_t cj = (uint64_t)(b & 15u) << (4 * (j & 15));
-    if (j < 16) r.cls[0] |= cj;
-    else r.cls[1] |= cj;
-    r.m_head |= ((b >> 4) & 1u) << j;
-#pragma unroll
-    for (int m = 1; m < kMaxLevels; ++m) r.m_lvl[m] |= ((b >> (4 + m)) & 1u) << j;
+// Four words' descriptor bytes (one dword) at once: the low nibbles packed
+// into 16 bits (the classes), the high nibbles as a transposed 4 x 4 bit
+// matrix, so that nibble f holds flag f (head, level-1..3 head) of the four
+// words.
+__device__ __forceinline__ uint32_t pack_nibbles(uint32_t x) {   // nibbles at bits 0, 8, 16, 24
+    x = (x | (x >> 4)) & 0x00FF00FFu;
+    return (x | (x >> 8)) & 0xFFFFu;
+}
+__device__ __forceinline__ uint32_t transpose4x4(uint32_t y) {   // bit 4k + f -> bit 4f + k
+    uint32_t t = ((y >> 3) ^ y) & 0x0A0Au;
+    y ^= t ^ (t << 3);
+    t = ((y >> 6) ^ y) & 0x00CCu;
+    return y ^ t ^ (t << 6);
 }
 
 template <int ITEMS>
@@ -120,15 +126,30 @@ __device__ __forceinline__ Run run_from_desc(const ScanArgs& a, uint64_t my0, ui
     // (the descriptor buffer has room for a whole run past the last word)
     Run r{};
     r.cnt = my0 < n ? (uint32_t)min<uint64_t>(ITEMS, n - my0) : 0u;
-    const uint32_t valid = valid_mask(r.cnt);
     const uint4* q = reinterpret_cast<const uint4*>(a.desc + (r.cnt ? my0 : 0));
 #pragma unroll
     for (int i = 0; i < ITEMS / 16; ++i) {
         const uint4 v = q[i];
-        const uint32_t d[4] = {v.x, v.y, v.z, v.w};
+        uint32_t d[4] = {v.x, v.y, v.z, v.w};
+        if (r.cnt < ITEMS) {
+            // the bytes of words past the end read as 0
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
-            decode(r, 16 * i + j, ((valid >> (16 * i + j)) & 1u) ? (d[j >> 2] >> (8 * (j & 3))) & 0xFFu : 0u);
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t s0 = 16u * i + 4u * k;
+                d[k] = s0 >= r.cnt ? 0u : s0 + 4u > r.cnt ? d[k] & ((1u << (8u * (r.cnt - s0))) - 1u) : d[k];
+            }
+        }
+        uint64_t c = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            c |= (uint64_t)pack_nibbles(d[k] & 0x0F0F0F0Fu) << (16 * k);
+            const uint32_t f = transpose4x4(pack_nibbles((d[k] >> 4) & 0x0F0F0F0Fu));
+            const int at = 16 * i + 4 * k;
+            r.m_head |= (f & 15u) << at;
+#pragma unroll
+            for (int m = 1; m < kMaxLevels; ++m) r.m_lvl[m] |= ((f >> (4 * m)) & 15u) << at;
+        }
+        r.cls[i] = c;
     }
     return r;
 }
@@ -531,28 +552,48 @@ __global__ __launch_bounds__(kMsThreads) void k_ms_down(ScanArgs a) {
     const uint32_t lpar = L >= 4 ? 3u : L == 3 ? 2u : 1u;
     const uint32_t par_tile = tcnt[lpar] - 1u, par_local = cexcl[lpar];
     uint32_t my_lo = 0xFFFFFFFFu, my_hi = 0u, err = 0;
+    // First every word's state, without branches (the class maps' LDS reads
+    // do not wait on the instance bookkeeping): 4 bits per word and property.
+    uint64_t st[PMAX][ITEMS / 16];
 #pragma unroll
+    for (int p = 0; p < PMAX; ++p)
+#pragma unroll
+        for (int h = 0; h < ITEMS / 16; ++h) st[p][h] = 0;
+#pragma clang loop unroll(full)
     for (int j = 0; j < ITEMS; ++j) {
         const uint32_t c = run_class(r, j);
         const bool hd = (r.m_head >> j) & 1u;
-#pragma unroll
-        for (int p = 0; p < PMAX; ++p)
-            if (p < (int)P) cur[p] = bm_at<MW>(bm_load<MW>(s_cm[p][c]), hd ? s_q0[p] : cur[p]);
-        if ((m_end >> j) & 1u) {
-            const uint32_t upto = j == 31 ? kAll : (2u << j) - 1u;
-            const uint32_t slot = cexcl[0] + __popc(r.m_head & upto);     // 1-based, within the tile
-            const uint64_t id = (uint64_t)id_base + slot - 1u;
-            if (id < a.inst_limit) {
-#pragma unroll
-                for (int p = 0; p < PMAX; ++p)
-                    if (p < (int)P) s_iv[p * kIvStride + slot] = (s_lab[p][cur[p] >> 3] >> (4 * (cur[p] & 7u))) & 15u;
-                if (kParents && L >= 2) s_par[slot] = (uint16_t)(par_local + __popc(m_par & upto));
-                my_lo = min(my_lo, (uint32_t)id);
-                my_hi = max(my_hi, (uint32_t)id + 1u);
-                if (structure && a.inst_keys) a.inst_keys[id] = a.words[my0 + j] >> a.cbits;
-            } else {
-                err |= kErrCapacity;
+#pragma clang loop unroll(full)
+        for (int p = 0; p < PMAX; ++p) {    // (a launch has at least one property)
+            if (p > 0 && p >= (int)P) continue;
+            cur[p] = bm_at<MW>(bm_load<MW>(s_cm[p][c]), hd ? s_q0[p] : cur[p]);
+            st[p][j >> 4] |= (uint64_t)cur[p] << (4 * (j & 15));
+        }
+    }
+    // Then the instances ending in the run, one loop step per end.
+    for (uint32_t rest = m_end; rest != 0u; rest &= rest - 1u) {
+        const uint32_t j = (uint32_t)__ffs(rest) - 1u;
+        const uint32_t upto = j == 31u ? kAll : (2u << j) - 1u;
+        const uint32_t slot = cexcl[0] + __popc(r.m_head & upto);     // 1-based, within the tile
+        const uint64_t id = (uint64_t)id_base + slot - 1u;
+        if (id < a.inst_limit) {
+            const uint32_t sh = 4u * (j & 15u);
+#pragma clang loop unroll(full)
+            for (int p = 0; p < PMAX; ++p) {
+                if (p > 0 && p >= (int)P) continue;
+                // both halves shifted before the choice, and kept apart so that
+                // the choice is not turned into an indexed register array
+                uint32_t s0 = (uint32_t)(st[p][0] >> sh) & 15u, s1 = (uint32_t)(st[p][ITEMS / 16 - 1] >> sh) & 15u;
+                asm("" : "+v"(s0), "+v"(s1));
+                const uint32_t q = ITEMS > 16 && j >= 16u ? s1 : s0;
+                s_iv[p * kIvStride + slot] = (s_lab[p][q >> 3] >> (4 * (q & 7u))) & 15u;
             }
+            if (kParents && L >= 2) s_par[slot] = (uint16_t)(par_local + __popc(m_par & upto));
+            my_lo = min(my_lo, (uint32_t)id);
+            my_hi = max(my_hi, (uint32_t)id + 1u);
+            if (structure && a.inst_keys) a.inst_keys[id] = a.words[my0 + j] >> a.cbits;
+        } else {
+            err |= kErrCapacity;
         }
     }
     // On request, the verdict timeline: a second walk from the thread's
