@@ -155,22 +155,30 @@ __device__ __forceinline__ Run run_from_desc(const ScanArgs& a, uint64_t my0, ui
 }
 
 // The composed map of a run per property: a head restarts the monitor at q0.
-template <int PMAX, int MW, int ITEMS>
-__device__ __forceinline__ void run_maps(const Run& r, uint32_t P, const uint32_t (*s_cm)[16][MW], const uint32_t* s_q0,
-                                         BMap<MW>* f) {
-    const uint32_t valid = valid_mask(r.cnt);
+// FULL: every word of the run is valid (all threads but the trace's last).
+template <int PMAX, int MW, int ITEMS, bool FULL>
+__device__ __forceinline__ void run_maps_t(const Run& r, uint32_t P, const uint32_t (*s_cm)[16][MW],
+                                           const uint32_t* s_q0, BMap<MW>* f) {
+    const uint32_t valid = FULL ? kAll : valid_mask(r.cnt);
 #pragma unroll
     for (int p = 0; p < PMAX; ++p) {
         f[p] = bm_identity<MW>();
-        if (p >= (int)P) continue;
+        if (p > 0 && p >= (int)P) continue;    // (a launch has at least one property)
         const BMap<MW> start = bm_const<MW>(s_q0[p]);
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             const BMap<MW> cm = bm_load<MW>(s_cm[p][run_class(r, j)]);
             const BMap<MW> g = bm_compose<MW>(cm, ((r.m_head >> j) & 1u) ? start : f[p]);
-            if ((valid >> j) & 1u) f[p] = g;
+            if (FULL || ((valid >> j) & 1u)) f[p] = g;
         }
     }
+}
+template <int PMAX, int MW, int ITEMS>
+__device__ __forceinline__ void run_maps(const Run& r, uint32_t P, const uint32_t (*s_cm)[16][MW], const uint32_t* s_q0,
+                                         BMap<MW>* f) {
+    // (four 16-state maps keep the one path: the second copy costs them registers)
+    if (PMAX * MW <= 8 && r.cnt == ITEMS) run_maps_t<PMAX, MW, ITEMS, true>(r, P, s_cm, s_q0, f);
+    else run_maps_t<PMAX, MW, ITEMS, false>(r, P, s_cm, s_q0, f);
 }
 
 // The class maps of the launch's properties, one table word per thread
