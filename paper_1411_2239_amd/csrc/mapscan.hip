@@ -613,7 +613,6 @@ __global__ __launch_bounds__(kMsThreads) void k_ms_down(ScanArgs a) {
     // The verdict after every event goes to the event's trace index, which
     // rides in the word between class and key.
     if (timeline) {
-        const uint64_t cls0 = r.cls[0], cls1 = r.cls[1];
         // trace indices of the thread's words: all loads in flight at once,
         // then one taken per step and the rest moved down a register
         uint32_t evi[ITEMS];
@@ -628,12 +627,19 @@ __global__ __launch_bounds__(kMsThreads) void k_ms_down(ScanArgs a) {
                 evi[2 * k + 1] = (uint32_t)((((uint64_t)v.w << 32) | v.z) >> a.index_shift) & a.index_mask;
             }
         }
+        // the states come from the first walk (4 bits per word), the labels
+        // of the states from registers
+        uint32_t lab[PMAX][2], q0v[PMAX], prev[PMAX];
+#pragma unroll
+        for (int p = 0; p < PMAX; ++p) {
+            lab[p][0] = s_lab[p][0];
+            lab[p][1] = s_lab[p][1];
+            q0v[p] = s_q0[p];
+            prev[p] = cur0[p];
+        }
 #pragma unroll 1
         for (uint32_t j = 0; j < r.cnt; ++j) {
-            // both halves shifted before the choice (no indexed register array)
-            const uint32_t sh = 4 * (j & 15u);
-            const uint32_t c0 = (uint32_t)(cls0 >> sh) & 15u, c1 = (uint32_t)(cls1 >> sh) & 15u;
-            const uint32_t c = j < 16u ? c0 : c1;
+            const uint32_t sh = 4u * (j & 15u);
             const bool hd = (r.m_head >> j) & 1u, end = (m_end >> j) & 1u;
             const uint32_t upto = j == 31u ? kAll : (2u << j) - 1u;
             const uint64_t id = (uint64_t)id_base + cexcl[0] + __popc(r.m_head & upto) - 1u;
@@ -643,17 +649,21 @@ __global__ __launch_bounds__(kMsThreads) void k_ms_down(ScanArgs a) {
             const uint64_t ev = evi[0];
 #pragma unroll
             for (int k = 0; k + 1 < ITEMS; ++k) evi[k] = evi[k + 1];
-#pragma unroll
+#pragma clang loop unroll(full)
             for (int p = 0; p < PMAX; ++p) {
-                if (p >= (int)P) continue;
-                const uint32_t pre = hd ? s_q0[p] : cur0[p];
-                const uint32_t post = bm_at<MW>(bm_load<MW>(s_cm[p][c]), pre);
-                cur0[p] = post;
-                const uint32_t lpost = (s_lab[p][post >> 3] >> (4 * (post & 7u))) & 15u;
+                if (p > 0 && p >= (int)P) continue;
+                // both halves shifted before the choice, kept apart (no
+                // indexed register array)
+                uint32_t s0 = (uint32_t)(st[p][0] >> sh) & 15u, s1 = (uint32_t)(st[p][ITEMS / 16 - 1] >> sh) & 15u;
+                asm("" : "+v"(s0), "+v"(s1));
+                const uint32_t post = ITEMS > 16 && j >= 16u ? s1 : s0;
+                const uint32_t pre = hd ? q0v[p] : prev[p];
+                prev[p] = post;
+                const uint32_t lpost = ((post < 8u ? lab[p][0] : lab[p][1]) >> (4u * (post & 7u))) & 15u;
                 if (a.event_verdict) a.event_verdict[a.prop_idx[p] * a.n_events + ev] = (uint8_t)lpost;
                 if (!conc_out) continue;
                 uint32_t* out = a.inst_conc + a.prop_idx[p] * a.inst_stride + id;
-                const uint32_t lpre = (s_lab[p][pre >> 3] >> (4 * (pre & 7u))) & 15u;
+                const uint32_t lpre = ((pre < 8u ? lab[p][0] : lab[p][1]) >> (4u * (pre & 7u))) & 15u;
                 const bool cpre = lpre == 0u || lpre == 5u, cpost = lpost == 0u || lpost == 5u;
                 if (hd && cpre) *out = pos;
                 else if (cpost && !cpre) *out = pos + 1u;
