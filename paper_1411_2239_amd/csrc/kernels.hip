@@ -1731,11 +1731,15 @@ hipError_t launch_scan(const ScanArgs& a, int variant, hipStream_t s) {
 }
 
 hipError_t launch_count(const CountArgs& a, hipStream_t s) {
-    const uint64_t tile = (uint64_t)kCountThreads * (a.items >= 16 ? 16 : 2);
+    // the root level takes one child per thread: more blocks in flight
+    const uint32_t items = a.items >= 16 ? 16 : a.level == 0 ? 1 : 2;
+    const uint64_t tile = (uint64_t)kCountThreads * items;
     const uint64_t want = (a.child_limit + tile - 1) / tile;
     const uint32_t blocks = (uint32_t)(want < 2048 ? (want ? want : 1) : 2048);
-    if (a.items >= 16)
+    if (items == 16)
         hipLaunchKernelGGL(k_count_leaves, dim3(blocks), dim3(kCountThreads), 0, s, a);
+    else if (items == 1)
+        hipLaunchKernelGGL(k_count<1>, dim3(blocks), dim3(kCountThreads), 0, s, a);
     else
         hipLaunchKernelGGL(k_count<2>, dim3(blocks), dim3(kCountThreads), 0, s, a);
     return hipGetLastError();
