@@ -378,6 +378,38 @@ def tune_all(out_path, log=print):
     return found
 
 
+def copy_reference(per_kernel, n, reps=10, nbytes=512 << 20):
+    """A plain device-to-device copy of 512 MiB (torch's copy, the runtime's
+    blit kernel), timed with events on torch's stream: the HBM rate a streaming
+    read + write reaches in practice, beside the 8 TB/s peak.  The streaming
+    kernels' algorithmic rates are given as fractions of it."""
+    import torch
+
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0").fill_(1)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(reps):
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    del src, dst
+    torch.cuda.empty_cache()
+    t = sorted(times)[len(times) // 2]
+    rate = 2 * nbytes / t / 1e9
+    vs = {}
+    for k in ("classify", "sort_pass"):
+        if k in per_kernel:
+            kr = ALG_BYTES_PER_EVENT[k] * n / (per_kernel[k]["avg_us_per_launch"] * 1e-6) / 1e9
+            vs[k] = {"algorithmic_GBps": kr, "frac_of_copy": kr / rate}
+    return {"bytes_read": nbytes, "bytes_written": nbytes, "median_us": t * 1e6, "GBps": rate,
+            "frac_of_peak": rate / HBM_PEAK_GBS, "kernels": vs}
+
+
 def graphs_bench(reps=30, log=print):
     """One captured kernel sequence (hipGraph) per call against the same
     calls enqueued launch by launch: the socket trace (100k events, latency
@@ -811,6 +843,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    log("[bench] plain device copy for reference")
+    copy_ref = copy_reference(per_kernel, n)
+
     root = res.root_verdict.cpu().numpy().tolist()
     counts = res.root_counts.cpu().numpy().reshape(len(ids), 6).tolist()
 
@@ -859,6 +894,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(dom, prof[dom][1] / args.steps)},
+        "hbm_copy_reference": copy_ref,
         "scan_reduce_path": {"kernels": ["scan", "count"], "ms_per_step": scan_path_s * 1e3,
                              "frac_of_hbm_peak": scan_frac},
         "step_stats": step_stats,
