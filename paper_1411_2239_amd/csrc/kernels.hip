@@ -175,7 +175,8 @@ __device__ __forceinline__ bool pred_holds(uint32_t op, uint32_t x, uint32_t v) 
     }
 }
 
-template <int RDW, bool GROUP, bool PRED>
+// NK: the number of key levels when fixed at compile time (0: a.n_keys)
+template <int RDW, bool GROUP, bool PRED, int NK>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_classify(ClassifyArgs a) {
     __shared__ uint8_t s_cls[256];
     __shared__ uint8_t s_kp[256];
@@ -196,6 +197,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
     }
     __syncthreads();
     uint32_t err = 0, kept = 0, npar = 0;
+    const int nk = NK ? NK : (int)a.n_keys;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     // Records of one grid-stride step are loaded before any is processed, so
     // that each thread keeps U loads in flight.
@@ -212,9 +214,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
         uint32_t over = 0;
 #pragma unroll
         for (int m = 0; m < kMaxLevels; ++m) {
-            if (m < (int)a.n_keys) {
+            if (m < nk) {
                 const uint32_t b = a.key_bits[m];
-                const uint32_t v = par && m + 1 == (int)a.n_keys ? 0u : a.rank[m] ? a.rank[m][i] : f[m];
+                const uint32_t v = par && m + 1 == nk ? 0u : a.rank[m] ? a.rank[m][i] : f[m];
                 over |= b < 32 ? (v >> b) : 0u;
                 key = (key << b) | v;
             }
@@ -270,7 +272,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                 t = (dw[u][a.type_dw] >> a.type_shift) & a.type_mask;
 #pragma unroll
                 for (int m = 0; m < kMaxLevels; ++m)
-                    f[m] = m < (int)a.n_keys ? (dw[u][a.key_dw[m]] >> a.key_shift[m]) & a.key_mask[m] : 0u;
+                    f[m] = m < nk ? (dw[u][a.key_dw[m]] >> a.key_shift[m]) & a.key_mask[m] : 0u;
                 if (PRED) {
 #pragma unroll
                     for (int q = 0; q < 3; ++q)
@@ -283,7 +285,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void 
                 t = (rec[a.type_dw] >> a.type_shift) & a.type_mask;
 #pragma unroll
                 for (int m = 0; m < kMaxLevels; ++m)
-                    f[m] = m < (int)a.n_keys ? (rec[a.key_dw[m]] >> a.key_shift[m]) & a.key_mask[m] : 0u;
+                    f[m] = m < nk ? (rec[a.key_dw[m]] >> a.key_shift[m]) & a.key_mask[m] : 0u;
                 if (PRED) {
 #pragma unroll
                     for (int q = 0; q < 3; ++q)
@@ -1628,8 +1630,10 @@ hipError_t launch_zero(const ZeroArgs& a, uint32_t blocks, hipStream_t s) {
 
 template <int RDW, bool GROUP>
 static void launch_classify_t(const ClassifyArgs& a, uint32_t blocks, hipStream_t s) {
-    if (a.n_preds > 0) hipLaunchKernelGGL((k_classify<RDW, GROUP, true>), dim3(blocks), dim3(1024), 0, s, a);
-    else hipLaunchKernelGGL((k_classify<RDW, GROUP, false>), dim3(blocks), dim3(1024), 0, s, a);
+    if (a.n_preds > 0) hipLaunchKernelGGL((k_classify<RDW, GROUP, true, 0>), dim3(blocks), dim3(1024), 0, s, a);
+    else if (RDW == 4 && !GROUP && a.n_keys == 2) hipLaunchKernelGGL((k_classify<RDW, GROUP, false, 2>), dim3(blocks), dim3(1024), 0, s, a);
+    else if (RDW == 4 && !GROUP && a.n_keys == 1) hipLaunchKernelGGL((k_classify<RDW, GROUP, false, 1>), dim3(blocks), dim3(1024), 0, s, a);
+    else hipLaunchKernelGGL((k_classify<RDW, GROUP, false, 0>), dim3(blocks), dim3(1024), 0, s, a);
 }
 
 hipError_t launch_classify(const ClassifyArgs& a, hipStream_t s) {
